@@ -1,0 +1,28 @@
+"""CPU oracle for the KZG commit / accumulation-fold hot path.
+
+TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, obviously-correct
+Python big-integer statement of what the GPU library computes.  Only the test
+suite, the package smoke check and the CPU-baseline leg of the benchmark may
+import it; the product path never does, and it shares no code with the HIP
+kernels or their host library.
+
+Modules and what they follow (section names refer to the ZKTorch paper,
+"Compiling ML Inference to Zero-Knowledge Proofs via Parallel Proof
+Accumulation"):
+
+* ``field`` -- BN254 prime fields Fq (coordinates) and Fr (scalars); the paper
+  fixes BN254 (Experimental Setup) and writes p for the group order
+  (Preliminaries), which this code calls r.
+* ``g1``    -- affine short-Weierstrass group G1, [x]_1 = xG (Preliminaries).
+* ``msm``   -- KZG commit com = [f(tau)]_1 = sum_i f_i [tau^i]_1 as a naive sum of
+  scalar multiples, and its closed form (Polynomial Commitment).
+* ``ntt``   -- evaluations on H = {omega^i} (Foldable basic blocks), O(n^2) DFT,
+  plain recursive FFT, coset evaluation for the X^n - 1 quotients (Mul,
+  Poly-IOP), barycentric commit-from-evaluations.
+* ``fold``  -- the random linear combination gamma*v + v' of the accumulation
+  prover (Parallel Accumulation, prover step 5) and its tree schedule.
+* ``srs``   -- [tau^i]_1 for a known test trapdoor (Polynomial Commitment: srs).
+
+Every function here is pinned by a CPU test against something other than
+itself (closed forms, invariants, brute force); see ``tests/test_oracle_*``.
+"""

@@ -1,0 +1,98 @@
+"""Planted mistakes in the oracle (on the CPU) must be caught by its pins.
+
+Each case patches one plausible slip into an oracle function -- a swapped
+sign, a dropped special case, a transposed operand, an off-by-one index --
+and re-runs the pin that is meant to catch it, expecting it to fail.
+"""
+import random
+
+import pytest
+
+from oracle import field, fold, g1, msm, ntt, srs
+from tests import test_oracle_g1 as tg
+from tests import test_oracle_msm_fold as tm
+from tests import test_oracle_ntt as tn
+
+R = field.R
+
+
+def _fails(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+def test_swapped_butterfly_sign_is_caught(monkeypatch):
+    def bad_fft(a, w):
+        n = len(a)
+        if n == 1:
+            return [a[0] % R]
+        even, odd = bad_fft(a[0::2], w * w % R), bad_fft(a[1::2], w * w % R)
+        out, t, h = [0] * n, 1, n // 2
+        for j in range(h):
+            v = odd[j] * t % R
+            out[j], out[j + h] = (even[j] - v) % R, (even[j] + v) % R
+            t = t * w % R
+        return out
+    monkeypatch.setattr(ntt, "_fft", bad_fft)
+    _fails(tn.test_fft_equals_dft_and_inverse, random.Random(1), 3)
+
+
+def test_wrong_root_is_caught(monkeypatch):
+    good = ntt.root_of_unity
+    monkeypatch.setattr(ntt, "root_of_unity", lambda n: good(n) * good(n) % R)
+    _fails(tn.test_root_of_unity_is_primitive, 5)
+
+
+def test_dropped_coset_shift_is_caught(monkeypatch):
+    good = ntt.coset_evals
+    monkeypatch.setattr(ntt, "coset_evals", lambda c, lb, s=5: good(c, lb, 1))
+    _fails(tn.test_coset_equals_interleaved_small_transforms, random.Random(2))
+
+
+def test_missing_doubling_case_is_caught(monkeypatch):
+    def bad_add(p1, p2):
+        if p1 is None:
+            return p2
+        if p2 is None:
+            return p1
+        if p1[0] == p2[0]:
+            return None
+        lam = (p2[1] - p1[1]) * pow(p2[0] - p1[0], -1, field.P) % field.P
+        x3 = (lam * lam - p1[0] - p2[0]) % field.P
+        return (x3, (lam * (p1[0] - x3) - p1[1]) % field.P)
+    monkeypatch.setattr(g1, "add", bad_add)
+    _fails(tg.test_special_cases)
+
+
+def test_fold_operands_transposed_is_caught(monkeypatch):
+    monkeypatch.setattr(fold, "fold_pair",
+                        lambda gam, a, b: [g1.add(x, g1.mul(gam % R, y)) for x, y in zip(a, b)])
+    _fails(tm.test_extractor_identity, random.Random(3))
+
+
+def test_srs_index_shift_is_caught(monkeypatch):
+    monkeypatch.setattr(msm, "srs_msm_closed_form",
+                        lambda tau, s: g1.gen_mul(sum(int(c) * pow(tau, i + 1, R) for i, c in enumerate(s))))
+    _fails(tm.test_naive_msm_equals_closed_form_on_srs, random.Random(4))
+
+
+def test_dropped_flat_coefficient_is_caught(monkeypatch):
+    good = fold.flat_coefficients
+
+    def bad(m, gam):
+        s = good(m, gam)
+        s[0] = 1
+        return s
+    monkeypatch.setattr(fold, "flat_coefficients", bad)
+    _fails(tm.test_tree_equals_flat_on_points, random.Random(5), 5)
+
+
+def test_barycentric_missing_scale_is_caught(monkeypatch):
+    good = ntt.barycentric_eval
+    monkeypatch.setattr(ntt, "barycentric_eval", lambda v, x: good(v, x) * len(v) % R)
+    _fails(tn.test_barycentric_matches_interpolation, random.Random(6))
+
+
+def test_srs_generator_off_by_one_is_caught(monkeypatch):
+    monkeypatch.setattr(srs, "srs", lambda tau, n: [g1.gen_mul(pow(tau, i + 1, R)) for i in range(n)])
+    _fails(tm.test_srs_points, random.Random(7))
