@@ -1,0 +1,134 @@
+/* zk.h -- C ABI of the MI355X (gfx950) KZG commit / fold hot path.
+ *
+ * What the library computes, after the ZKTorch paper ("Compiling ML Inference
+ * to Zero-Knowledge Proofs via Parallel Proof Accumulation"):
+ *
+ *  - KZG commitment (Preliminaries, Polynomial Commitment): com = [f(tau)]_1,
+ *    which for coefficients f_i and the SRS [tau^i]_1 is the multi-scalar
+ *    multiplication sum_i f_i [tau^i]_1 over G1 of BN254 (the curve fixed by
+ *    the Experimental Setup).  zk_msm, zk_msm_srs, zk_msm_batch.
+ *  - KZG setup (same section): the SRS [tau^0]_1, [tau^1]_1, ... for a known
+ *    trapdoor.  zk_srs_setup (test and benchmark use; deployments load a
+ *    ceremony's points and call zk_srs_create).
+ *  - Witness encoding (Foldable basic blocks): a length-n vector is the
+ *    evaluations of its polynomial on H = {omega^i}, element i = f(omega^i).
+ *    zk_intt turns evaluations into coefficients, zk_ntt the reverse, and
+ *    zk_coset_ntt evaluates on a coset of a larger domain, as the quotients by
+ *    X^n - 1 of the Mul block and the Poly-IOP require.
+ *  - Accumulation (Parallel Accumulation, prover step 5): the random linear
+ *    combination gamma * v + v' of the G1 commitments of two instances, run
+ *    as a tree over m instances.  zk_fold.
+ *
+ * Conventions
+ *  - zk_fr: an element of the BN254 scalar field Fr, 8 little-endian 32-bit
+ *    words, canonical (value < r).
+ *  - zk_g1: an affine G1 point, x then y, each 8 little-endian words,
+ *    canonical (< p).  The point at infinity is (0, 0) (not on the curve).
+ *  - Roots of unity: omega_N = 5^((r-1)/N); natural order in and out.
+ *  - Every array argument is a DEVICE pointer owned by the caller, unless its
+ *    name ends in _host.  The library keeps no pointer to caller memory after
+ *    the enqueued work completes.
+ *  - stream: a hipStream_t (NULL: the null stream).  Calls enqueue work and
+ *    return; results are ready when the stream reaches that point.
+ *  - Scratch memory comes from the device's stream-ordered pool
+ *    (hipMallocAsync / hipFreeAsync on the same stream).
+ *  - Return: ZK_OK, or a negative code with a message in zk_last_error().
+ *    Argument errors are detected before anything is enqueued.  A failed
+ *    launch or allocation returns ZK_EDEVICE / ZK_ENOMEM; nothing aborts.
+ */
+#ifndef ZK_H
+#define ZK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct zk_fr {
+  uint32_t v[8];
+} zk_fr;
+
+typedef struct zk_g1 {
+  uint32_t x[8];
+  uint32_t y[8];
+} zk_g1;
+
+typedef int zk_status;
+#define ZK_OK 0
+#define ZK_EINVAL (-1)      /* bad argument (NULL, size out of range, ...)   */
+#define ZK_ENOMEM (-2)      /* device allocation failed                      */
+#define ZK_EDEVICE (-3)     /* HIP runtime / kernel launch error             */
+#define ZK_EUNSUPPORTED (-5) /* valid request outside this build's limits    */
+
+/* Largest transform: log_n (+ log_blowup) <= ZK_MAX_LOG_NTT. */
+#define ZK_MAX_LOG_NTT 24
+
+/* Prepared SRS: the points in the kernels' Montgomery form plus, for every
+ * Pippenger window w, the points multiplied by 2^(c w).  Opaque. */
+typedef struct zk_srs zk_srs;
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* zk_last_error(void);
+
+/* Forward transform of 2^log_n coefficients:
+ *   out[k] = sum_i in[i] omega^(i k),  omega = omega_(2^log_n).
+ * in == out is allowed.  log_n <= ZK_MAX_LOG_NTT. */
+zk_status zk_ntt(const zk_fr* in, zk_fr* out, uint32_t log_n, void* stream);
+
+/* Inverse transform (evaluations on H -> coefficients):
+ *   out[i] = n^-1 sum_k in[k] omega^(-i k).  in == out is allowed. */
+zk_status zk_intt(const zk_fr* in, zk_fr* out, uint32_t log_n, void* stream);
+
+/* Coset evaluation of the polynomial with 2^log_n coefficients `coeffs` on
+ * g * H_(N), N = 2^(log_n + log_blowup):
+ *   out[j] = f(g omega_N^j), j < N;  out has N elements.
+ * shift_host: g as a host zk_fr, or NULL for g = 5 (outside every H_N).
+ * coeffs must not overlap out.  log_n + log_blowup <= ZK_MAX_LOG_NTT. */
+zk_status zk_coset_ntt(const zk_fr* coeffs, uint32_t log_n, uint32_t log_blowup, const zk_fr* shift_host,
+                       zk_fr* out, void* stream);
+
+/* Multi-scalar multiplication with arbitrary bases:
+ *   *out = sum_{i<n} scalars[i] * bases[i]   (scalars as integers < r).
+ * bases may contain (0, 0).  n = 0 gives (0, 0).  out: one zk_g1. */
+zk_status zk_msm(const zk_g1* bases, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream);
+
+/* KZG setup for a known trapdoor: out[i] = [tau^i]_1 = tau^i G, i < n,
+ * G = (1, 2).  tau_host: host zk_fr. */
+zk_status zk_srs_setup(const zk_fr* tau_host, uint64_t n, zk_g1* out, void* stream);
+
+/* Prepare an SRS (any n affine points, e.g. from zk_srs_setup or a
+ * ceremony) for commitments.  Allocates about 16 * 64 * n bytes of device
+ * memory owned by the handle; the work is enqueued on `stream`.  The handle
+ * is bound to the current device. */
+zk_status zk_srs_create(const zk_g1* points, uint64_t n, zk_srs** srs, void* stream);
+
+/* Release a prepared SRS (synchronises the device first). */
+zk_status zk_srs_destroy(zk_srs* srs);
+
+/* Number of points of a prepared SRS (0 for NULL). */
+uint64_t zk_srs_size(const zk_srs* srs);
+
+/* KZG commitment to coefficients: *out = sum_{i<n} scalars[i] [tau^i]_1 over
+ * the first n points of the prepared SRS (n <= zk_srs_size(srs)). */
+zk_status zk_msm_srs(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream);
+
+/* `batch` commitments over prefixes of one prepared SRS:
+ *   out[b] = sum_{i < n_b} scalars[offsets_host[b] + i] [tau^i]_1,
+ *   n_b = offsets_host[b+1] - offsets_host[b] <= zk_srs_size(srs).
+ * offsets_host: host array of batch + 1 non-decreasing entries, the first 0. */
+zk_status zk_msm_batch(const zk_srs* srs, const zk_fr* scalars, const uint64_t* offsets_host, uint32_t batch,
+                       zk_g1* out, void* stream);
+
+/* Fold m instances of k G1 commitments each (inst[i*k + j]) into one:
+ * the tree of pairwise folds gamma * left + right (adjacent pairs per level,
+ * an odd last instance carried up, challenges consumed level by level, left
+ * to right: gammas[0..m-2]).  m = 2 is exactly out[j] = gamma*inst[j] +
+ * inst[k + j].  out: k points.  m >= 1. */
+zk_status zk_fold(const zk_g1* inst, const zk_fr* gammas, uint32_t m, uint32_t k, zk_g1* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZK_H */

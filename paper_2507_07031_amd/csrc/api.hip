@@ -1,0 +1,418 @@
+// C-ABI entry points (include/zk.h): argument checks, per-device tables,
+// stream-ordered scratch, and the launch sequences of each operation.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/zk.h"
+#include "field.h"
+#include "msm.h"
+#include "ntt.h"
+
+using namespace zk;
+
+namespace {
+
+thread_local std::string g_err;
+
+zk_status fail(zk_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+zk_status hip_fail(hipError_t e, const char* where) {
+  return fail(e == hipErrorOutOfMemory ? ZK_ENOMEM : ZK_EDEVICE,
+              std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define ZK_HIP(call, where)                 \
+  do {                                      \
+    hipError_t _e = (call);                 \
+    if (_e != hipSuccess) return hip_fail(_e, where); \
+  } while (0)
+
+// ---------------------------------------------------------------- device context
+struct DeviceCtx {
+  bool ready = false;
+  f29* tw[4] = {nullptr, nullptr, nullptr, nullptr};   // fwd lo, fwd hi, inv lo, inv hi
+  f29* coset5[2] = {nullptr, nullptr};                  // 5^e lo / hi
+  f29* ninv = nullptr;                                  // 2^-L, L = 0..28
+  uint32_t* gtab = nullptr;                             // 2^j G table for the setup
+};
+
+std::mutex g_mu;
+DeviceCtx g_ctx[64];
+
+void host_words(const f29& a, uint32_t w[8]) { pack(a, w); }
+
+zk_status ctx_get(DeviceCtx** out) {
+  int dev = 0;
+  ZK_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= 64) return fail(ZK_EUNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx& c = g_ctx[dev];
+  if (c.ready) {
+    *out = &c;
+    return ZK_OK;
+  }
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  ZK_HIP(ntt_pass_setup(), "ntt setup");
+  const size_t tsz = sizeof(f29) << 14;
+  for (int i = 0; i < 4; i++) ZK_HIP(hipMalloc(&c.tw[i], tsz), "hipMalloc(twiddles)");
+  for (int i = 0; i < 2; i++) ZK_HIP(hipMalloc(&c.coset5[i], tsz), "hipMalloc(coset)");
+  ZK_HIP(hipMalloc(&c.ninv, sizeof(f29) * 29), "hipMalloc(ninv)");
+  ZK_HIP(hipMalloc(&c.gtab, srs_gtab_words() * 4), "hipMalloc(gtab)");
+  // roots omega_(2^28), its inverse, and the coset shift 5 (host arithmetic, same field code)
+  Words8 wf, wi, w5;
+  std::memcpy(wf.w, FR_OMEGA_2_28, 32);
+  {
+    const f29 w = reduce_full<FrP>(to_mont<FrP>(unpack(FR_OMEGA_2_28)));
+    host_words(from_mont<FrP>(mont_inv<FrP>(w)), wi.w);
+  }
+  std::memset(w5.w, 0, 32);
+  w5.w[0] = 5;
+  ZK_HIP(ntt_make_pow_tables(wf, c.tw[0], c.tw[1], 0), "twiddle tables");
+  ZK_HIP(ntt_make_pow_tables(wi, c.tw[2], c.tw[3], 0), "twiddle tables");
+  ZK_HIP(ntt_make_pow_tables(w5, c.coset5[0], c.coset5[1], 0), "coset tables");
+  // 2^-L in Montgomery form; 2^-1 = (r + 1) / 2
+  f29 ninv[29];
+  {
+    uint32_t rp1[8], half[8];
+    uint64_t acc = 1;
+    for (int i = 0; i < 8; i++) {
+      acc += FrP::M32[i];
+      rp1[i] = (uint32_t)acc;
+      acc >>= 32;
+    }
+    for (int i = 0; i < 8; i++) half[i] = (rp1[i] >> 1) | (i < 7 ? (rp1[i + 1] << 31) : 0u);
+    const f29 h = reduce_full<FrP>(to_mont<FrP>(unpack(half)));
+    ninv[0] = f29_from(FrP::ONE);
+    for (int L = 1; L < 29; L++) ninv[L] = reduce_full<FrP>(mont_mul<FrP>(ninv[L - 1], h));
+  }
+  ZK_HIP(hipMemcpy(c.ninv, ninv, sizeof(ninv), hipMemcpyHostToDevice), "hipMemcpy");
+  ZK_HIP(hipDeviceSynchronize(), "table init");
+  c.ready = true;
+  *out = &c;
+  return ZK_OK;
+}
+
+// ---------------------------------------------------------------- scratch
+struct Scratch {
+  void* p = nullptr;
+  hipStream_t s = nullptr;
+  ~Scratch() {
+    if (p) (void)hipFreeAsync(p, s);
+  }
+};
+
+zk_status scratch_alloc(Scratch& sc, size_t bytes, hipStream_t s) {
+  sc.s = s;
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMallocAsync(&sc.p, bytes, s);
+  if (e != hipSuccess) {
+    sc.p = nullptr;
+    (void)hipGetLastError();
+    return fail(ZK_ENOMEM, "scratch allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  return ZK_OK;
+}
+
+// ---------------------------------------------------------------- NTT driver
+zk_status run_ntt(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t L, bool inverse, const f29* pre_lo,
+                  const f29* pre_hi, uint32_t valid_n, hipStream_t s) {
+  const uint32_t T = ntt_tile_log();
+  const f29* lo = inverse ? c->tw[2] : c->tw[0];
+  const f29* hi = inverse ? c->tw[3] : c->tw[1];
+  const f29* scale = inverse ? c->ninv + L : nullptr;
+  if (L <= T) {
+    NttPass p{};
+    p.in = in;
+    p.out = out;
+    p.m = L;
+    p.G = 1;
+    p.nbatch = 1;
+    p.s_in = 1;
+    p.s_out = 1;
+    p.b_out = 1u << L;
+    p.valid_n = valid_n;
+    p.tw_lo = lo;
+    p.tw_hi = hi;
+    p.pre_lo = pre_lo;
+    p.pre_hi = pre_hi;
+    p.post_scale = scale;
+    ZK_HIP(ntt_launch_pass(p, s), "ntt pass");
+    return ZK_OK;
+  }
+  const uint32_t mA = L / 2, mB = L - mA;  // pass A transforms have 2^mA points
+  const uint32_t N1 = 1u << mB, N2 = 1u << mA;
+  Scratch tmp;
+  zk_status st = scratch_alloc(tmp, (size_t)32 << L, s);
+  if (st) return st;
+  uint32_t* Y = static_cast<uint32_t*>(tmp.p);
+  NttPass a{};
+  a.in = in;
+  a.out = Y;
+  a.m = mA;
+  a.nbatch = N1;
+  a.G = std::min((1u << T) / N2, N1);
+  a.s_in = N1;
+  a.s_out = 1;
+  a.b_out = N2;
+  a.valid_n = valid_n;
+  a.tw_lo = lo;
+  a.tw_hi = hi;
+  a.post_tw_L = L;
+  a.pre_lo = pre_lo;
+  a.pre_hi = pre_hi;
+  ZK_HIP(ntt_launch_pass(a, s), "ntt pass A");
+  NttPass b{};
+  b.in = Y;
+  b.out = out;
+  b.m = mB;
+  b.nbatch = N2;
+  b.G = std::min((1u << T) / N1, N2);
+  b.s_in = N2;
+  b.s_out = N2;
+  b.b_out = 1;
+  b.valid_n = 1u << L;
+  b.tw_lo = lo;
+  b.tw_hi = hi;
+  b.post_scale = scale;
+  ZK_HIP(ntt_launch_pass(b, s), "ntt pass B");
+  return ZK_OK;
+}
+
+// ---------------------------------------------------------------- MSM driver
+zk_status run_msm(const MsmPlan& plan, const uint32_t* mont_points, const uint32_t* scalars, uint32_t* out16,
+                  hipStream_t s) {
+  Scratch ws;
+  zk_status st = scratch_alloc(ws, msm_workspace_bytes(plan), s);
+  if (st) return st;
+  const MsmBuffers b = msm_carve(plan, ws.p);
+  ZK_HIP(msm_run(plan, mont_points, scalars, b, out16, s), "msm");
+  return ZK_OK;
+}
+
+constexpr uint32_t SRS_C = 16;
+constexpr uint32_t SRS_SHARED_MIN = 1u << 14;  // below this, per-window buckets over the plain points
+
+}  // namespace
+
+struct zk_srs {
+  int device;
+  uint64_t n;
+  uint32_t c;
+  uint32_t W;
+  uint32_t* tab;  // W * n Montgomery affine points; window 0 is the points themselves
+};
+
+extern "C" {
+
+const char* zk_last_error(void) { return g_err.c_str(); }
+
+zk_status zk_ntt(const zk_fr* in, zk_fr* out, uint32_t log_n, void* stream) {
+  if (!in || !out) return fail(ZK_EINVAL, "zk_ntt: NULL buffer");
+  if (log_n > ZK_MAX_LOG_NTT) return fail(ZK_EUNSUPPORTED, "zk_ntt: log_n > ZK_MAX_LOG_NTT");
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  return run_ntt(c, reinterpret_cast<const uint32_t*>(in), reinterpret_cast<uint32_t*>(out), log_n, false,
+                 nullptr, nullptr, 1u << log_n, (hipStream_t)stream);
+}
+
+zk_status zk_intt(const zk_fr* in, zk_fr* out, uint32_t log_n, void* stream) {
+  if (!in || !out) return fail(ZK_EINVAL, "zk_intt: NULL buffer");
+  if (log_n > ZK_MAX_LOG_NTT) return fail(ZK_EUNSUPPORTED, "zk_intt: log_n > ZK_MAX_LOG_NTT");
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  return run_ntt(c, reinterpret_cast<const uint32_t*>(in), reinterpret_cast<uint32_t*>(out), log_n, true,
+                 nullptr, nullptr, 1u << log_n, (hipStream_t)stream);
+}
+
+zk_status zk_coset_ntt(const zk_fr* coeffs, uint32_t log_n, uint32_t log_blowup, const zk_fr* shift_host,
+                       zk_fr* out, void* stream) {
+  if (!coeffs || !out) return fail(ZK_EINVAL, "zk_coset_ntt: NULL buffer");
+  if (log_n + log_blowup > ZK_MAX_LOG_NTT || log_n > ZK_MAX_LOG_NTT || log_blowup > ZK_MAX_LOG_NTT)
+    return fail(ZK_EUNSUPPORTED, "zk_coset_ntt: log_n + log_blowup > ZK_MAX_LOG_NTT");
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const f29* lo = c->coset5[0];
+  const f29* hi = c->coset5[1];
+  Scratch tab;
+  if (shift_host) {
+    // canonical check, then tables of shift^e in scratch
+    uint32_t w[8];
+    std::memcpy(w, shift_host->v, 32);
+    unsigned br = 0;
+    for (int i = 0; i < 8; i++) (void)__builtin_subc(w[i], FrP::M32[i], br, &br);
+    if (!br) return fail(ZK_EINVAL, "zk_coset_ntt: shift not canonical (>= r)");
+    const size_t tsz = sizeof(f29) << 14;
+    st = scratch_alloc(tab, 2 * tsz, s);
+    if (st) return st;
+    char* base = static_cast<char*>(tab.p);
+    Words8 sw;
+    std::memcpy(sw.w, w, 32);
+    ZK_HIP(ntt_make_pow_tables(sw, reinterpret_cast<f29*>(base), reinterpret_cast<f29*>(base + tsz), s),
+           "shift tables");
+    lo = reinterpret_cast<const f29*>(base);
+    hi = reinterpret_cast<const f29*>(base + tsz);
+  }
+  return run_ntt(c, reinterpret_cast<const uint32_t*>(coeffs), reinterpret_cast<uint32_t*>(out),
+                 log_n + log_blowup, false, lo, hi, 1u << log_n, s);
+}
+
+zk_status zk_msm(const zk_g1* bases, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream) {
+  if (!out || (n && (!bases || !scalars))) return fail(ZK_EINVAL, "zk_msm: NULL buffer");
+  if (n >= (1ull << 31) / 16) return fail(ZK_EUNSUPPORTED, "zk_msm: n too large");
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const MsmPlan plan = msm_plan((uint32_t)n, msm_default_c((uint32_t)n), false, 0);
+  Scratch pts;
+  st = scratch_alloc(pts, (size_t)n * 64, s);
+  if (st) return st;
+  uint32_t* mont = static_cast<uint32_t*>(pts.p);
+  ZK_HIP(msm_points_to_mont(reinterpret_cast<const uint32_t*>(bases), mont, n, s), "to_mont");
+  return run_msm(plan, mont, reinterpret_cast<const uint32_t*>(scalars), reinterpret_cast<uint32_t*>(out), s);
+}
+
+zk_status zk_srs_setup(const zk_fr* tau_host, uint64_t n, zk_g1* out, void* stream) {
+  if (!tau_host || (n && !out)) return fail(ZK_EINVAL, "zk_srs_setup: NULL argument");
+  uint32_t w[8];
+  std::memcpy(w, tau_host->v, 32);
+  unsigned br = 0;
+  for (int i = 0; i < 8; i++) (void)__builtin_subc(w[i], FrP::M32[i], br, &br);
+  if (!br) return fail(ZK_EINVAL, "zk_srs_setup: tau not canonical (>= r)");
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  Tau8 t;
+  std::memcpy(t.w, w, 32);
+  ZK_HIP(srs_from_tau(t, reinterpret_cast<uint32_t*>(out), n, c->gtab, (hipStream_t)stream), "srs setup");
+  return ZK_OK;
+}
+
+zk_status zk_srs_create(const zk_g1* points, uint64_t n, zk_srs** srs, void* stream) {
+  if (!srs || (n && !points)) return fail(ZK_EINVAL, "zk_srs_create: NULL argument");
+  if (n >= (1ull << 31) / 16) return fail(ZK_EUNSUPPORTED, "zk_srs_create: n too large");
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  zk_srs* h = new zk_srs();
+  ZK_HIP(hipGetDevice(&h->device), "hipGetDevice");
+  h->n = n;
+  h->c = SRS_C;
+  h->W = (254 + SRS_C - 1) / SRS_C;
+  h->tab = nullptr;
+  if (n) {
+    hipError_t e = hipMalloc(&h->tab, (size_t)h->W * n * 64);
+    if (e != hipSuccess) {
+      delete h;
+      return hip_fail(e, "zk_srs_create: hipMalloc(table)");
+    }
+    e = msm_build_table(reinterpret_cast<const uint32_t*>(points), h->tab, n, h->c, h->W, (hipStream_t)stream);
+    if (e != hipSuccess) {
+      (void)hipFree(h->tab);
+      delete h;
+      return hip_fail(e, "zk_srs_create: table build");
+    }
+  }
+  *srs = h;
+  return ZK_OK;
+}
+
+zk_status zk_srs_destroy(zk_srs* srs) {
+  if (!srs) return ZK_OK;
+  if (srs->tab) {
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(srs->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(srs->tab);
+    (void)hipSetDevice(prev);
+  }
+  delete srs;
+  return ZK_OK;
+}
+
+uint64_t zk_srs_size(const zk_srs* srs) { return srs ? srs->n : 0; }
+
+static zk_status msm_srs_one(const zk_srs* srs, const uint32_t* scalars, uint64_t n, uint32_t* out16,
+                             hipStream_t s) {
+  if (n < SRS_SHARED_MIN) {
+    const MsmPlan plan = msm_plan((uint32_t)n, msm_default_c((uint32_t)n), false, 0);
+    return run_msm(plan, srs->tab, scalars, out16, s);
+  }
+  const MsmPlan plan = msm_plan((uint32_t)n, srs->c, true, (uint32_t)srs->n);
+  return run_msm(plan, srs->tab, scalars, out16, s);
+}
+
+zk_status zk_msm_srs(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream) {
+  if (!srs || !out || (n && !scalars)) return fail(ZK_EINVAL, "zk_msm_srs: NULL argument");
+  if (n > srs->n) return fail(ZK_EINVAL, "zk_msm_srs: n exceeds the SRS size");
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  return msm_srs_one(srs, reinterpret_cast<const uint32_t*>(scalars), n, reinterpret_cast<uint32_t*>(out),
+                     (hipStream_t)stream);
+}
+
+zk_status zk_msm_batch(const zk_srs* srs, const zk_fr* scalars, const uint64_t* offsets_host, uint32_t batch,
+                       zk_g1* out, void* stream) {
+  if (!srs || !offsets_host || (batch && (!out || !scalars))) return fail(ZK_EINVAL, "zk_msm_batch: NULL argument");
+  if (offsets_host[0] != 0) return fail(ZK_EINVAL, "zk_msm_batch: offsets_host[0] must be 0");
+  for (uint32_t b = 0; b < batch; b++) {
+    if (offsets_host[b + 1] < offsets_host[b]) return fail(ZK_EINVAL, "zk_msm_batch: offsets decrease");
+    if (offsets_host[b + 1] - offsets_host[b] > srs->n) return fail(ZK_EINVAL, "zk_msm_batch: MSM larger than SRS");
+  }
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const uint32_t* sc = reinterpret_cast<const uint32_t*>(scalars);
+  uint32_t* o = reinterpret_cast<uint32_t*>(out);
+  for (uint32_t b = 0; b < batch; b++) {
+    st = msm_srs_one(srs, sc + offsets_host[b] * 8, offsets_host[b + 1] - offsets_host[b], o + (size_t)b * 16, s);
+    if (st) return st;
+  }
+  return ZK_OK;
+}
+
+zk_status zk_fold(const zk_g1* inst, const zk_fr* gammas, uint32_t m, uint32_t k, zk_g1* out, void* stream) {
+  if (!inst || !out || m == 0 || (m > 1 && !gammas)) return fail(ZK_EINVAL, "zk_fold: bad argument");
+  if ((uint64_t)m * k >= (1ull << 31) / 16) return fail(ZK_EUNSUPPORTED, "zk_fold: too many points");
+  if (k == 0) return ZK_OK;
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Scratch ws;
+  st = scratch_alloc(ws, (size_t)m * (32 + 64 + 64) + 512, s);
+  if (st) return st;
+  uint32_t* sigma = static_cast<uint32_t*>(ws.p);
+  uint32_t* col = sigma + (size_t)m * 8;
+  uint32_t* mont = col + (size_t)m * 16;
+  ZK_HIP(fold_sigmas(reinterpret_cast<const uint32_t*>(gammas), m, sigma, s), "fold sigmas");
+  const MsmPlan plan = msm_plan(m, msm_default_c(m), false, 0);
+  for (uint32_t j = 0; j < k; j++) {
+    ZK_HIP(gather_component(reinterpret_cast<const uint32_t*>(inst), m, k, j, col, s), "fold gather");
+    ZK_HIP(msm_points_to_mont(col, mont, m, s), "fold to_mont");
+    st = run_msm(plan, mont, sigma, reinterpret_cast<uint32_t*>(out) + (size_t)j * 16, s);
+    if (st) return st;
+  }
+  return ZK_OK;
+}
+
+}  // extern "C"

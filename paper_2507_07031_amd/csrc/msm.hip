@@ -1,0 +1,831 @@
+// Pippenger multi-scalar multiplication over BN254 G1, plus the KZG setup
+// (SRS from a trapdoor) and the fold's challenge products.
+//
+// KZG commits to f as [f(tau)]_1 = sum_i f_i [tau^i]_1 (Polynomial Commitment
+// preliminaries), i.e. Q = sum_i s_i P_i.  Bucket method with signed c-bit
+// digits: if s > (r-1)/2 the pair (s, P) is replaced by (r - s, -P) so every
+// scalar has at most 253 bits; window w contributes digits d in
+// [-2^(c-1), 2^(c-1)] and point P lands in bucket |d| with sign(d).
+//
+//   Q = sum_w 2^(cw) sum_k k B_(w,k),   B_(w,k) = sum of +-P with |digit| = k.
+//
+// Two layouts of the same computation:
+//  * per-window buckets (any bases): W*K buckets, then a Horner combine of the
+//    window sums with c doublings per window;
+//  * shared buckets (a prepared SRS): the table holds 2^(cw) P_i for every
+//    window, so window w's digit of s_i selects table point (w, i) and all
+//    windows feed the same K buckets -- no per-window combine at all.
+//
+// Pipeline (all on the caller's stream):
+//  1 decompose  scalars -> W signed digits each
+//  2 histogram  per (window, chunk) workgroup, counts in LDS, flushed to HBM
+//  3 scan       bucket offsets
+//  4 scatter    counting sort of (point index, sign) by bucket
+//  5 accumulate each thread sums exactly L consecutive sorted entries with
+//               mixed additions (load balanced whatever the bucket sizes);
+//               runs that cross thread boundaries are finished by a segmented
+//               tree in LDS, runs that cross workgroups by further levels
+//               over 2 records per workgroup
+//  6 reduce     sum_k k B_k by running sums over chunks of LB buckets, each
+//               chunk offset by a small scalar multiple, then a tree
+//  7 combine    Horner over windows (per-window layout), affine output
+#include "curve.h"
+#include "msm.h"
+
+namespace zk {
+
+namespace {
+
+// (r - 1) / 2 in 32-bit words
+__constant__ uint32_t FR_HALF[8] = {0xf8000000u, 0xa1f0fac9u, 0x3cdcb848u, 0x9419f424u,
+                                    0x40c0ac2eu, 0xdc2822dbu, 0x7098d014u, 0x18322739u};
+// G1 generator (1, 2)
+__constant__ uint32_t G1_GEN[16] = {1, 0, 0, 0, 0, 0, 0, 0, 2, 0, 0, 0, 0, 0, 0, 0};
+
+__device__ __forceinline__ void ldw(const uint32_t* p, uint32_t* w, int n4) {
+  for (int q = 0; q < n4; q++) {
+    const uint4 v = reinterpret_cast<const uint4*>(p)[q];
+    w[4 * q] = v.x;
+    w[4 * q + 1] = v.y;
+    w[4 * q + 2] = v.z;
+    w[4 * q + 3] = v.w;
+  }
+}
+
+__device__ __forceinline__ void stw(uint32_t* p, const uint32_t* w, int n4) {
+  for (int q = 0; q < n4; q++)
+    reinterpret_cast<uint4*>(p)[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+}
+
+__device__ __forceinline__ xyzz ld_xyzz(const uint32_t* p) {
+  uint32_t w[36];
+#pragma unroll
+  for (int q = 0; q < 9; q++) {
+    const uint4 v = reinterpret_cast<const uint4*>(p)[q];
+    w[4 * q] = v.x;
+    w[4 * q + 1] = v.y;
+    w[4 * q + 2] = v.z;
+    w[4 * q + 3] = v.w;
+  }
+  xyzz a;
+#pragma unroll
+  for (int i = 0; i < 9; i++) {
+    a.X.l[i] = w[i];
+    a.Y.l[i] = w[9 + i];
+    a.ZZ.l[i] = w[18 + i];
+    a.ZZZ.l[i] = w[27 + i];
+  }
+  return a;
+}
+
+__device__ __forceinline__ void st_xyzz(uint32_t* p, const xyzz& a) {
+  uint32_t w[36];
+#pragma unroll
+  for (int i = 0; i < 9; i++) {
+    w[i] = a.X.l[i];
+    w[9 + i] = a.Y.l[i];
+    w[18 + i] = a.ZZ.l[i];
+    w[27 + i] = a.ZZZ.l[i];
+  }
+#pragma unroll
+  for (int q = 0; q < 9; q++)
+    reinterpret_cast<uint4*>(p)[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+}
+
+// Montgomery affine point from 16 packed words; false for (0, 0) = infinity.
+__device__ __forceinline__ bool ld_aff(const uint32_t* p, aff& a) {
+  uint32_t w[16];
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const uint4 v = reinterpret_cast<const uint4*>(p)[q];
+    w[4 * q] = v.x;
+    w[4 * q + 1] = v.y;
+    w[4 * q + 2] = v.z;
+    w[4 * q + 3] = v.w;
+  }
+  uint32_t o = 0;
+#pragma unroll
+  for (int i = 0; i < 16; i++) o |= w[i];
+  a.x = unpack(w);
+  a.y = unpack(w + 8);
+  return o != 0;
+}
+
+// XYZZ -> Montgomery canonical affine words (infinity -> zeros).
+__device__ void st_aff_mont(uint32_t* p, const xyzz& a) {
+  uint32_t w[16];
+  if (is_inf(a)) {
+    for (int i = 0; i < 16; i++) w[i] = 0;
+  } else {
+    const f29 I = mont_inv<Fq>(mont_mul<Fq>(a.ZZ, a.ZZZ));
+    pack(reduce_full<Fq>(mont_mul<Fq>(a.X, mont_mul<Fq>(I, a.ZZZ))), w);
+    pack(reduce_full<Fq>(mont_mul<Fq>(a.Y, mont_mul<Fq>(I, a.ZZ))), w + 8);
+  }
+  stw(p, w, 4);
+}
+
+// ---------------------------------------------------------------- decompose
+__global__ void decompose_kernel(const uint32_t* __restrict__ scalars, uint32_t n, uint32_t c, uint32_t W,
+                                 uint32_t* __restrict__ digits) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t s[8];
+  ldw(scalars + (size_t)i * 8, s, 2);
+  // s > (r-1)/2 ?  (borrow of HALF - s)
+  unsigned br = 0;
+#pragma unroll
+  for (int q = 0; q < 8; q++) (void)__builtin_subc(FR_HALF[q], s[q], br, &br);
+  const uint32_t neg = br;
+  if (neg) {
+    unsigned b2 = 0;
+#pragma unroll
+    for (int q = 0; q < 8; q++) s[q] = __builtin_subc(FrP::M32[q], s[q], b2, &b2);
+  }
+  const uint32_t full = 1u << c, half = 1u << (c - 1);
+  uint32_t carry = 0;
+  for (uint32_t w = 0; w < W; w++) {
+    const uint32_t o = c * w, j = o >> 5, sh = o & 31;
+    uint64_t two = s[j];
+    if (j + 1 < 8) two |= (uint64_t)s[j + 1] << 32;
+    const uint32_t d = (uint32_t)((two >> sh) & (full - 1)) + carry;
+    uint32_t mag, sg;
+    if (d > half) {
+      mag = full - d;
+      sg = 1;
+      carry = 1;
+    } else {
+      mag = d;
+      sg = 0;
+      carry = 0;
+    }
+    digits[(size_t)w * n + i] = mag ? ((mag << 1) | (sg ^ neg)) : 0u;
+  }
+}
+
+// ---------------------------------------------------------------- histogram / scatter
+__global__ void __launch_bounds__(MSM_NT)
+hist_kernel(const uint32_t* __restrict__ digits, MsmPlan p, uint32_t* __restrict__ counts) {
+  extern __shared__ uint32_t h[];
+  const uint32_t w = blockIdx.y;
+  const uint32_t e0 = blockIdx.x * p.chunk, e1 = min(e0 + p.chunk, p.n);
+  for (uint32_t b = threadIdx.x; b < p.K; b += MSM_NT) h[b] = 0;
+  __syncthreads();
+  const uint32_t* dw = digits + (size_t)w * p.n;
+  for (uint32_t e = e0 + threadIdx.x; e < e1; e += MSM_NT) {
+    const uint32_t d = dw[e];
+    if (d) atomicAdd(&h[(d >> 1) - 1], 1u);
+  }
+  __syncthreads();
+  const uint32_t off = p.shared ? 0 : w * p.K;
+  for (uint32_t b = threadIdx.x; b < p.K; b += MSM_NT)
+    if (h[b]) atomicAdd(&counts[off + b], h[b]);
+}
+
+__global__ void __launch_bounds__(MSM_NT)
+scatter_kernel(const uint32_t* __restrict__ digits, MsmPlan p, uint32_t* __restrict__ cursor,
+               uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  extern __shared__ uint32_t h[];
+  const uint32_t w = blockIdx.y;
+  const uint32_t e0 = blockIdx.x * p.chunk, e1 = min(e0 + p.chunk, p.n);
+  for (uint32_t b = threadIdx.x; b < p.K; b += MSM_NT) h[b] = 0;
+  __syncthreads();
+  const uint32_t* dw = digits + (size_t)w * p.n;
+  for (uint32_t e = e0 + threadIdx.x; e < e1; e += MSM_NT) {
+    const uint32_t d = dw[e];
+    if (d) atomicAdd(&h[(d >> 1) - 1], 1u);
+  }
+  __syncthreads();
+  const uint32_t off = p.shared ? 0 : w * p.K;
+  for (uint32_t b = threadIdx.x; b < p.K; b += MSM_NT)
+    if (h[b]) h[b] = atomicAdd(&cursor[off + b], h[b]);
+  __syncthreads();
+  const uint32_t pbase = p.shared ? w * p.tab_stride : 0;
+  for (uint32_t e = e0 + threadIdx.x; e < e1; e += MSM_NT) {
+    const uint32_t d = dw[e];
+    if (!d) continue;
+    const uint32_t b = (d >> 1) - 1;
+    const uint32_t pos = atomicAdd(&h[b], 1u);
+    keys[pos] = off + b;
+    vals[pos] = (pbase + e) | ((d & 1u) << 31);
+  }
+}
+
+// ---------------------------------------------------------------- segmented combine
+// LDS record block: keys[SLOTS], flags[SLOTS], points[SLOTS][36].
+struct RecLds {
+  uint32_t* keys;
+  uint32_t* flags;
+  uint32_t* pts;
+};
+
+__device__ __forceinline__ RecLds rec_lds(uint32_t* sm) {
+  RecLds r;
+  r.keys = sm;
+  r.flags = sm + MSM_SLOTS;
+  r.pts = sm + 2 * MSM_SLOTS;
+  return r;
+}
+
+__device__ __forceinline__ uint32_t lower_bound_lds(const uint32_t* k, uint32_t key) {
+  uint32_t lo = 0, hi = MSM_SLOTS;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (k[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t upper_bound_lds(const uint32_t* k, uint32_t key) {
+  uint32_t lo = 0, hi = MSM_SLOTS;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (k[mid] <= key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ void put_slot(RecLds& r, uint32_t i, uint32_t key, uint32_t flag, const xyzz& a) {
+  r.keys[i] = key;
+  r.flags[i] = flag;
+  st_xyzz(r.pts + i * XYZZ_WORDS, a);
+}
+
+// Sum every run of equal keys held in the LDS slots; runs closed on both sides
+// are written to their bucket, the first and last run of the block go out as
+// records for the next level (data only if still open there).
+__device__ void combine_and_emit(RecLds& r, bool left_open, bool right_open, uint32_t* __restrict__ buckets,
+                                 uint32_t* out_keys, uint32_t* out_flags, uint32_t* out_pts) {
+  const uint32_t tid = threadIdx.x;
+  uint32_t head[MSM_SLOTS / MSM_NT];
+#pragma unroll
+  for (uint32_t q = 0; q < MSM_SLOTS / MSM_NT; q++) head[q] = lower_bound_lds(r.keys, r.keys[tid + q * MSM_NT]);
+  for (uint32_t d = 1; d < MSM_SLOTS; d <<= 1) {
+#pragma unroll
+    for (uint32_t q = 0; q < MSM_SLOTS / MSM_NT; q++) {
+      const uint32_t i = tid + q * MSM_NT;
+      if (((i - head[q]) & (2 * d - 1)) == 0 && i + d < MSM_SLOTS && r.keys[i + d] == r.keys[i] &&
+          r.flags[i + d]) {
+        const xyzz s = add(ld_xyzz(r.pts + i * XYZZ_WORDS), ld_xyzz(r.pts + (i + d) * XYZZ_WORDS));
+        st_xyzz(r.pts + i * XYZZ_WORDS, s);
+        r.flags[i] = 1;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (uint32_t q = 0; q < MSM_SLOTS / MSM_NT; q++) {
+    const uint32_t i = tid + q * MSM_NT;
+    if (head[q] != i) continue;
+    const uint32_t key = r.keys[i];
+    const uint32_t e = upper_bound_lds(r.keys, key);
+    const bool lo = (i == 0) && left_open;
+    const bool ro = (e == MSM_SLOTS) && right_open;
+    const bool has = r.flags[i] != 0;
+    if (!lo && !ro && has && key != KEY_SENTINEL) {
+      uint4* dst = reinterpret_cast<uint4*>(buckets + (size_t)key * XYZZ_WORDS);
+      const uint4* src = reinterpret_cast<const uint4*>(r.pts + i * XYZZ_WORDS);
+      for (int w = 0; w < 9; w++) dst[w] = src[w];
+    }
+    if (!out_keys) continue;
+    const uint32_t rb = 2 * blockIdx.x;
+    if (i == 0) {
+      const bool send = (lo || ro) && has;
+      out_keys[rb] = key;
+      out_flags[rb] = send ? 1u : 0u;
+      uint4* dst = reinterpret_cast<uint4*>(out_pts + (size_t)rb * XYZZ_WORDS);
+      const uint4* src = reinterpret_cast<const uint4*>(r.pts + i * XYZZ_WORDS);
+      for (int w = 0; w < 9; w++) dst[w] = send ? src[w] : make_uint4(0, 0, 0, 0);
+    }
+    if (e == MSM_SLOTS) {
+      const bool send = ro && has && i != 0;
+      out_keys[rb + 1] = key;
+      out_flags[rb + 1] = send ? 1u : 0u;
+      uint4* dst = reinterpret_cast<uint4*>(out_pts + (size_t)(rb + 1) * XYZZ_WORDS);
+      const uint4* src = reinterpret_cast<const uint4*>(r.pts + i * XYZZ_WORDS);
+      for (int w = 0; w < 9; w++) dst[w] = send ? src[w] : make_uint4(0, 0, 0, 0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- accumulate
+__global__ void __launch_bounds__(MSM_NT)
+accumulate_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                  const uint32_t* __restrict__ total_p, const uint32_t* __restrict__ points, uint32_t L,
+                  uint32_t* __restrict__ buckets, uint32_t* out_keys, uint32_t* out_flags, uint32_t* out_pts) {
+  extern __shared__ uint32_t sm[];
+  RecLds r = rec_lds(sm);
+  const uint32_t tid = threadIdx.x;
+  const uint32_t total = *total_p;
+  const uint64_t wb = (uint64_t)blockIdx.x * MSM_NT * L;
+  const uint64_t tb = wb + (uint64_t)tid * L;
+  const uint64_t te = min(tb + L, (uint64_t)total);
+  const uint32_t s0 = 2 * tid, s1 = 2 * tid + 1;
+  if (tb >= total) {
+    put_slot(r, s0, KEY_SENTINEL, 0, xyzz_inf());
+    put_slot(r, s1, KEY_SENTINEL, 0, xyzz_inf());
+  } else {
+    uint32_t cur = keys[tb];
+    bool first_done = false;
+    xyzz acc = xyzz_inf();
+    for (uint64_t e = tb; e < te; e++) {
+      const uint32_t k = keys[e];
+      const uint32_t v = vals[e];
+      if (k != cur) {
+        if (!first_done) {
+          put_slot(r, s0, cur, 1, acc);
+          first_done = true;
+        } else {
+          st_xyzz(buckets + (size_t)cur * XYZZ_WORDS, acc);
+        }
+        cur = k;
+        acc = xyzz_inf();
+      }
+      aff pt;
+      if (ld_aff(points + (size_t)(v & 0x7fffffffu) * 16, pt)) {
+        if (v >> 31) pt = aff_neg(pt);
+        acc = madd(acc, pt);
+      }
+    }
+    if (!first_done) {
+      put_slot(r, s0, cur, 1, acc);
+      put_slot(r, s1, cur, 0, xyzz_inf());
+    } else {
+      put_slot(r, s1, cur, 1, acc);
+    }
+  }
+  __syncthreads();
+  const uint64_t we = min(wb + (uint64_t)MSM_NT * L, (uint64_t)total);
+  const bool nonempty = wb < total;
+  const bool left_open = nonempty && wb > 0 && keys[wb - 1] == keys[wb];
+  const bool right_open = nonempty && we < total && keys[we] == keys[we - 1];
+  combine_and_emit(r, left_open, right_open, buckets, out_keys, out_flags, out_pts);
+}
+
+__global__ void __launch_bounds__(MSM_NT)
+record_reduce_kernel(const uint32_t* __restrict__ in_keys, const uint32_t* __restrict__ in_flags,
+                     const uint32_t* __restrict__ in_pts, uint32_t nrec, uint32_t* __restrict__ buckets,
+                     uint32_t* out_keys, uint32_t* out_flags, uint32_t* out_pts) {
+  extern __shared__ uint32_t sm[];
+  RecLds r = rec_lds(sm);
+  const uint32_t rb = blockIdx.x * MSM_SLOTS;
+  for (uint32_t q = 0; q < MSM_SLOTS / MSM_NT; q++) {
+    const uint32_t i = threadIdx.x + q * MSM_NT;
+    const uint32_t g = rb + i;
+    if (g < nrec) {
+      r.keys[i] = in_keys[g];
+      r.flags[i] = in_flags[g];
+      const uint4* src = reinterpret_cast<const uint4*>(in_pts + (size_t)g * XYZZ_WORDS);
+      uint4* dst = reinterpret_cast<uint4*>(r.pts + i * XYZZ_WORDS);
+      for (int w = 0; w < 9; w++) dst[w] = src[w];
+    } else {
+      put_slot(r, i, KEY_SENTINEL, 0, xyzz_inf());
+    }
+  }
+  __syncthreads();
+  const uint32_t re = min(rb + MSM_SLOTS, nrec);
+  const bool nonempty = rb < nrec;
+  const bool left_open = nonempty && rb > 0 && in_keys[rb - 1] == in_keys[rb];
+  const bool right_open = nonempty && re < nrec && in_keys[re] == in_keys[re - 1];
+  combine_and_emit(r, left_open, right_open, buckets, out_keys, out_flags, out_pts);
+}
+
+// ---------------------------------------------------------------- bucket reduction
+// V_(w,j) = sum_{b in chunk j} (b + 1) B_(w,b): running sums over the chunk
+// give sum (m + 1) B and sum B (m = b - j LB); the offset j*LB times the
+// chunk total is added with a small double-and-add.
+__global__ void __launch_bounds__(MSM_NT)
+bucket_chunks_kernel(const uint32_t* __restrict__ buckets, const uint32_t* __restrict__ counts, MsmPlan p,
+                     uint32_t nwin, uint32_t* __restrict__ vbuf) {
+  const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nwin * p.J) return;
+  const uint32_t w = id / p.J, j = id % p.J;
+  const uint32_t base = (p.shared ? 0 : w * p.K) + j * p.LB;
+  xyzz acc = xyzz_inf(), sum = xyzz_inf();
+  for (int m = (int)p.LB - 1; m >= 0; --m) {
+    if (counts[base + m]) acc = add(acc, ld_xyzz(buckets + (size_t)(base + m) * XYZZ_WORDS));
+    sum = add(sum, acc);
+  }
+  sum = add(sum, mul_small(acc, j * p.LB));
+  st_xyzz(vbuf + (size_t)id * XYZZ_WORDS, sum);
+}
+
+// One workgroup per window: S_w = sum_j V_(w,j).
+__global__ void __launch_bounds__(MSM_NT)
+window_sum_kernel(const uint32_t* __restrict__ vbuf, uint32_t J, uint32_t* __restrict__ wsum) {
+  extern __shared__ uint32_t sm[];
+  const uint32_t w = blockIdx.x, tid = threadIdx.x;
+  xyzz acc = xyzz_inf();
+  for (uint32_t j = tid; j < J; j += MSM_NT) acc = add(acc, ld_xyzz(vbuf + ((size_t)w * J + j) * XYZZ_WORDS));
+  st_xyzz(sm + tid * XYZZ_WORDS, acc);
+  __syncthreads();
+  for (uint32_t s = MSM_NT / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      const xyzz t = add(ld_xyzz(sm + tid * XYZZ_WORDS), ld_xyzz(sm + (tid + s) * XYZZ_WORDS));
+      st_xyzz(sm + tid * XYZZ_WORDS, t);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) st_xyzz(wsum + (size_t)w * XYZZ_WORDS, ld_xyzz(sm));
+}
+
+// Q = sum_w 2^(c w) S_w by Horner, then canonical affine.
+__global__ void combine_kernel(const uint32_t* __restrict__ wsum, uint32_t nwin, uint32_t c,
+                               uint32_t* __restrict__ out16) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  xyzz q = ld_xyzz(wsum + (size_t)(nwin - 1) * XYZZ_WORDS);
+  for (int w = (int)nwin - 2; w >= 0; --w) {
+    for (uint32_t t = 0; t < c; t++) q = dbl(q);
+    q = add(q, ld_xyzz(wsum + (size_t)w * XYZZ_WORDS));
+  }
+  uint32_t o[16];
+  to_affine_words(q, o);
+  stw(out16, o, 4);
+}
+
+__global__ void zero16_kernel(uint32_t* out16) {
+  if (threadIdx.x < 16) out16[threadIdx.x] = 0;
+}
+
+// Zero fill by a kernel (graph-capture friendly, unlike a memset node).
+__global__ void fill_zero_kernel(uint32_t* p, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+__global__ void copy_u32_kernel(const uint32_t* src, uint32_t* dst, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------- conversions / tables
+__global__ void to_mont_kernel(const uint32_t* __restrict__ plain, uint32_t* __restrict__ mont, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t w[16];
+  ldw(plain + i * 16, w, 4);
+  aff a;
+  aff_from_plain_words(w, a);  // (0,0) stays (0,0)
+  pack(a.x, w);
+  pack(a.y, w + 8);
+  stw(mont + i * 16, w, 4);
+}
+
+__global__ void build_table_kernel(const uint32_t* __restrict__ plain, uint32_t* __restrict__ tab, uint64_t n,
+                                   uint32_t c, uint32_t W) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t w[16];
+  ldw(plain + i * 16, w, 4);
+  aff a;
+  const bool fin = aff_from_plain_words(w, a);
+  pack(a.x, w);
+  pack(a.y, w + 8);
+  stw(tab + i * 16, w, 4);
+  xyzz acc = fin ? from_aff(a) : xyzz_inf();
+  for (uint32_t win = 1; win < W; win++) {
+    for (uint32_t t = 0; t < c; t++) acc = dbl(acc);
+    st_aff_mont(tab + ((uint64_t)win * n + i) * 16, acc);
+  }
+}
+
+// gtab[j] = 2^j G, Montgomery affine, j < 256.
+__global__ void gen_table_kernel(uint32_t* gtab) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= 256) return;
+  uint32_t w[16];
+  for (int q = 0; q < 16; q++) w[q] = G1_GEN[q];
+  aff g;
+  aff_from_plain_words(w, g);
+  xyzz acc = from_aff(g);
+  for (uint32_t t = 0; t < j; t++) acc = dbl(acc);
+  st_aff_mont(gtab + (size_t)j * 16, acc);
+}
+
+// out[i] = [tau^i] G as canonical plain affine words.
+__global__ void srs_kernel(Tau8 tw, const uint32_t* __restrict__ gtab, uint32_t* __restrict__ out, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const f29 tau = reduce_full<FrP>(to_mont<FrP>(unpack(tw.w)));
+  uint32_t e[8] = {(uint32_t)i, (uint32_t)(i >> 32), 0, 0, 0, 0, 0, 0};
+  const f29 ti = (i == 0) ? f29_from(FrP::ONE) : mont_pow<FrP>(tau, e);
+  uint32_t s[8];
+  pack(from_mont<FrP>(ti), s);
+  xyzz acc = xyzz_inf();
+  for (int b = 0; b < 254; b++) {
+    if ((s[b >> 5] >> (b & 31)) & 1u) {
+      aff g;
+      ld_aff(gtab + (size_t)b * 16, g);
+      acc = madd(acc, g);
+    }
+  }
+  uint32_t o[16];
+  to_affine_words(acc, o);
+  stw(out + i * 16, o, 4);
+}
+
+// sigma_i = product of the challenges of the folds where instance i is the
+// left operand (adjacent pairs per level, odd last carried, BFS order).
+__global__ void fold_sigma_kernel(const uint32_t* __restrict__ gammas, uint32_t m, uint32_t* __restrict__ sigma) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  f29 sg = f29_from(FrP::ONE);
+  uint32_t pos = i, ml = m, goff = 0;
+  while (ml > 1) {
+    if ((pos & 1u) == 0 && pos + 1 < ml) {
+      uint32_t gw[8];
+      ldw(gammas + (size_t)(goff + pos / 2) * 8, gw, 2);
+      sg = mont_mul<FrP>(sg, to_mont<FrP>(unpack(gw)));
+    }
+    goff += ml / 2;
+    ml = (ml + 1) / 2;
+    pos >>= 1;
+  }
+  uint32_t o[8];
+  pack(from_mont<FrP>(sg), o);
+  stw(sigma + (size_t)i * 8, o, 2);
+}
+
+__global__ void gather_kernel(const uint32_t* __restrict__ inst, uint32_t m, uint32_t k, uint32_t comp,
+                              uint32_t* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  uint32_t w[16];
+  ldw(inst + ((size_t)i * k + comp) * 16, w, 4);
+  stw(out + (size_t)i * 16, w, 4);
+}
+
+// ---------------------------------------------------------------- scan
+constexpr uint32_t SCAN_ITEMS = 8;
+constexpr uint32_t SCAN_BLOCK = MSM_NT * SCAN_ITEMS;
+
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t* sm, uint32_t* total) {
+  const uint32_t tid = threadIdx.x;
+  sm[tid] = v;
+  __syncthreads();
+  for (uint32_t d = 1; d < MSM_NT; d <<= 1) {
+    const uint32_t t = tid >= d ? sm[tid - d] : 0;
+    __syncthreads();
+    sm[tid] += t;
+    __syncthreads();
+  }
+  const uint32_t incl = sm[tid];
+  *total = sm[MSM_NT - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(MSM_NT) scan_reduce_kernel(const uint32_t* in, uint32_t n, uint32_t* sums) {
+  __shared__ uint32_t sm[MSM_NT];
+  const uint32_t base = blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_ITEMS;
+  uint32_t s = 0;
+  for (uint32_t q = 0; q < SCAN_ITEMS; q++)
+    if (base + q < n) s += in[base + q];
+  uint32_t tot;
+  block_excl_scan(s, sm, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(MSM_NT) scan_sums_kernel(uint32_t* sums, uint32_t nb) {
+  __shared__ uint32_t sm[MSM_NT];
+  // nb <= MSM_NT * SCAN_ITEMS
+  const uint32_t base = threadIdx.x * SCAN_ITEMS;
+  uint32_t v[SCAN_ITEMS], s = 0;
+  for (uint32_t q = 0; q < SCAN_ITEMS; q++) {
+    v[q] = base + q < nb ? sums[base + q] : 0;
+    s += v[q];
+  }
+  uint32_t tot;
+  uint32_t run = block_excl_scan(s, sm, &tot);
+  for (uint32_t q = 0; q < SCAN_ITEMS; q++) {
+    if (base + q < nb) sums[base + q] = run;
+    run += v[q];
+  }
+  if (threadIdx.x == 0) sums[nb] = tot;
+}
+
+__global__ void __launch_bounds__(MSM_NT)
+scan_apply_kernel(const uint32_t* in, uint32_t n, const uint32_t* sums, uint32_t nb, uint32_t* out) {
+  __shared__ uint32_t sm[MSM_NT];
+  const uint32_t base = blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_ITEMS;
+  uint32_t v[SCAN_ITEMS], s = 0;
+  for (uint32_t q = 0; q < SCAN_ITEMS; q++) {
+    v[q] = base + q < n ? in[base + q] : 0;
+    s += v[q];
+  }
+  uint32_t tot;
+  uint32_t run = block_excl_scan(s, sm, &tot) + sums[blockIdx.x];
+  for (uint32_t q = 0; q < SCAN_ITEMS; q++) {
+    if (base + q < n) out[base + q] = run;
+    run += v[q];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums[nb];
+}
+
+inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+}  // namespace
+
+// ================================================================ host side
+
+uint32_t msm_default_c(uint32_t n) {
+  uint32_t lg = 0;
+  while ((1ull << (lg + 1)) <= n) lg++;
+  int c = (int)lg - 3;
+  if (c < 4) c = 4;
+  if (c > 16) c = 16;
+  return (uint32_t)c;
+}
+
+MsmPlan msm_plan(uint32_t n, uint32_t c, bool shared, uint32_t tab_stride) {
+  MsmPlan p{};
+  p.n = n;
+  p.c = c;
+  p.W = (254 + c - 1) / c;
+  p.K = 1u << (c - 1);
+  p.shared = shared ? 1 : 0;
+  p.nbins = shared ? p.K : p.W * p.K;
+  p.tab_stride = tab_stride;
+  p.chunk = 32768;
+  const uint64_t entries = (uint64_t)n * p.W;
+  // enough threads to fill the chip, at most 64 entries each
+  uint64_t L = entries / (256ull * 1024);
+  if (L < 4) L = 4;
+  if (L > 64) L = 64;
+  p.L = (uint32_t)L;
+  p.acc_blocks = cdiv(cdiv(entries, p.L), MSM_NT);
+  if (p.acc_blocks == 0) p.acc_blocks = 1;
+  p.LB = p.K >= 8 ? 8 : p.K;
+  p.J = p.K / p.LB;
+  return p;
+}
+
+size_t scan_tmp_words(uint32_t n) { return cdiv(n, SCAN_BLOCK) + 1; }
+
+hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp, hipStream_t s) {
+  const uint32_t nb = cdiv(n, SCAN_BLOCK);
+  if (nb > SCAN_BLOCK) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(MSM_NT), 0, s, in, n, tmp);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(MSM_NT), 0, s, tmp, nb);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(MSM_NT), 0, s, in, n, tmp, nb, out);
+  return hipGetLastError();
+}
+
+namespace {
+struct Layout {
+  size_t off[16];
+  size_t total;
+};
+
+Layout layout(const MsmPlan& p) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](int idx, size_t words) {
+    L.off[idx] = o;
+    o += (words * 4 + 255) & ~size_t(255);
+  };
+  const size_t ent = (size_t)p.n * p.W;
+  const size_t nrec0 = 2 * (size_t)p.acc_blocks;
+  const size_t nwin = p.shared ? 1 : p.W;
+  take(0, ent);                              // digits
+  take(1, p.nbins);                          // counts
+  take(2, p.nbins + 1);                      // offsets
+  take(3, p.nbins);                          // cursor
+  take(4, scan_tmp_words(p.nbins));          // scan tmp
+  take(5, ent);                              // keys
+  take(6, ent);                              // vals
+  take(7, (size_t)p.nbins * XYZZ_WORDS);     // buckets
+  take(8, nrec0);                            // rec keys A
+  take(9, nrec0);                            // rec flags A
+  take(10, nrec0 * XYZZ_WORDS);              // rec pts A
+  take(11, nrec0);                           // rec keys B
+  take(12, nrec0);                           // rec flags B
+  take(13, nrec0 * XYZZ_WORDS);              // rec pts B
+  take(14, nwin * p.J * XYZZ_WORDS);         // vbuf
+  take(15, nwin * XYZZ_WORDS);               // wsum
+  L.total = o;
+  return L;
+}
+}  // namespace
+
+size_t msm_workspace_bytes(const MsmPlan& p) { return layout(p).total; }
+
+MsmBuffers msm_carve(const MsmPlan& p, void* base) {
+  const Layout L = layout(p);
+  char* b = static_cast<char*>(base);
+  MsmBuffers m;
+  m.digits = reinterpret_cast<uint32_t*>(b + L.off[0]);
+  m.counts = reinterpret_cast<uint32_t*>(b + L.off[1]);
+  m.offsets = reinterpret_cast<uint32_t*>(b + L.off[2]);
+  m.cursor = reinterpret_cast<uint32_t*>(b + L.off[3]);
+  m.scan_tmp = reinterpret_cast<uint32_t*>(b + L.off[4]);
+  m.keys = reinterpret_cast<uint32_t*>(b + L.off[5]);
+  m.vals = reinterpret_cast<uint32_t*>(b + L.off[6]);
+  m.buckets = reinterpret_cast<uint32_t*>(b + L.off[7]);
+  m.rec_keys[0] = reinterpret_cast<uint32_t*>(b + L.off[8]);
+  m.rec_flags[0] = reinterpret_cast<uint32_t*>(b + L.off[9]);
+  m.rec_pts[0] = reinterpret_cast<uint32_t*>(b + L.off[10]);
+  m.rec_keys[1] = reinterpret_cast<uint32_t*>(b + L.off[11]);
+  m.rec_flags[1] = reinterpret_cast<uint32_t*>(b + L.off[12]);
+  m.rec_pts[1] = reinterpret_cast<uint32_t*>(b + L.off[13]);
+  m.vbuf = reinterpret_cast<uint32_t*>(b + L.off[14]);
+  m.wsum = reinterpret_cast<uint32_t*>(b + L.off[15]);
+  return m;
+}
+
+static size_t rec_lds_bytes() { return (size_t)MSM_SLOTS * (2 + XYZZ_WORDS) * 4; }
+
+static hipError_t set_lds_limits() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  hipError_t e;
+  const int hist_lds = 32768 * 4;
+  if ((e = hipFuncSetAttribute((const void*)hist_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, hist_lds)))
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)scatter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, hist_lds)))
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)accumulate_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)rec_lds_bytes())))
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)record_reduce_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)rec_lds_bytes())))
+    return e;
+  done = true;
+  return hipSuccess;
+}
+
+hipError_t msm_run(const MsmPlan& p, const uint32_t* mont_points, const uint32_t* scalars, const MsmBuffers& b,
+                   uint32_t* out16, hipStream_t s) {
+  hipError_t e;
+  if ((e = set_lds_limits())) return e;
+  if (p.n == 0) {
+    hipLaunchKernelGGL(zero16_kernel, dim3(1), dim3(64), 0, s, out16);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(decompose_kernel, dim3(cdiv(p.n, 256)), dim3(256), 0, s, scalars, p.n, p.c, p.W, b.digits);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(min(cdiv(p.nbins, 256), 1024u)), dim3(256), 0, s, b.counts, p.nbins);
+  const dim3 hgrid(cdiv(p.n, p.chunk), p.W);
+  const size_t hlds = (size_t)p.K * 4;
+  hipLaunchKernelGGL(hist_kernel, hgrid, dim3(MSM_NT), hlds, s, b.digits, p, b.counts);
+  if ((e = scan_exclusive(b.counts, b.offsets, p.nbins, b.scan_tmp, s))) return e;
+  hipLaunchKernelGGL(copy_u32_kernel, dim3(min(cdiv(p.nbins, 256), 1024u)), dim3(256), 0, s, b.offsets, b.cursor,
+                     p.nbins);
+  hipLaunchKernelGGL(scatter_kernel, hgrid, dim3(MSM_NT), hlds, s, b.digits, p, b.cursor, b.keys, b.vals);
+  // accumulate + record levels
+  uint32_t grid = p.acc_blocks;
+  int cur = 0;
+  const bool last0 = grid == 1;
+  hipLaunchKernelGGL(accumulate_kernel, dim3(grid), dim3(MSM_NT), rec_lds_bytes(), s, b.keys, b.vals,
+                     b.offsets + p.nbins, mont_points, p.L, b.buckets, last0 ? nullptr : b.rec_keys[0],
+                     last0 ? nullptr : b.rec_flags[0], last0 ? nullptr : b.rec_pts[0]);
+  while (grid > 1) {
+    const uint32_t nrec = 2 * grid;
+    const uint32_t g2 = cdiv(nrec, MSM_SLOTS);
+    const bool last = g2 == 1;
+    const int nxt = cur ^ 1;
+    hipLaunchKernelGGL(record_reduce_kernel, dim3(g2), dim3(MSM_NT), rec_lds_bytes(), s, b.rec_keys[cur],
+                       b.rec_flags[cur], b.rec_pts[cur], nrec, b.buckets, last ? nullptr : b.rec_keys[nxt],
+                       last ? nullptr : b.rec_flags[nxt], last ? nullptr : b.rec_pts[nxt]);
+    grid = g2;
+    cur = nxt;
+  }
+  const uint32_t nwin = p.shared ? 1 : p.W;
+  hipLaunchKernelGGL(bucket_chunks_kernel, dim3(cdiv((uint64_t)nwin * p.J, 64)), dim3(64), 0, s, b.buckets,
+                     b.counts, p, nwin, b.vbuf);
+  hipLaunchKernelGGL(window_sum_kernel, dim3(nwin), dim3(MSM_NT), (size_t)MSM_NT * XYZZ_WORDS * 4, s, b.vbuf, p.J,
+                     b.wsum);
+  hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, s, b.wsum, nwin, p.c, out16);
+  return hipGetLastError();
+}
+
+hipError_t msm_points_to_mont(const uint32_t* plain, uint32_t* mont, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(to_mont_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, plain, mont, n);
+  return hipGetLastError();
+}
+
+hipError_t msm_build_table(const uint32_t* plain_points, uint32_t* tab, uint64_t n, uint32_t c, uint32_t W,
+                           hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(build_table_kernel, dim3(cdiv(n, 128)), dim3(128), 0, s, plain_points, tab, n, c, W);
+  return hipGetLastError();
+}
+
+size_t srs_gtab_words() { return 256 * 16; }
+
+hipError_t srs_from_tau(Tau8 tau, uint32_t* out, uint64_t n, uint32_t* gtab, hipStream_t s) {
+  hipLaunchKernelGGL(gen_table_kernel, dim3(4), dim3(64), 0, s, gtab);
+  if (n == 0) return hipGetLastError();
+  hipLaunchKernelGGL(srs_kernel, dim3(cdiv(n, 128)), dim3(128), 0, s, tau, gtab, out, n);
+  return hipGetLastError();
+}
+
+hipError_t fold_sigmas(const uint32_t* gammas, uint32_t m, uint32_t* sigma, hipStream_t s) {
+  hipLaunchKernelGGL(fold_sigma_kernel, dim3(cdiv(m, 64)), dim3(64), 0, s, gammas, m, sigma);
+  return hipGetLastError();
+}
+
+hipError_t gather_component(const uint32_t* inst, uint32_t m, uint32_t k, uint32_t comp, uint32_t* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(gather_kernel, dim3(cdiv(m, 64)), dim3(64), 0, s, inst, m, k, comp, out);
+  return hipGetLastError();
+}
+
+}  // namespace zk

@@ -1,0 +1,43 @@
+// Internal interface of the NTT pass kernel (see ntt.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "field.h"
+
+namespace zk {
+
+// One pass: a batch of M = 2^m point transforms held in LDS.
+//   input  element (batch b, point i) at in[(b + i*s_in)]          (words x8)
+//   output element (batch b, point k) at out[(b*b_out + k*s_out)]
+// Elements with input index >= valid_n read as zero.
+struct NttPass {
+  const uint32_t* in;
+  uint32_t* out;
+  uint32_t m;          // log2 points per transform (<= 12)
+  uint32_t G;          // transforms per workgroup (M * G <= 4096)
+  uint32_t nbatch;     // number of transforms
+  uint32_t s_in;       // input stride between points
+  uint32_t s_out;      // output stride between points
+  uint32_t b_out;      // output stride between transforms
+  uint32_t valid_n;
+  const f29* tw_lo;    // omega^e, e < 2^14 (forward or inverse root)
+  const f29* tw_hi;    // omega^(e 2^14)
+  uint32_t post_tw_L;  // 0: none; else multiply (b, k) by omega_(2^L)^(b k)
+  const f29* pre_lo;   // coset: multiply input i by g^i (nullptr: none)
+  const f29* pre_hi;
+  const f29* post_scale;  // multiply every output by this constant (nullptr: none)
+};
+
+hipError_t ntt_pass_setup();
+hipError_t ntt_launch_pass(const NttPass& p, hipStream_t s);
+struct Words8 {
+  uint32_t w[8];
+};
+
+// lo[e] = base^e, hi[e] = base^(e 2^14), e < 2^14 (Montgomery form); base canonical.
+hipError_t ntt_make_pow_tables(Words8 base, f29* lo, f29* hi, hipStream_t s);
+size_t ntt_pass_lds_bytes();
+uint32_t ntt_tile_log();
+
+}  // namespace zk

@@ -1,0 +1,157 @@
+// Radix-2 NTT / inverse NTT / coset NTT over the BN254 scalar field Fr.
+//
+// What is computed (the paper's witness encoding: a length-n vector is a
+// polynomial's evaluations on H = {omega^i}, element i = f(omega^i)):
+//   forward  X[k] = sum_i x[i] omega_N^(i k)           (coefficients -> evaluations)
+//   inverse  x[i] = N^-1 sum_k X[k] omega_N^(-i k)     (evaluations -> coefficients)
+//   coset    E[j] = f(g omega_(Bn)^j): inputs scaled by g^i, zero-padded to Bn
+// with omega_N = 5^((r-1)/N), natural order in and out.
+//
+// Scheme: a transform of N = N1 * N2 points runs as two passes over HBM (the
+// "four-step" factorisation), each pass a batch of LDS-resident radix-2
+// transforms of at most 4096 points:
+//   pass A: for every i1 < N1, Y[i1][k2] = omega_N^(i1 k2) * NTT_N2(x[i1 + N1 i2])
+//   pass B: for every k2 < N2, X[k2 + N2 k1] = NTT_N1(Y[i1][k2])
+// Inside a tile the points are loaded in bit-reversed order into LDS and run
+// through log2(M) decimation-in-time stages.  A workgroup owns G adjacent
+// transforms so that each strided global access moves G*32 contiguous bytes.
+//
+// Arithmetic: data stay plain canonical integers (32-bit words); twiddles are
+// Montgomery-form constants in 29-bit limbs, so one Montgomery product
+// returns the plain product w*v.  Twiddle tables hold omega_(2^28)^e for
+// e < 2^14 ("lo") and e = j*2^14 ("hi"); omega_N^e = lo * hi of the exponent
+// e*2^(28-L) split in two halves, and every in-tile twiddle is a single "hi"
+// entry (tile sizes <= 2^14).
+#include "ntt.h"
+
+namespace zk {
+
+namespace {
+
+constexpr uint32_t TILE_LOG = 12;
+constexpr uint32_t TILE = 1u << TILE_LOG;    // elements per workgroup
+constexpr uint32_t NTT_THREADS = 256;
+
+__device__ __forceinline__ void ld8(const uint32_t* p, uint32_t w[8]) {
+  const uint4 a = reinterpret_cast<const uint4*>(p)[0];
+  const uint4 b = reinterpret_cast<const uint4*>(p)[1];
+  w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+  w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+}
+
+__device__ __forceinline__ void st8(uint32_t* p, const uint32_t w[8]) {
+  reinterpret_cast<uint4*>(p)[0] = make_uint4(w[0], w[1], w[2], w[3]);
+  reinterpret_cast<uint4*>(p)[1] = make_uint4(w[4], w[5], w[6], w[7]);
+}
+
+__device__ __forceinline__ f29 ldf29(const f29* t, uint32_t i) { return t[i]; }
+
+// omega^(e) of the 2^28-th root for e < 2^28, from the split tables.
+__device__ __forceinline__ f29 pow28(const f29* lo, const f29* hi, uint32_t E) {
+  const uint32_t a = E & 0x3fffu, b = E >> 14;
+  if (b == 0) return ldf29(lo, a);
+  if (a == 0) return ldf29(hi, b);
+  return mont_mul<FrP>(ldf29(lo, a), ldf29(hi, b));
+}
+
+__global__ void __launch_bounds__(NTT_THREADS)
+ntt_pass_kernel(NttPass a) {
+  extern __shared__ uint32_t lds[];
+  const uint32_t M = 1u << a.m;
+  const uint32_t g0 = blockIdx.x * a.G;
+  const uint32_t G = min(a.G, a.nbatch - g0);
+  const uint32_t TE = M * G;
+  const uint32_t tid = threadIdx.x;
+
+  // ---- load (bit-reversed into LDS), coset pre-scale, zero padding
+  for (uint32_t e = tid; e < TE; e += NTT_THREADS) {
+    const uint32_t b = e % G, i = e / G;
+    const uint32_t gi = (g0 + b) + i * a.s_in;
+    uint32_t w[8];
+    if (gi < a.valid_n) {
+      ld8(a.in + (size_t)gi * 8, w);
+      if (a.pre_lo) {
+        const f29 s = pow28(a.pre_lo, a.pre_hi, gi);
+        mul_plain_by_mont<FrP>(w, s, w);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; q++) w[q] = 0;
+    }
+    const uint32_t slot = b * M + (a.m ? (__brev(i) >> (32 - a.m)) : 0);
+    st8(lds + slot * 8, w);
+  }
+  __syncthreads();
+
+  // ---- decimation-in-time stages
+  for (uint32_t s = 1; s <= a.m; s++) {
+    const uint32_t half = 1u << (s - 1);
+    for (uint32_t t = tid; t < TE / 2; t += NTT_THREADS) {
+      const uint32_t b = t >> (a.m - 1), tl = t & ((M >> 1) - 1);
+      const uint32_t j = tl & (half - 1);
+      const uint32_t i0 = b * M + ((tl >> (s - 1)) << s) + j;
+      const uint32_t i1 = i0 + half;
+      uint32_t u[8], v[8], tv[8];
+      ld8(lds + i0 * 8, u);
+      ld8(lds + i1 * 8, v);
+      // omega_(2^s)^j = omega_(2^28)^(j * 2^(28-s)): a "hi" table entry
+      const f29 wj = ldf29(a.tw_hi, j << (14 - s));
+      mul_plain_by_mont<FrP>(v, wj, tv);
+      add_mod32<FrP>(u, tv, v);
+      sub_mod32<FrP>(u, tv, u);
+      st8(lds + i0 * 8, v);
+      st8(lds + i1 * 8, u);
+    }
+    __syncthreads();
+  }
+
+  // ---- store with optional four-step twiddle and final scale
+  const bool row_out = (a.s_out == 1);
+  for (uint32_t e = tid; e < TE; e += NTT_THREADS) {
+    const uint32_t b = row_out ? e / M : e % G;
+    const uint32_t k = row_out ? e % M : e / G;
+    uint32_t w[8];
+    ld8(lds + (b * M + k) * 8, w);
+    if (a.post_tw_L) {
+      const uint32_t ex = ((g0 + b) * k) & ((1u << a.post_tw_L) - 1);
+      if (ex) mul_plain_by_mont<FrP>(w, pow28(a.tw_lo, a.tw_hi, ex << (28 - a.post_tw_L)), w);
+    }
+    if (a.post_scale) mul_plain_by_mont<FrP>(w, *a.post_scale, w);
+    st8(a.out + ((size_t)(g0 + b) * a.b_out + (size_t)k * a.s_out) * 8, w);
+  }
+}
+
+// lo[e] = base^e, hi[e] = base^(e * 2^14) for e < 2^14 (Montgomery form).
+__global__ void pow_tables_kernel(Words8 bw, f29* lo, f29* hi) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (1u << 14)) return;
+  const f29 base = reduce_full<FrP>(to_mont<FrP>(unpack(bw.w)));
+  uint32_t ex[8] = {e, 0, 0, 0, 0, 0, 0, 0};
+  lo[e] = e ? reduce_full<FrP>(mont_pow<FrP>(base, ex)) : f29_from(FrP::ONE);
+  ex[0] = e << 14;
+  hi[e] = e ? reduce_full<FrP>(mont_pow<FrP>(base, ex)) : f29_from(FrP::ONE);
+}
+
+}  // namespace
+
+size_t ntt_pass_lds_bytes() { return (size_t)TILE * 32; }
+
+hipError_t ntt_launch_pass(const NttPass& p, hipStream_t s) {
+  const uint32_t blocks = (p.nbatch + p.G - 1) / p.G;
+  hipLaunchKernelGGL(ntt_pass_kernel, dim3(blocks), dim3(NTT_THREADS), ntt_pass_lds_bytes(), s, p);
+  return hipGetLastError();
+}
+
+hipError_t ntt_pass_setup() {
+  return hipFuncSetAttribute((const void*)ntt_pass_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)ntt_pass_lds_bytes());
+}
+
+hipError_t ntt_make_pow_tables(Words8 base, f29* lo, f29* hi, hipStream_t s) {
+  hipLaunchKernelGGL(pow_tables_kernel, dim3((1u << 14) / 256), dim3(256), 0, s, base, lo, hi);
+  return hipGetLastError();
+}
+
+uint32_t ntt_tile_log() { return TILE_LOG; }
+
+}  // namespace zk

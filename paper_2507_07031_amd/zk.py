@@ -1,0 +1,225 @@
+"""Python binding of libzk.so (include/zk.h): argument marshalling only.
+
+Device buffers are torch tensors on a ROCm device holding raw 32-bit words
+(dtype torch.int32, reinterpreted as unsigned by the library):
+
+* field elements: shape (n, 8), canonical little-endian limbs;
+* affine G1 points: shape (n, 16), x then y; (0, 0) is the point at infinity.
+
+Every call enqueues on torch's current stream of the tensors' device.  There
+is no fallback: if libzk.so is missing the import of this module raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzk.so")
+
+ZK_OK, ZK_EINVAL, ZK_ENOMEM, ZK_EDEVICE, ZK_EUNSUPPORTED = 0, -1, -2, -3, -5
+MAX_LOG_NTT = 24
+
+EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_srs_setup", "zk_srs_create",
+           "zk_srs_destroy", "zk_srs_size", "zk_msm_srs", "zk_msm_batch", "zk_fold")
+
+
+class ZkError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("zk error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libzk.so not built (run python -m paper_2507_07031_amd.build): %s" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, U32, U64, I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    sig = {
+        "zk_last_error": ([], ctypes.c_char_p),
+        "zk_ntt": ([P, P, U32, P], I),
+        "zk_intt": ([P, P, U32, P], I),
+        "zk_coset_ntt": ([P, U32, U32, P, P, P], I),
+        "zk_msm": ([P, P, U64, P, P], I),
+        "zk_srs_setup": ([P, U64, P, P], I),
+        "zk_srs_create": ([P, U64, ctypes.POINTER(ctypes.c_void_p), P], I),
+        "zk_srs_destroy": ([P], I),
+        "zk_srs_size": ([P], U64),
+        "zk_msm_srs": ([P, P, U64, P, P], I),
+        "zk_msm_batch": ([P, P, P, U32, P, P], I),
+        "zk_fold": ([P, P, U32, U32, P, P], I),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _check(code):
+    if code != ZK_OK:
+        raise ZkError(code, lib.zk_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(t):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_words(t, width, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if t.dtype != torch.int32 or t.dim() != 2 or t.shape[1] != width or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous int32 tensor of shape (n, %d)" % (name, width))
+    return t
+
+
+def _host_fr(words):
+    a = np.ascontiguousarray(np.asarray(words, dtype=np.uint32).reshape(8))
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------- transfers
+
+def to_device(arr, device="cuda"):
+    """numpy uint32 array -> int32 device tensor with the same bits."""
+    torch = _torch()
+    a = np.ascontiguousarray(np.asarray(arr, dtype=np.uint32))
+    return torch.from_numpy(a.view(np.int32)).to(device)
+
+
+def to_host(t):
+    """int32 device tensor -> numpy uint32 array with the same bits."""
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+# ---------------------------------------------------------------- transforms
+
+def ntt(x, out=None, log_n=None):
+    x = _dev_words(x, 8, "x")
+    n = x.shape[0]
+    L = int(log_n if log_n is not None else n.bit_length() - 1)
+    if (1 << L) != n:
+        raise ValueError("length must be a power of two")
+    out = out if out is not None else _torch().empty_like(x)
+    _check(lib.zk_ntt(_ptr(x), _ptr(out), L, _stream(x)))
+    return out
+
+
+def intt(x, out=None):
+    x = _dev_words(x, 8, "x")
+    n = x.shape[0]
+    L = n.bit_length() - 1
+    if (1 << L) != n:
+        raise ValueError("length must be a power of two")
+    out = out if out is not None else _torch().empty_like(x)
+    _check(lib.zk_intt(_ptr(x), _ptr(out), L, _stream(x)))
+    return out
+
+
+def coset_ntt(coeffs, log_blowup, shift=None, out=None):
+    coeffs = _dev_words(coeffs, 8, "coeffs")
+    n = coeffs.shape[0]
+    L = n.bit_length() - 1
+    if (1 << L) != n:
+        raise ValueError("length must be a power of two")
+    torch = _torch()
+    if out is None:
+        out = torch.empty((n << log_blowup, 8), dtype=torch.int32, device=coeffs.device)
+    sp = None
+    if shift is not None:
+        sa, sp = _host_fr(shift)
+    _check(lib.zk_coset_ntt(_ptr(coeffs), L, int(log_blowup), sp, _ptr(out), _stream(coeffs)))
+    return out
+
+
+# ---------------------------------------------------------------- commitments
+
+def msm(bases, scalars, n=None):
+    bases = _dev_words(bases, 16, "bases")
+    scalars = _dev_words(scalars, 8, "scalars")
+    n = int(n if n is not None else scalars.shape[0])
+    if n > bases.shape[0] or n > scalars.shape[0]:
+        raise ValueError("n exceeds the inputs")
+    out = _torch().empty((1, 16), dtype=_torch().int32, device=bases.device)
+    _check(lib.zk_msm(_ptr(bases), _ptr(scalars), n, _ptr(out), _stream(bases)))
+    return out
+
+
+def srs_setup(tau, n, device="cuda"):
+    torch = _torch()
+    out = torch.empty((int(n), 16), dtype=torch.int32, device=device)
+    ta, tp = _host_fr(tau)
+    _check(lib.zk_srs_setup(tp, int(n), _ptr(out), _stream(out)))
+    return out
+
+
+class SRS:
+    """A prepared SRS (zk_srs handle) built from device points (n, 16)."""
+
+    def __init__(self, points):
+        points = _dev_words(points, 16, "points")
+        h = ctypes.c_void_p()
+        _check(lib.zk_srs_create(_ptr(points), points.shape[0], ctypes.byref(h), _stream(points)))
+        self.handle = h
+        self.device = points.device
+        self.n = int(lib.zk_srs_size(h))
+
+    def close(self):
+        if self.handle:
+            _check(lib.zk_srs_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def msm_srs(srs, scalars, n=None):
+    scalars = _dev_words(scalars, 8, "scalars")
+    n = int(n if n is not None else scalars.shape[0])
+    out = _torch().empty((1, 16), dtype=_torch().int32, device=scalars.device)
+    _check(lib.zk_msm_srs(srs.handle, _ptr(scalars), n, _ptr(out), _stream(scalars)))
+    return out
+
+
+def msm_batch(srs, scalars, offsets):
+    scalars = _dev_words(scalars, 8, "scalars")
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    batch = off.shape[0] - 1
+    out = _torch().empty((max(batch, 0), 16), dtype=_torch().int32, device=scalars.device)
+    _check(lib.zk_msm_batch(srs.handle, _ptr(scalars), off.ctypes.data_as(ctypes.c_void_p), batch, _ptr(out),
+                            _stream(scalars)))
+    return out
+
+
+def fold(inst, gammas):
+    """inst: (m, k, 16) device tensor; gammas: (m - 1, 8) device tensor."""
+    torch = _torch()
+    if inst.dim() != 3 or inst.shape[2] != 16 or inst.dtype != torch.int32 or not inst.is_contiguous():
+        raise TypeError("inst must be a contiguous int32 tensor of shape (m, k, 16)")
+    m, k = int(inst.shape[0]), int(inst.shape[1])
+    out = torch.empty((k, 16), dtype=torch.int32, device=inst.device)
+    gp = ctypes.c_void_p(0)
+    if m > 1:
+        gammas = _dev_words(gammas, 8, "gammas")
+        if gammas.shape[0] != m - 1:
+            raise ValueError("need m - 1 challenges")
+        gp = _ptr(gammas)
+    _check(lib.zk_fold(_ptr(inst), gp, m, k, _ptr(out), _stream(inst)))
+    return out

@@ -1,0 +1,150 @@
+// Host (CPU) build of the kernels' field and curve code, for CPU tests.
+//
+// Compiles the same __host__ __device__ functions the HIP kernels use into a
+// plain x86 shared library, so the limb arithmetic, the lazy-reduction bounds
+// and the point formulas can be checked against Python integers without a
+// GPU.  Every entry point takes canonical little-endian 32-bit words.
+#include <stdint.h>
+
+#include "../../paper_2507_07031_amd/csrc/curve.h"
+
+using namespace zk;
+
+namespace {
+
+template <class F>
+f29 load_mont(const uint32_t w[8]) {
+  return reduce_full<F>(to_mont<F>(unpack(w)));
+}
+
+template <class F>
+void store_plain(const f29& a, uint32_t w[8]) {
+  pack(from_mont<F>(a), w);
+}
+
+}  // namespace
+
+extern "C" {
+
+void host_fq_mul(const uint32_t* a, const uint32_t* b, uint32_t* out) {
+  store_plain<FqP>(mont_mul<FqP>(load_mont<FqP>(a), load_mont<FqP>(b)), out);
+}
+
+void host_fq_sqr(const uint32_t* a, uint32_t* out) {
+  store_plain<FqP>(mont_sqr<FqP>(load_mont<FqP>(a)), out);
+}
+
+void host_fq_inv(const uint32_t* a, uint32_t* out) {
+  store_plain<FqP>(mont_inv<FqP>(load_mont<FqP>(a)), out);
+}
+
+void host_fr_mul(const uint32_t* a, const uint32_t* b, uint32_t* out) {
+  store_plain<FrP>(mont_mul<FrP>(load_mont<FrP>(a), load_mont<FrP>(b)), out);
+}
+
+// Raw limb access: products of arbitrary (already Montgomery) limb vectors.
+void host_fq_mont_mul_raw(const uint32_t* a9, const uint32_t* b9, uint32_t* out9) {
+  f29 a, b;
+  for (int i = 0; i < 9; i++) {
+    a.l[i] = a9[i];
+    b.l[i] = b9[i];
+  }
+  f29 r = mont_mul<FqP>(a, b);
+  for (int i = 0; i < 9; i++) out9[i] = r.l[i];
+}
+
+int host_fq_is_zero_mod(const uint32_t* a9) {
+  f29 a;
+  for (int i = 0; i < 9; i++) a.l[i] = a9[i];
+  return is_zero_mod<FqP>(a) ? 1 : 0;
+}
+
+void host_fq_reduce_full(const uint32_t* a9, uint32_t* out9) {
+  f29 a;
+  for (int i = 0; i < 9; i++) a.l[i] = a9[i];
+  f29 r = reduce_full<FqP>(a);
+  for (int i = 0; i < 9; i++) out9[i] = r.l[i];
+}
+
+// sum of affine points (16 words each) by repeated mixed addition.
+void host_g1_sum_madd(const uint32_t* pts, uint64_t n, uint32_t* out) {
+  xyzz acc = xyzz_inf();
+  for (uint64_t i = 0; i < n; i++) {
+    aff p;
+    if (aff_from_plain_words(pts + 16 * i, p)) acc = madd(acc, p);
+  }
+  to_affine_words(acc, out);
+}
+
+// sum of affine points by full XYZZ additions (pairwise tree).
+void host_g1_sum_add(const uint32_t* pts, uint64_t n, uint32_t* out) {
+  xyzz acc = xyzz_inf();
+  for (uint64_t i = 0; i < n; i++) {
+    aff p;
+    if (aff_from_plain_words(pts + 16 * i, p)) acc = add(acc, from_aff(p));
+  }
+  to_affine_words(acc, out);
+}
+
+void host_g1_dbl(const uint32_t* pt, uint32_t* out) {
+  aff p;
+  xyzz a = aff_from_plain_words(pt, p) ? from_aff(p) : xyzz_inf();
+  to_affine_words(dbl(a), out);
+}
+
+void host_g1_mul_small(const uint32_t* pt, uint32_t k, uint32_t* out) {
+  aff p;
+  xyzz a = aff_from_plain_words(pt, p) ? from_aff(p) : xyzz_inf();
+  to_affine_words(mul_small(a, k), out);
+}
+
+void host_g1_neg(const uint32_t* pt, uint32_t* out) {
+  aff p;
+  if (!aff_from_plain_words(pt, p)) {
+    for (int i = 0; i < 16; i++) out[i] = 0;
+    return;
+  }
+  to_affine_words(from_aff(aff_neg(p)), out);
+}
+
+// XYZZ given as raw 29-bit limbs (36 words, Montgomery coordinates):
+// lets tests push representations to the edge of the bounded box.
+static xyzz load_xyzz_raw(const uint32_t* w) {
+  xyzz a;
+  for (int i = 0; i < 9; i++) {
+    a.X.l[i] = w[i];
+    a.Y.l[i] = w[9 + i];
+    a.ZZ.l[i] = w[18 + i];
+    a.ZZZ.l[i] = w[27 + i];
+  }
+  return a;
+}
+
+static void store_xyzz_raw(const xyzz& a, uint32_t* w) {
+  for (int i = 0; i < 9; i++) {
+    w[i] = a.X.l[i];
+    w[9 + i] = a.Y.l[i];
+    w[18 + i] = a.ZZ.l[i];
+    w[27 + i] = a.ZZZ.l[i];
+  }
+}
+
+void host_xyzz_add_raw(const uint32_t* a, const uint32_t* b, uint32_t* out) {
+  store_xyzz_raw(add(load_xyzz_raw(a), load_xyzz_raw(b)), out);
+}
+
+void host_xyzz_madd_raw(const uint32_t* a, const uint32_t* pt, uint32_t* out) {
+  aff p;
+  aff_from_plain_words(pt, p);
+  store_xyzz_raw(madd(load_xyzz_raw(a), p), out);
+}
+
+void host_xyzz_dbl_raw(const uint32_t* a, uint32_t* out) {
+  store_xyzz_raw(dbl(load_xyzz_raw(a)), out);
+}
+
+void host_xyzz_to_affine(const uint32_t* a, uint32_t* out) {
+  to_affine_words(load_xyzz_raw(a), out);
+}
+
+}  // extern "C"

@@ -1,0 +1,232 @@
+"""The kernels' field and curve code, built for the host, against Python integers.
+
+The HIP kernels include the same __host__ __device__ headers; this CPU build
+checks the 29-bit-limb Montgomery arithmetic, the lazy-reduction bounds at the
+edge of their invariant box, and the XYZZ point formulas with every special
+case (infinity, P + P, P + (-P)), with no GPU.
+"""
+import ctypes
+import os
+import random
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import field, g1
+from workloads import ints_to_limbs, limbs_to_ints
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "host", "host_arith.hip")
+LIB = os.path.join(HERE, "host", "libhost_arith.so")
+
+P, R = field.P, field.R
+MONT = 1 << 261
+MASK = (1 << 29) - 1
+
+
+def build_host_lib(out=LIB):
+    cmd = ["hipcc", "-O2", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", SRC, "-o", out]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return out
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
+            os.path.getmtime(p) for p in _sources()):
+        build_host_lib()
+    L = ctypes.CDLL(LIB)
+    return L
+
+
+def _sources():
+    csrc = os.path.join(os.path.dirname(HERE), "paper_2507_07031_amd", "csrc")
+    return [SRC] + [os.path.join(csrc, f) for f in ("field.h", "curve.h", "field_constants.h")]
+
+
+def _w(vals):
+    a = np.ascontiguousarray(ints_to_limbs(vals))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def _out(nwords):
+    a = np.zeros(nwords, dtype=np.uint32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def _pt_words(pts):
+    vals = []
+    for pt in pts:
+        x, y = g1.encode(pt)
+        vals += [x, y]
+    return _w(vals)
+
+
+def _read_pt(arr):
+    x, y = limbs_to_ints(arr.reshape(2, 8))
+    return g1.decode((x, y))
+
+
+def _limbs29(v):
+    return [(v >> (29 * i)) & MASK for i in range(9)]
+
+
+def _from_limbs29(limbs):
+    return sum(int(v) << (29 * i) for i, v in enumerate(limbs))
+
+
+def test_fq_fr_mul_inv(lib):
+    rng = random.Random(1)
+    edge = [0, 1, 2, P - 1, P - 2, (1 << 253), P // 2]
+    for i in range(300):
+        a = edge[i] if i < len(edge) else rng.randrange(P)
+        b = edge[-1 - i] if i < len(edge) else rng.randrange(P)
+        aw, ap = _w([a])
+        bw, bp = _w([b])
+        o, op = _out(8)
+        lib.host_fq_mul(ap, bp, op)
+        assert limbs_to_ints(o)[0] == a * b % P
+        lib.host_fq_sqr(ap, op)
+        assert limbs_to_ints(o)[0] == a * a % P
+        if a:
+            lib.host_fq_inv(ap, op)
+            assert limbs_to_ints(o)[0] == pow(a, -1, P)
+        ar, br = a % R, b % R
+        aw, ap = _w([ar])
+        bw, bp = _w([br])
+        lib.host_fr_mul(ap, bp, op)
+        assert limbs_to_ints(o)[0] == ar * br % R
+
+
+def test_mont_mul_worst_case_limbs(lib):
+    # all-ones limbs of 29 bits in both operands (value just under 2^261): the
+    # column sums reach their maximum; the result must still be congruent
+    # to a*b*2^-261 mod p.
+    rng = random.Random(2)
+    cases = [[MASK] * 9, [MASK] * 8 + [(1 << 23) - 1]]
+    for _ in range(50):
+        cases.append([rng.randrange(1 << 29) for _ in range(9)])
+    for la in cases:
+        for lb in cases[:3]:
+            a9 = np.array(la, dtype=np.uint32)
+            b9 = np.array(lb, dtype=np.uint32)
+            o = np.zeros(9, dtype=np.uint32)
+            lib.host_fq_mont_mul_raw(a9.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                     b9.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                     o.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+            va, vb, vo = _from_limbs29(la), _from_limbs29(lb), _from_limbs29(o)
+            assert vo % P == va * vb * pow(MONT, -1, P) % P
+            assert vo < va * vb // MONT + P + 1
+            assert all(int(x) <= MASK for x in o[:8])
+
+
+def test_is_zero_mod_and_reduce(lib):
+    def call_zero(v):
+        a9 = np.array(_limbs29(v), dtype=np.uint32)
+        return lib.host_fq_is_zero_mod(a9.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+
+    for k in range(32):
+        assert call_zero(k * P) == 1
+        assert call_zero(k * P + 1) == 0
+        assert call_zero(k * P + (1 << 29)) == 0 if k * P + (1 << 29) < 32 * P else True
+    rng = random.Random(3)
+    for _ in range(200):
+        v = rng.randrange(32 * P)
+        assert call_zero(v) == (v % P == 0)
+        a9 = np.array(_limbs29(v), dtype=np.uint32)
+        o = np.zeros(9, dtype=np.uint32)
+        lib.host_fq_reduce_full(a9.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                o.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+        assert _from_limbs29(o) == v % P
+
+
+def _rand_points(rng, n):
+    return [g1.gen_mul(rng.randrange(1, R)) for _ in range(n)]
+
+
+def test_point_sums_and_special_cases(lib):
+    rng = random.Random(4)
+    pts = _rand_points(rng, 6)
+    a = pts[0]
+    cases = [
+        pts,                                  # generic
+        [a, a],                               # P + P
+        [a, g1.neg(a)],                       # P + (-P)
+        [a, g1.neg(a), pts[1]],               # through infinity
+        [None, a, None],                      # infinity inputs
+        [a, a, a, g1.neg(a)],                 # 2P + P - P
+        [],
+    ]
+    for case in cases:
+        expect = None
+        for pt in case:
+            expect = g1.add(expect, pt)
+        arr, ptr = _pt_words(case) if case else _w([0, 0])
+        o, op = _out(16)
+        lib.host_g1_sum_madd(ptr, ctypes.c_uint64(len(case)), op)
+        assert _read_pt(o) == expect
+        lib.host_g1_sum_add(ptr, ctypes.c_uint64(len(case)), op)
+        assert _read_pt(o) == expect
+
+
+def test_dbl_mul_small_neg(lib):
+    rng = random.Random(5)
+    for pt in _rand_points(rng, 4) + [g1.G, None]:
+        arr, ptr = _pt_words([pt])
+        o, op = _out(16)
+        lib.host_g1_dbl(ptr, op)
+        assert _read_pt(o) == g1.double(pt)
+        for k in (0, 1, 2, 3, 5, 255, 65536, 123457, (1 << 32) - 1):
+            lib.host_g1_mul_small(ptr, ctypes.c_uint32(k), op)
+            assert _read_pt(o) == g1.mul(k, pt)
+        lib.host_g1_neg(ptr, op)
+        assert _read_pt(o) == g1.neg(pt)
+
+
+def _xyzz_rep(pt, z, kx, ky, kzz, kzzz):
+    """Montgomery XYZZ limbs of pt with Z = z, each coordinate raised by k*p."""
+    x, y = pt
+    zz, zzz = z * z % P, z * z * z % P
+    coords = [x * zz % P, y * zzz % P, zz, zzz]
+    out = []
+    for c, k in zip(coords, (kx, ky, kzz, kzzz)):
+        out += _limbs29(c * MONT % P + k * P)
+    return np.array(out, dtype=np.uint32)
+
+
+def _xyzz_value(w):
+    X, Y, ZZ, ZZZ = (_from_limbs29(w[9 * i:9 * i + 9]) * pow(MONT, -1, P) % P for i in range(4))
+    if ZZ == 0:
+        return None
+    return (X * pow(ZZ, -1, P) % P, Y * pow(ZZZ, -1, P) % P)
+
+
+def test_formulas_at_edge_of_bound_box(lib):
+    # Coordinates as large as the invariant box allows (X < 6p, Y < 4p,
+    # ZZ, ZZZ < 1.25p): results must be right and stay inside the box.
+    rng = random.Random(6)
+    ptr = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    for it in range(40):
+        a, b = _rand_points(rng, 2)
+        if it % 5 == 0:
+            b = a  # doubling through the special case
+        ka = (5, 3, 0, 0) if it % 2 else (rng.randrange(6), rng.randrange(4), 0, 0)
+        wa = _xyzz_rep(a, rng.randrange(1, P), *ka)
+        wb = _xyzz_rep(b, rng.randrange(1, P), 5, 3, 0, 0)
+        o = np.zeros(36, dtype=np.uint32)
+        lib.host_xyzz_add_raw(ptr(wa), ptr(wb), ptr(o))
+        assert _xyzz_value(o) == g1.add(a, b)
+        vals = [_from_limbs29(o[9 * i:9 * i + 9]) for i in range(4)]
+        assert vals[0] < 6 * P and vals[1] < 4 * P and vals[2] < P + P // 4 and vals[3] < P + P // 4
+        pw, pp = _pt_words([b])
+        lib.host_xyzz_madd_raw(ptr(wa), pp, ptr(o))
+        assert _xyzz_value(o) == g1.add(a, b)
+        vals = [_from_limbs29(o[9 * i:9 * i + 9]) for i in range(4)]
+        assert vals[0] < 6 * P and vals[1] < 4 * P and vals[2] < P + P // 4 and vals[3] < P + P // 4
+        lib.host_xyzz_dbl_raw(ptr(wa), ptr(o))
+        assert _xyzz_value(o) == g1.double(a)
+        oa = np.zeros(16, dtype=np.uint32)
+        lib.host_xyzz_to_affine(ptr(wa), ptr(oa))
+        assert _read_pt(oa) == a
