@@ -1,0 +1,283 @@
+#!/usr/bin/env python3
+"""Benchmark of the KZG commit / fold hot path on one MI355X.
+
+One step = the large basic-block commit job, inputs resident in HBM:
+2^20 uniform Fr evaluations -> inverse NTT -> MSM of the 2^20 coefficients
+against the prepared SRS [tau^i]_1 -> 4x coset NTT (2^20 -> 2^22).
+`value` is that job's throughput in committed points per second.
+
+Printed as one JSON line, with
+* per-operation throughputs (MSM points/s, NTT / iNTT / coset elements/s),
+* the quantized-activation MSM at 2^22 against uniform scalars at 2^22,
+* 256 uneven MSMs (log-uniform 2^8..2^18) batched vs one call each, and the
+  fold of 64 of the resulting commitments,
+* `roofline` of the dominant kernel (bucket accumulation) from HIP events
+  recorded by the library on its launch stream over the timed region,
+* `cpu_baseline`: the CPU oracle on a bounded sample of the same job.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from workloads import generators as gen  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0
+# v_mad_u64_u32 issues once per lane per cycle: 256 CUs x 64 lanes x 2.4 GHz
+PEAK_MAD_TOPS = 256 * 64 * 2.4e9 / 1e12
+# algorithmic word products of one 256-bit Montgomery product with 32-bit
+# words (operand-scanning CIOS: 8x8 for a*b, 8x8 for m*q, 8 for the m_i)
+MADS_PER_MONT = 136
+# Fq products of a mixed XYZZ addition (8M + 2S)
+MONT_PER_MADD = 10
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def nonzero_digits(scalars_u32, c=16):
+    """Exact number of nonzero signed c-bit digits (c = 16) after the negation
+    trick: the number of mixed additions bucket accumulation must perform."""
+    assert c == 16
+    s = np.array(scalars_u32, dtype=np.uint64)
+    r = np.array([(gen.FR_MODULUS >> (32 * i)) & 0xFFFFFFFF for i in range(8)], dtype=np.uint64)
+    half = np.array([((gen.FR_MODULUS - 1) // 2 >> (32 * i)) & 0xFFFFFFFF for i in range(8)], dtype=np.uint64)
+    gt = np.zeros(s.shape[0], dtype=bool)
+    eq = np.ones(s.shape[0], dtype=bool)
+    for i in range(7, -1, -1):
+        gt |= eq & (s[:, i] > half[i])
+        eq &= s[:, i] == half[i]
+    neg = s.copy()
+    borrow = np.zeros(s.shape[0], dtype=np.uint64)
+    for i in range(8):
+        d = r[i] - s[:, i] - borrow
+        borrow = (r[i] < s[:, i] + borrow).astype(np.uint64)
+        neg[:, i] = d & 0xFFFFFFFF
+    s = np.where(gt[:, None], neg, s).astype(np.uint32)
+    h = s.view(np.uint16).astype(np.int64)  # 16 little-endian 16-bit windows
+    carry = np.zeros(s.shape[0], dtype=np.int64)
+    count = 0
+    for w in range(16):
+        d = h[:, w] + carry
+        big = d > (1 << 15)
+        mag = np.where(big, (1 << 16) - d, d)
+        carry = big.astype(np.int64)
+        count += int(np.count_nonzero(mag))
+    return count
+
+
+# ----------------------------------------------------------------- CPU oracle
+
+def _oracle_srs_chunk(args):
+    tau, lo, hi = args
+    from oracle import srs as osrs
+    return [osrs.srs_point(tau, i) for i in range(lo, hi)]
+
+
+def _oracle_naive_sum(args):
+    pts, scal = args
+    from oracle import g1, msm as omsm
+    return g1.encode(omsm.naive_msm(pts, scal))
+
+
+def cpu_baseline(tau_int, log_n=12):
+    """The oracle on a 2^12-point commit job: inverse transform, naive MSM over
+    the oracle's own SRS (split over every host core), 4x coset evaluation."""
+    from oracle import g1, ntt as ontt
+    n = 1 << log_n
+    cores = len(os.sched_getaffinity(0))
+    evals = gen.limbs_to_ints(gen.uniform_fr(gen.CONFIG_SEEDS["commit"], n, tag=99))
+    chunks = [(i * n // cores, (i + 1) * n // cores) for i in range(cores)]
+    with mp.get_context("fork").Pool(cores) as pool:
+        srs_parts = pool.map(_oracle_srs_chunk, [(tau_int, lo, hi) for lo, hi in chunks])  # setup, untimed
+        t0 = time.perf_counter()
+        coeffs = ontt.ifft(evals)
+        parts = pool.map(_oracle_naive_sum, [(srs_parts[k], coeffs[lo:hi]) for k, (lo, hi) in enumerate(chunks)])
+        acc = None
+        for p in parts:
+            acc = g1.add(acc, g1.decode(p))
+        ontt.coset_evals(coeffs, 2, 5)
+        dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
+            "sample": "2^12-point commit job (oracle iNTT 2^12, naive MSM of 2^12 points split over %d "
+                      "processes, 4x coset 2^12->2^14); %.1f s wall" % (cores, dt)}
+
+
+# ----------------------------------------------------------------- GPU
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2507_07031_amd import zk
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = 1 << 20
+    tau = gen.tau_scalar()
+    tau_int = gen.limbs_to_ints(tau[None, :])[0]
+
+    log("setup: SRS 2^22 + prepared table")
+    srs_pts = zk.srs_setup(tau, 1 << 22)
+    srs = zk.SRS(srs_pts)
+    evals_h = gen.uniform_fr(gen.CONFIG_SEEDS["commit"], n)
+    evals = zk.to_device(evals_h)
+    coeffs = torch.empty_like(evals)
+    coset = torch.empty((4 * n, 8), dtype=torch.int32, device=dev)
+    com = torch.empty((1, 16), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        zk.intt(evals, out=coeffs)
+        zk.msm_srs(srs, coeffs, out=com)
+        zk.coset_ntt(coeffs, 2, out=coset)
+
+    log("warmup", args.warmup)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    zk.profile_read("msm.accumulate")
+    zk.profile_read("msm.sort")
+    zk.profile_read("msm.reduce")
+    zk.profile_read("ntt.pass")
+    zk.profile_enable(True)
+    log("timed", args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    zk.profile_enable(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    acc_ms, acc_n = zk.profile_read("msm.accumulate")
+    sort_ms, sort_n = zk.profile_read("msm.sort")
+    red_ms, red_n = zk.profile_read("msm.reduce")
+    ntt_ms, ntt_n = zk.profile_read("ntt.pass")
+
+    # algorithmic work of one accumulation launch
+    coeffs_h = zk.to_host(coeffs)
+    madds = nonzero_digits(coeffs_h)
+    acc_avg_s = acc_ms / max(acc_n, 1) / 1e3
+    achieved = madds * MONT_PER_MADD * MADS_PER_MONT / acc_avg_s / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_MAD_TOPS, 3),
+                "unit": "TOP/s", "frac": round(achieved / PEAK_MAD_TOPS, 4), "traffic": None,
+                "kernel": "msm.accumulate", "launch_ms": round(acc_avg_s * 1e3, 4),
+                "work_per_launch": "%d mixed additions x %d Fq products x %d word mads"
+                                   % (madds, MONT_PER_MADD, MADS_PER_MONT)}
+
+    extras = {"timed_regions_ms_per_step": {
+        "msm.sort": round(sort_ms / args.steps, 4), "msm.accumulate": round(acc_ms / args.steps, 4),
+        "msm.reduce": round(red_ms / args.steps, 4), "ntt.pass(all)": round(ntt_ms / args.steps, 4),
+        "ntt.pass launches/step": ntt_n / args.steps}}
+
+    def timed(fn, reps=10):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    if not args.no_extras:
+        log("per-op")
+        t_intt = timed(lambda: zk.intt(evals, out=coeffs))
+        t_ntt = timed(lambda: zk.ntt(coeffs, out=evals))
+        zk.intt(evals, out=coeffs)
+        t_msm = timed(lambda: zk.msm_srs(srs, coeffs, out=com))
+        t_coset = timed(lambda: zk.coset_ntt(coeffs, 2, out=coset))
+        extras["ops_2^20"] = {
+            "intt_ms": round(t_intt, 4), "ntt_ms": round(t_ntt, 4), "msm_ms": round(t_msm, 4),
+            "coset_4x_ms": round(t_coset, 4),
+            "msm_points_per_s": n / (t_msm / 1e3), "ntt_elems_per_s": n / (t_ntt / 1e3),
+            "intt_elems_per_s": n / (t_intt / 1e3), "coset_out_elems_per_s": 4 * n / (t_coset / 1e3),
+            "ntt_hbm_frac_2pass": round(2 * 2 * 32 * n / (t_ntt / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+
+        log("quantized 2^22")
+        N22 = 1 << 22
+        q = zk.to_device(gen.quantized_fr(gen.CONFIG_SEEDS["quantized"], N22))
+        u = zk.to_device(gen.uniform_fr(gen.CONFIG_SEEDS["quantized"], N22, tag=5))
+        t_q = timed(lambda: zk.msm_srs(srs, q, out=com), reps=5)
+        t_u = timed(lambda: zk.msm_srs(srs, u, out=com), reps=3)
+        extras["quantized_2^22"] = {"msm_ms": round(t_q, 4), "points_per_s": N22 / (t_q / 1e3),
+                                    "uniform_msm_ms": round(t_u, 4), "uniform_points_per_s": N22 / (t_u / 1e3),
+                                    "speedup_vs_uniform": round(t_u / t_q, 3)}
+        del q, u
+
+        log("batched 256")
+        sizes = gen.log_uniform_sizes(gen.CONFIG_SEEDS["batched"], 256, 8, 18)
+        off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+        sc = zk.to_device(gen.uniform_fr(gen.CONFIG_SEEDS["batched"], int(off[-1]), tag=1))
+        outs = torch.empty((256, 16), dtype=torch.int32, device=dev)
+        t_batch = timed(lambda: zk.msm_batch(srs, sc, off, out=outs), reps=3)
+        views = [sc[int(off[b]):int(off[b + 1])] for b in range(256)]
+
+        def per_call():
+            for b in range(256):
+                zk.msm_srs(srs, views[b], out=outs[b:b + 1])
+        t_call = timed(per_call, reps=3)
+        tot = int(off[-1])
+        extras["batched_256"] = {"total_points": tot, "batched_ms": round(t_batch, 3),
+                                 "per_call_ms": round(t_call, 3), "batched_points_per_s": tot / (t_batch / 1e3),
+                                 "per_call_points_per_s": tot / (t_call / 1e3),
+                                 "batched_over_per_call": round(t_call / t_batch, 3)}
+        log("fold 64")
+        inst = outs[:64].contiguous().reshape(64, 1, 16)
+        gam = zk.to_device(gen.uniform_fr(gen.CONFIG_SEEDS["batched"], 63, tag=2))
+        fout = torch.empty((1, 16), dtype=torch.int32, device=dev)
+        t_fold = timed(lambda: zk.fold(inst, gam, out=fout), reps=5)
+        extras["fold_64"] = {"latency_ms": round(t_fold, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(tau_int)
+
+    rec = {
+        "metric": "MSM points/s (2^20) + NTT elems/s; batched vs per-call throughput, p99 latency",
+        "value": n / (ms_step / 1e3),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32 limbs (BN254 Fr/Fq, exact)",
+        "data": "synthetic: seeded uniform Fr evaluations; SRS [tau^i]G from a seeded tau",
+        "config": {"workload": "commit job: iNTT 2^20 -> MSM 2^20 vs SRS -> 4x coset NTT 2^20->2^22",
+                   "n": n, "curve": "BN254", "msm_window_bits": 16},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    rec.update(extras)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

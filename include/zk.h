@@ -127,6 +127,17 @@ zk_status zk_msm_batch(const zk_srs* srs, const zk_fr* scalars, const uint64_t* 
  * inst[k + j].  out: k points.  m >= 1. */
 zk_status zk_fold(const zk_g1* inst, const zk_fr* gammas, uint32_t m, uint32_t k, zk_g1* out, void* stream);
 
+/* Observability: when enabled, the library brackets named kernel regions
+ * with HIP events recorded on the stream the kernels run on.  Regions:
+ *   "msm.sort"        decompose + histogram + scan + counting-sort scatter
+ *   "msm.accumulate"  the bucket-accumulation kernel (mixed additions)
+ *   "msm.reduce"      record levels + bucket reduction + window combine
+ *   "ntt.pass"        one LDS-tiled NTT pass (1 or 2 per transform)
+ * zk_profile_read waits for the recorded regions named `region` and returns
+ * the sum of their durations and their count; reset != 0 forgets them. */
+zk_status zk_profile_enable(int on);
+zk_status zk_profile_read(const char* region, double* total_ms, uint64_t* launches, int reset);
+
 #ifdef __cplusplus
 }
 #endif

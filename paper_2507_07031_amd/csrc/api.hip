@@ -12,6 +12,7 @@
 #include "field.h"
 #include "msm.h"
 #include "ntt.h"
+#include "prof.h"
 
 using namespace zk;
 
@@ -217,6 +218,19 @@ struct zk_srs {
 extern "C" {
 
 const char* zk_last_error(void) { return g_err.c_str(); }
+
+zk_status zk_profile_enable(int on) {
+  prof_set_enabled(on != 0);
+  return ZK_OK;
+}
+
+zk_status zk_profile_read(const char* region, double* total_ms, uint64_t* launches, int reset) {
+  if (!region || !total_ms || !launches) return fail(ZK_EINVAL, "zk_profile_read: NULL argument");
+  unsigned long long n = 0;
+  if (prof_read(region, total_ms, &n, reset != 0) != 0) return fail(ZK_EDEVICE, "zk_profile_read: event error");
+  *launches = n;
+  return ZK_OK;
+}
 
 zk_status zk_ntt(const zk_fr* in, zk_fr* out, uint32_t log_n, void* stream) {
   if (!in || !out) return fail(ZK_EINVAL, "zk_ntt: NULL buffer");

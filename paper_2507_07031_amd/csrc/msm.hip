@@ -31,6 +31,7 @@
 //  7 combine    Horner over windows (per-window layout), affine output
 #include "curve.h"
 #include "msm.h"
+#include "prof.h"
 
 namespace zk {
 
@@ -759,6 +760,7 @@ hipError_t msm_run(const MsmPlan& p, const uint32_t* mont_points, const uint32_t
     hipLaunchKernelGGL(zero16_kernel, dim3(1), dim3(64), 0, s, out16);
     return hipGetLastError();
   }
+  const ProfToken t_sort = prof_begin("msm.sort", s);
   hipLaunchKernelGGL(decompose_kernel, dim3(cdiv(p.n, 256)), dim3(256), 0, s, scalars, p.n, p.c, p.W, b.digits);
   hipLaunchKernelGGL(fill_zero_kernel, dim3(min(cdiv(p.nbins, 256), 1024u)), dim3(256), 0, s, b.counts, p.nbins);
   const dim3 hgrid(cdiv(p.n, p.chunk), p.W);
@@ -768,13 +770,17 @@ hipError_t msm_run(const MsmPlan& p, const uint32_t* mont_points, const uint32_t
   hipLaunchKernelGGL(copy_u32_kernel, dim3(min(cdiv(p.nbins, 256), 1024u)), dim3(256), 0, s, b.offsets, b.cursor,
                      p.nbins);
   hipLaunchKernelGGL(scatter_kernel, hgrid, dim3(MSM_NT), hlds, s, b.digits, p, b.cursor, b.keys, b.vals);
+  prof_end(t_sort, s);
   // accumulate + record levels
   uint32_t grid = p.acc_blocks;
   int cur = 0;
   const bool last0 = grid == 1;
+  const ProfToken t_acc = prof_begin("msm.accumulate", s);
   hipLaunchKernelGGL(accumulate_kernel, dim3(grid), dim3(MSM_NT), rec_lds_bytes(), s, b.keys, b.vals,
                      b.offsets + p.nbins, mont_points, p.L, b.buckets, last0 ? nullptr : b.rec_keys[0],
                      last0 ? nullptr : b.rec_flags[0], last0 ? nullptr : b.rec_pts[0]);
+  prof_end(t_acc, s);
+  const ProfToken t_red = prof_begin("msm.reduce", s);
   while (grid > 1) {
     const uint32_t nrec = 2 * grid;
     const uint32_t g2 = cdiv(nrec, MSM_SLOTS);
@@ -792,6 +798,7 @@ hipError_t msm_run(const MsmPlan& p, const uint32_t* mont_points, const uint32_t
   hipLaunchKernelGGL(window_sum_kernel, dim3(nwin), dim3(MSM_NT), (size_t)MSM_NT * XYZZ_WORDS * 4, s, b.vbuf, p.J,
                      b.wsum);
   hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, s, b.wsum, nwin, p.c, out16);
+  prof_end(t_red, s);
   return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@
 // e*2^(28-L) split in two halves, and every in-tile twiddle is a single "hi"
 // entry (tile sizes <= 2^14).
 #include "ntt.h"
+#include "prof.h"
 
 namespace zk {
 
@@ -138,7 +139,9 @@ size_t ntt_pass_lds_bytes() { return (size_t)TILE * 32; }
 
 hipError_t ntt_launch_pass(const NttPass& p, hipStream_t s) {
   const uint32_t blocks = (p.nbatch + p.G - 1) / p.G;
+  const ProfToken t = prof_begin("ntt.pass", s);
   hipLaunchKernelGGL(ntt_pass_kernel, dim3(blocks), dim3(NTT_THREADS), ntt_pass_lds_bytes(), s, p);
+  prof_end(t, s);
   return hipGetLastError();
 }
 

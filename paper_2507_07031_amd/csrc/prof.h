@@ -1,0 +1,20 @@
+// Optional kernel timing: named regions bracketed by HIP events on the
+// stream the kernels are launched on (enabled by zk_profile_enable).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace zk {
+
+struct ProfToken {
+  int id = -1;
+};
+
+bool prof_enabled();
+void prof_set_enabled(bool on);
+ProfToken prof_begin(const char* name, hipStream_t s);
+void prof_end(ProfToken t, hipStream_t s);
+// Sum of elapsed times (ms) and count of completed regions called `name`;
+// waits for their events.  reset: forget them afterwards.
+int prof_read(const char* name, double* total_ms, unsigned long long* count, bool reset);
+
+}  // namespace zk

@@ -21,7 +21,8 @@ ZK_OK, ZK_EINVAL, ZK_ENOMEM, ZK_EDEVICE, ZK_EUNSUPPORTED = 0, -1, -2, -3, -5
 MAX_LOG_NTT = 24
 
 EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_srs_setup", "zk_srs_create",
-           "zk_srs_destroy", "zk_srs_size", "zk_msm_srs", "zk_msm_batch", "zk_fold")
+           "zk_srs_destroy", "zk_srs_size", "zk_msm_srs", "zk_msm_batch", "zk_fold", "zk_profile_enable",
+           "zk_profile_read")
 
 
 class ZkError(RuntimeError):
@@ -48,6 +49,8 @@ def _load():
         "zk_msm_srs": ([P, P, U64, P, P], I),
         "zk_msm_batch": ([P, P, P, U32, P, P], I),
         "zk_fold": ([P, P, U32, U32, P, P], I),
+        "zk_profile_enable": ([I], I),
+        "zk_profile_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U64), I], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -148,13 +151,14 @@ def coset_ntt(coeffs, log_blowup, shift=None, out=None):
 
 # ---------------------------------------------------------------- commitments
 
-def msm(bases, scalars, n=None):
+def msm(bases, scalars, n=None, out=None):
     bases = _dev_words(bases, 16, "bases")
     scalars = _dev_words(scalars, 8, "scalars")
     n = int(n if n is not None else scalars.shape[0])
     if n > bases.shape[0] or n > scalars.shape[0]:
         raise ValueError("n exceeds the inputs")
-    out = _torch().empty((1, 16), dtype=_torch().int32, device=bases.device)
+    if out is None:
+        out = _torch().empty((1, 16), dtype=_torch().int32, device=bases.device)
     _check(lib.zk_msm(_ptr(bases), _ptr(scalars), n, _ptr(out), _stream(bases)))
     return out
 
@@ -190,31 +194,38 @@ class SRS:
             pass
 
 
-def msm_srs(srs, scalars, n=None):
+def msm_srs(srs, scalars, n=None, out=None):
     scalars = _dev_words(scalars, 8, "scalars")
     n = int(n if n is not None else scalars.shape[0])
-    out = _torch().empty((1, 16), dtype=_torch().int32, device=scalars.device)
+    if n > scalars.shape[0]:
+        raise ValueError("n exceeds the scalars")
+    if out is None:
+        out = _torch().empty((1, 16), dtype=_torch().int32, device=scalars.device)
     _check(lib.zk_msm_srs(srs.handle, _ptr(scalars), n, _ptr(out), _stream(scalars)))
     return out
 
 
-def msm_batch(srs, scalars, offsets):
+def msm_batch(srs, scalars, offsets, out=None):
     scalars = _dev_words(scalars, 8, "scalars")
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
     batch = off.shape[0] - 1
-    out = _torch().empty((max(batch, 0), 16), dtype=_torch().int32, device=scalars.device)
+    if batch < 0 or int(off[-1]) > scalars.shape[0]:
+        raise ValueError("offsets exceed the scalars")
+    if out is None:
+        out = _torch().empty((max(batch, 0), 16), dtype=_torch().int32, device=scalars.device)
     _check(lib.zk_msm_batch(srs.handle, _ptr(scalars), off.ctypes.data_as(ctypes.c_void_p), batch, _ptr(out),
                             _stream(scalars)))
     return out
 
 
-def fold(inst, gammas):
+def fold(inst, gammas, out=None):
     """inst: (m, k, 16) device tensor; gammas: (m - 1, 8) device tensor."""
     torch = _torch()
     if inst.dim() != 3 or inst.shape[2] != 16 or inst.dtype != torch.int32 or not inst.is_contiguous():
         raise TypeError("inst must be a contiguous int32 tensor of shape (m, k, 16)")
     m, k = int(inst.shape[0]), int(inst.shape[1])
-    out = torch.empty((k, 16), dtype=torch.int32, device=inst.device)
+    if out is None:
+        out = torch.empty((k, 16), dtype=torch.int32, device=inst.device)
     gp = ctypes.c_void_p(0)
     if m > 1:
         gammas = _dev_words(gammas, 8, "gammas")
@@ -223,3 +234,17 @@ def fold(inst, gammas):
         gp = _ptr(gammas)
     _check(lib.zk_fold(_ptr(inst), gp, m, k, _ptr(out), _stream(inst)))
     return out
+
+
+# ---------------------------------------------------------------- observability
+
+def profile_enable(on=True):
+    _check(lib.zk_profile_enable(1 if on else 0))
+
+
+def profile_read(region, reset=True):
+    """(total milliseconds, number of regions) recorded for `region`."""
+    ms = ctypes.c_double()
+    cnt = ctypes.c_uint64()
+    _check(lib.zk_profile_read(region.encode(), ctypes.byref(ms), ctypes.byref(cnt), 1 if reset else 0))
+    return ms.value, cnt.value
