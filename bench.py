@@ -148,10 +148,18 @@ def main():
     com = torch.empty((1, 16), dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
 
+    # the MSM and the coset evaluation both consume the coefficients: the
+    # coset transform runs on a second stream beside the MSM
+    side = torch.cuda.Stream(device=dev)
+    main_s = torch.cuda.current_stream(dev)
+
     def step():
         zk.intt(evals, out=coeffs)
+        side.wait_stream(main_s)
         zk.msm_srs(srs, coeffs, out=com)
-        zk.coset_ntt(coeffs, 2, out=coset)
+        with torch.cuda.stream(side):
+            zk.coset_ntt(coeffs, 2, out=coset)
+        main_s.wait_stream(side)
 
     log("warmup", args.warmup)
     for _ in range(args.warmup):

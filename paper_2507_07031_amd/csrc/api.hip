@@ -192,13 +192,13 @@ zk_status run_ntt(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t L, b
 }
 
 // ---------------------------------------------------------------- MSM driver
-zk_status run_msm(const MsmPlan& plan, const uint32_t* mont_points, const uint32_t* scalars, uint32_t* out16,
-                  hipStream_t s) {
+zk_status run_msm(const MsmPlan& plan, const uint64_t* offsets, const uint32_t* mont_points, const uint32_t* scalars,
+                  uint32_t* out, hipStream_t s) {
   Scratch ws;
   zk_status st = scratch_alloc(ws, msm_workspace_bytes(plan), s);
   if (st) return st;
   const MsmBuffers b = msm_carve(plan, ws.p);
-  ZK_HIP(msm_run(plan, mont_points, scalars, b, out16, s), "msm");
+  ZK_HIP(msm_run(plan, offsets, mont_points, scalars, b, out, s), "msm");
   return ZK_OK;
 }
 
@@ -293,13 +293,14 @@ zk_status zk_msm(const zk_g1* bases, const zk_fr* scalars, uint64_t n, zk_g1* ou
   zk_status st = ctx_get(&c);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
-  const MsmPlan plan = msm_plan((uint32_t)n, msm_default_c((uint32_t)n), false, 0);
+  const MsmPlan plan = msm_plan_generic((uint32_t)n, msm_default_c((uint32_t)n));
   Scratch pts;
   st = scratch_alloc(pts, (size_t)n * 64, s);
   if (st) return st;
   uint32_t* mont = static_cast<uint32_t*>(pts.p);
   ZK_HIP(msm_points_to_mont(reinterpret_cast<const uint32_t*>(bases), mont, n, s), "to_mont");
-  return run_msm(plan, mont, reinterpret_cast<const uint32_t*>(scalars), reinterpret_cast<uint32_t*>(out), s);
+  return run_msm(plan, nullptr, mont, reinterpret_cast<const uint32_t*>(scalars), reinterpret_cast<uint32_t*>(out),
+                 s);
 }
 
 zk_status zk_srs_setup(const zk_fr* tau_host, uint64_t n, zk_g1* out, void* stream) {
@@ -366,11 +367,12 @@ uint64_t zk_srs_size(const zk_srs* srs) { return srs ? srs->n : 0; }
 static zk_status msm_srs_one(const zk_srs* srs, const uint32_t* scalars, uint64_t n, uint32_t* out16,
                              hipStream_t s) {
   if (n < SRS_SHARED_MIN) {
-    const MsmPlan plan = msm_plan((uint32_t)n, msm_default_c((uint32_t)n), false, 0);
-    return run_msm(plan, srs->tab, scalars, out16, s);
+    const MsmPlan plan = msm_plan_generic((uint32_t)n, msm_default_c((uint32_t)n));
+    return run_msm(plan, nullptr, srs->tab, scalars, out16, s);
   }
-  const MsmPlan plan = msm_plan((uint32_t)n, srs->c, true, (uint32_t)srs->n);
-  return run_msm(plan, srs->tab, scalars, out16, s);
+  const uint64_t off[2] = {0, n};
+  const MsmPlan plan = msm_plan_shared(off, 1, srs->c, (uint32_t)srs->n);
+  return run_msm(plan, off, srs->tab, scalars, out16, s);
 }
 
 zk_status zk_msm_srs(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream) {
@@ -394,14 +396,13 @@ zk_status zk_msm_batch(const zk_srs* srs, const zk_fr* scalars, const uint64_t* 
   DeviceCtx* c;
   zk_status st = ctx_get(&c);
   if (st) return st;
-  hipStream_t s = (hipStream_t)stream;
-  const uint32_t* sc = reinterpret_cast<const uint32_t*>(scalars);
-  uint32_t* o = reinterpret_cast<uint32_t*>(out);
-  for (uint32_t b = 0; b < batch; b++) {
-    st = msm_srs_one(srs, sc + offsets_host[b] * 8, offsets_host[b + 1] - offsets_host[b], o + (size_t)b * 16, s);
-    if (st) return st;
-  }
-  return ZK_OK;
+  if (batch == 0) return ZK_OK;
+  if (offsets_host[batch] >= (1ull << 31) / 16) return fail(ZK_EUNSUPPORTED, "zk_msm_batch: too many scalars");
+  // one Pippenger run over every MSM: digits of all scalars sorted into
+  // per-MSM buckets, one accumulation, one reduction, one output per MSM
+  const MsmPlan plan = msm_plan_shared(offsets_host, batch, srs->c, (uint32_t)srs->n);
+  return run_msm(plan, offsets_host, srs->tab, reinterpret_cast<const uint32_t*>(scalars),
+                 reinterpret_cast<uint32_t*>(out), (hipStream_t)stream);
 }
 
 zk_status zk_fold(const zk_g1* inst, const zk_fr* gammas, uint32_t m, uint32_t k, zk_g1* out, void* stream) {
@@ -419,11 +420,11 @@ zk_status zk_fold(const zk_g1* inst, const zk_fr* gammas, uint32_t m, uint32_t k
   uint32_t* col = sigma + (size_t)m * 8;
   uint32_t* mont = col + (size_t)m * 16;
   ZK_HIP(fold_sigmas(reinterpret_cast<const uint32_t*>(gammas), m, sigma, s), "fold sigmas");
-  const MsmPlan plan = msm_plan(m, msm_default_c(m), false, 0);
+  const MsmPlan plan = msm_plan_generic(m, msm_default_c(m));
   for (uint32_t j = 0; j < k; j++) {
     ZK_HIP(gather_component(reinterpret_cast<const uint32_t*>(inst), m, k, j, col, s), "fold gather");
     ZK_HIP(msm_points_to_mont(col, mont, m, s), "fold to_mont");
-    st = run_msm(plan, mont, sigma, reinterpret_cast<uint32_t*>(out) + (size_t)j * 16, s);
+    st = run_msm(plan, nullptr, mont, sigma, reinterpret_cast<uint32_t*>(out) + (size_t)j * 16, s);
     if (st) return st;
   }
   return ZK_OK;

@@ -249,7 +249,7 @@ ZK_HD f29 mont_pow(const f29& a, const uint32_t e[8]) {
 
 // Inverse by Fermat: a^(q-2); a must be nonzero mod q.
 template <class F>
-ZK_HD f29 mont_inv(const f29& a) {
+ZK_HD f29 mont_inv_fermat(const f29& a) {
   uint32_t e[8];
 #pragma unroll
   for (int i = 0; i < 8; i++) e[i] = F::M32[i];
@@ -258,6 +258,8 @@ ZK_HD f29 mont_inv(const f29& a) {
 }
 
 // ---- 32-bit-word canonical arithmetic (values in [0, q)) -------------------
+
+
 
 // r = a + b mod q for canonical a, b (2q < 2^256, so the sum never carries out).
 template <class F>
@@ -301,6 +303,84 @@ template <class F>
 ZK_HD void mul_plain_by_mont(const uint32_t a[8], const f29& w, uint32_t r[8]) {
   pack(mont_mul<F>(unpack(a), w), r);  // < q*q/2^261 + q < 2q
   canon32<F>(r);
+}
+
+// ---- inversion -------------------------------------------------------------
+
+ZK_HD bool w8_is_one(const uint32_t a[8]) {
+  uint32_t o = a[0] ^ 1u;
+#pragma unroll
+  for (int i = 1; i < 8; i++) o |= a[i];
+  return o == 0;
+}
+
+// a >>= 1 over 8 words (with `top` shifted into bit 255).
+ZK_HD void w8_shr1(uint32_t a[8], uint32_t top) {
+#pragma unroll
+  for (int i = 0; i < 7; i++) a[i] = (a[i] >> 1) | (a[i + 1] << 31);
+  a[7] = (a[7] >> 1) | (top << 31);
+}
+
+// x / 2 mod q for canonical x (q odd): x even -> x >> 1, else (x + q) >> 1.
+template <class F>
+ZK_HD void half_mod32(uint32_t x[8]) {
+  const uint32_t mask = 0u - (x[0] & 1u);
+  unsigned c = 0;
+#pragma unroll
+  for (int i = 0; i < 8; i++) x[i] = __builtin_addc(x[i], F::M32[i] & mask, c, &c);
+  w8_shr1(x, c);
+}
+
+// Plain inverse x^-1 mod q of a canonical nonzero x by the binary extended
+// Euclidean algorithm (invariants: x1 * x = u, x2 * x = v mod q).
+template <class F>
+ZK_HD void inv_binary32(const uint32_t x[8], uint32_t out[8]) {
+  uint32_t u[8], v[8], x1[8], x2[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    u[i] = x[i];
+    v[i] = F::M32[i];
+    x1[i] = 0;
+    x2[i] = 0;
+  }
+  x1[0] = 1;
+  while (!w8_is_one(u) && !w8_is_one(v)) {
+    while ((u[0] & 1u) == 0) {
+      w8_shr1(u, 0);
+      half_mod32<F>(x1);
+    }
+    while ((v[0] & 1u) == 0) {
+      w8_shr1(v, 0);
+      half_mod32<F>(x2);
+    }
+    uint32_t d[8];
+    unsigned br = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) d[i] = __builtin_subc(u[i], v[i], br, &br);
+    if (!br) {  // u >= v
+#pragma unroll
+      for (int i = 0; i < 8; i++) u[i] = d[i];
+      sub_mod32<F>(x1, x2, x1);
+    } else {
+      unsigned b2 = 0;
+#pragma unroll
+      for (int i = 0; i < 8; i++) v[i] = __builtin_subc(v[i], u[i], b2, &b2);
+      sub_mod32<F>(x2, x1, x2);
+    }
+  }
+  const bool uone = w8_is_one(u);
+#pragma unroll
+  for (int i = 0; i < 8; i++) out[i] = uone ? x1[i] : x2[i];
+}
+
+// Inverse in Montgomery form: (a R)^-1 by the binary algorithm, times R^3
+// through one Montgomery product gives a^-1 R.  a must be nonzero mod q.
+template <class F>
+ZK_HD f29 mont_inv(const f29& a) {
+  uint32_t w[8], iw[8];
+  pack(reduce_full<F>(a), w);
+  inv_binary32<F>(w, iw);
+  return mont_mul<F>(unpack(iw), f29_from(F::R3));
 }
 
 }  // namespace zk

@@ -5,54 +5,66 @@
 
 namespace zk {
 
-constexpr uint32_t MSM_NT = 256;          // threads per workgroup (accumulate / reduce)
+constexpr uint32_t MSM_NT = 256;           // threads per workgroup
 constexpr uint32_t MSM_SLOTS = 2 * MSM_NT; // records combined per workgroup
 constexpr uint32_t KEY_SENTINEL = 0xfffffffeu;
-constexpr uint32_t XYZZ_WORDS = 36;       // four 9-limb coordinates
+constexpr uint32_t XYZZ_WORDS = 36;        // four 9-limb coordinates
+constexpr uint32_t REC_WORDS = 40;         // key, flag, pad, pad, point (36): 160 bytes
 
-// Geometry of one Pippenger run.
+// Geometry of one Pippenger run over one or several independent sums.
+//  generic: one MSM over arbitrary (Montgomery) bases; W windows with K
+//           buckets each ("segments" = windows), Horner-combined at the end.
+//  shared:  `nseg` MSMs over one pre-shifted table (tab[w*tab_stride + i] =
+//           2^(c w) P_i); all windows of an MSM feed its K buckets, and every
+//           MSM (segment) has its own output.
 struct MsmPlan {
-  uint32_t n;          // points / scalars
+  uint32_t n;          // scalars in total (all segments)
   uint32_t c;          // window bits; digits are signed in [-2^(c-1), 2^(c-1)]
   uint32_t W;          // windows = ceil(254 / c)
-  uint32_t K;          // buckets per window = 2^(c-1)
-  uint32_t shared;     // 1: all windows share K buckets (bases pre-shifted by 2^(cw))
-  uint32_t nbins;      // shared ? K : W*K
-  uint32_t tab_stride; // shared: point index of window w = w*tab_stride + i
-  uint32_t chunk;      // digits per histogram / scatter workgroup
+  uint32_t K;          // buckets per segment = 2^(c-1)
+  uint32_t shared;
+  uint32_t nseg;
+  uint32_t nbins;      // nseg * K
+  uint32_t tab_stride;
+  uint32_t chunk;      // scalars per histogram / scatter item
+  uint32_t nitems;     // items per window
   uint32_t L;          // sorted entries per accumulating thread
   uint32_t acc_blocks; // accumulate workgroups
   uint32_t LB;         // buckets per thread in the running-sum reduction
-  uint32_t J;          // LB-chunks per window = K / LB
+  uint32_t J;          // LB-chunks per segment = K / LB
 };
 
-MsmPlan msm_plan(uint32_t n, uint32_t c, bool shared, uint32_t tab_stride);
+MsmPlan msm_plan_generic(uint32_t n, uint32_t c);
+// offsets: nmsm + 1 scalar offsets (host), offsets[0] = 0.
+MsmPlan msm_plan_shared(const uint64_t* offsets, uint32_t nmsm, uint32_t c, uint32_t tab_stride);
 uint32_t msm_default_c(uint32_t n);
 
-// Scratch buffers of one run (device pointers), sizes from msm_workspace_layout.
+// Scratch buffers of one run (device pointers), carved from one allocation.
 struct MsmBuffers {
   uint32_t* digits;    // W*n
   uint32_t* counts;    // nbins
   uint32_t* offsets;   // nbins + 1
   uint32_t* cursor;    // nbins
   uint32_t* scan_tmp;  // scan block sums
-  uint32_t* keys;      // W*n
-  uint32_t* vals;      // W*n
+  uint2* entries;      // W*n (bucket key, point index | sign << 31), sorted by key
   uint32_t* buckets;   // nbins * 36
-  uint32_t* rec_keys[2];
-  uint32_t* rec_flags[2];
-  uint32_t* rec_pts[2];
-  uint32_t* vbuf;      // (shared ? 1 : W) * J * 36
-  uint32_t* wsum;      // (shared ? 1 : W) * 36
+  uint32_t* rec[2];    // records (REC_WORDS each), ping-pong between levels
+  uint32_t* vbuf;      // nseg * J * 36
+  uint32_t* wsum;      // nseg * 36
+  uint32_t* seg_off;   // nseg + 1 (shared) / 2 (generic)
+  uint4* items;        // nitems: (segment, first scalar, end scalar, 0)
 };
 
 size_t msm_workspace_bytes(const MsmPlan& p);
 MsmBuffers msm_carve(const MsmPlan& p, void* base);
 
-// Full pipeline: scalars (canonical, 8 words each) against Montgomery-form
-// affine points (16 words each) -> canonical affine result (16 words, device).
-hipError_t msm_run(const MsmPlan& p, const uint32_t* mont_points, const uint32_t* scalars,
-                   const MsmBuffers& b, uint32_t* out16, hipStream_t s);
+// Full pipeline.  Scalars: canonical, 8 words each, concatenated per segment.
+// points: Montgomery affine (16 words each) -- the bases (generic) or the
+// pre-shifted table (shared).  offsets: host segment offsets (shared), or
+// nullptr (generic).  out: 16 words per output (1 for generic, nseg for
+// shared), canonical affine.
+hipError_t msm_run(const MsmPlan& p, const uint64_t* offsets, const uint32_t* points, const uint32_t* scalars,
+                   const MsmBuffers& b, uint32_t* out, hipStream_t s);
 
 // Canonical plain affine points -> Montgomery-form affine points (count n).
 hipError_t msm_points_to_mont(const uint32_t* plain, uint32_t* mont, uint64_t n, hipStream_t s);

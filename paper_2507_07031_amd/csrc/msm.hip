@@ -29,6 +29,8 @@
 //  6 reduce     sum_k k B_k by running sums over chunks of LB buckets, each
 //               chunk offset by a small scalar multiple, then a tree
 //  7 combine    Horner over windows (per-window layout), affine output
+#include <algorithm>
+
 #include "curve.h"
 #include "msm.h"
 #include "prof.h"
@@ -163,51 +165,82 @@ __global__ void decompose_kernel(const uint32_t* __restrict__ scalars, uint32_t 
   }
 }
 
+// ---------------------------------------------------------------- items
+// Host segment offsets travel as kernel arguments (no host buffer outlives
+// the call; capture-safe).  One thread per segment writes its offset and its
+// histogram items (chunks of at most p.chunk scalars of one segment).
+constexpr uint32_t SEG_ARGS = 128;
+struct SegArgs {
+  uint32_t first;                 // first segment of this launch
+  uint32_t count;                 // segments in this launch
+  uint32_t off[SEG_ARGS + 1];     // scalar offsets of segments first..first+count
+  uint32_t item0[SEG_ARGS];       // first item index of each segment
+};
+
+__global__ void make_items_kernel(SegArgs a, uint32_t chunk, uint32_t* __restrict__ seg_off,
+                                  uint4* __restrict__ items) {
+  const uint32_t t = threadIdx.x;
+  if (t >= a.count) return;
+  const uint32_t b = a.first + t;
+  const uint32_t g0 = a.off[t], g1 = a.off[t + 1];
+  seg_off[b] = g0;
+  if (t + 1 == a.count) seg_off[b + 1] = g1;
+  uint32_t it = a.item0[t];
+  for (uint32_t g = g0; g < g1; g += chunk) items[it++] = make_uint4(b, g, min(g + chunk, g1), 0);
+}
+
 // ---------------------------------------------------------------- histogram / scatter
+// Block (item, window): counts of the item's digits in window w, in LDS over
+// the segment's K buckets, flushed to the global bucket counts.
+__device__ __forceinline__ uint32_t bin_base(const MsmPlan& p, uint32_t seg, uint32_t w) {
+  return (p.shared ? seg : w) * p.K;
+}
+
 __global__ void __launch_bounds__(MSM_NT)
-hist_kernel(const uint32_t* __restrict__ digits, MsmPlan p, uint32_t* __restrict__ counts) {
+hist_kernel(const uint32_t* __restrict__ digits, MsmPlan p, const uint4* __restrict__ items,
+            uint32_t* __restrict__ counts) {
   extern __shared__ uint32_t h[];
   const uint32_t w = blockIdx.y;
-  const uint32_t e0 = blockIdx.x * p.chunk, e1 = min(e0 + p.chunk, p.n);
+  const uint4 it = items[blockIdx.x];
   for (uint32_t b = threadIdx.x; b < p.K; b += MSM_NT) h[b] = 0;
   __syncthreads();
   const uint32_t* dw = digits + (size_t)w * p.n;
-  for (uint32_t e = e0 + threadIdx.x; e < e1; e += MSM_NT) {
+  for (uint32_t e = it.y + threadIdx.x; e < it.z; e += MSM_NT) {
     const uint32_t d = dw[e];
     if (d) atomicAdd(&h[(d >> 1) - 1], 1u);
   }
   __syncthreads();
-  const uint32_t off = p.shared ? 0 : w * p.K;
+  const uint32_t off = bin_base(p, it.x, w);
   for (uint32_t b = threadIdx.x; b < p.K; b += MSM_NT)
     if (h[b]) atomicAdd(&counts[off + b], h[b]);
 }
 
 __global__ void __launch_bounds__(MSM_NT)
-scatter_kernel(const uint32_t* __restrict__ digits, MsmPlan p, uint32_t* __restrict__ cursor,
-               uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+scatter_kernel(const uint32_t* __restrict__ digits, MsmPlan p, const uint4* __restrict__ items,
+               const uint32_t* __restrict__ seg_off, uint32_t* __restrict__ cursor, uint2* __restrict__ entries) {
   extern __shared__ uint32_t h[];
   const uint32_t w = blockIdx.y;
-  const uint32_t e0 = blockIdx.x * p.chunk, e1 = min(e0 + p.chunk, p.n);
+  const uint4 it = items[blockIdx.x];
   for (uint32_t b = threadIdx.x; b < p.K; b += MSM_NT) h[b] = 0;
   __syncthreads();
   const uint32_t* dw = digits + (size_t)w * p.n;
-  for (uint32_t e = e0 + threadIdx.x; e < e1; e += MSM_NT) {
+  for (uint32_t e = it.y + threadIdx.x; e < it.z; e += MSM_NT) {
     const uint32_t d = dw[e];
     if (d) atomicAdd(&h[(d >> 1) - 1], 1u);
   }
   __syncthreads();
-  const uint32_t off = p.shared ? 0 : w * p.K;
+  const uint32_t off = bin_base(p, it.x, w);
   for (uint32_t b = threadIdx.x; b < p.K; b += MSM_NT)
     if (h[b]) h[b] = atomicAdd(&cursor[off + b], h[b]);
   __syncthreads();
-  const uint32_t pbase = p.shared ? w * p.tab_stride : 0;
-  for (uint32_t e = e0 + threadIdx.x; e < e1; e += MSM_NT) {
+  // point index: the base itself (generic) or table row w of the segment's point
+  const uint32_t pbase = p.shared ? (w * p.tab_stride - seg_off[it.x]) : 0u;
+  for (uint32_t e = it.y + threadIdx.x; e < it.z; e += MSM_NT) {
     const uint32_t d = dw[e];
     if (!d) continue;
     const uint32_t b = (d >> 1) - 1;
     const uint32_t pos = atomicAdd(&h[b], 1u);
-    keys[pos] = off + b;
-    vals[pos] = (pbase + e) | ((d & 1u) << 31);
+    entries[pos] = make_uint2(off + b, (pbase + e) | ((d & 1u) << 31));
   }
 }
 
@@ -254,8 +287,15 @@ __device__ void put_slot(RecLds& r, uint32_t i, uint32_t key, uint32_t flag, con
 // Sum every run of equal keys held in the LDS slots; runs closed on both sides
 // are written to their bucket, the first and last run of the block go out as
 // records for the next level (data only if still open there).
+__device__ __forceinline__ void put_rec(uint32_t* rec, uint32_t key, uint32_t flag, const uint32_t* pts_or_null) {
+  reinterpret_cast<uint4*>(rec)[0] = make_uint4(key, flag, 0, 0);
+  uint4* dst = reinterpret_cast<uint4*>(rec + 4);
+  const uint4* src = reinterpret_cast<const uint4*>(pts_or_null);
+  for (int w = 0; w < 9; w++) dst[w] = pts_or_null ? src[w] : make_uint4(0, 0, 0, 0);
+}
+
 __device__ void combine_and_emit(RecLds& r, bool left_open, bool right_open, uint32_t* __restrict__ buckets,
-                                 uint32_t* out_keys, uint32_t* out_flags, uint32_t* out_pts) {
+                                 uint32_t* out_rec) {
   const uint32_t tid = threadIdx.x;
   uint32_t head[MSM_SLOTS / MSM_NT];
 #pragma unroll
@@ -287,85 +327,107 @@ __device__ void combine_and_emit(RecLds& r, bool left_open, bool right_open, uin
       const uint4* src = reinterpret_cast<const uint4*>(r.pts + i * XYZZ_WORDS);
       for (int w = 0; w < 9; w++) dst[w] = src[w];
     }
-    if (!out_keys) continue;
-    const uint32_t rb = 2 * blockIdx.x;
+    if (!out_rec) continue;
+    const size_t rb = 2 * (size_t)blockIdx.x;
     if (i == 0) {
       const bool send = (lo || ro) && has;
-      out_keys[rb] = key;
-      out_flags[rb] = send ? 1u : 0u;
-      uint4* dst = reinterpret_cast<uint4*>(out_pts + (size_t)rb * XYZZ_WORDS);
-      const uint4* src = reinterpret_cast<const uint4*>(r.pts + i * XYZZ_WORDS);
-      for (int w = 0; w < 9; w++) dst[w] = send ? src[w] : make_uint4(0, 0, 0, 0);
+      put_rec(out_rec + rb * REC_WORDS, key, send ? 1u : 0u, send ? r.pts + i * XYZZ_WORDS : nullptr);
     }
     if (e == MSM_SLOTS) {
       const bool send = ro && has && i != 0;
-      out_keys[rb + 1] = key;
-      out_flags[rb + 1] = send ? 1u : 0u;
-      uint4* dst = reinterpret_cast<uint4*>(out_pts + (size_t)(rb + 1) * XYZZ_WORDS);
-      const uint4* src = reinterpret_cast<const uint4*>(r.pts + i * XYZZ_WORDS);
-      for (int w = 0; w < 9; w++) dst[w] = send ? src[w] : make_uint4(0, 0, 0, 0);
+      put_rec(out_rec + (rb + 1) * REC_WORDS, key, send ? 1u : 0u, send ? r.pts + i * XYZZ_WORDS : nullptr);
     }
   }
 }
 
 // ---------------------------------------------------------------- accumulate
-__global__ void __launch_bounds__(MSM_NT)
-accumulate_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-                  const uint32_t* __restrict__ total_p, const uint32_t* __restrict__ points, uint32_t L,
-                  uint32_t* __restrict__ buckets, uint32_t* out_keys, uint32_t* out_flags, uint32_t* out_pts) {
-  extern __shared__ uint32_t sm[];
-  RecLds r = rec_lds(sm);
-  const uint32_t tid = threadIdx.x;
-  const uint32_t total = *total_p;
-  const uint64_t wb = (uint64_t)blockIdx.x * MSM_NT * L;
-  const uint64_t tb = wb + (uint64_t)tid * L;
-  const uint64_t te = min(tb + L, (uint64_t)total);
-  const uint32_t s0 = 2 * tid, s1 = 2 * tid + 1;
-  if (tb >= total) {
-    put_slot(r, s0, KEY_SENTINEL, 0, xyzz_inf());
-    put_slot(r, s1, KEY_SENTINEL, 0, xyzz_inf());
-  } else {
-    uint32_t cur = keys[tb];
-    bool first_done = false;
-    xyzz acc = xyzz_inf();
-    for (uint64_t e = tb; e < te; e++) {
-      const uint32_t k = keys[e];
-      const uint32_t v = vals[e];
-      if (k != cur) {
-        if (!first_done) {
-          put_slot(r, s0, cur, 1, acc);
-          first_done = true;
-        } else {
-          st_xyzz(buckets + (size_t)cur * XYZZ_WORDS, acc);
-        }
-        cur = k;
-        acc = xyzz_inf();
-      }
-      aff pt;
-      if (ld_aff(points + (size_t)(v & 0x7fffffffu) * 16, pt)) {
-        if (v >> 31) pt = aff_neg(pt);
-        acc = madd(acc, pt);
-      }
-    }
-    if (!first_done) {
-      put_slot(r, s0, cur, 1, acc);
-      put_slot(r, s1, cur, 0, xyzz_inf());
-    } else {
-      put_slot(r, s1, cur, 1, acc);
-    }
-  }
-  __syncthreads();
-  const uint64_t we = min(wb + (uint64_t)MSM_NT * L, (uint64_t)total);
-  const bool nonempty = wb < total;
-  const bool left_open = nonempty && wb > 0 && keys[wb - 1] == keys[wb];
-  const bool right_open = nonempty && we < total && keys[we] == keys[we - 1];
-  combine_and_emit(r, left_open, right_open, buckets, out_keys, out_flags, out_pts);
+__device__ __forceinline__ void ld_pt_words(const uint32_t* __restrict__ points, uint32_t v, uint4 q[4]) {
+  const uint4* src = reinterpret_cast<const uint4*>(points + (size_t)(v & 0x7fffffffu) * 16);
+#pragma unroll
+  for (int k = 0; k < 4; k++) q[k] = src[k];
 }
 
+__device__ __forceinline__ void st_rec_xyzz(uint32_t* rec, uint32_t key, uint32_t flag, const xyzz& a) {
+  reinterpret_cast<uint4*>(rec)[0] = make_uint4(key, flag, 0, 0);
+  st_xyzz(rec + 4, a);
+}
+
+// Each thread sums L consecutive sorted entries.  Runs of one key strictly
+// inside the range are complete buckets and go straight to HBM; the first
+// and last run of the range become the thread's two records, finished by the
+// record levels.  The next entry and its point are loaded one step ahead.
+__global__ void __launch_bounds__(MSM_NT) __attribute__((amdgpu_waves_per_eu(3, 3)))
+accumulate_kernel(const uint2* __restrict__ entries, const uint32_t* __restrict__ total_p,
+                  const uint32_t* __restrict__ points, uint32_t L, uint32_t* __restrict__ buckets,
+                  uint32_t* __restrict__ rec) {
+  const uint64_t t = (uint64_t)blockIdx.x * MSM_NT + threadIdx.x;
+  const uint32_t total = *total_p;
+  const uint64_t tb = t * L;
+  uint32_t* r0 = rec + (2 * t) * REC_WORDS;
+  uint32_t* r1 = r0 + REC_WORDS;
+  if (tb >= total) {
+    st_rec_xyzz(r0, KEY_SENTINEL, 0, xyzz_inf());
+    st_rec_xyzz(r1, KEY_SENTINEL, 0, xyzz_inf());
+    return;
+  }
+  const uint64_t te = min(tb + L, (uint64_t)total);
+  uint2 ent = entries[tb];
+  uint4 q[4];
+  ld_pt_words(points, ent.y, q);
+  uint32_t cur = ent.x;
+  bool first_done = false;
+  xyzz acc = xyzz_inf();
+  for (uint64_t e = tb; e < te; e++) {
+    uint2 nent = ent;
+    uint4 nq[4] = {q[0], q[1], q[2], q[3]};
+    if (e + 1 < te) {
+      nent = entries[e + 1];
+      ld_pt_words(points, nent.y, nq);
+    }
+    if (ent.x != cur) {
+      if (!first_done) {
+        st_rec_xyzz(r0, cur, 1, acc);
+        first_done = true;
+      } else {
+        st_xyzz(buckets + (size_t)cur * XYZZ_WORDS, acc);
+      }
+      cur = ent.x;
+      acc = xyzz_inf();
+    }
+    uint32_t w[16];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      w[4 * k] = q[k].x;
+      w[4 * k + 1] = q[k].y;
+      w[4 * k + 2] = q[k].z;
+      w[4 * k + 3] = q[k].w;
+    }
+    uint32_t o = 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) o |= w[k];
+    if (o) {
+      aff pt;
+      pt.x = unpack(w);
+      pt.y = unpack(w + 8);
+      if (ent.y >> 31) pt = aff_neg(pt);
+      acc = madd(acc, pt);
+    }
+    ent = nent;
+#pragma unroll
+    for (int k = 0; k < 4; k++) q[k] = nq[k];
+  }
+  if (!first_done) {
+    st_rec_xyzz(r0, cur, 1, acc);
+    st_rec_xyzz(r1, cur, 0, xyzz_inf());
+  } else {
+    st_rec_xyzz(r1, cur, 1, acc);
+  }
+}
+
+// Level of the record reduction: 2*MSM_NT records per workgroup.
 __global__ void __launch_bounds__(MSM_NT)
-record_reduce_kernel(const uint32_t* __restrict__ in_keys, const uint32_t* __restrict__ in_flags,
-                     const uint32_t* __restrict__ in_pts, uint32_t nrec, uint32_t* __restrict__ buckets,
-                     uint32_t* out_keys, uint32_t* out_flags, uint32_t* out_pts) {
+record_reduce_kernel(const uint32_t* __restrict__ in_rec, uint32_t nrec, uint32_t* __restrict__ buckets,
+                     uint32_t* out_rec) {
   extern __shared__ uint32_t sm[];
   RecLds r = rec_lds(sm);
   const uint32_t rb = blockIdx.x * MSM_SLOTS;
@@ -373,11 +435,13 @@ record_reduce_kernel(const uint32_t* __restrict__ in_keys, const uint32_t* __res
     const uint32_t i = threadIdx.x + q * MSM_NT;
     const uint32_t g = rb + i;
     if (g < nrec) {
-      r.keys[i] = in_keys[g];
-      r.flags[i] = in_flags[g];
-      const uint4* src = reinterpret_cast<const uint4*>(in_pts + (size_t)g * XYZZ_WORDS);
+      const uint32_t* src = in_rec + (size_t)g * REC_WORDS;
+      const uint4 kf = reinterpret_cast<const uint4*>(src)[0];
+      r.keys[i] = kf.x;
+      r.flags[i] = kf.y;
+      const uint4* s4 = reinterpret_cast<const uint4*>(src + 4);
       uint4* dst = reinterpret_cast<uint4*>(r.pts + i * XYZZ_WORDS);
-      for (int w = 0; w < 9; w++) dst[w] = src[w];
+      for (int w = 0; w < 9; w++) dst[w] = s4[w];
     } else {
       put_slot(r, i, KEY_SENTINEL, 0, xyzz_inf());
     }
@@ -385,9 +449,10 @@ record_reduce_kernel(const uint32_t* __restrict__ in_keys, const uint32_t* __res
   __syncthreads();
   const uint32_t re = min(rb + MSM_SLOTS, nrec);
   const bool nonempty = rb < nrec;
-  const bool left_open = nonempty && rb > 0 && in_keys[rb - 1] == in_keys[rb];
-  const bool right_open = nonempty && re < nrec && in_keys[re] == in_keys[re - 1];
-  combine_and_emit(r, left_open, right_open, buckets, out_keys, out_flags, out_pts);
+  const bool left_open = nonempty && rb > 0 && in_rec[(size_t)(rb - 1) * REC_WORDS] == in_rec[(size_t)rb * REC_WORDS];
+  const bool right_open =
+      nonempty && re < nrec && in_rec[(size_t)re * REC_WORDS] == in_rec[(size_t)(re - 1) * REC_WORDS];
+  combine_and_emit(r, left_open, right_open, buckets, out_rec);
 }
 
 // ---------------------------------------------------------------- bucket reduction
@@ -396,11 +461,11 @@ record_reduce_kernel(const uint32_t* __restrict__ in_keys, const uint32_t* __res
 // chunk total is added with a small double-and-add.
 __global__ void __launch_bounds__(MSM_NT)
 bucket_chunks_kernel(const uint32_t* __restrict__ buckets, const uint32_t* __restrict__ counts, MsmPlan p,
-                     uint32_t nwin, uint32_t* __restrict__ vbuf) {
+                     uint32_t* __restrict__ vbuf) {
   const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= nwin * p.J) return;
-  const uint32_t w = id / p.J, j = id % p.J;
-  const uint32_t base = (p.shared ? 0 : w * p.K) + j * p.LB;
+  if (id >= p.nseg * p.J) return;
+  const uint32_t sg = id / p.J, j = id % p.J;
+  const uint32_t base = sg * p.K + j * p.LB;
   xyzz acc = xyzz_inf(), sum = xyzz_inf();
   for (int m = (int)p.LB - 1; m >= 0; --m) {
     if (counts[base + m]) acc = add(acc, ld_xyzz(buckets + (size_t)(base + m) * XYZZ_WORDS));
@@ -441,6 +506,15 @@ __global__ void combine_kernel(const uint32_t* __restrict__ wsum, uint32_t nwin,
   uint32_t o[16];
   to_affine_words(q, o);
   stw(out16, o, 4);
+}
+
+// One canonical affine output per segment (shared layout).
+__global__ void affine_out_kernel(const uint32_t* __restrict__ wsum, uint32_t nseg, uint32_t* __restrict__ out) {
+  const uint32_t sg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sg >= nseg) return;
+  uint32_t o[16];
+  to_affine_words(ld_xyzz(wsum + (size_t)sg * XYZZ_WORDS), o);
+  stw(out + (size_t)sg * 16, o, 4);
 }
 
 __global__ void zero16_kernel(uint32_t* out16) {
@@ -635,17 +709,9 @@ uint32_t msm_default_c(uint32_t n) {
   return (uint32_t)c;
 }
 
-MsmPlan msm_plan(uint32_t n, uint32_t c, bool shared, uint32_t tab_stride) {
-  MsmPlan p{};
-  p.n = n;
-  p.c = c;
-  p.W = (254 + c - 1) / c;
-  p.K = 1u << (c - 1);
-  p.shared = shared ? 1 : 0;
-  p.nbins = shared ? p.K : p.W * p.K;
-  p.tab_stride = tab_stride;
-  p.chunk = 32768;
-  const uint64_t entries = (uint64_t)n * p.W;
+static void plan_common(MsmPlan& p) {
+  p.nbins = p.nseg * p.K;
+  const uint64_t entries = (uint64_t)p.n * p.W;
   // enough threads to fill the chip, at most 64 entries each
   uint64_t L = entries / (256ull * 1024);
   if (L < 4) L = 4;
@@ -655,52 +721,103 @@ MsmPlan msm_plan(uint32_t n, uint32_t c, bool shared, uint32_t tab_stride) {
   if (p.acc_blocks == 0) p.acc_blocks = 1;
   p.LB = p.K >= 8 ? 8 : p.K;
   p.J = p.K / p.LB;
+}
+
+MsmPlan msm_plan_generic(uint32_t n, uint32_t c) {
+  MsmPlan p{};
+  p.n = n;
+  p.c = c;
+  p.W = (254 + c - 1) / c;
+  p.K = 1u << (c - 1);
+  p.shared = 0;
+  p.nseg = p.W;
+  p.tab_stride = 0;
+  p.chunk = 32768;
+  p.nitems = cdiv(n, p.chunk);
+  plan_common(p);
   return p;
 }
 
-size_t scan_tmp_words(uint32_t n) { return cdiv(n, SCAN_BLOCK) + 1; }
+MsmPlan msm_plan_shared(const uint64_t* off, uint32_t nmsm, uint32_t c, uint32_t tab_stride) {
+  MsmPlan p{};
+  p.n = (uint32_t)off[nmsm];
+  p.c = c;
+  p.W = (254 + c - 1) / c;
+  p.K = 1u << (c - 1);
+  p.shared = 1;
+  p.nseg = nmsm;
+  p.tab_stride = tab_stride;
+  p.chunk = 32768;
+  p.nitems = 0;
+  for (uint32_t b = 0; b < nmsm; b++) p.nitems += cdiv(off[b + 1] - off[b], p.chunk);
+  plan_common(p);
+  return p;
+}
+
+// Scan: block sums, recursive scan of the sums, then per-block rescans.
+size_t scan_tmp_words(uint32_t n) {
+  size_t words = 0;
+  while (n > SCAN_BLOCK) {
+    const uint32_t nb = cdiv(n, SCAN_BLOCK);
+    words += 2 * ((size_t)nb + 1) + 64;
+    n = nb;
+  }
+  return words + 64;
+}
 
 hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp, hipStream_t s) {
   const uint32_t nb = cdiv(n, SCAN_BLOCK);
-  if (nb > SCAN_BLOCK) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(MSM_NT), 0, s, in, n, tmp);
-  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(MSM_NT), 0, s, tmp, nb);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(MSM_NT), 0, s, in, n, tmp, nb, out);
+  if (nb <= 1) {
+    // single block: sums = {0}, total written by the apply kernel from sums[1]
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3(1), dim3(MSM_NT), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(MSM_NT), 0, s, tmp, 1u);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3(1), dim3(MSM_NT), 0, s, in, n, tmp, 1u, out);
+    return hipGetLastError();
+  }
+  uint32_t* sums = tmp;                 // nb + 1
+  uint32_t* scanned = tmp + nb + 1;     // nb + 1
+  uint32_t* rest = scanned + nb + 1 + 32;
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(MSM_NT), 0, s, in, n, sums);
+  hipError_t e;
+  if (nb <= SCAN_BLOCK) {
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(MSM_NT), 0, s, sums, nb);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(MSM_NT), 0, s, in, n, sums, nb, out);
+  } else {
+    if ((e = scan_exclusive(sums, scanned, nb, rest, s))) return e;
+    hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(MSM_NT), 0, s, in, n, scanned, nb, out);
+  }
   return hipGetLastError();
 }
 
 namespace {
 struct Layout {
-  size_t off[16];
+  size_t off[14];
   size_t total;
 };
 
 Layout layout(const MsmPlan& p) {
   Layout L{};
   size_t o = 0;
-  auto take = [&](int idx, size_t words) {
+  auto take = [&](int idx, size_t bytes) {
     L.off[idx] = o;
-    o += (words * 4 + 255) & ~size_t(255);
+    o += (bytes + 255) & ~size_t(255);
   };
   const size_t ent = (size_t)p.n * p.W;
-  const size_t nrec0 = 2 * (size_t)p.acc_blocks;
-  const size_t nwin = p.shared ? 1 : p.W;
-  take(0, ent);                              // digits
-  take(1, p.nbins);                          // counts
-  take(2, p.nbins + 1);                      // offsets
-  take(3, p.nbins);                          // cursor
-  take(4, scan_tmp_words(p.nbins));          // scan tmp
-  take(5, ent);                              // keys
-  take(6, ent);                              // vals
-  take(7, (size_t)p.nbins * XYZZ_WORDS);     // buckets
-  take(8, nrec0);                            // rec keys A
-  take(9, nrec0);                            // rec flags A
-  take(10, nrec0 * XYZZ_WORDS);              // rec pts A
-  take(11, nrec0);                           // rec keys B
-  take(12, nrec0);                           // rec flags B
-  take(13, nrec0 * XYZZ_WORDS);              // rec pts B
-  take(14, nwin * p.J * XYZZ_WORDS);         // vbuf
-  take(15, nwin * XYZZ_WORDS);               // wsum
+  const size_t nrec0 = 2 * (size_t)p.acc_blocks * MSM_NT;
+  const size_t nrec1 = 2 * (size_t)p.acc_blocks;
+  take(0, ent * 4);                               // digits
+  take(1, (size_t)p.nbins * 4);                   // counts
+  take(2, ((size_t)p.nbins + 1) * 4);             // offsets
+  take(3, (size_t)p.nbins * 4);                   // cursor
+  take(4, scan_tmp_words(p.nbins) * 4);           // scan tmp
+  take(5, ent * 8);                               // entries
+  take(6, (size_t)p.nbins * XYZZ_WORDS * 4);      // buckets
+  take(7, nrec0 * REC_WORDS * 4);                 // records, thread level (and odd levels)
+  take(8, nrec1 * REC_WORDS * 4);                 // records, even levels
+  take(9, (size_t)p.nseg * p.J * XYZZ_WORDS * 4); // vbuf
+  take(10, (size_t)p.nseg * XYZZ_WORDS * 4);      // wsum
+  take(11, ((size_t)p.nseg + 2) * 4);             // seg_off
+  take(12, ((size_t)p.nitems + 1) * 16);          // items
   L.total = o;
   return L;
 }
@@ -717,17 +834,14 @@ MsmBuffers msm_carve(const MsmPlan& p, void* base) {
   m.offsets = reinterpret_cast<uint32_t*>(b + L.off[2]);
   m.cursor = reinterpret_cast<uint32_t*>(b + L.off[3]);
   m.scan_tmp = reinterpret_cast<uint32_t*>(b + L.off[4]);
-  m.keys = reinterpret_cast<uint32_t*>(b + L.off[5]);
-  m.vals = reinterpret_cast<uint32_t*>(b + L.off[6]);
-  m.buckets = reinterpret_cast<uint32_t*>(b + L.off[7]);
-  m.rec_keys[0] = reinterpret_cast<uint32_t*>(b + L.off[8]);
-  m.rec_flags[0] = reinterpret_cast<uint32_t*>(b + L.off[9]);
-  m.rec_pts[0] = reinterpret_cast<uint32_t*>(b + L.off[10]);
-  m.rec_keys[1] = reinterpret_cast<uint32_t*>(b + L.off[11]);
-  m.rec_flags[1] = reinterpret_cast<uint32_t*>(b + L.off[12]);
-  m.rec_pts[1] = reinterpret_cast<uint32_t*>(b + L.off[13]);
-  m.vbuf = reinterpret_cast<uint32_t*>(b + L.off[14]);
-  m.wsum = reinterpret_cast<uint32_t*>(b + L.off[15]);
+  m.entries = reinterpret_cast<uint2*>(b + L.off[5]);
+  m.buckets = reinterpret_cast<uint32_t*>(b + L.off[6]);
+  m.rec[0] = reinterpret_cast<uint32_t*>(b + L.off[7]);
+  m.rec[1] = reinterpret_cast<uint32_t*>(b + L.off[8]);
+  m.vbuf = reinterpret_cast<uint32_t*>(b + L.off[9]);
+  m.wsum = reinterpret_cast<uint32_t*>(b + L.off[10]);
+  m.seg_off = reinterpret_cast<uint32_t*>(b + L.off[11]);
+  m.items = reinterpret_cast<uint4*>(b + L.off[12]);
   return m;
 }
 
@@ -742,9 +856,6 @@ static hipError_t set_lds_limits() {
     return e;
   if ((e = hipFuncSetAttribute((const void*)scatter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, hist_lds)))
     return e;
-  if ((e = hipFuncSetAttribute((const void*)accumulate_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)rec_lds_bytes())))
-    return e;
   if ((e = hipFuncSetAttribute((const void*)record_reduce_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)rec_lds_bytes())))
     return e;
@@ -752,52 +863,86 @@ static hipError_t set_lds_limits() {
   return hipSuccess;
 }
 
-hipError_t msm_run(const MsmPlan& p, const uint32_t* mont_points, const uint32_t* scalars, const MsmBuffers& b,
-                   uint32_t* out16, hipStream_t s) {
+// Segment offsets and histogram items, from host offsets via kernel arguments.
+static hipError_t launch_items(const MsmPlan& p, const uint64_t* off, const MsmBuffers& b, hipStream_t s) {
+  uint32_t item = 0;
+  for (uint32_t first = 0; first < p.nseg || first == 0; first += SEG_ARGS) {
+    SegArgs a{};
+    a.first = first;
+    a.count = std::min<uint32_t>(SEG_ARGS, p.nseg - first);
+    if (!p.shared) {  // generic: one segment covering every scalar
+      a.first = 0;
+      a.count = 1;
+      a.off[0] = 0;
+      a.off[1] = p.n;
+      a.item0[0] = 0;
+    } else {
+      for (uint32_t t = 0; t < a.count; t++) {
+        a.off[t] = (uint32_t)off[first + t];
+        a.item0[t] = item;
+        item += cdiv(off[first + t + 1] - off[first + t], p.chunk);
+      }
+      a.off[a.count] = (uint32_t)off[first + a.count];
+    }
+    hipLaunchKernelGGL(make_items_kernel, dim3(1), dim3(SEG_ARGS), 0, s, a, p.chunk, b.seg_off, b.items);
+    if (!p.shared) break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points, const uint32_t* scalars,
+                   const MsmBuffers& b, uint32_t* out, hipStream_t s) {
   hipError_t e;
   if ((e = set_lds_limits())) return e;
+  const uint32_t nout = p.shared ? p.nseg : 1;
   if (p.n == 0) {
-    hipLaunchKernelGGL(zero16_kernel, dim3(1), dim3(64), 0, s, out16);
+    for (uint32_t i = 0; i < nout; i++) hipLaunchKernelGGL(zero16_kernel, dim3(1), dim3(64), 0, s, out + 16 * i);
     return hipGetLastError();
   }
   const ProfToken t_sort = prof_begin("msm.sort", s);
+  if ((e = launch_items(p, off, b, s))) return e;
   hipLaunchKernelGGL(decompose_kernel, dim3(cdiv(p.n, 256)), dim3(256), 0, s, scalars, p.n, p.c, p.W, b.digits);
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(min(cdiv(p.nbins, 256), 1024u)), dim3(256), 0, s, b.counts, p.nbins);
-  const dim3 hgrid(cdiv(p.n, p.chunk), p.W);
-  const size_t hlds = (size_t)p.K * 4;
-  hipLaunchKernelGGL(hist_kernel, hgrid, dim3(MSM_NT), hlds, s, b.digits, p, b.counts);
-  if ((e = scan_exclusive(b.counts, b.offsets, p.nbins, b.scan_tmp, s))) return e;
-  hipLaunchKernelGGL(copy_u32_kernel, dim3(min(cdiv(p.nbins, 256), 1024u)), dim3(256), 0, s, b.offsets, b.cursor,
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(std::min(cdiv(p.nbins, 256), 1024u)), dim3(256), 0, s, b.counts,
                      p.nbins);
-  hipLaunchKernelGGL(scatter_kernel, hgrid, dim3(MSM_NT), hlds, s, b.digits, p, b.cursor, b.keys, b.vals);
+  const size_t hlds = (size_t)p.K * 4;
+  if (p.nitems) {
+    const dim3 hgrid(p.nitems, p.W);
+    hipLaunchKernelGGL(hist_kernel, hgrid, dim3(MSM_NT), hlds, s, b.digits, p, b.items, b.counts);
+  }
+  if ((e = scan_exclusive(b.counts, b.offsets, p.nbins, b.scan_tmp, s))) return e;
+  hipLaunchKernelGGL(copy_u32_kernel, dim3(std::min(cdiv(p.nbins, 256), 1024u)), dim3(256), 0, s, b.offsets,
+                     b.cursor, p.nbins);
+  if (p.nitems) {
+    const dim3 hgrid(p.nitems, p.W);
+    hipLaunchKernelGGL(scatter_kernel, hgrid, dim3(MSM_NT), hlds, s, b.digits, p, b.items, b.seg_off, b.cursor,
+                       b.entries);
+  }
   prof_end(t_sort, s);
-  // accumulate + record levels
-  uint32_t grid = p.acc_blocks;
-  int cur = 0;
-  const bool last0 = grid == 1;
   const ProfToken t_acc = prof_begin("msm.accumulate", s);
-  hipLaunchKernelGGL(accumulate_kernel, dim3(grid), dim3(MSM_NT), rec_lds_bytes(), s, b.keys, b.vals,
-                     b.offsets + p.nbins, mont_points, p.L, b.buckets, last0 ? nullptr : b.rec_keys[0],
-                     last0 ? nullptr : b.rec_flags[0], last0 ? nullptr : b.rec_pts[0]);
+  hipLaunchKernelGGL(accumulate_kernel, dim3(p.acc_blocks), dim3(MSM_NT), 0, s, b.entries, b.offsets + p.nbins,
+                     points, p.L, b.buckets, b.rec[0]);
   prof_end(t_acc, s);
   const ProfToken t_red = prof_begin("msm.reduce", s);
-  while (grid > 1) {
-    const uint32_t nrec = 2 * grid;
+  uint32_t nrec = 2 * p.acc_blocks * MSM_NT;
+  int cur = 0;
+  while (true) {
     const uint32_t g2 = cdiv(nrec, MSM_SLOTS);
     const bool last = g2 == 1;
-    const int nxt = cur ^ 1;
-    hipLaunchKernelGGL(record_reduce_kernel, dim3(g2), dim3(MSM_NT), rec_lds_bytes(), s, b.rec_keys[cur],
-                       b.rec_flags[cur], b.rec_pts[cur], nrec, b.buckets, last ? nullptr : b.rec_keys[nxt],
-                       last ? nullptr : b.rec_flags[nxt], last ? nullptr : b.rec_pts[nxt]);
-    grid = g2;
-    cur = nxt;
+    hipLaunchKernelGGL(record_reduce_kernel, dim3(g2), dim3(MSM_NT), rec_lds_bytes(), s, b.rec[cur], nrec,
+                       b.buckets, last ? nullptr : b.rec[cur ^ 1]);
+    if (last) break;
+    nrec = 2 * g2;
+    cur ^= 1;
   }
-  const uint32_t nwin = p.shared ? 1 : p.W;
-  hipLaunchKernelGGL(bucket_chunks_kernel, dim3(cdiv((uint64_t)nwin * p.J, 64)), dim3(64), 0, s, b.buckets,
-                     b.counts, p, nwin, b.vbuf);
-  hipLaunchKernelGGL(window_sum_kernel, dim3(nwin), dim3(MSM_NT), (size_t)MSM_NT * XYZZ_WORDS * 4, s, b.vbuf, p.J,
-                     b.wsum);
-  hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, s, b.wsum, nwin, p.c, out16);
+  hipLaunchKernelGGL(bucket_chunks_kernel, dim3(cdiv((uint64_t)p.nseg * p.J, 64)), dim3(64), 0, s, b.buckets,
+                     b.counts, p, b.vbuf);
+  hipLaunchKernelGGL(window_sum_kernel, dim3(p.nseg), dim3(MSM_NT), (size_t)MSM_NT * XYZZ_WORDS * 4, s, b.vbuf,
+                     p.J, b.wsum);
+  if (p.shared) {
+    hipLaunchKernelGGL(affine_out_kernel, dim3(cdiv(p.nseg, 64)), dim3(64), 0, s, b.wsum, p.nseg, out);
+  } else {
+    hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, s, b.wsum, p.W, p.c, out);
+  }
   prof_end(t_red, s);
   return hipGetLastError();
 }

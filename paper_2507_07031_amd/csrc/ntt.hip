@@ -31,7 +31,7 @@ namespace {
 
 constexpr uint32_t TILE_LOG = 12;
 constexpr uint32_t TILE = 1u << TILE_LOG;    // elements per workgroup
-constexpr uint32_t NTT_THREADS = 256;
+constexpr uint32_t NTT_THREADS = 512;
 
 __device__ __forceinline__ void ld8(const uint32_t* p, uint32_t w[8]) {
   const uint4 a = reinterpret_cast<const uint4*>(p)[0];

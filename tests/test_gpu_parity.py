@@ -279,6 +279,37 @@ def test_msm_batch_uneven(zk, tau, srs_big):
         assert out[b] == omsm.srs_msm_closed_form(tau[1], sv[off[b]:off[b + 1]]), b
 
 
+def test_msm_batch_many_segments(zk, tau, srs_big):
+    # more MSMs than one kernel-argument block of segment offsets, with empty
+    # and one-point MSMs among them
+    _, h = srs_big
+    rng = np.random.default_rng(5)
+    sizes = [int(v) for v in rng.integers(0, 400, 300)]
+    sizes[3] = 0
+    sizes[129] = 0
+    sizes[130] = 1
+    sizes[-1] = 40000
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    s = gen.uniform_fr(901, int(off[-1]))
+    sv = fr_from_host(s)
+    log("msm batch", len(sizes), "segments")
+    out = points_from_host(_host(zk, zk.msm_batch(h, _dev(zk, s), off)))
+    for b in range(len(sizes)):
+        assert out[b] == omsm.srs_msm_closed_form(tau[1], sv[off[b]:off[b + 1]]), b
+
+
+def test_msm_batch_quantized_segments(zk, tau, srs_big):
+    _, h = srs_big
+    sizes = [1 << 16, 1000, 1 << 18]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    x = gen.quantized_values(77, int(off[-1]))
+    q = gen.quantized_fr(77, int(off[-1]))
+    out = points_from_host(_host(zk, zk.msm_batch(h, _dev(zk, q), off)))
+    xv = [int(v) % R for v in x]
+    for b in range(len(sizes)):
+        assert out[b] == omsm.srs_msm_closed_form(tau[1], xv[off[b]:off[b + 1]]), b
+
+
 # ------------------------------------------------------------------ fold
 
 @pytest.mark.parametrize("m,k", [(1, 1), (2, 3), (3, 1), (5, 2), (64, 1)])
