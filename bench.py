@@ -13,6 +13,8 @@ Printed as one JSON line, with
   fold of 64 of the resulting commitments,
 * `roofline` of the dominant kernel (bucket accumulation) from HIP events
   recorded by the library on its launch stream over the timed region,
+* a Poisson stream of commit jobs (2^10..2^22 points) through the serving
+  loop: p50 / p99 latency and jobs/s, continuous admission vs serial,
 * `cpu_baseline`: the CPU oracle on a bounded sample of the same job.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -116,6 +118,32 @@ def cpu_baseline(tau_int, log_n=12):
 
 # ----------------------------------------------------------------- GPU
 
+def serving_runs(zk, srs, count):
+    """Poisson stream (mean 200 jobs/s) of commit jobs, sizes log-uniform
+    2^10..2^22, through the continuous-admission loop: 4 stream slots at a
+    generous and at a tight HBM budget, and one slot (plain per-call serial
+    execution of the same stream)."""
+    from paper_2507_07031_amd.serve import GpuExecutor, Job, serve, summarize
+    seed = gen.CONFIG_SEEDS["serving"]
+    sizes = gen.log_uniform_sizes(seed, count, 10, 22)
+    arrivals = gen.poisson_arrivals(seed, count, 200.0)
+    pool_n = 1 << 23
+    pool = zk.to_device(gen.uniform_fr(seed, pool_n, tag=1))
+    rng = gen.rng_for(seed, 2)
+    offs = rng.integers(0, pool_n - (1 << 22), size=count)
+    out = {"offered_jobs_per_s": 200.0, "jobs": count, "size_log2_range": [10, 22]}
+    for name, slots, budget in (("continuous_4slots_64GiB", 4, 64 << 30),
+                                ("continuous_4slots_4GiB", 4, 4 << 30),
+                                ("serial_1slot", 1, 64 << 30)):
+        jobs = [Job(i, int(n), float(a), int(o)) for i, (n, a, o) in enumerate(zip(sizes, arrivals, offs))]
+        ex = GpuExecutor(zk, srs, pool, slots)
+        fin, rej, wall = serve(jobs, ex, budget, slots)
+        rec = summarize(fin, wall)
+        rec["rejected"] = len(rej)
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rec.items()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +151,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -216,11 +245,18 @@ def main():
         t_intt = timed(lambda: zk.intt(evals, out=coeffs))
         t_ntt = timed(lambda: zk.ntt(coeffs, out=evals))
         zk.intt(evals, out=coeffs)
+        torch.cuda.synchronize()
+        zk.profile_enable(True)
         t_msm = timed(lambda: zk.msm_srs(srs, coeffs, out=com))
+        zk.profile_enable(False)
+        phases = {}
+        for reg in ("msm.sort", "msm.accumulate", "msm.reduce"):
+            ms_tot, cnt = zk.profile_read(reg)
+            phases[reg] = round(ms_tot / max(cnt, 1), 4)
         t_coset = timed(lambda: zk.coset_ntt(coeffs, 2, out=coset))
         extras["ops_2^20"] = {
             "intt_ms": round(t_intt, 4), "ntt_ms": round(t_ntt, 4), "msm_ms": round(t_msm, 4),
-            "coset_4x_ms": round(t_coset, 4),
+            "coset_4x_ms": round(t_coset, 4), "msm_phases_ms_standalone": phases,
             "msm_points_per_s": n / (t_msm / 1e3), "ntt_elems_per_s": n / (t_ntt / 1e3),
             "intt_elems_per_s": n / (t_intt / 1e3), "coset_out_elems_per_s": 4 * n / (t_coset / 1e3),
             "ntt_hbm_frac_2pass": round(2 * 2 * 32 * n / (t_ntt / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
@@ -259,6 +295,10 @@ def main():
         fout = torch.empty((1, 16), dtype=torch.int32, device=dev)
         t_fold = timed(lambda: zk.fold(inst, gam, out=fout), reps=5)
         extras["fold_64"] = {"latency_ms": round(t_fold, 4)}
+        del sc, outs
+
+        log("serving")
+        extras["serving"] = serving_runs(zk, srs, args.serve_jobs)
 
     cpu = None
     if not args.no_cpu_baseline:

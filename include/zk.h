@@ -30,8 +30,10 @@
  *    the enqueued work completes.
  *  - stream: a hipStream_t (NULL: the null stream).  Calls enqueue work and
  *    return; results are ready when the stream reaches that point.
- *  - Scratch memory comes from the device's stream-ordered pool
- *    (hipMallocAsync / hipFreeAsync on the same stream).
+ *  - Scratch memory comes from a library cache of device blocks: a block
+ *    freed by a call is reused by later calls (on another stream only after
+ *    that stream waits on the block's last use); hipMalloc runs only when no
+ *    cached block fits.  zk_release_cached_memory() returns the cache.
  *  - Return: ZK_OK, or a negative code with a message in zk_last_error().
  *    Argument errors are detected before anything is enqueued.  A failed
  *    launch or allocation returns ZK_EDEVICE / ZK_ENOMEM; nothing aborts.
@@ -98,9 +100,10 @@ zk_status zk_msm(const zk_g1* bases, const zk_fr* scalars, uint64_t n, zk_g1* ou
 zk_status zk_srs_setup(const zk_fr* tau_host, uint64_t n, zk_g1* out, void* stream);
 
 /* Prepare an SRS (any n affine points, e.g. from zk_srs_setup or a
- * ceremony) for commitments.  Allocates about 16 * 64 * n bytes of device
- * memory owned by the handle; the work is enqueued on `stream`.  The handle
- * is bound to the current device. */
+ * ceremony) for commitments.  Allocates 16 * 64 * n bytes (the points times
+ * 2^(16 w), w < 16) plus 32 * 64 * min(n, 2^15) bytes (times 2^(8 w), for
+ * small commitments) of device memory owned by the handle; the work is
+ * enqueued on `stream`.  The handle is bound to the current device. */
 zk_status zk_srs_create(const zk_g1* points, uint64_t n, zk_srs** srs, void* stream);
 
 /* Release a prepared SRS (synchronises the device first). */
@@ -112,6 +115,14 @@ uint64_t zk_srs_size(const zk_srs* srs);
 /* KZG commitment to coefficients: *out = sum_{i<n} scalars[i] [tau^i]_1 over
  * the first n points of the prepared SRS (n <= zk_srs_size(srs)). */
 zk_status zk_msm_srs(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream);
+
+/* Device scratch (bytes) that zk_msm_srs takes from the stream-ordered pool
+ * for an n-point commitment (srs NULL: a 16-bit-window SRS of n points), and
+ * that zk_ntt / zk_intt / zk_coset_ntt take for a 2^log_n-point transform.
+ * Host-only queries, for admission control by memory budget; 0 if the size
+ * is out of range. */
+uint64_t zk_msm_srs_workspace_bytes(const zk_srs* srs, uint64_t n);
+uint64_t zk_ntt_workspace_bytes(uint32_t log_n);
 
 /* `batch` commitments over prefixes of one prepared SRS:
  *   out[b] = sum_{i < n_b} scalars[offsets_host[b] + i] [tau^i]_1,
@@ -126,6 +137,9 @@ zk_status zk_msm_batch(const zk_srs* srs, const zk_fr* scalars, const uint64_t* 
  * to right: gammas[0..m-2]).  m = 2 is exactly out[j] = gamma*inst[j] +
  * inst[k + j].  out: k points.  m >= 1. */
 zk_status zk_fold(const zk_g1* inst, const zk_fr* gammas, uint32_t m, uint32_t k, zk_g1* out, void* stream);
+
+/* Wait for and free every cached scratch block of the current device. */
+zk_status zk_release_cached_memory(void);
 
 /* Observability: when enabled, the library brackets named kernel regions
  * with HIP events recorded on the stream the kernels run on.  Regions:

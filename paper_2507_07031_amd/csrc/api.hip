@@ -2,6 +2,7 @@
 // stream-ordered scratch, and the launch sequences of each operation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -106,24 +107,96 @@ zk_status ctx_get(DeviceCtx** out) {
 }
 
 // ---------------------------------------------------------------- scratch
-struct Scratch {
+// Caching allocator for per-call scratch.  A freed block keeps its device
+// memory and an event recorded on the stream that last used it; the next
+// request that fits reuses it at once (same stream) or after making its
+// stream wait on that event (another stream) -- no HIP allocation call on the
+// hot path.  hipMalloc runs only when no cached block fits.
+struct Block {
   void* p = nullptr;
-  hipStream_t s = nullptr;
-  ~Scratch() {
-    if (p) (void)hipFreeAsync(p, s);
+  size_t size = 0;
+  hipEvent_t done = nullptr;
+  hipStream_t stream = nullptr;
+  int device = 0;
+};
+
+std::mutex g_cache_mu;
+std::vector<Block> g_free_blocks;
+
+size_t round_up(size_t b) {
+  const size_t g = b <= (size_t(1) << 20) ? 4096 : (size_t(2) << 20);
+  return (b + g - 1) / g * g;
+}
+
+zk_status block_alloc(Block& out, size_t bytes, hipStream_t s) {
+  int dev = 0;
+  ZK_HIP(hipGetDevice(&dev), "hipGetDevice");
+  bytes = round_up(bytes ? bytes : 256);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    int best = -1;
+    for (int i = 0; i < (int)g_free_blocks.size(); i++) {
+      const Block& b = g_free_blocks[i];
+      if (b.device != dev || b.size < bytes || b.size > bytes + bytes / 4) continue;
+      if (best < 0 || b.size < g_free_blocks[best].size) best = i;
+    }
+    if (best >= 0) {
+      out = g_free_blocks[best];
+      g_free_blocks.erase(g_free_blocks.begin() + best);
+    }
   }
+  if (out.p) {
+    if (out.stream != s) ZK_HIP(hipStreamWaitEvent(s, out.done, 0), "hipStreamWaitEvent(scratch)");
+    out.stream = s;
+    return ZK_OK;
+  }
+  hipError_t e = hipMalloc(&out.p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    // drop cached blocks of this device and retry once
+    std::vector<Block> keep, drop;
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      for (Block& b : g_free_blocks) (b.device == dev ? drop : keep).push_back(b);
+      g_free_blocks.swap(keep);
+    }
+    for (Block& b : drop) {
+      (void)hipEventSynchronize(b.done);
+      (void)hipFree(b.p);
+      (void)hipEventDestroy(b.done);
+    }
+    e = hipMalloc(&out.p, bytes);
+    if (e != hipSuccess) {
+      out.p = nullptr;
+      (void)hipGetLastError();
+      return fail(ZK_ENOMEM, "scratch allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  out.size = bytes;
+  out.device = dev;
+  out.stream = s;
+  ZK_HIP(hipEventCreateWithFlags(&out.done, hipEventDisableTiming), "hipEventCreate(scratch)");
+  return ZK_OK;
+}
+
+void block_free(Block& b) {
+  if (!b.p) return;
+  (void)hipEventRecord(b.done, b.stream);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_free_blocks.push_back(b);
+  b.p = nullptr;
+}
+
+struct Scratch {
+  Block blk;
+  void* p = nullptr;
+  ~Scratch() { block_free(blk); }
 };
 
 zk_status scratch_alloc(Scratch& sc, size_t bytes, hipStream_t s) {
-  sc.s = s;
-  if (bytes == 0) bytes = 256;
-  hipError_t e = hipMallocAsync(&sc.p, bytes, s);
-  if (e != hipSuccess) {
-    sc.p = nullptr;
-    (void)hipGetLastError();
-    return fail(ZK_ENOMEM, "scratch allocation of " + std::to_string(bytes) + " bytes failed");
-  }
-  return ZK_OK;
+  zk_status st = block_alloc(sc.blk, bytes, s);
+  sc.p = sc.blk.p;
+  return st;
 }
 
 // ---------------------------------------------------------------- NTT driver
@@ -202,8 +275,9 @@ zk_status run_msm(const MsmPlan& plan, const uint64_t* offsets, const uint32_t* 
   return ZK_OK;
 }
 
-constexpr uint32_t SRS_C = 16;
-constexpr uint32_t SRS_SHARED_MIN = 1u << 14;  // below this, per-window buckets over the plain points
+constexpr uint32_t SRS_C = 16;                 // window bits of the main table
+constexpr uint32_t SRS_C_SMALL = 8;            // window bits of the small-MSM table
+constexpr uint32_t SRS_SMALL_MAX = 1u << 15;   // MSMs below this size use the small table
 
 }  // namespace
 
@@ -212,12 +286,33 @@ struct zk_srs {
   uint64_t n;
   uint32_t c;
   uint32_t W;
-  uint32_t* tab;  // W * n Montgomery affine points; window 0 is the points themselves
+  uint32_t* tab;        // W * n Montgomery affine points, row w = 2^(c w) P_i; row 0 = the points
+  uint64_t n_small;     // min(n, SRS_SMALL_MAX)
+  uint32_t c_small;
+  uint32_t W_small;
+  uint32_t* tab_small;  // W_small * n_small points for small MSMs
 };
 
 extern "C" {
 
 const char* zk_last_error(void) { return g_err.c_str(); }
+
+zk_status zk_release_cached_memory(void) {
+  int dev = 0;
+  ZK_HIP(hipGetDevice(&dev), "hipGetDevice");
+  std::vector<Block> keep, drop;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (Block& b : g_free_blocks) (b.device == dev ? drop : keep).push_back(b);
+    g_free_blocks.swap(keep);
+  }
+  for (Block& b : drop) {
+    ZK_HIP(hipEventSynchronize(b.done), "hipEventSynchronize");
+    ZK_HIP(hipFree(b.p), "hipFree");
+    ZK_HIP(hipEventDestroy(b.done), "hipEventDestroy");
+  }
+  return ZK_OK;
+}
 
 zk_status zk_profile_enable(int on) {
   prof_set_enabled(on != 0);
@@ -331,15 +426,21 @@ zk_status zk_srs_create(const zk_g1* points, uint64_t n, zk_srs** srs, void* str
   h->c = SRS_C;
   h->W = (254 + SRS_C - 1) / SRS_C;
   h->tab = nullptr;
+  h->n_small = std::min<uint64_t>(n, SRS_SMALL_MAX);
+  h->c_small = SRS_C_SMALL;
+  h->W_small = (254 + SRS_C_SMALL - 1) / SRS_C_SMALL;
+  h->tab_small = nullptr;
   if (n) {
     hipError_t e = hipMalloc(&h->tab, (size_t)h->W * n * 64);
+    if (e == hipSuccess) e = hipMalloc(&h->tab_small, (size_t)h->W_small * h->n_small * 64);
+    if (e == hipSuccess)
+      e = msm_build_table(reinterpret_cast<const uint32_t*>(points), h->tab, n, h->c, h->W, (hipStream_t)stream);
+    if (e == hipSuccess)
+      e = msm_build_table(reinterpret_cast<const uint32_t*>(points), h->tab_small, h->n_small, h->c_small,
+                          h->W_small, (hipStream_t)stream);
     if (e != hipSuccess) {
-      delete h;
-      return hip_fail(e, "zk_srs_create: hipMalloc(table)");
-    }
-    e = msm_build_table(reinterpret_cast<const uint32_t*>(points), h->tab, n, h->c, h->W, (hipStream_t)stream);
-    if (e != hipSuccess) {
-      (void)hipFree(h->tab);
+      if (h->tab) (void)hipFree(h->tab);
+      if (h->tab_small) (void)hipFree(h->tab_small);
       delete h;
       return hip_fail(e, "zk_srs_create: table build");
     }
@@ -356,6 +457,7 @@ zk_status zk_srs_destroy(zk_srs* srs) {
     (void)hipSetDevice(srs->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(srs->tab);
+    if (srs->tab_small) (void)hipFree(srs->tab_small);
     (void)hipSetDevice(prev);
   }
   delete srs;
@@ -364,15 +466,30 @@ zk_status zk_srs_destroy(zk_srs* srs) {
 
 uint64_t zk_srs_size(const zk_srs* srs) { return srs ? srs->n : 0; }
 
+static MsmPlan srs_plan(const zk_srs* srs, uint64_t n, const uint64_t off[2]) {
+  if (n < SRS_SMALL_MAX)
+    return msm_plan_table(off, 1, SRS_C_SMALL, srs ? (uint32_t)srs->n_small : (uint32_t)n, true);
+  return msm_plan_table(off, 1, SRS_C, srs ? (uint32_t)srs->n : (uint32_t)n, true);
+}
+
+// One commitment: the small-window table below SRS_SMALL_MAX points, the
+// main table above; either way every window keeps its own buckets.
 static zk_status msm_srs_one(const zk_srs* srs, const uint32_t* scalars, uint64_t n, uint32_t* out16,
                              hipStream_t s) {
-  if (n < SRS_SHARED_MIN) {
-    const MsmPlan plan = msm_plan_generic((uint32_t)n, msm_default_c((uint32_t)n));
-    return run_msm(plan, nullptr, srs->tab, scalars, out16, s);
-  }
   const uint64_t off[2] = {0, n};
-  const MsmPlan plan = msm_plan_shared(off, 1, srs->c, (uint32_t)srs->n);
-  return run_msm(plan, off, srs->tab, scalars, out16, s);
+  const MsmPlan plan = srs_plan(srs, n, off);
+  return run_msm(plan, off, n < SRS_SMALL_MAX ? srs->tab_small : srs->tab, scalars, out16, s);
+}
+
+uint64_t zk_msm_srs_workspace_bytes(const zk_srs* srs, uint64_t n) {
+  if (n >= (1ull << 31) / 16) return 0;
+  const uint64_t off[2] = {0, n};
+  return msm_workspace_bytes(srs_plan(srs, n, off));
+}
+
+uint64_t zk_ntt_workspace_bytes(uint32_t log_n) {
+  if (log_n > ZK_MAX_LOG_NTT) return 0;
+  return log_n <= ntt_tile_log() ? 0 : ((uint64_t)32 << log_n);
 }
 
 zk_status zk_msm_srs(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream) {
@@ -400,7 +517,7 @@ zk_status zk_msm_batch(const zk_srs* srs, const zk_fr* scalars, const uint64_t* 
   if (offsets_host[batch] >= (1ull << 31) / 16) return fail(ZK_EUNSUPPORTED, "zk_msm_batch: too many scalars");
   // one Pippenger run over every MSM: digits of all scalars sorted into
   // per-MSM buckets, one accumulation, one reduction, one output per MSM
-  const MsmPlan plan = msm_plan_shared(offsets_host, batch, srs->c, (uint32_t)srs->n);
+  const MsmPlan plan = msm_plan_table(offsets_host, batch, srs->c, (uint32_t)srs->n, false);
   return run_msm(plan, offsets_host, srs->tab, reinterpret_cast<const uint32_t*>(scalars),
                  reinterpret_cast<uint32_t*>(out), (hipStream_t)stream);
 }

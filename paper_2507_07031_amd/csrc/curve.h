@@ -166,4 +166,22 @@ ZK_HD bool aff_from_plain_words(const uint32_t w[16], aff& p) {
   return o != 0;
 }
 
+// Keep a value in vector registers.  Work done by one lane on wave-uniform
+// data would otherwise be moved to the scalar unit, whose 32x32 multiplies
+// and carry chains are several times slower for this arithmetic.
+ZK_HD void force_vgpr(f29& a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+  for (int i = 0; i < 9; i++) asm volatile("" : "+v"(a.l[i]));
+#else
+  (void)a;
+#endif
+}
+ZK_HD void force_vgpr(xyzz& a) {
+  force_vgpr(a.X);
+  force_vgpr(a.Y);
+  force_vgpr(a.ZZ);
+  force_vgpr(a.ZZZ);
+}
+
 }  // namespace zk

@@ -12,31 +12,37 @@ constexpr uint32_t XYZZ_WORDS = 36;        // four 9-limb coordinates
 constexpr uint32_t REC_WORDS = 40;         // key, flag, pad, pad, point (36): 160 bytes
 
 // Geometry of one Pippenger run over one or several independent sums.
-//  generic: one MSM over arbitrary (Montgomery) bases; W windows with K
-//           buckets each ("segments" = windows), Horner-combined at the end.
-//  shared:  `nseg` MSMs over one pre-shifted table (tab[w*tab_stride + i] =
-//           2^(c w) P_i); all windows of an MSM feed its K buckets, and every
-//           MSM (segment) has its own output.
+//  generic: one MSM over arbitrary (Montgomery) bases; one set of K buckets
+//           per window, window sums Horner-combined at the end.
+//  table:   `nseg` MSMs over one pre-shifted table (tab[w*tab_stride + i] =
+//           2^(c w) P_i), every MSM with its own output.  Window w's digit of
+//           s_i selects table point (w, i), so window sums are simply added:
+//           either every window keeps its own buckets (Wb = W: short runs,
+//           W-fold parallel reduction) or all windows of an MSM share K
+//           buckets (Wb = 1: fewest buckets, for batches of many MSMs).
 struct MsmPlan {
   uint32_t n;          // scalars in total (all segments)
   uint32_t c;          // window bits; digits are signed in [-2^(c-1), 2^(c-1)]
   uint32_t W;          // windows = ceil(254 / c)
-  uint32_t K;          // buckets per segment = 2^(c-1)
-  uint32_t shared;
-  uint32_t nseg;
-  uint32_t nbins;      // nseg * K
+  uint32_t K;          // buckets per bucket set = 2^(c-1)
+  uint32_t table;      // 1: pre-shifted table layout
+  uint32_t nseg;       // outputs: 1 (generic) or the number of MSMs (table)
+  uint32_t Wb;         // bucket sets per output: W or 1
+  uint32_t groups;     // nseg * Wb bucket sets
+  uint32_t nbins;      // groups * K
   uint32_t tab_stride;
   uint32_t chunk;      // scalars per histogram / scatter item
   uint32_t nitems;     // items per window
   uint32_t L;          // sorted entries per accumulating thread
   uint32_t acc_blocks; // accumulate workgroups
   uint32_t LB;         // buckets per thread in the running-sum reduction
-  uint32_t J;          // LB-chunks per segment = K / LB
+  uint32_t J;          // LB-chunks per bucket set = K / LB
 };
 
 MsmPlan msm_plan_generic(uint32_t n, uint32_t c);
-// offsets: nmsm + 1 scalar offsets (host), offsets[0] = 0.
-MsmPlan msm_plan_shared(const uint64_t* offsets, uint32_t nmsm, uint32_t c, uint32_t tab_stride);
+// offsets: nmsm + 1 scalar offsets (host), offsets[0] = 0.  per_window:
+// every window keeps its own buckets (Wb = W) instead of sharing them.
+MsmPlan msm_plan_table(const uint64_t* offsets, uint32_t nmsm, uint32_t c, uint32_t tab_stride, bool per_window);
 uint32_t msm_default_c(uint32_t n);
 
 // Scratch buffers of one run (device pointers), carved from one allocation.
@@ -49,8 +55,8 @@ struct MsmBuffers {
   uint2* entries;      // W*n (bucket key, point index | sign << 31), sorted by key
   uint32_t* buckets;   // nbins * 36
   uint32_t* rec[2];    // records (REC_WORDS each), ping-pong between levels
-  uint32_t* vbuf;      // nseg * J * 36
-  uint32_t* wsum;      // nseg * 36
+  uint32_t* vbuf;      // groups * J * 36
+  uint32_t* wsum;      // groups * 36
   uint32_t* seg_off;   // nseg + 1 (shared) / 2 (generic)
   uint4* items;        // nitems: (segment, first scalar, end scalar, 0)
 };
@@ -60,9 +66,8 @@ MsmBuffers msm_carve(const MsmPlan& p, void* base);
 
 // Full pipeline.  Scalars: canonical, 8 words each, concatenated per segment.
 // points: Montgomery affine (16 words each) -- the bases (generic) or the
-// pre-shifted table (shared).  offsets: host segment offsets (shared), or
-// nullptr (generic).  out: 16 words per output (1 for generic, nseg for
-// shared), canonical affine.
+// pre-shifted table (table layout).  offsets: host segment offsets (table),
+// or nullptr (generic).  out: 16 words per output (nseg), canonical affine.
 hipError_t msm_run(const MsmPlan& p, const uint64_t* offsets, const uint32_t* points, const uint32_t* scalars,
                    const MsmBuffers& b, uint32_t* out, hipStream_t s);
 

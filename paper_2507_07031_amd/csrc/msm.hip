@@ -10,11 +10,13 @@
 //   Q = sum_w 2^(cw) sum_k k B_(w,k),   B_(w,k) = sum of +-P with |digit| = k.
 //
 // Two layouts of the same computation:
-//  * per-window buckets (any bases): W*K buckets, then a Horner combine of the
-//    window sums with c doublings per window;
-//  * shared buckets (a prepared SRS): the table holds 2^(cw) P_i for every
-//    window, so window w's digit of s_i selects table point (w, i) and all
-//    windows feed the same K buckets -- no per-window combine at all.
+//  * generic (any bases): W*K buckets, then a Horner combine of the window
+//    sums with c doublings per window;
+//  * table (a prepared SRS): the table holds 2^(cw) P_i for every window, so
+//    window w's digit of s_i selects table point (w, i) and the window sums
+//    are simply added -- no doubling chain.  Windows keep their own buckets
+//    (one large MSM: short runs, parallel reduction) or share K buckets (a
+//    batch of many MSMs, one bucket set each).
 //
 // Pipeline (all on the caller's stream):
 //  1 decompose  scalars -> W signed digits each
@@ -28,7 +30,7 @@
 //               over 2 records per workgroup
 //  6 reduce     sum_k k B_k by running sums over chunks of LB buckets, each
 //               chunk offset by a small scalar multiple, then a tree
-//  7 combine    Horner over windows (per-window layout), affine output
+//  7 combine    Horner over windows (generic) or a plain sum (table), affine
 #include <algorithm>
 
 #include "curve.h"
@@ -193,7 +195,7 @@ __global__ void make_items_kernel(SegArgs a, uint32_t chunk, uint32_t* __restric
 // Block (item, window): counts of the item's digits in window w, in LDS over
 // the segment's K buckets, flushed to the global bucket counts.
 __device__ __forceinline__ uint32_t bin_base(const MsmPlan& p, uint32_t seg, uint32_t w) {
-  return (p.shared ? seg : w) * p.K;
+  return (seg * p.Wb + (p.Wb > 1 ? w : 0u)) * p.K;
 }
 
 __global__ void __launch_bounds__(MSM_NT)
@@ -234,7 +236,7 @@ scatter_kernel(const uint32_t* __restrict__ digits, MsmPlan p, const uint4* __re
     if (h[b]) h[b] = atomicAdd(&cursor[off + b], h[b]);
   __syncthreads();
   // point index: the base itself (generic) or table row w of the segment's point
-  const uint32_t pbase = p.shared ? (w * p.tab_stride - seg_off[it.x]) : 0u;
+  const uint32_t pbase = p.table ? (w * p.tab_stride - seg_off[it.x]) : 0u;
   for (uint32_t e = it.y + threadIdx.x; e < it.z; e += MSM_NT) {
     const uint32_t d = dw[e];
     if (!d) continue;
@@ -463,7 +465,7 @@ __global__ void __launch_bounds__(MSM_NT)
 bucket_chunks_kernel(const uint32_t* __restrict__ buckets, const uint32_t* __restrict__ counts, MsmPlan p,
                      uint32_t* __restrict__ vbuf) {
   const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= p.nseg * p.J) return;
+  if (id >= p.groups * p.J) return;
   const uint32_t sg = id / p.J, j = id % p.J;
   const uint32_t base = sg * p.K + j * p.LB;
   xyzz acc = xyzz_inf(), sum = xyzz_inf();
@@ -475,16 +477,17 @@ bucket_chunks_kernel(const uint32_t* __restrict__ buckets, const uint32_t* __res
   st_xyzz(vbuf + (size_t)id * XYZZ_WORDS, sum);
 }
 
-// One workgroup per window: S_w = sum_j V_(w,j).
-__global__ void __launch_bounds__(MSM_NT)
+// One workgroup per bucket set: S = sum_j V_j.
+constexpr uint32_t WSUM_NT = 512;
+__global__ void __launch_bounds__(WSUM_NT)
 window_sum_kernel(const uint32_t* __restrict__ vbuf, uint32_t J, uint32_t* __restrict__ wsum) {
   extern __shared__ uint32_t sm[];
   const uint32_t w = blockIdx.x, tid = threadIdx.x;
   xyzz acc = xyzz_inf();
-  for (uint32_t j = tid; j < J; j += MSM_NT) acc = add(acc, ld_xyzz(vbuf + ((size_t)w * J + j) * XYZZ_WORDS));
+  for (uint32_t j = tid; j < J; j += WSUM_NT) acc = add(acc, ld_xyzz(vbuf + ((size_t)w * J + j) * XYZZ_WORDS));
   st_xyzz(sm + tid * XYZZ_WORDS, acc);
   __syncthreads();
-  for (uint32_t s = MSM_NT / 2; s > 0; s >>= 1) {
+  for (uint32_t s = WSUM_NT / 2; s > 0; s >>= 1) {
     if (tid < s) {
       const xyzz t = add(ld_xyzz(sm + tid * XYZZ_WORDS), ld_xyzz(sm + (tid + s) * XYZZ_WORDS));
       st_xyzz(sm + tid * XYZZ_WORDS, t);
@@ -495,26 +498,49 @@ window_sum_kernel(const uint32_t* __restrict__ vbuf, uint32_t J, uint32_t* __res
 }
 
 // Q = sum_w 2^(c w) S_w by Horner, then canonical affine.
-__global__ void combine_kernel(const uint32_t* __restrict__ wsum, uint32_t nwin, uint32_t c,
+__global__ void __launch_bounds__(64) combine_kernel(const uint32_t* __restrict__ wsum, uint32_t nwin, uint32_t c,
                                uint32_t* __restrict__ out16) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   xyzz q = ld_xyzz(wsum + (size_t)(nwin - 1) * XYZZ_WORDS);
   for (int w = (int)nwin - 2; w >= 0; --w) {
-    for (uint32_t t = 0; t < c; t++) q = dbl(q);
-    q = add(q, ld_xyzz(wsum + (size_t)w * XYZZ_WORDS));
+    for (uint32_t t = 0; t < c; t++) {
+      force_vgpr(q);
+      q = dbl(q);
+    }
+    xyzz s = ld_xyzz(wsum + (size_t)w * XYZZ_WORDS);
+    force_vgpr(s);
+    q = add(q, s);
   }
+  force_vgpr(q);
   uint32_t o[16];
   to_affine_words(q, o);
   stw(out16, o, 4);
 }
 
-// One canonical affine output per segment (shared layout).
-__global__ void affine_out_kernel(const uint32_t* __restrict__ wsum, uint32_t nseg, uint32_t* __restrict__ out) {
-  const uint32_t sg = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sg >= nseg) return;
-  uint32_t o[16];
-  to_affine_words(ld_xyzz(wsum + (size_t)sg * XYZZ_WORDS), o);
-  stw(out + (size_t)sg * 16, o, 4);
+// Table layout: output s = sum of its Wb bucket-set sums, canonical affine.
+// One workgroup of 64 threads per output; tree over the Wb (<= 64) sums.
+__global__ void __launch_bounds__(64)
+seg_sum_kernel(const uint32_t* __restrict__ wsum, uint32_t Wb, uint32_t* __restrict__ out) {
+  __shared__ uint32_t sm[64 * XYZZ_WORDS];
+  const uint32_t sg = blockIdx.x, tid = threadIdx.x;
+  xyzz a = tid < Wb ? ld_xyzz(wsum + ((size_t)sg * Wb + tid) * XYZZ_WORDS) : xyzz_inf();
+  st_xyzz(sm + tid * XYZZ_WORDS, a);
+  __syncthreads();
+  for (uint32_t s = 32; s > 0; s >>= 1) {
+    if (tid < s) {
+      xyzz x = ld_xyzz(sm + tid * XYZZ_WORDS), y = ld_xyzz(sm + (tid + s) * XYZZ_WORDS);
+      force_vgpr(x);
+      st_xyzz(sm + tid * XYZZ_WORDS, add(x, y));
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    xyzz q = ld_xyzz(sm);
+    force_vgpr(q);
+    uint32_t o[16];
+    to_affine_words(q, o);
+    stw(out + (size_t)sg * 16, o, 4);
+  }
 }
 
 __global__ void zero16_kernel(uint32_t* out16) {
@@ -710,7 +736,8 @@ uint32_t msm_default_c(uint32_t n) {
 }
 
 static void plan_common(MsmPlan& p) {
-  p.nbins = p.nseg * p.K;
+  p.groups = p.nseg * p.Wb;
+  p.nbins = p.groups * p.K;
   const uint64_t entries = (uint64_t)p.n * p.W;
   // enough threads to fill the chip, at most 64 entries each
   uint64_t L = entries / (256ull * 1024);
@@ -729,8 +756,9 @@ MsmPlan msm_plan_generic(uint32_t n, uint32_t c) {
   p.c = c;
   p.W = (254 + c - 1) / c;
   p.K = 1u << (c - 1);
-  p.shared = 0;
-  p.nseg = p.W;
+  p.table = 0;
+  p.nseg = 1;
+  p.Wb = p.W;
   p.tab_stride = 0;
   p.chunk = 32768;
   p.nitems = cdiv(n, p.chunk);
@@ -738,14 +766,15 @@ MsmPlan msm_plan_generic(uint32_t n, uint32_t c) {
   return p;
 }
 
-MsmPlan msm_plan_shared(const uint64_t* off, uint32_t nmsm, uint32_t c, uint32_t tab_stride) {
+MsmPlan msm_plan_table(const uint64_t* off, uint32_t nmsm, uint32_t c, uint32_t tab_stride, bool per_window) {
   MsmPlan p{};
   p.n = (uint32_t)off[nmsm];
   p.c = c;
   p.W = (254 + c - 1) / c;
   p.K = 1u << (c - 1);
-  p.shared = 1;
+  p.table = 1;
   p.nseg = nmsm;
+  p.Wb = per_window ? p.W : 1;
   p.tab_stride = tab_stride;
   p.chunk = 32768;
   p.nitems = 0;
@@ -814,8 +843,8 @@ Layout layout(const MsmPlan& p) {
   take(6, (size_t)p.nbins * XYZZ_WORDS * 4);      // buckets
   take(7, nrec0 * REC_WORDS * 4);                 // records, thread level (and odd levels)
   take(8, nrec1 * REC_WORDS * 4);                 // records, even levels
-  take(9, (size_t)p.nseg * p.J * XYZZ_WORDS * 4); // vbuf
-  take(10, (size_t)p.nseg * XYZZ_WORDS * 4);      // wsum
+  take(9, (size_t)p.groups * p.J * XYZZ_WORDS * 4); // vbuf
+  take(10, (size_t)p.groups * XYZZ_WORDS * 4);      // wsum
   take(11, ((size_t)p.nseg + 2) * 4);             // seg_off
   take(12, ((size_t)p.nitems + 1) * 16);          // items
   L.total = o;
@@ -859,6 +888,9 @@ static hipError_t set_lds_limits() {
   if ((e = hipFuncSetAttribute((const void*)record_reduce_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)rec_lds_bytes())))
     return e;
+  if ((e = hipFuncSetAttribute((const void*)window_sum_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(WSUM_NT * XYZZ_WORDS * 4))))
+    return e;
   done = true;
   return hipSuccess;
 }
@@ -870,7 +902,7 @@ static hipError_t launch_items(const MsmPlan& p, const uint64_t* off, const MsmB
     SegArgs a{};
     a.first = first;
     a.count = std::min<uint32_t>(SEG_ARGS, p.nseg - first);
-    if (!p.shared) {  // generic: one segment covering every scalar
+    if (!p.table) {  // generic: one segment covering every scalar
       a.first = 0;
       a.count = 1;
       a.off[0] = 0;
@@ -885,7 +917,7 @@ static hipError_t launch_items(const MsmPlan& p, const uint64_t* off, const MsmB
       a.off[a.count] = (uint32_t)off[first + a.count];
     }
     hipLaunchKernelGGL(make_items_kernel, dim3(1), dim3(SEG_ARGS), 0, s, a, p.chunk, b.seg_off, b.items);
-    if (!p.shared) break;
+    if (!p.table) break;
   }
   return hipGetLastError();
 }
@@ -894,7 +926,7 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points
                    const MsmBuffers& b, uint32_t* out, hipStream_t s) {
   hipError_t e;
   if ((e = set_lds_limits())) return e;
-  const uint32_t nout = p.shared ? p.nseg : 1;
+  const uint32_t nout = p.nseg;
   if (p.n == 0) {
     for (uint32_t i = 0; i < nout; i++) hipLaunchKernelGGL(zero16_kernel, dim3(1), dim3(64), 0, s, out + 16 * i);
     return hipGetLastError();
@@ -934,12 +966,12 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points
     nrec = 2 * g2;
     cur ^= 1;
   }
-  hipLaunchKernelGGL(bucket_chunks_kernel, dim3(cdiv((uint64_t)p.nseg * p.J, 64)), dim3(64), 0, s, b.buckets,
+  hipLaunchKernelGGL(bucket_chunks_kernel, dim3(cdiv((uint64_t)p.groups * p.J, 64)), dim3(64), 0, s, b.buckets,
                      b.counts, p, b.vbuf);
-  hipLaunchKernelGGL(window_sum_kernel, dim3(p.nseg), dim3(MSM_NT), (size_t)MSM_NT * XYZZ_WORDS * 4, s, b.vbuf,
+  hipLaunchKernelGGL(window_sum_kernel, dim3(p.groups), dim3(WSUM_NT), (size_t)WSUM_NT * XYZZ_WORDS * 4, s, b.vbuf,
                      p.J, b.wsum);
-  if (p.shared) {
-    hipLaunchKernelGGL(affine_out_kernel, dim3(cdiv(p.nseg, 64)), dim3(64), 0, s, b.wsum, p.nseg, out);
+  if (p.table) {
+    hipLaunchKernelGGL(seg_sum_kernel, dim3(p.nseg), dim3(64), 0, s, b.wsum, p.Wb, out);
   } else {
     hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, s, b.wsum, p.W, p.c, out);
   }

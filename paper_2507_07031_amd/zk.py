@@ -22,7 +22,7 @@ MAX_LOG_NTT = 24
 
 EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_srs_setup", "zk_srs_create",
            "zk_srs_destroy", "zk_srs_size", "zk_msm_srs", "zk_msm_batch", "zk_fold", "zk_profile_enable",
-           "zk_profile_read")
+           "zk_profile_read", "zk_msm_srs_workspace_bytes", "zk_ntt_workspace_bytes", "zk_release_cached_memory")
 
 
 class ZkError(RuntimeError):
@@ -50,6 +50,9 @@ def _load():
         "zk_msm_batch": ([P, P, P, U32, P, P], I),
         "zk_fold": ([P, P, U32, U32, P, P], I),
         "zk_profile_enable": ([I], I),
+        "zk_release_cached_memory": ([], I),
+        "zk_msm_srs_workspace_bytes": ([P, U64], U64),
+        "zk_ntt_workspace_bytes": ([U32], U64),
         "zk_profile_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U64), I], I),
     }
     for name, (args, res) in sig.items():
@@ -234,6 +237,21 @@ def fold(inst, gammas, out=None):
         gp = _ptr(gammas)
     _check(lib.zk_fold(_ptr(inst), gp, m, k, _ptr(out), _stream(inst)))
     return out
+
+
+def msm_srs_workspace_bytes(srs, n):
+    """Scratch bytes of one n-point commitment (host-only query)."""
+    return int(lib.zk_msm_srs_workspace_bytes(srs.handle if srs is not None else None, int(n)))
+
+
+def ntt_workspace_bytes(log_n):
+    """Scratch bytes of one 2^log_n-point transform (host-only query)."""
+    return int(lib.zk_ntt_workspace_bytes(int(log_n)))
+
+
+def release_cached_memory():
+    """Free the library's cached scratch blocks on the current device."""
+    _check(lib.zk_release_cached_memory())
 
 
 # ---------------------------------------------------------------- observability

@@ -330,3 +330,43 @@ def test_fold_matches_tree(zk, tau, srs_big, m, k):
     if m <= 5:
         inst_pts = [[osrs.srs_point(t, idx[i * k + j]) for j in range(k)] for i in range(m)]
         assert out == ofold.tree_fold(inst_pts, gv)
+
+
+# ------------------------------------------------------------------ serving
+
+def test_serving_mix_equals_alone(zk, tau, srs_big):
+    # jobs admitted while others run overlap on the device; every result must
+    # be bit-identical to the same job run alone
+    from paper_2507_07031_amd.serve import GpuExecutor, Job, serve
+    _, h = srs_big
+    pool = _dev(zk, gen.uniform_fr(gen.CONFIG_SEEDS["serving"], 1 << 21, tag=1))
+    sizes = [1000, 1 << 12, 70000, 1 << 18, 333, 1 << 16, 5000, 1 << 20, 1, 2]
+    rng = np.random.default_rng(3)
+    offs = [int(rng.integers(0, (1 << 21) - (1 << 20))) for _ in sizes]
+
+    def mk():
+        return [Job(i, n, 1e-4 * i, o) for i, (n, o) in enumerate(zip(sizes, offs))]
+
+    log("serving mix")
+    ex = GpuExecutor(zk, h, pool, slots=4, keep_results=True)
+    fin, rej, _ = serve(mk(), ex, 64 << 30, 4)
+    assert not rej and len(fin) == len(sizes)
+    mixed = {j.jid: j.result for j in fin}
+    assert max(j.start for j in fin) < max(j.finish for j in fin)
+    for job in mk():
+        ex1 = GpuExecutor(zk, h, pool, slots=1, keep_results=True)
+        f1, _, _ = serve([job], ex1, 64 << 30, 1)
+        com, coset = f1[0].result
+        assert np.array_equal(com, mixed[job.jid][0]), job.jid
+        assert np.array_equal(coset, mixed[job.jid][1]), job.jid
+    # the smallest padded job against the oracle: commitment straight from the
+    # evaluations (barycentric) and coset samples from the coefficients
+    j = 0
+    N = 1024
+    ev = fr_from_host(_host(zk, pool[offs[j]:offs[j] + sizes[j]])) + [0] * (N - sizes[j])
+    com = points_from_host(mixed[j][0])[0]
+    assert com == g1.gen_mul(ontt.barycentric_eval(ev, tau[1]))
+    coeffs = ontt.ifft(ev)
+    cos = fr_from_host(mixed[j][1])
+    for k in (0, 5, 4 * N - 1):
+        assert cos[k] == ontt.coset_eval_at(coeffs, 2, k, 5)

@@ -1,0 +1,108 @@
+"""Admission logic of the serving loop on the CPU, with a mock executor that
+only models durations and bytes (no device code)."""
+import numpy as np
+
+from paper_2507_07031_amd.serve import Admission, Job, serve, summarize
+from workloads import generators as gen
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def tick(self):
+        self.t += 1e-4
+
+
+class MockExecutor:
+    """Job of N points takes N * 1e-8 s; checks budget and slots as it runs."""
+
+    def __init__(self, clock, budget, slots, per_point=1e-8):
+        self.clock = clock
+        self.budget = budget
+        self.slots = slots
+        self.per_point = per_point
+        self.live = {}
+        self.max_bytes = 0
+        self.max_live = 0
+        self.starts = []
+
+    def footprint(self, job):
+        return job.N * 200
+
+    def start(self, job):
+        self.live[job.jid] = job
+        self.starts.append(job.jid)
+        b = sum(self.footprint(j) for j in self.live.values())
+        self.max_bytes = max(self.max_bytes, b)
+        self.max_live = max(self.max_live, len(self.live))
+        assert b <= self.budget and len(self.live) <= self.slots
+        job.handle = self.clock() + job.N * self.per_point
+
+    def poll(self, job):
+        if self.clock() >= job.handle:
+            del self.live[job.jid]
+            return True
+        return False
+
+
+def _jobs(count, seed=5, lo=10, hi=22, rate=200.0):
+    sizes = gen.log_uniform_sizes(seed, count, lo, hi)
+    arr = gen.poisson_arrivals(seed, count, rate)
+    return [Job(i, n, a) for i, (n, a) in enumerate(zip(sizes, arr))]
+
+
+def test_job_padding():
+    assert [Job(0, n, 0).N for n in (1, 2, 3, 1024, 1025)] == [1, 2, 4, 1024, 2048]
+
+
+def test_budget_and_slots_hold_and_all_finish():
+    clock = FakeClock()
+    budget = 1 << 30
+    ex = MockExecutor(clock, budget, 4)
+    jobs = _jobs(300)
+    fin, rej, wall = serve(jobs, ex, budget, 4, clock=clock, sleep=clock.tick)
+    assert len(fin) + len(rej) == 300
+    assert all(j.footprint <= budget for j in fin)
+    assert all(j.footprint > budget for j in rej)
+    assert ex.max_bytes <= budget and ex.max_live <= 4
+    assert ex.max_live > 1  # jobs do overlap
+    # strict FIFO: starts follow arrival order
+    assert ex.starts == sorted(ex.starts)
+    s = summarize(fin, wall)
+    assert s["jobs"] == len(fin) and s["p99_ms"] >= s["p50_ms"]
+
+
+def test_tight_budget_serialises_large_jobs():
+    clock = FakeClock()
+    budget = (1 << 22) * 200  # exactly one 2^22 job
+    ex = MockExecutor(clock, budget, 8)
+    jobs = [Job(i, 1 << 22, 0.0) for i in range(3)] + [Job(3, 1 << 10, 0.0)]
+    fin, rej, _ = serve(jobs, ex, budget, 8, clock=clock, sleep=clock.tick)
+    assert not rej and len(fin) == 4
+    big = sorted((j for j in fin if j.N == 1 << 22), key=lambda j: j.start)
+    for a, b in zip(big, big[1:]):
+        assert b.start >= a.finish  # never two at once
+    small = [j for j in fin if j.N == 1 << 10][0]
+    assert small.start >= big[-1].start  # FIFO: no overtaking
+
+
+def test_oversize_rejected():
+    clock = FakeClock()
+    ex = MockExecutor(clock, 1000, 2)
+    fin, rej, _ = serve([Job(0, 4, 0.0), Job(1, 1 << 20, 0.0)], ex, 1000, 2, clock=clock, sleep=clock.tick)
+    assert [j.jid for j in rej] == [1] and [j.jid for j in fin] == [0]
+
+
+def test_admission_queue_unit():
+    adm = Admission(100, 2, lambda j: j.n)
+    a, b, c = Job(0, 60, 0), Job(1, 50, 0), Job(2, 10, 0)
+    for j in (a, b, c):
+        assert adm.submit(j)
+    assert adm.admissible() == [a]          # b does not fit beside a; c must wait behind b
+    adm.release(a)
+    assert adm.admissible() == [b, c]
+    assert adm.used == 60 and np.isclose(adm.used, 60)
