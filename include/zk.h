@@ -116,6 +116,14 @@ uint64_t zk_srs_size(const zk_srs* srs);
  * the first n points of the prepared SRS (n <= zk_srs_size(srs)). */
 zk_status zk_msm_srs(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream);
 
+/* zk_msm_srs that also records `accumulate_done_event` (a hipEvent_t, may be
+ * NULL) on `stream` as soon as its bucket-accumulation kernel is enqueued.
+ * What follows on the stream is a latency-bound reduction that leaves most
+ * compute units idle: independent work (e.g. the same polynomial's coset
+ * evaluation) made to wait on this event on another stream overlaps it. */
+zk_status zk_msm_srs_ex(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream,
+                        void* accumulate_done_event);
+
 /* Device scratch (bytes) that zk_msm_srs takes from the stream-ordered pool
  * for an n-point commitment (srs NULL: a 16-bit-window SRS of n points), and
  * that zk_ntt / zk_intt / zk_coset_ntt take for a 2^log_n-point transform.

@@ -266,12 +266,12 @@ zk_status run_ntt(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t L, b
 
 // ---------------------------------------------------------------- MSM driver
 zk_status run_msm(const MsmPlan& plan, const uint64_t* offsets, const uint32_t* mont_points, const uint32_t* scalars,
-                  uint32_t* out, hipStream_t s) {
+                  uint32_t* out, hipStream_t s, hipEvent_t after_accumulate = nullptr) {
   Scratch ws;
   zk_status st = scratch_alloc(ws, msm_workspace_bytes(plan), s);
   if (st) return st;
   const MsmBuffers b = msm_carve(plan, ws.p);
-  ZK_HIP(msm_run(plan, offsets, mont_points, scalars, b, out, s), "msm");
+  ZK_HIP(msm_run(plan, offsets, mont_points, scalars, b, out, s, after_accumulate), "msm");
   return ZK_OK;
 }
 
@@ -468,17 +468,17 @@ uint64_t zk_srs_size(const zk_srs* srs) { return srs ? srs->n : 0; }
 
 static MsmPlan srs_plan(const zk_srs* srs, uint64_t n, const uint64_t off[2]) {
   if (n < SRS_SMALL_MAX)
-    return msm_plan_table(off, 1, SRS_C_SMALL, srs ? (uint32_t)srs->n_small : (uint32_t)n, true);
-  return msm_plan_table(off, 1, SRS_C, srs ? (uint32_t)srs->n : (uint32_t)n, true);
+    return msm_plan_table(off, 1, SRS_C_SMALL, srs ? (uint32_t)srs->n_small : (uint32_t)n);
+  return msm_plan_table(off, 1, SRS_C, srs ? (uint32_t)srs->n : (uint32_t)n);
 }
 
 // One commitment: the small-window table below SRS_SMALL_MAX points, the
 // main table above; either way every window keeps its own buckets.
 static zk_status msm_srs_one(const zk_srs* srs, const uint32_t* scalars, uint64_t n, uint32_t* out16,
-                             hipStream_t s) {
+                             hipStream_t s, hipEvent_t after_accumulate = nullptr) {
   const uint64_t off[2] = {0, n};
   const MsmPlan plan = srs_plan(srs, n, off);
-  return run_msm(plan, off, n < SRS_SMALL_MAX ? srs->tab_small : srs->tab, scalars, out16, s);
+  return run_msm(plan, off, n < SRS_SMALL_MAX ? srs->tab_small : srs->tab, scalars, out16, s, after_accumulate);
 }
 
 uint64_t zk_msm_srs_workspace_bytes(const zk_srs* srs, uint64_t n) {
@@ -490,6 +490,17 @@ uint64_t zk_msm_srs_workspace_bytes(const zk_srs* srs, uint64_t n) {
 uint64_t zk_ntt_workspace_bytes(uint32_t log_n) {
   if (log_n > ZK_MAX_LOG_NTT) return 0;
   return log_n <= ntt_tile_log() ? 0 : ((uint64_t)32 << log_n);
+}
+
+zk_status zk_msm_srs_ex(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream,
+                        void* accumulate_done_event) {
+  if (!srs || !out || (n && !scalars)) return fail(ZK_EINVAL, "zk_msm_srs_ex: NULL argument");
+  if (n > srs->n) return fail(ZK_EINVAL, "zk_msm_srs_ex: n exceeds the SRS size");
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  return msm_srs_one(srs, reinterpret_cast<const uint32_t*>(scalars), n, reinterpret_cast<uint32_t*>(out),
+                     (hipStream_t)stream, (hipEvent_t)accumulate_done_event);
 }
 
 zk_status zk_msm_srs(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream) {
@@ -517,7 +528,7 @@ zk_status zk_msm_batch(const zk_srs* srs, const zk_fr* scalars, const uint64_t* 
   if (offsets_host[batch] >= (1ull << 31) / 16) return fail(ZK_EUNSUPPORTED, "zk_msm_batch: too many scalars");
   // one Pippenger run over every MSM: digits of all scalars sorted into
   // per-MSM buckets, one accumulation, one reduction, one output per MSM
-  const MsmPlan plan = msm_plan_table(offsets_host, batch, srs->c, (uint32_t)srs->n, false);
+  const MsmPlan plan = msm_plan_table(offsets_host, batch, srs->c, (uint32_t)srs->n);
   return run_msm(plan, offsets_host, srs->tab, reinterpret_cast<const uint32_t*>(scalars),
                  reinterpret_cast<uint32_t*>(out), (hipStream_t)stream);
 }

@@ -314,72 +314,204 @@ ZK_HD bool w8_is_one(const uint32_t a[8]) {
   return o == 0;
 }
 
-// a >>= 1 over 8 words (with `top` shifted into bit 255).
-ZK_HD void w8_shr1(uint32_t a[8], uint32_t top) {
+// ---- inversion by the binary GCD with word-sized approximations ----------
+// The binary GCD keeps (a, b) with b odd; a step subtracts the smaller from
+// the larger when a is odd (swapping so that a - b >= 0) and halves a, while
+// coefficients u, v with a = u x, b = v x (mod q) follow along; it ends with
+// a = 0, b = gcd = 1, v = x^-1.  Thirty steps depend only on the low 30 bits
+// of a and b (their parities) and on comparisons, which the top bits decide
+// almost always.  So thirty steps run on 64-bit stand-ins (top 34 and low
+// 30 bits), recording a 2x2 integer matrix [f0 g0; f1 g1] (rows scaled so
+// that halving a becomes doubling the other row); one exact update
+// (a, b) <- ((f0 a + g0 b), (f1 a + g1 b)) / 2^30 then applies them to the
+// full values (and to u, v modulo q).  A misjudged comparison can make a new
+// value negative; it is negated together with its matrix row.  This is the
+// batched binary GCD of T. Pornin, "Optimized Binary GCD for Modular
+// Inversion" (IACR ePrint 2020/972); the loop runs until a = 0, and a
+// Fermat inversion backs it up should the iteration bound ever be reached.
+constexpr int BGCD_STEPS = 30;
+
+ZK_HD bool w8_is_zero(const uint32_t a[8]) {
+  uint32_t o = 0;
 #pragma unroll
-  for (int i = 0; i < 7; i++) a[i] = (a[i] >> 1) | (a[i + 1] << 31);
-  a[7] = (a[7] >> 1) | (top << 31);
+  for (int i = 0; i < 8; i++) o |= a[i];
+  return o == 0;
 }
 
-// x / 2 mod q for canonical x (q odd): x even -> x >> 1, else (x + q) >> 1.
-template <class F>
-ZK_HD void half_mod32(uint32_t x[8]) {
-  const uint32_t mask = 0u - (x[0] & 1u);
-  unsigned c = 0;
+// Bit length of a (0 for a = 0).
+ZK_HD uint32_t w8_bitlen(const uint32_t a[8]) {
+  uint32_t n = 0;
 #pragma unroll
-  for (int i = 0; i < 8; i++) x[i] = __builtin_addc(x[i], F::M32[i] & mask, c, &c);
-  w8_shr1(x, c);
+  for (int i = 0; i < 8; i++)
+    if (a[i]) n = 32u * i + 32u - (uint32_t)__builtin_clz(a[i]);
+  return n;
 }
 
-// Plain inverse x^-1 mod q of a canonical nonzero x by the binary extended
-// Euclidean algorithm (invariants: x1 * x = u, x2 * x = v mod q).
-template <class F>
-ZK_HD void inv_binary32(const uint32_t x[8], uint32_t out[8]) {
-  uint32_t u[8], v[8], x1[8], x2[8];
+// floor(a / 2^p) mod 2^64 for 0 <= p < 256.
+ZK_HD uint64_t w8_bits_at(const uint32_t a[8], uint32_t p) {
+  const uint32_t k = p >> 5, sh = p & 31u;
+  uint32_t w0 = 0, w1 = 0, w2 = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < 8; i++) {
+    if (i == k) w0 = a[i];
+    if (i == k + 1) w1 = a[i];
+    if (i == k + 2) w2 = a[i];
+  }
+  const uint64_t lo = (uint64_t)w0 | ((uint64_t)w1 << 32);
+  return sh ? (lo >> sh) | ((uint64_t)w2 << (64u - sh)) : lo;
+}
+
+// r = a * m (8 words times a 32-bit word) into 9 words.
+ZK_HD void w8_mul_u32(const uint32_t a[8], uint32_t m, uint32_t r[9]) {
+  uint64_t c = 0;
 #pragma unroll
   for (int i = 0; i < 8; i++) {
-    u[i] = x[i];
-    v[i] = F::M32[i];
-    x1[i] = 0;
-    x2[i] = 0;
+    c += (uint64_t)a[i] * m;
+    r[i] = (uint32_t)c;
+    c >>= 32;
   }
-  x1[0] = 1;
-  while (!w8_is_one(u) && !w8_is_one(v)) {
-    while ((u[0] & 1u) == 0) {
-      w8_shr1(u, 0);
-      half_mod32<F>(x1);
-    }
-    while ((v[0] & 1u) == 0) {
-      w8_shr1(v, 0);
-      half_mod32<F>(x2);
-    }
-    uint32_t d[8];
-    unsigned br = 0;
-#pragma unroll
-    for (int i = 0; i < 8; i++) d[i] = __builtin_subc(u[i], v[i], br, &br);
-    if (!br) {  // u >= v
-#pragma unroll
-      for (int i = 0; i < 8; i++) u[i] = d[i];
-      sub_mod32<F>(x1, x2, x1);
-    } else {
-      unsigned b2 = 0;
-#pragma unroll
-      for (int i = 0; i < 8; i++) v[i] = __builtin_subc(v[i], u[i], b2, &b2);
-      sub_mod32<F>(x2, x1, x2);
-    }
-  }
-  const bool uone = w8_is_one(u);
-#pragma unroll
-  for (int i = 0; i < 8; i++) out[i] = uone ? x1[i] : x2[i];
+  r[8] = (uint32_t)c;
 }
 
-// Inverse in Montgomery form: (a R)^-1 by the binary algorithm, times R^3
+// Two's complement negation of a 9-word value when neg is set.
+ZK_HD void w9_cneg(uint32_t r[9], bool neg) {
+  const uint32_t mask = neg ? 0xffffffffu : 0u;
+  unsigned c = neg ? 1u : 0u;
+#pragma unroll
+  for (int i = 0; i < 9; i++) r[i] = __builtin_addc(r[i] ^ mask, 0u, c, &c);
+}
+
+// (f a + g b) / 2^30 for |f| + |g| <= 2^30 and a, b < 2^254 (the division is
+// exact by construction).  Returns the magnitude in out and whether the
+// result is negative.
+ZK_HD bool bgcd_update(const uint32_t a[8], const uint32_t b[8], int64_t f, int64_t g, uint32_t out[8]) {
+  uint32_t pa[9], pb[9], s[9];
+  w8_mul_u32(a, (uint32_t)(f < 0 ? -f : f), pa);
+  w8_mul_u32(b, (uint32_t)(g < 0 ? -g : g), pb);
+  w9_cneg(pa, f < 0);
+  w9_cneg(pb, g < 0);
+  unsigned c = 0;
+#pragma unroll
+  for (int i = 0; i < 9; i++) s[i] = __builtin_addc(pa[i], pb[i], c, &c);
+  const bool neg = (s[8] >> 31) != 0;
+  w9_cneg(s, neg);
+#pragma unroll
+  for (int i = 0; i < 8; i++) out[i] = (s[i] >> BGCD_STEPS) | (s[i + 1] << (32 - BGCD_STEPS));
+  return neg;
+}
+
+// (f u + g v) / 2^30 mod q for canonical u, v and |f| + |g| <= 2^30: negative
+// coefficients use q - u (= -u), and the division is a Montgomery step with
+// 2^30 (add the multiple of q that clears the low 30 bits).
+template <class F>
+ZK_HD void bgcd_update_mod(const uint32_t u[8], const uint32_t v[8], int64_t f, int64_t g, uint32_t out[8]) {
+  uint32_t us[8], vs[8], pu[9], pv[9], t[10];
+  unsigned bu = 0, bv = 0;
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    const uint32_t du = __builtin_subc(F::M32[i], u[i], bu, &bu);
+    const uint32_t dv = __builtin_subc(F::M32[i], v[i], bv, &bv);
+    us[i] = f < 0 ? du : u[i];
+    vs[i] = g < 0 ? dv : v[i];
+  }
+  w8_mul_u32(us, (uint32_t)(f < 0 ? -f : f), pu);
+  w8_mul_u32(vs, (uint32_t)(g < 0 ? -g : g), pv);
+  unsigned c = 0;
+#pragma unroll
+  for (int i = 0; i < 9; i++) t[i] = __builtin_addc(pu[i], pv[i], c, &c);
+  t[9] = c;
+  // -q^-1 mod 2^32 by Newton's iteration from the low word (q odd)
+  uint32_t qi = F::M32[0];
+#pragma unroll
+  for (int k = 0; k < 5; k++) qi *= 2u - F::M32[0] * qi;
+  const uint32_t m = (t[0] * (0u - qi)) & ((1u << BGCD_STEPS) - 1u);
+  uint32_t mq[9];
+  w8_mul_u32(F::M32, m, mq);
+  c = 0;
+#pragma unroll
+  for (int i = 0; i < 9; i++) t[i] = __builtin_addc(t[i], mq[i], c, &c);
+  t[9] += c;
+#pragma unroll
+  for (int i = 0; i < 8; i++) out[i] = (t[i] >> BGCD_STEPS) | (t[i + 1] << (32 - BGCD_STEPS));
+  canon32<F>(out);  // the quotient is < 2q
+}
+
+// x^-1 mod q for canonical nonzero x.  Returns false (out unspecified) if the
+// iteration bound was reached without finishing.
+template <class F>
+ZK_HD bool inv_bgcd32(const uint32_t x[8], uint32_t out[8]) {
+  uint32_t a[8], b[8], u[8], v[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    a[i] = x[i];
+    b[i] = F::M32[i];
+    u[i] = 0;
+    v[i] = 0;
+  }
+  u[0] = 1;
+  // 2 log2(q) single steps suffice for the exact algorithm; allow slack
+  for (int it = 0; it < 40 && !w8_is_zero(a); it++) {
+    uint32_t ab[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) ab[i] = a[i] | b[i];
+    const uint32_t n = w8_bitlen(ab);
+    uint64_t xa, xb;
+    if (n <= 64) {
+      xa = (uint64_t)a[0] | ((uint64_t)a[1] << 32);
+      xb = (uint64_t)b[0] | ((uint64_t)b[1] << 32);
+    } else {
+      const uint32_t p = n - (64 - BGCD_STEPS);
+      const uint64_t lowmask = (1ull << BGCD_STEPS) - 1ull;
+      xa = (w8_bits_at(a, p) << BGCD_STEPS) | (a[0] & lowmask);
+      xb = (w8_bits_at(b, p) << BGCD_STEPS) | (b[0] & lowmask);
+    }
+    int64_t f0 = 1, g0 = 0, f1 = 0, g1 = 1;
+#pragma unroll
+    for (int k = 0; k < BGCD_STEPS; k++) {
+      const bool odd = (xa & 1u) != 0;
+      const bool sw = odd && xa < xb;
+      const uint64_t ta = sw ? xb : xa, tb = sw ? xa : xb;
+      const int64_t tf0 = sw ? f1 : f0, tg0 = sw ? g1 : g0;
+      const int64_t tf1 = sw ? f0 : f1, tg1 = sw ? g0 : g1;
+      xa = (odd ? ta - tb : ta) >> 1;
+      xb = tb;
+      f0 = odd ? tf0 - tf1 : tf0;
+      g0 = odd ? tg0 - tg1 : tg0;
+      f1 = tf1 * 2;
+      g1 = tg1 * 2;
+    }
+    uint32_t na[8], nb[8];
+    if (bgcd_update(a, b, f0, g0, na)) {
+      f0 = -f0;
+      g0 = -g0;
+    }
+    if (bgcd_update(a, b, f1, g1, nb)) {
+      f1 = -f1;
+      g1 = -g1;
+    }
+    uint32_t nu[8], nv[8];
+    bgcd_update_mod<F>(u, v, f0, g0, nu);
+    bgcd_update_mod<F>(u, v, f1, g1, nv);
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+      a[i] = na[i];
+      b[i] = nb[i];
+      u[i] = nu[i];
+      v[i] = nv[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 8; i++) out[i] = v[i];
+  return w8_is_zero(a) && w8_is_one(b);
+}
+
+// Inverse in Montgomery form: (a R)^-1 by the batched binary GCD, times R^3
 // through one Montgomery product gives a^-1 R.  a must be nonzero mod q.
 template <class F>
 ZK_HD f29 mont_inv(const f29& a) {
   uint32_t w[8], iw[8];
   pack(reduce_full<F>(a), w);
-  inv_binary32<F>(w, iw);
+  if (!inv_bgcd32<F>(w, iw)) return mont_inv_fermat<F>(a);
   return mont_mul<F>(unpack(iw), f29_from(F::R3));
 }
 

@@ -16,10 +16,8 @@ constexpr uint32_t REC_WORDS = 40;         // key, flag, pad, pad, point (36): 1
 //           per window, window sums Horner-combined at the end.
 //  table:   `nseg` MSMs over one pre-shifted table (tab[w*tab_stride + i] =
 //           2^(c w) P_i), every MSM with its own output.  Window w's digit of
-//           s_i selects table point (w, i), so window sums are simply added:
-//           either every window keeps its own buckets (Wb = W: short runs,
-//           W-fold parallel reduction) or all windows of an MSM share K
-//           buckets (Wb = 1: fewest buckets, for batches of many MSMs).
+//           s_i selects table point (w, i), so window sums are simply added
+//           and all windows of an MSM share one set of K buckets (Wb = 1).
 struct MsmPlan {
   uint32_t n;          // scalars in total (all segments)
   uint32_t c;          // window bits; digits are signed in [-2^(c-1), 2^(c-1)]
@@ -35,14 +33,16 @@ struct MsmPlan {
   uint32_t nitems;     // items per window
   uint32_t L;          // sorted entries per accumulating thread
   uint32_t acc_blocks; // accumulate workgroups
-  uint32_t LB;         // buckets per thread in the running-sum reduction
-  uint32_t J;          // LB-chunks per bucket set = K / LB
+  uint32_t LB;         // buckets per chunk in the running-sum reduction
+  uint32_t lgLB;       // log2 LB
+  uint32_t J;          // chunks per bucket set = K / LB
+  uint32_t nbits;      // log2 J: bit slices of the chunk index
+  uint32_t parts;      // partial sums per bit slice
 };
 
 MsmPlan msm_plan_generic(uint32_t n, uint32_t c);
-// offsets: nmsm + 1 scalar offsets (host), offsets[0] = 0.  per_window:
-// every window keeps its own buckets (Wb = W) instead of sharing them.
-MsmPlan msm_plan_table(const uint64_t* offsets, uint32_t nmsm, uint32_t c, uint32_t tab_stride, bool per_window);
+// offsets: nmsm + 1 scalar offsets (host), offsets[0] = 0.
+MsmPlan msm_plan_table(const uint64_t* offsets, uint32_t nmsm, uint32_t c, uint32_t tab_stride);
 uint32_t msm_default_c(uint32_t n);
 
 // Scratch buffers of one run (device pointers), carved from one allocation.
@@ -52,11 +52,12 @@ struct MsmBuffers {
   uint32_t* offsets;   // nbins + 1
   uint32_t* cursor;    // nbins
   uint32_t* scan_tmp;  // scan block sums
-  uint2* entries;      // W*n (bucket key, point index | sign << 31), sorted by key
+  uint32_t* entries;   // W*n point index | sign << 31, sorted by bucket (ranges from offsets)
   uint32_t* buckets;   // nbins * 36
   uint32_t* rec[2];    // records (REC_WORDS each), ping-pong between levels
-  uint32_t* vbuf;      // groups * J * 36
-  uint32_t* wsum;      // groups * 36
+  uint32_t* vbuf;      // groups * J * 2 * 36: chunk totals S_j and weighted sums T_j
+  uint32_t* partial;   // groups * (nbits + 1) * parts * 36: bit-slice partial sums
+  uint32_t* wsum;      // groups * 36 (generic: window sums)
   uint32_t* seg_off;   // nseg + 1 (shared) / 2 (generic)
   uint4* items;        // nitems: (segment, first scalar, end scalar, 0)
 };
@@ -68,8 +69,11 @@ MsmBuffers msm_carve(const MsmPlan& p, void* base);
 // points: Montgomery affine (16 words each) -- the bases (generic) or the
 // pre-shifted table (table layout).  offsets: host segment offsets (table),
 // or nullptr (generic).  out: 16 words per output (nseg), canonical affine.
+// after_accumulate: if not null, recorded on s right after the accumulation
+// kernel (the rest of the run is latency-bound reduction; work that waits on
+// this event can fill the idle compute units).
 hipError_t msm_run(const MsmPlan& p, const uint64_t* offsets, const uint32_t* points, const uint32_t* scalars,
-                   const MsmBuffers& b, uint32_t* out, hipStream_t s);
+                   const MsmBuffers& b, uint32_t* out, hipStream_t s, hipEvent_t after_accumulate = nullptr);
 
 // Canonical plain affine points -> Montgomery-form affine points (count n).
 hipError_t msm_points_to_mont(const uint32_t* plain, uint32_t* mont, uint64_t n, hipStream_t s);

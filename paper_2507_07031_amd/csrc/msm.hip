@@ -28,8 +28,9 @@
 //               runs that cross thread boundaries are finished by a segmented
 //               tree in LDS, runs that cross workgroups by further levels
 //               over 2 records per workgroup
-//  6 reduce     sum_k k B_k by running sums over chunks of LB buckets, each
-//               chunk offset by a small scalar multiple, then a tree
+//  6 reduce     sum_k k B_k by running sums over chunks of LB buckets and
+//               bit-sliced sums of the chunk totals (wide trees, one short
+//               doubling chain per bucket set)
 //  7 combine    Horner over windows (generic) or a plain sum (table), affine
 #include <algorithm>
 
@@ -219,7 +220,7 @@ hist_kernel(const uint32_t* __restrict__ digits, MsmPlan p, const uint4* __restr
 
 __global__ void __launch_bounds__(MSM_NT)
 scatter_kernel(const uint32_t* __restrict__ digits, MsmPlan p, const uint4* __restrict__ items,
-               const uint32_t* __restrict__ seg_off, uint32_t* __restrict__ cursor, uint2* __restrict__ entries) {
+               const uint32_t* __restrict__ seg_off, uint32_t* __restrict__ cursor, uint32_t* __restrict__ entries) {
   extern __shared__ uint32_t h[];
   const uint32_t w = blockIdx.y;
   const uint4 it = items[blockIdx.x];
@@ -242,7 +243,7 @@ scatter_kernel(const uint32_t* __restrict__ digits, MsmPlan p, const uint4* __re
     if (!d) continue;
     const uint32_t b = (d >> 1) - 1;
     const uint32_t pos = atomicAdd(&h[b], 1u);
-    entries[pos] = make_uint2(off + b, (pbase + e) | ((d & 1u) << 31));
+    entries[pos] = (pbase + e) | ((d & 1u) << 31);
   }
 }
 
@@ -286,9 +287,6 @@ __device__ void put_slot(RecLds& r, uint32_t i, uint32_t key, uint32_t flag, con
   st_xyzz(r.pts + i * XYZZ_WORDS, a);
 }
 
-// Sum every run of equal keys held in the LDS slots; runs closed on both sides
-// are written to their bucket, the first and last run of the block go out as
-// records for the next level (data only if still open there).
 __device__ __forceinline__ void put_rec(uint32_t* rec, uint32_t key, uint32_t flag, const uint32_t* pts_or_null) {
   reinterpret_cast<uint4*>(rec)[0] = make_uint4(key, flag, 0, 0);
   uint4* dst = reinterpret_cast<uint4*>(rec + 4);
@@ -296,22 +294,47 @@ __device__ __forceinline__ void put_rec(uint32_t* rec, uint32_t key, uint32_t fl
   for (int w = 0; w < 9; w++) dst[w] = pts_or_null ? src[w] : make_uint4(0, 0, 0, 0);
 }
 
+// Sum every run of equal keys held in the LDS slots; runs closed on both sides
+// are written to their bucket, the first and last run of the block go out as
+// records for the next level (data only if still open there).  The runs are
+// summed by a segmented tree: at level d the slot at offset 0 mod 2d of its
+// run adds the slot d further on.  The pairs that have work at a level are
+// listed first and handed to consecutive threads, so a wave only runs
+// additions when its lanes have them (runs are often long, and most pairs
+// of a naive slot-per-thread sweep would be idle).
 __device__ void combine_and_emit(RecLds& r, bool left_open, bool right_open, uint32_t* __restrict__ buckets,
                                  uint32_t* out_rec) {
+  __shared__ uint32_t act[MSM_SLOTS / 2];  // pairs are disjoint: at most SLOTS/2 per level
+  __shared__ uint32_t nact, maxrun;
   const uint32_t tid = threadIdx.x;
+  if (tid == 0) maxrun = 1;
+  __syncthreads();
   uint32_t head[MSM_SLOTS / MSM_NT];
 #pragma unroll
-  for (uint32_t q = 0; q < MSM_SLOTS / MSM_NT; q++) head[q] = lower_bound_lds(r.keys, r.keys[tid + q * MSM_NT]);
-  for (uint32_t d = 1; d < MSM_SLOTS; d <<= 1) {
+  for (uint32_t q = 0; q < MSM_SLOTS / MSM_NT; q++) {
+    const uint32_t i = tid + q * MSM_NT;
+    head[q] = lower_bound_lds(r.keys, r.keys[i]);
+    if (head[q] == i) atomicMax(&maxrun, upper_bound_lds(r.keys, r.keys[i]) - i);
+  }
+  __syncthreads();
+  const uint32_t runmax = maxrun;
+  for (uint32_t d = 1; d < runmax; d <<= 1) {
+    if (tid == 0) nact = 0;
+    __syncthreads();
 #pragma unroll
     for (uint32_t q = 0; q < MSM_SLOTS / MSM_NT; q++) {
       const uint32_t i = tid + q * MSM_NT;
       if (((i - head[q]) & (2 * d - 1)) == 0 && i + d < MSM_SLOTS && r.keys[i + d] == r.keys[i] &&
-          r.flags[i + d]) {
-        const xyzz s = add(ld_xyzz(r.pts + i * XYZZ_WORDS), ld_xyzz(r.pts + (i + d) * XYZZ_WORDS));
-        st_xyzz(r.pts + i * XYZZ_WORDS, s);
-        r.flags[i] = 1;
-      }
+          r.flags[i + d])
+        act[atomicAdd(&nact, 1u)] = i;
+    }
+    __syncthreads();
+    const uint32_t n = nact;
+    for (uint32_t k = tid; k < n; k += MSM_NT) {
+      const uint32_t i = act[k];
+      const xyzz s = add(ld_xyzz(r.pts + i * XYZZ_WORDS), ld_xyzz(r.pts + (i + d) * XYZZ_WORDS));
+      st_xyzz(r.pts + i * XYZZ_WORDS, s);
+      r.flags[i] = 1;
     }
     __syncthreads();
   }
@@ -354,16 +377,18 @@ __device__ __forceinline__ void st_rec_xyzz(uint32_t* rec, uint32_t key, uint32_
   st_xyzz(rec + 4, a);
 }
 
-// Each thread sums L consecutive sorted entries.  Runs of one key strictly
-// inside the range are complete buckets and go straight to HBM; the first
-// and last run of the range become the thread's two records, finished by the
-// record levels.  The next entry and its point are loaded one step ahead.
+// Each thread sums L consecutive sorted entries.  An entry is only its point
+// index and sign; its bucket is the one whose offset range contains the
+// entry's position (found once by binary search, then followed).  Runs of
+// one bucket strictly inside the range are complete and go straight to HBM;
+// the first and last run of the range become the thread's two records,
+// finished by the record levels.  The next point is loaded one step ahead.
 __global__ void __launch_bounds__(MSM_NT) __attribute__((amdgpu_waves_per_eu(3, 3)))
-accumulate_kernel(const uint2* __restrict__ entries, const uint32_t* __restrict__ total_p,
+accumulate_kernel(const uint32_t* __restrict__ entries, const uint32_t* __restrict__ offsets, uint32_t nbins,
                   const uint32_t* __restrict__ points, uint32_t L, uint32_t* __restrict__ buckets,
                   uint32_t* __restrict__ rec) {
   const uint64_t t = (uint64_t)blockIdx.x * MSM_NT + threadIdx.x;
-  const uint32_t total = *total_p;
+  const uint32_t total = offsets[nbins];
   const uint64_t tb = t * L;
   uint32_t* r0 = rec + (2 * t) * REC_WORDS;
   uint32_t* r1 = r0 + REC_WORDS;
@@ -372,28 +397,38 @@ accumulate_kernel(const uint2* __restrict__ entries, const uint32_t* __restrict_
     st_rec_xyzz(r1, KEY_SENTINEL, 0, xyzz_inf());
     return;
   }
-  const uint64_t te = min(tb + L, (uint64_t)total);
-  uint2 ent = entries[tb];
+  const uint32_t te = (uint32_t)min(tb + L, (uint64_t)total);
+  // bucket of entry tb: the largest b with offsets[b] <= tb
+  uint32_t lo = 0, hi = nbins;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (offsets[mid] <= (uint32_t)tb) lo = mid; else hi = mid - 1;
+  }
+  uint32_t cur = lo;
+  uint32_t bend = offsets[cur + 1];
+  uint32_t v = entries[tb];
   uint4 q[4];
-  ld_pt_words(points, ent.y, q);
-  uint32_t cur = ent.x;
+  ld_pt_words(points, v, q);
   bool first_done = false;
   xyzz acc = xyzz_inf();
-  for (uint64_t e = tb; e < te; e++) {
-    uint2 nent = ent;
+  for (uint32_t e = (uint32_t)tb; e < te; e++) {
+    uint32_t nv = v;
     uint4 nq[4] = {q[0], q[1], q[2], q[3]};
     if (e + 1 < te) {
-      nent = entries[e + 1];
-      ld_pt_words(points, nent.y, nq);
+      nv = entries[e + 1];
+      ld_pt_words(points, nv, nq);
     }
-    if (ent.x != cur) {
+    if (e == bend) {
       if (!first_done) {
         st_rec_xyzz(r0, cur, 1, acc);
         first_done = true;
       } else {
         st_xyzz(buckets + (size_t)cur * XYZZ_WORDS, acc);
       }
-      cur = ent.x;
+      do {
+        cur++;
+        bend = offsets[cur + 1];
+      } while (bend == e);
       acc = xyzz_inf();
     }
     uint32_t w[16];
@@ -411,10 +446,10 @@ accumulate_kernel(const uint2* __restrict__ entries, const uint32_t* __restrict_
       aff pt;
       pt.x = unpack(w);
       pt.y = unpack(w + 8);
-      if (ent.y >> 31) pt = aff_neg(pt);
+      if (v >> 31) pt = aff_neg(pt);
       acc = madd(acc, pt);
     }
-    ent = nent;
+    v = nv;
 #pragma unroll
     for (int k = 0; k < 4; k++) q[k] = nq[k];
   }
@@ -458,46 +493,122 @@ record_reduce_kernel(const uint32_t* __restrict__ in_rec, uint32_t nrec, uint32_
 }
 
 // ---------------------------------------------------------------- bucket reduction
-// V_(w,j) = sum_{b in chunk j} (b + 1) B_(w,b): running sums over the chunk
-// give sum (m + 1) B and sum B (m = b - j LB); the offset j*LB times the
-// chunk total is added with a small double-and-add.
-__global__ void __launch_bounds__(MSM_NT)
-bucket_chunks_kernel(const uint32_t* __restrict__ buckets, const uint32_t* __restrict__ counts, MsmPlan p,
-                     uint32_t* __restrict__ vbuf) {
+// A bucket set's weighted sum V = sum_b (b + 1) B_b, b < K, is split over
+// J = K / LB chunks of LB buckets: with b = j LB + m,
+//   V = sum_j T_j + LB sum_j j S_j,  S_j = sum_m B_(j,m),  T_j = sum_m (m + 1) B_(j,m).
+// One thread per chunk forms S_j and T_j by running sums (2 LB dependent
+// additions).  sum_j j S_j is taken bit by bit: U_i = sum of the S_j whose
+// index j has bit i set, so sum_j j S_j = sum_i 2^i U_i.  The U_i and
+// sum_j T_j are wide plain sums (parallel trees); only one doubling chain of
+// log2(K) steps per bucket set remains, instead of a small scalar multiple
+// per chunk.
+__global__ void __launch_bounds__(64)
+chunk_sums_kernel(const uint32_t* __restrict__ buckets, const uint32_t* __restrict__ counts, MsmPlan p,
+                  uint32_t* __restrict__ vbuf) {
   const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= p.groups * p.J) return;
-  const uint32_t sg = id / p.J, j = id % p.J;
-  const uint32_t base = sg * p.K + j * p.LB;
+  const uint32_t g = id / p.J, j = id % p.J;
+  const uint32_t base = g * p.K + j * p.LB;
   xyzz acc = xyzz_inf(), sum = xyzz_inf();
   for (int m = (int)p.LB - 1; m >= 0; --m) {
     if (counts[base + m]) acc = add(acc, ld_xyzz(buckets + (size_t)(base + m) * XYZZ_WORDS));
     sum = add(sum, acc);
   }
-  sum = add(sum, mul_small(acc, j * p.LB));
-  st_xyzz(vbuf + (size_t)id * XYZZ_WORDS, sum);
+  st_xyzz(vbuf + (size_t)id * 2 * XYZZ_WORDS, acc);
+  st_xyzz(vbuf + ((size_t)id * 2 + 1) * XYZZ_WORDS, sum);
 }
 
-// One workgroup per bucket set: S = sum_j V_j.
-constexpr uint32_t WSUM_NT = 512;
-__global__ void __launch_bounds__(WSUM_NT)
-window_sum_kernel(const uint32_t* __restrict__ vbuf, uint32_t J, uint32_t* __restrict__ wsum) {
-  extern __shared__ uint32_t sm[];
-  const uint32_t w = blockIdx.x, tid = threadIdx.x;
+// Partial sums of one bit slice: block (part, i, g) adds its share of the
+// terms of slice i of bucket set g -- the S_j with bit i of j set (i < nbits)
+// or every T_j (i = nbits) -- sequentially per thread, then by a tree in LDS.
+constexpr uint32_t BITS_NT = 64;
+__global__ void __launch_bounds__(BITS_NT)
+bit_sums_kernel(const uint32_t* __restrict__ vbuf, MsmPlan p, uint32_t* __restrict__ partial) {
+  __shared__ uint32_t sm[BITS_NT * XYZZ_WORDS];
+  const uint32_t part = blockIdx.x, i = blockIdx.y, g = blockIdx.z, tid = threadIdx.x;
+  const bool tslice = i == p.nbits;
+  const uint32_t count = tslice ? p.J : p.J / 2;
+  const uint32_t per = (count + p.parts - 1) / p.parts;
+  const uint32_t t0 = part * per, t1 = min(t0 + per, count);
+  const uint32_t low = (1u << i) - 1u;
   xyzz acc = xyzz_inf();
-  for (uint32_t j = tid; j < J; j += WSUM_NT) acc = add(acc, ld_xyzz(vbuf + ((size_t)w * J + j) * XYZZ_WORDS));
+  for (uint32_t t = t0 + tid; t < t1; t += BITS_NT) {
+    const uint32_t j = tslice ? t : (((t >> i) << (i + 1)) | (1u << i) | (t & low));
+    acc = add(acc, ld_xyzz(vbuf + ((size_t)(g * p.J + j) * 2 + (tslice ? 1 : 0)) * XYZZ_WORDS));
+  }
   st_xyzz(sm + tid * XYZZ_WORDS, acc);
   __syncthreads();
-  for (uint32_t s = WSUM_NT / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      const xyzz t = add(ld_xyzz(sm + tid * XYZZ_WORDS), ld_xyzz(sm + (tid + s) * XYZZ_WORDS));
-      st_xyzz(sm + tid * XYZZ_WORDS, t);
+  for (uint32_t h = BITS_NT / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      const xyzz a = add(ld_xyzz(sm + tid * XYZZ_WORDS), ld_xyzz(sm + (tid + h) * XYZZ_WORDS));
+      st_xyzz(sm + tid * XYZZ_WORDS, a);
     }
     __syncthreads();
   }
-  if (tid == 0) st_xyzz(wsum + (size_t)w * XYZZ_WORDS, ld_xyzz(sm));
+  if (tid == 0)
+    st_xyzz(partial + ((size_t)(g * (p.nbits + 1) + i) * p.parts + part) * XYZZ_WORDS, ld_xyzz(sm));
 }
 
-// Q = sum_w 2^(c w) S_w by Horner, then canonical affine.
+// Bucket set g: U_i from the slice partials, V = U_T + sum_i 2^(log2 LB + i) U_i
+// (every slice doubled in its own thread, then a tree), and the result written
+// as canonical affine (table layout: the set is one output) or as XYZZ (the
+// generic layout's window sums, combined by Horner next).
+constexpr uint32_t FIN_SLICES = 16;  // nbits + 1 <= 16
+constexpr uint32_t FIN_NT = 256;     // 16 threads per slice
+__global__ void __launch_bounds__(FIN_NT)
+bit_finish_kernel(const uint32_t* __restrict__ partial, MsmPlan p, uint32_t* __restrict__ out_affine,
+                  uint32_t* __restrict__ out_xyzz) {
+  __shared__ uint32_t sm[FIN_NT * XYZZ_WORDS];
+  const uint32_t g = blockIdx.x, tid = threadIdx.x;
+  const uint32_t i = tid / 16, q = tid % 16;
+  const uint32_t ns = p.nbits + 1;
+  xyzz acc = xyzz_inf();
+  if (i < ns)
+    for (uint32_t k = q; k < p.parts; k += 16)
+      acc = add(acc, ld_xyzz(partial + ((size_t)(g * ns + i) * p.parts + k) * XYZZ_WORDS));
+  st_xyzz(sm + tid * XYZZ_WORDS, acc);
+  __syncthreads();
+  for (uint32_t h = 8; h > 0; h >>= 1) {
+    if (q < h) {
+      const xyzz a = add(ld_xyzz(sm + tid * XYZZ_WORDS), ld_xyzz(sm + (tid + h) * XYZZ_WORDS));
+      st_xyzz(sm + tid * XYZZ_WORDS, a);
+    }
+    __syncthreads();
+  }
+  // slice i's sum sits in slot 16 i; scale it into slot i
+  xyzz u = xyzz_inf();
+  if (tid < FIN_SLICES) {
+    u = ld_xyzz(sm + tid * 16 * XYZZ_WORDS);
+    if (tid < p.nbits) {
+      const uint32_t e = p.lgLB + tid;
+      for (uint32_t k = 0; k < e; k++) u = dbl(u);
+    } else if (tid > p.nbits) {
+      u = xyzz_inf();
+    }
+  }
+  __syncthreads();
+  if (tid < FIN_SLICES) st_xyzz(sm + tid * XYZZ_WORDS, u);
+  __syncthreads();
+  for (uint32_t h = FIN_SLICES / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      const xyzz a = add(ld_xyzz(sm + tid * XYZZ_WORDS), ld_xyzz(sm + (tid + h) * XYZZ_WORDS));
+      st_xyzz(sm + tid * XYZZ_WORDS, a);
+    }
+    __syncthreads();
+  }
+  if (tid != 0) return;
+  xyzz v = ld_xyzz(sm);
+  force_vgpr(v);
+  if (out_xyzz) {
+    st_xyzz(out_xyzz + (size_t)g * XYZZ_WORDS, v);
+  } else {
+    uint32_t o[16];
+    to_affine_words(v, o);
+    stw(out_affine + (size_t)g * 16, o, 4);
+  }
+}
+
+// Generic layout: Q = sum_w 2^(c w) S_w by Horner, then canonical affine.
 __global__ void __launch_bounds__(64) combine_kernel(const uint32_t* __restrict__ wsum, uint32_t nwin, uint32_t c,
                                uint32_t* __restrict__ out16) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -515,32 +626,6 @@ __global__ void __launch_bounds__(64) combine_kernel(const uint32_t* __restrict_
   uint32_t o[16];
   to_affine_words(q, o);
   stw(out16, o, 4);
-}
-
-// Table layout: output s = sum of its Wb bucket-set sums, canonical affine.
-// One workgroup of 64 threads per output; tree over the Wb (<= 64) sums.
-__global__ void __launch_bounds__(64)
-seg_sum_kernel(const uint32_t* __restrict__ wsum, uint32_t Wb, uint32_t* __restrict__ out) {
-  __shared__ uint32_t sm[64 * XYZZ_WORDS];
-  const uint32_t sg = blockIdx.x, tid = threadIdx.x;
-  xyzz a = tid < Wb ? ld_xyzz(wsum + ((size_t)sg * Wb + tid) * XYZZ_WORDS) : xyzz_inf();
-  st_xyzz(sm + tid * XYZZ_WORDS, a);
-  __syncthreads();
-  for (uint32_t s = 32; s > 0; s >>= 1) {
-    if (tid < s) {
-      xyzz x = ld_xyzz(sm + tid * XYZZ_WORDS), y = ld_xyzz(sm + (tid + s) * XYZZ_WORDS);
-      force_vgpr(x);
-      st_xyzz(sm + tid * XYZZ_WORDS, add(x, y));
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    xyzz q = ld_xyzz(sm);
-    force_vgpr(q);
-    uint32_t o[16];
-    to_affine_words(q, o);
-    stw(out + (size_t)sg * 16, o, 4);
-  }
 }
 
 __global__ void zero16_kernel(uint32_t* out16) {
@@ -746,8 +831,18 @@ static void plan_common(MsmPlan& p) {
   p.L = (uint32_t)L;
   p.acc_blocks = cdiv(cdiv(entries, p.L), MSM_NT);
   if (p.acc_blocks == 0) p.acc_blocks = 1;
-  p.LB = p.K >= 8 ? 8 : p.K;
+  // chunk length: short chains for one or a few bucket sets (latency), longer
+  // ones when many sets already fill the chip (less bit-slice work)
+  uint32_t lb = (uint64_t)p.groups * p.K >= (1u << 20) ? 16 : 4;
+  if (lb > p.K) lb = p.K;
+  p.LB = lb;
+  p.lgLB = 31 - __builtin_clz(lb);
   p.J = p.K / p.LB;
+  p.nbits = 31 - __builtin_clz(p.J);
+  uint32_t parts = p.J / 256;
+  if (parts < 1) parts = 1;
+  if (parts > 64) parts = 64;
+  p.parts = parts;
 }
 
 MsmPlan msm_plan_generic(uint32_t n, uint32_t c) {
@@ -766,7 +861,7 @@ MsmPlan msm_plan_generic(uint32_t n, uint32_t c) {
   return p;
 }
 
-MsmPlan msm_plan_table(const uint64_t* off, uint32_t nmsm, uint32_t c, uint32_t tab_stride, bool per_window) {
+MsmPlan msm_plan_table(const uint64_t* off, uint32_t nmsm, uint32_t c, uint32_t tab_stride) {
   MsmPlan p{};
   p.n = (uint32_t)off[nmsm];
   p.c = c;
@@ -774,7 +869,7 @@ MsmPlan msm_plan_table(const uint64_t* off, uint32_t nmsm, uint32_t c, uint32_t 
   p.K = 1u << (c - 1);
   p.table = 1;
   p.nseg = nmsm;
-  p.Wb = per_window ? p.W : 1;
+  p.Wb = 1;
   p.tab_stride = tab_stride;
   p.chunk = 32768;
   p.nitems = 0;
@@ -820,7 +915,7 @@ hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_
 
 namespace {
 struct Layout {
-  size_t off[14];
+  size_t off[15];
   size_t total;
 };
 
@@ -839,14 +934,15 @@ Layout layout(const MsmPlan& p) {
   take(2, ((size_t)p.nbins + 1) * 4);             // offsets
   take(3, (size_t)p.nbins * 4);                   // cursor
   take(4, scan_tmp_words(p.nbins) * 4);           // scan tmp
-  take(5, ent * 8);                               // entries
+  take(5, ent * 4);                               // entries
   take(6, (size_t)p.nbins * XYZZ_WORDS * 4);      // buckets
   take(7, nrec0 * REC_WORDS * 4);                 // records, thread level (and odd levels)
   take(8, nrec1 * REC_WORDS * 4);                 // records, even levels
-  take(9, (size_t)p.groups * p.J * XYZZ_WORDS * 4); // vbuf
-  take(10, (size_t)p.groups * XYZZ_WORDS * 4);      // wsum
-  take(11, ((size_t)p.nseg + 2) * 4);             // seg_off
-  take(12, ((size_t)p.nitems + 1) * 16);          // items
+  take(9, (size_t)p.groups * p.J * 2 * XYZZ_WORDS * 4);                // vbuf
+  take(10, (size_t)p.groups * XYZZ_WORDS * 4);                         // wsum
+  take(11, ((size_t)p.nseg + 2) * 4);                                  // seg_off
+  take(12, ((size_t)p.nitems + 1) * 16);                               // items
+  take(13, (size_t)p.groups * (p.nbits + 1) * p.parts * XYZZ_WORDS * 4); // partial
   L.total = o;
   return L;
 }
@@ -863,7 +959,7 @@ MsmBuffers msm_carve(const MsmPlan& p, void* base) {
   m.offsets = reinterpret_cast<uint32_t*>(b + L.off[2]);
   m.cursor = reinterpret_cast<uint32_t*>(b + L.off[3]);
   m.scan_tmp = reinterpret_cast<uint32_t*>(b + L.off[4]);
-  m.entries = reinterpret_cast<uint2*>(b + L.off[5]);
+  m.entries = reinterpret_cast<uint32_t*>(b + L.off[5]);
   m.buckets = reinterpret_cast<uint32_t*>(b + L.off[6]);
   m.rec[0] = reinterpret_cast<uint32_t*>(b + L.off[7]);
   m.rec[1] = reinterpret_cast<uint32_t*>(b + L.off[8]);
@@ -871,6 +967,7 @@ MsmBuffers msm_carve(const MsmPlan& p, void* base) {
   m.wsum = reinterpret_cast<uint32_t*>(b + L.off[10]);
   m.seg_off = reinterpret_cast<uint32_t*>(b + L.off[11]);
   m.items = reinterpret_cast<uint4*>(b + L.off[12]);
+  m.partial = reinterpret_cast<uint32_t*>(b + L.off[13]);
   return m;
 }
 
@@ -887,9 +984,6 @@ static hipError_t set_lds_limits() {
     return e;
   if ((e = hipFuncSetAttribute((const void*)record_reduce_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)rec_lds_bytes())))
-    return e;
-  if ((e = hipFuncSetAttribute((const void*)window_sum_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(WSUM_NT * XYZZ_WORDS * 4))))
     return e;
   done = true;
   return hipSuccess;
@@ -923,12 +1017,13 @@ static hipError_t launch_items(const MsmPlan& p, const uint64_t* off, const MsmB
 }
 
 hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points, const uint32_t* scalars,
-                   const MsmBuffers& b, uint32_t* out, hipStream_t s) {
+                   const MsmBuffers& b, uint32_t* out, hipStream_t s, hipEvent_t after_accumulate) {
   hipError_t e;
   if ((e = set_lds_limits())) return e;
   const uint32_t nout = p.nseg;
   if (p.n == 0) {
     for (uint32_t i = 0; i < nout; i++) hipLaunchKernelGGL(zero16_kernel, dim3(1), dim3(64), 0, s, out + 16 * i);
+    if (after_accumulate && (e = hipEventRecord(after_accumulate, s))) return e;
     return hipGetLastError();
   }
   const ProfToken t_sort = prof_begin("msm.sort", s);
@@ -951,9 +1046,11 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points
   }
   prof_end(t_sort, s);
   const ProfToken t_acc = prof_begin("msm.accumulate", s);
-  hipLaunchKernelGGL(accumulate_kernel, dim3(p.acc_blocks), dim3(MSM_NT), 0, s, b.entries, b.offsets + p.nbins,
+  hipLaunchKernelGGL(accumulate_kernel, dim3(p.acc_blocks), dim3(MSM_NT), 0, s, b.entries, b.offsets, p.nbins,
                      points, p.L, b.buckets, b.rec[0]);
   prof_end(t_acc, s);
+  if (after_accumulate && (e = hipEventRecord(after_accumulate, s))) return e;
+  if (p.nbits + 1 > FIN_SLICES) return hipErrorInvalidValue;
   const ProfToken t_red = prof_begin("msm.reduce", s);
   uint32_t nrec = 2 * p.acc_blocks * MSM_NT;
   int cur = 0;
@@ -966,13 +1063,14 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points
     nrec = 2 * g2;
     cur ^= 1;
   }
-  hipLaunchKernelGGL(bucket_chunks_kernel, dim3(cdiv((uint64_t)p.groups * p.J, 64)), dim3(64), 0, s, b.buckets,
+  hipLaunchKernelGGL(chunk_sums_kernel, dim3(cdiv((uint64_t)p.groups * p.J, 64)), dim3(64), 0, s, b.buckets,
                      b.counts, p, b.vbuf);
-  hipLaunchKernelGGL(window_sum_kernel, dim3(p.groups), dim3(WSUM_NT), (size_t)WSUM_NT * XYZZ_WORDS * 4, s, b.vbuf,
-                     p.J, b.wsum);
+  hipLaunchKernelGGL(bit_sums_kernel, dim3(p.parts, p.nbits + 1, p.groups), dim3(BITS_NT), 0, s, b.vbuf, p,
+                     b.partial);
   if (p.table) {
-    hipLaunchKernelGGL(seg_sum_kernel, dim3(p.nseg), dim3(64), 0, s, b.wsum, p.Wb, out);
+    hipLaunchKernelGGL(bit_finish_kernel, dim3(p.groups), dim3(FIN_NT), 0, s, b.partial, p, out, nullptr);
   } else {
+    hipLaunchKernelGGL(bit_finish_kernel, dim3(p.groups), dim3(FIN_NT), 0, s, b.partial, p, nullptr, b.wsum);
     hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, s, b.wsum, p.W, p.c, out);
   }
   prof_end(t_red, s);

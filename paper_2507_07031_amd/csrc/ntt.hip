@@ -55,6 +55,65 @@ __device__ __forceinline__ f29 pow28(const f29* lo, const f29* hi, uint32_t E) {
   return mont_mul<FrP>(ldf29(lo, a), ldf29(hi, b));
 }
 
+// One butterfly of stage s+T on registers x[q], x[q + 2^T] of a unit (q with
+// bit T clear); its twiddle is omega_(2^(s+T))^jt, jt = j + (q mod 2^T) h.
+// Twiddles that are 1 (j = 0 in the first stage of a tile) are skipped.
+template <int Q, int T, int P>
+__device__ __forceinline__ void dit_butterflies(uint32_t (&x)[Q][8], uint32_t s, uint32_t j, uint32_t h,
+                                                const f29* __restrict__ tw_hi) {
+  constexpr uint32_t q = ((P >> T) << (T + 1)) | (P & ((1u << T) - 1));
+  constexpr uint32_t r = q + (1u << T);
+  constexpr uint32_t qlow = q & ((1u << T) - 1);
+  uint32_t tv[8];
+  if (s == 1 && qlow == 0) {
+#pragma unroll
+    for (int w = 0; w < 8; w++) tv[w] = x[r][w];
+  } else {
+    // omega_(2^(s+T))^jt = omega_(2^28)^(jt * 2^(28-s-T)): a "hi" table entry
+    const uint32_t jt = j + qlow * h;
+    mul_plain_by_mont<FrP>(x[r], ldf29(tw_hi, jt << (14 - s - T)), tv);
+  }
+  add_mod32<FrP>(x[q], tv, x[r]);
+  sub_mod32<FrP>(x[q], tv, tv);
+#pragma unroll
+  for (int w = 0; w < 8; w++) {
+    const uint32_t sum = x[r][w];
+    x[r][w] = tv[w];
+    x[q][w] = sum;
+  }
+  if constexpr (P + 1 < Q / 2) dit_butterflies<Q, T, P + 1>(x, s, j, h, tw_hi);
+}
+
+template <int Q, int T, int R>
+__device__ __forceinline__ void dit_levels(uint32_t (&x)[Q][8], uint32_t s, uint32_t j, uint32_t h,
+                                           const f29* __restrict__ tw_hi) {
+  dit_butterflies<Q, T, 0>(x, s, j, h, tw_hi);
+  if constexpr (T + 1 < R) dit_levels<Q, T + 1, R>(x, s, j, h, tw_hi);
+}
+
+// R consecutive decimation-in-time stages s .. s+R-1 on the LDS tile, each
+// thread holding 2^R points in registers.  A unit is the set of points
+// base + q*h (q < 2^R, h = 2^(s-1)) that these stages combine only among
+// themselves: stage s+T pairs q with q + 2^T.
+template <int R>
+__device__ __forceinline__ void dit_stages(uint32_t* lds, uint32_t s, uint32_t m, uint32_t TE,
+                                           const f29* __restrict__ tw_hi) {
+  constexpr int Q = 1 << R;
+  const uint32_t h = 1u << (s - 1);
+  const uint32_t units_per_tr = 1u << (m - R);
+  for (uint32_t u = threadIdx.x; u < TE / Q; u += NTT_THREADS) {
+    const uint32_t b = u >> (m - R), ul = u & (units_per_tr - 1);
+    const uint32_t j = ul & (h - 1), grp = ul >> (s - 1);
+    const uint32_t base = (b << m) + (grp << (s + R - 1)) + j;
+    uint32_t x[Q][8];
+#pragma unroll
+    for (int q = 0; q < Q; q++) ld8(lds + (base + q * h) * 8, x[q]);
+    dit_levels<Q, 0, R>(x, s, j, h, tw_hi);
+#pragma unroll
+    for (int q = 0; q < Q; q++) st8(lds + (base + q * h) * 8, x[q]);
+  }
+}
+
 __global__ void __launch_bounds__(NTT_THREADS)
 ntt_pass_kernel(NttPass a) {
   extern __shared__ uint32_t lds[];
@@ -84,24 +143,20 @@ ntt_pass_kernel(NttPass a) {
   }
   __syncthreads();
 
-  // ---- decimation-in-time stages
-  for (uint32_t s = 1; s <= a.m; s++) {
-    const uint32_t half = 1u << (s - 1);
-    for (uint32_t t = tid; t < TE / 2; t += NTT_THREADS) {
-      const uint32_t b = t >> (a.m - 1), tl = t & ((M >> 1) - 1);
-      const uint32_t j = tl & (half - 1);
-      const uint32_t i0 = b * M + ((tl >> (s - 1)) << s) + j;
-      const uint32_t i1 = i0 + half;
-      uint32_t u[8], v[8], tv[8];
-      ld8(lds + i0 * 8, u);
-      ld8(lds + i1 * 8, v);
-      // omega_(2^s)^j = omega_(2^28)^(j * 2^(28-s)): a "hi" table entry
-      const f29 wj = ldf29(a.tw_hi, j << (14 - s));
-      mul_plain_by_mont<FrP>(v, wj, tv);
-      add_mod32<FrP>(u, tv, v);
-      sub_mod32<FrP>(u, tv, u);
-      st8(lds + i0 * 8, v);
-      st8(lds + i1 * 8, u);
+  // ---- decimation-in-time stages, up to three per LDS round trip
+  for (uint32_t st = 1; st <= a.m;) {
+    const uint32_t left = a.m - st + 1;
+    if (left >= 3 || left == 1) {
+      if (left == 1) {
+        dit_stages<1>(lds, st, a.m, TE, a.tw_hi);
+        st += 1;
+      } else {
+        dit_stages<3>(lds, st, a.m, TE, a.tw_hi);
+        st += 3;
+      }
+    } else {
+      dit_stages<2>(lds, st, a.m, TE, a.tw_hi);
+      st += 2;
     }
     __syncthreads();
   }

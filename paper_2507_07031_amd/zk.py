@@ -22,7 +22,8 @@ MAX_LOG_NTT = 24
 
 EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_srs_setup", "zk_srs_create",
            "zk_srs_destroy", "zk_srs_size", "zk_msm_srs", "zk_msm_batch", "zk_fold", "zk_profile_enable",
-           "zk_profile_read", "zk_msm_srs_workspace_bytes", "zk_ntt_workspace_bytes", "zk_release_cached_memory")
+           "zk_profile_read", "zk_msm_srs_workspace_bytes", "zk_ntt_workspace_bytes", "zk_release_cached_memory",
+           "zk_msm_srs_ex")
 
 
 class ZkError(RuntimeError):
@@ -47,6 +48,7 @@ def _load():
         "zk_srs_destroy": ([P], I),
         "zk_srs_size": ([P], U64),
         "zk_msm_srs": ([P, P, U64, P, P], I),
+        "zk_msm_srs_ex": ([P, P, U64, P, P, P], I),
         "zk_msm_batch": ([P, P, P, U32, P, P], I),
         "zk_fold": ([P, P, U32, U32, P, P], I),
         "zk_profile_enable": ([I], I),
@@ -205,6 +207,20 @@ def msm_srs(srs, scalars, n=None, out=None):
     if out is None:
         out = _torch().empty((1, 16), dtype=_torch().int32, device=scalars.device)
     _check(lib.zk_msm_srs(srs.handle, _ptr(scalars), n, _ptr(out), _stream(scalars)))
+    return out
+
+
+def msm_srs_overlap(srs, scalars, accumulate_done, n=None, out=None):
+    """msm_srs that records the torch.cuda.Event `accumulate_done` on the
+    current stream right after the bucket-accumulation kernel."""
+    scalars = _dev_words(scalars, 8, "scalars")
+    n = int(n if n is not None else scalars.shape[0])
+    if n > scalars.shape[0]:
+        raise ValueError("n exceeds the scalars")
+    if out is None:
+        out = _torch().empty((1, 16), dtype=_torch().int32, device=scalars.device)
+    ev = ctypes.c_void_p(accumulate_done.cuda_event)
+    _check(lib.zk_msm_srs_ex(srs.handle, _ptr(scalars), n, _ptr(out), _stream(scalars), ev))
     return out
 
 

@@ -38,6 +38,10 @@ void host_fq_inv(const uint32_t* a, uint32_t* out) {
   store_plain<FqP>(mont_inv<FqP>(load_mont<FqP>(a)), out);
 }
 
+// The batched binary GCD alone (no Fermat backup): returns 1 if it finished.
+int host_fq_inv_bgcd(const uint32_t* a, uint32_t* out) { return inv_bgcd32<FqP>(a, out) ? 1 : 0; }
+int host_fr_inv_bgcd(const uint32_t* a, uint32_t* out) { return inv_bgcd32<FrP>(a, out) ? 1 : 0; }
+
 void host_fr_mul(const uint32_t* a, const uint32_t* b, uint32_t* out) {
   store_plain<FrP>(mont_mul<FrP>(load_mont<FrP>(a), load_mont<FrP>(b)), out);
 }

@@ -259,12 +259,45 @@ def test_msm_edge_scalars_and_bases(zk, tau, srs_big):
         assert got == expect
 
 
+@pytest.mark.parametrize("logn", [0, 10, 16, 20])
+def test_commit_step_overlapped(zk, tau, srs_big, logn):
+    # the commit step with the coset transform on a second stream, released by
+    # the event that zk_msm_srs_ex records after bucket accumulation: the
+    # commitment and the coset evaluations must equal the serial calls and the
+    # oracle (small table below 2^15 points, SRS table above)
+    import torch
+    n = 1 << logn
+    _, h = srs_big
+    ev = _dev(zk, gen.uniform_fr(gen.CONFIG_SEEDS["commit"], n, tag=30 + logn))
+    side = torch.cuda.Stream()
+    main_s = torch.cuda.current_stream()
+    acc_done = torch.cuda.Event()
+    log("commit step overlapped", logn)
+    coeffs = zk.intt(ev)
+    com = zk.msm_srs_overlap(h, coeffs, acc_done)
+    side.wait_event(acc_done)
+    with torch.cuda.stream(side):
+        coset = zk.coset_ntt(coeffs, 2)
+    main_s.wait_stream(side)
+    com_h, coset_h = _host(zk, com), _host(zk, coset)
+    assert np.array_equal(com_h, _host(zk, zk.msm_srs(h, coeffs)))
+    assert np.array_equal(coset_h, _host(zk, zk.coset_ntt(coeffs, 2)))
+    cv = fr_from_host(_host(zk, coeffs))
+    assert points_from_host(com_h)[0] == omsm.srs_msm_closed_form(tau[1], cv)
+    Ev = fr_from_host(coset_h)
+    for j in sorted({0, 1, 4 * n - 1, (7 * n) // 3}):
+        assert Ev[j] == ontt.coset_eval_at(cv, 2, j, 5), j
+
+
 def test_msm_empty(zk, srs_big):
     import torch
     pts, h = srs_big
     s = torch.zeros((1, 8), dtype=torch.int32, device="cuda")
     assert points_from_host(_host(zk, zk.msm(pts[:1].contiguous(), s, n=0)))[0] is None
     assert points_from_host(_host(zk, zk.msm_srs(h, s, n=0)))[0] is None
+    ev = torch.cuda.Event()
+    assert points_from_host(_host(zk, zk.msm_srs_overlap(h, s, ev, n=0)))[0] is None
+    assert ev.query()
 
 
 def test_msm_batch_uneven(zk, tau, srs_big):

@@ -100,6 +100,30 @@ def test_fq_fr_mul_inv(lib):
         assert limbs_to_ints(o)[0] == ar * br % R
 
 
+def test_batched_binary_gcd_inverse(lib):
+    # the inversion on its own (its Fermat backup disabled): it must finish
+    # within its iteration bound and return x^-1 for random values and for
+    # inputs that stress the approximations (tiny values, powers of two,
+    # q minus small values, operands of nearly equal length)
+    rng = random.Random(9)
+    for q, fn in ((P, lib.host_fq_inv_bgcd), (R, lib.host_fr_inv_bgcd)):
+        cases = [1, 2, 3, q - 1, q - 2, q // 2, q // 2 + 1, (q + 1) // 3]
+        cases += [1 << k for k in range(0, 254)]
+        cases += [q - (1 << k) for k in range(0, 253)]
+        cases += [(1 << k) - 1 for k in range(1, 254)]
+        cases += [q - rng.randrange(1 << 64) for _ in range(200)]
+        cases += [rng.randrange(1 << rng.randrange(1, 254)) or 1 for _ in range(2000)]
+        cases += [rng.randrange(1, q) for _ in range(3000)]
+        for x in cases:
+            x %= q
+            if x == 0:
+                continue
+            xw, xp = _w([x])
+            o, op = _out(8)
+            assert fn(xp, op) == 1, x
+            assert limbs_to_ints(o)[0] == pow(x, -1, q), x
+
+
 def test_mont_mul_worst_case_limbs(lib):
     # all-ones limbs of 29 bits in both operands (value just under 2^261): the
     # column sums reach their maximum; the result must still be congruent
