@@ -29,7 +29,9 @@ struct MsmPlan {
   uint32_t groups;     // nseg * Wb bucket sets
   uint32_t nbins;      // groups * K
   uint32_t tab_stride;
-  uint32_t chunk;      // scalars per histogram / scatter item
+  uint32_t S;          // fine bits of the two-level sort: coarse bin = bin >> S
+  uint32_t ncoarse;    // nbins >> S
+  uint32_t chunk;      // scalars per coarse-sort item
   uint32_t nitems;     // items per window
   uint32_t L;          // sorted entries per accumulating thread
   uint32_t acc_blocks; // accumulate workgroups
@@ -47,7 +49,10 @@ uint32_t msm_default_c(uint32_t n);
 
 // Scratch buffers of one run (device pointers), carved from one allocation.
 struct MsmBuffers {
-  uint32_t* digits;    // W*n
+  uint2* pairs;        // W*n (entry, bin), sorted by coarse bin
+  uint32_t* ccounts;   // ncoarse
+  uint32_t* coff;      // ncoarse + 1
+  uint32_t* ccursor;   // ncoarse
   uint32_t* counts;    // nbins
   uint32_t* offsets;   // nbins + 1
   uint32_t* cursor;    // nbins
@@ -96,7 +101,9 @@ hipError_t gather_component(const uint32_t* inst, uint32_t m, uint32_t k, uint32
                             hipStream_t s);
 
 // Exclusive scan of n u32 values; out has n + 1 entries (out[n] = total).
-hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp, hipStream_t s);
+// copy (if not null) receives out[0..n) as well.
+hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp, hipStream_t s,
+                          uint32_t* copy = nullptr);
 size_t scan_tmp_words(uint32_t n);
 
 }  // namespace zk

@@ -131,12 +131,14 @@ __device__ void st_aff_mont(uint32_t* p, const xyzz& a) {
 }
 
 // ---------------------------------------------------------------- decompose
-__global__ void decompose_kernel(const uint32_t* __restrict__ scalars, uint32_t n, uint32_t c, uint32_t W,
-                                 uint32_t* __restrict__ digits) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// Signed c-bit digits of a canonical scalar, with the negation trick: if
+// s > (r-1)/2 the pair (s, P) becomes (r - s, -P), so s has at most 253 bits
+// and W windows hold its digits d_w in [-2^(c-1), 2^(c-1)] with no carry out.
+// f(w, |d_w|, sign) is called for every nonzero digit.
+template <class Fn>
+__device__ __forceinline__ void for_each_digit(const uint32_t* __restrict__ scalar, uint32_t c, uint32_t W, Fn f) {
   uint32_t s[8];
-  ldw(scalars + (size_t)i * 8, s, 2);
+  ldw(scalar, s, 2);
   // s > (r-1)/2 ?  (borrow of HALF - s)
   unsigned br = 0;
 #pragma unroll
@@ -164,7 +166,7 @@ __global__ void decompose_kernel(const uint32_t* __restrict__ scalars, uint32_t 
       sg = 0;
       carry = 0;
     }
-    digits[(size_t)w * n + i] = mag ? ((mag << 1) | (sg ^ neg)) : 0u;
+    if (mag) f(w, mag, sg ^ neg);
   }
 }
 
@@ -192,58 +194,139 @@ __global__ void make_items_kernel(SegArgs a, uint32_t chunk, uint32_t* __restric
   for (uint32_t g = g0; g < g1; g += chunk) items[it++] = make_uint4(b, g, min(g + chunk, g1), 0);
 }
 
-// ---------------------------------------------------------------- histogram / scatter
-// Block (item, window): counts of the item's digits in window w, in LDS over
-// the segment's K buckets, flushed to the global bucket counts.
+// ---------------------------------------------------------------- two-level counting sort
+// Entries (point index | sign << 31) are sorted by bin = bucket set base +
+// |digit| - 1.  A one-level counting sort over the K = 2^15 buckets of an
+// MSM costs about one global atomic per entry (a block of a few thousand
+// scalars touches most buckets once) and scatters 4-byte writes over the
+// whole output.  Two levels avoid both:
+//  coarse  blocks of scalars partition their digits by bin >> S (at most a
+//          few thousand coarse bins per block, each receiving runs of
+//          entries): counts, scan, scatter of (entry, bin) pairs;
+//  fine    blocks of consecutive coarse-sorted pairs see only a few hundred
+//          distinct bins, so their histograms and claimed output ranges cost
+//          one global atomic per (block, bin) with many entries each.
 __device__ __forceinline__ uint32_t bin_base(const MsmPlan& p, uint32_t seg, uint32_t w) {
   return (seg * p.Wb + (p.Wb > 1 ? w : 0u)) * p.K;
 }
 
-__global__ void __launch_bounds__(MSM_NT)
-hist_kernel(const uint32_t* __restrict__ digits, MsmPlan p, const uint4* __restrict__ items,
-            uint32_t* __restrict__ counts) {
-  extern __shared__ uint32_t h[];
-  const uint32_t w = blockIdx.y;
-  const uint4 it = items[blockIdx.x];
-  for (uint32_t b = threadIdx.x; b < p.K; b += MSM_NT) h[b] = 0;
-  __syncthreads();
-  const uint32_t* dw = digits + (size_t)w * p.n;
-  for (uint32_t e = it.y + threadIdx.x; e < it.z; e += MSM_NT) {
-    const uint32_t d = dw[e];
-    if (d) atomicAdd(&h[(d >> 1) - 1], 1u);
-  }
-  __syncthreads();
-  const uint32_t off = bin_base(p, it.x, w);
-  for (uint32_t b = threadIdx.x; b < p.K; b += MSM_NT)
-    if (h[b]) atomicAdd(&counts[off + b], h[b]);
+// Coarse bins of one item's segment: [cbase, cbase + Wb * K >> S).
+__device__ __forceinline__ uint32_t coarse_span(const MsmPlan& p) { return (p.Wb * p.K) >> p.S; }
+
+// Block's item: from the item list (several segments) or, for one segment,
+// chunk blockIdx.x of [0, n).
+__device__ __forceinline__ uint4 block_item(const MsmPlan& p, const uint4* __restrict__ items) {
+  if (items) return items[blockIdx.x];
+  const uint32_t g0 = blockIdx.x * p.chunk;
+  return make_uint4(0u, g0, min(g0 + p.chunk, p.n), 0u);
 }
 
 __global__ void __launch_bounds__(MSM_NT)
-scatter_kernel(const uint32_t* __restrict__ digits, MsmPlan p, const uint4* __restrict__ items,
-               const uint32_t* __restrict__ seg_off, uint32_t* __restrict__ cursor, uint32_t* __restrict__ entries) {
+coarse_count_kernel(const uint32_t* __restrict__ scalars, MsmPlan p, const uint4* __restrict__ items,
+                    uint32_t* __restrict__ ccounts) {
   extern __shared__ uint32_t h[];
-  const uint32_t w = blockIdx.y;
-  const uint4 it = items[blockIdx.x];
-  for (uint32_t b = threadIdx.x; b < p.K; b += MSM_NT) h[b] = 0;
+  const uint4 it = block_item(p, items);
+  const uint32_t span = coarse_span(p), cbase = bin_base(p, it.x, 0) >> p.S;
+  for (uint32_t b = threadIdx.x; b < span; b += MSM_NT) h[b] = 0;
   __syncthreads();
-  const uint32_t* dw = digits + (size_t)w * p.n;
-  for (uint32_t e = it.y + threadIdx.x; e < it.z; e += MSM_NT) {
-    const uint32_t d = dw[e];
-    if (d) atomicAdd(&h[(d >> 1) - 1], 1u);
-  }
+  for (uint32_t i = it.y + threadIdx.x; i < it.z; i += MSM_NT)
+    for_each_digit(scalars + (size_t)i * 8, p.c, p.W, [&](uint32_t w, uint32_t mag, uint32_t) {
+      atomicAdd(&h[((bin_base(p, it.x, w) + mag - 1) >> p.S) - cbase], 1u);
+    });
   __syncthreads();
-  const uint32_t off = bin_base(p, it.x, w);
-  for (uint32_t b = threadIdx.x; b < p.K; b += MSM_NT)
-    if (h[b]) h[b] = atomicAdd(&cursor[off + b], h[b]);
+  for (uint32_t b = threadIdx.x; b < span; b += MSM_NT)
+    if (h[b]) atomicAdd(&ccounts[cbase + b], h[b]);
+}
+
+__global__ void __launch_bounds__(MSM_NT)
+coarse_scatter_kernel(const uint32_t* __restrict__ scalars, MsmPlan p, const uint4* __restrict__ items,
+                      const uint32_t* __restrict__ seg_off, uint32_t* __restrict__ ccursor,
+                      uint2* __restrict__ pairs) {
+  extern __shared__ uint32_t h[];
+  const uint4 it = block_item(p, items);
+  const uint32_t span = coarse_span(p), cbase = bin_base(p, it.x, 0) >> p.S;
+  for (uint32_t b = threadIdx.x; b < span; b += MSM_NT) h[b] = 0;
+  __syncthreads();
+  for (uint32_t i = it.y + threadIdx.x; i < it.z; i += MSM_NT)
+    for_each_digit(scalars + (size_t)i * 8, p.c, p.W, [&](uint32_t w, uint32_t mag, uint32_t) {
+      atomicAdd(&h[((bin_base(p, it.x, w) + mag - 1) >> p.S) - cbase], 1u);
+    });
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < span; b += MSM_NT)
+    if (h[b]) h[b] = atomicAdd(&ccursor[cbase + b], h[b]);
   __syncthreads();
   // point index: the base itself (generic) or table row w of the segment's point
-  const uint32_t pbase = p.table ? (w * p.tab_stride - seg_off[it.x]) : 0u;
-  for (uint32_t e = it.y + threadIdx.x; e < it.z; e += MSM_NT) {
-    const uint32_t d = dw[e];
-    if (!d) continue;
-    const uint32_t b = (d >> 1) - 1;
-    const uint32_t pos = atomicAdd(&h[b], 1u);
-    entries[pos] = (pbase + e) | ((d & 1u) << 31);
+  const uint32_t s0 = items ? seg_off[it.x] : 0u;
+  for (uint32_t i = it.y + threadIdx.x; i < it.z; i += MSM_NT)
+    for_each_digit(scalars + (size_t)i * 8, p.c, p.W, [&](uint32_t w, uint32_t mag, uint32_t sg) {
+      const uint32_t bin = bin_base(p, it.x, w) + mag - 1;
+      const uint32_t pos = atomicAdd(&h[(bin >> p.S) - cbase], 1u);
+      const uint32_t pt = p.table ? w * p.tab_stride + (i - s0) : i;
+      pairs[pos] = make_uint2(pt | (sg << 31), bin);
+    });
+}
+
+// Fine level: block k takes pairs [k * FINE_CHUNK, ...) of the coarse-sorted
+// list.  Its bins lie in [lo, hi) (whole coarse bins from the first to the
+// last pair's); a range that fits in LDS is histogrammed there, a wider one
+// (sparse pairs) goes straight to global atomics.
+constexpr uint32_t FINE_CHUNK = 4096;
+constexpr uint32_t FINE_LDS_BINS = 4096;
+
+__device__ __forceinline__ bool fine_range(const uint2* pairs, uint32_t e0, uint32_t e1, uint32_t S, uint32_t& lo,
+                                           uint32_t& hi) {
+  lo = (pairs[e0].y >> S) << S;
+  hi = ((pairs[e1 - 1].y >> S) + 1) << S;
+  return hi - lo <= FINE_LDS_BINS;
+}
+
+__global__ void __launch_bounds__(MSM_NT)
+fine_count_kernel(const uint2* __restrict__ pairs, const uint32_t* __restrict__ ctotal, MsmPlan p,
+                  uint32_t* __restrict__ counts) {
+  extern __shared__ uint32_t h[];
+  const uint32_t E = *ctotal;
+  const uint32_t e0 = blockIdx.x * FINE_CHUNK;
+  if (e0 >= E) return;
+  const uint32_t e1 = min(e0 + FINE_CHUNK, E);
+  uint32_t lo, hi;
+  if (!fine_range(pairs, e0, e1, p.S, lo, hi)) {
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += MSM_NT) atomicAdd(&counts[pairs[e].y], 1u);
+    return;
+  }
+  for (uint32_t b = threadIdx.x; b < hi - lo; b += MSM_NT) h[b] = 0;
+  __syncthreads();
+  for (uint32_t e = e0 + threadIdx.x; e < e1; e += MSM_NT) atomicAdd(&h[pairs[e].y - lo], 1u);
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < hi - lo; b += MSM_NT)
+    if (h[b]) atomicAdd(&counts[lo + b], h[b]);
+}
+
+__global__ void __launch_bounds__(MSM_NT)
+fine_scatter_kernel(const uint2* __restrict__ pairs, const uint32_t* __restrict__ ctotal, MsmPlan p,
+                    uint32_t* __restrict__ cursor, uint32_t* __restrict__ entries) {
+  extern __shared__ uint32_t h[];
+  const uint32_t E = *ctotal;
+  const uint32_t e0 = blockIdx.x * FINE_CHUNK;
+  if (e0 >= E) return;
+  const uint32_t e1 = min(e0 + FINE_CHUNK, E);
+  uint32_t lo, hi;
+  if (!fine_range(pairs, e0, e1, p.S, lo, hi)) {
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += MSM_NT) {
+      const uint2 q = pairs[e];
+      entries[atomicAdd(&cursor[q.y], 1u)] = q.x;
+    }
+    return;
+  }
+  for (uint32_t b = threadIdx.x; b < hi - lo; b += MSM_NT) h[b] = 0;
+  __syncthreads();
+  for (uint32_t e = e0 + threadIdx.x; e < e1; e += MSM_NT) atomicAdd(&h[pairs[e].y - lo], 1u);
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < hi - lo; b += MSM_NT)
+    if (h[b]) h[b] = atomicAdd(&cursor[lo + b], h[b]);
+  __syncthreads();
+  for (uint32_t e = e0 + threadIdx.x; e < e1; e += MSM_NT) {
+    const uint2 q = pairs[e];
+    entries[atomicAdd(&h[q.y - lo], 1u)] = q.x;
   }
 }
 
@@ -633,14 +716,6 @@ __global__ void zero16_kernel(uint32_t* out16) {
 }
 
 // Zero fill by a kernel (graph-capture friendly, unlike a memset node).
-__global__ void fill_zero_kernel(uint32_t* p, uint32_t n) {
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
-}
-
-__global__ void copy_u32_kernel(const uint32_t* src, uint32_t* dst, uint32_t n) {
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
-}
-
 // ---------------------------------------------------------------- conversions / tables
 __global__ void to_mont_kernel(const uint32_t* __restrict__ plain, uint32_t* __restrict__ mont, uint64_t n) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -769,26 +844,9 @@ __global__ void __launch_bounds__(MSM_NT) scan_reduce_kernel(const uint32_t* in,
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-__global__ void __launch_bounds__(MSM_NT) scan_sums_kernel(uint32_t* sums, uint32_t nb) {
-  __shared__ uint32_t sm[MSM_NT];
-  // nb <= MSM_NT * SCAN_ITEMS
-  const uint32_t base = threadIdx.x * SCAN_ITEMS;
-  uint32_t v[SCAN_ITEMS], s = 0;
-  for (uint32_t q = 0; q < SCAN_ITEMS; q++) {
-    v[q] = base + q < nb ? sums[base + q] : 0;
-    s += v[q];
-  }
-  uint32_t tot;
-  uint32_t run = block_excl_scan(s, sm, &tot);
-  for (uint32_t q = 0; q < SCAN_ITEMS; q++) {
-    if (base + q < nb) sums[base + q] = run;
-    run += v[q];
-  }
-  if (threadIdx.x == 0) sums[nb] = tot;
-}
-
 __global__ void __launch_bounds__(MSM_NT)
-scan_apply_kernel(const uint32_t* in, uint32_t n, const uint32_t* sums, uint32_t nb, uint32_t* out) {
+scan_apply_kernel(const uint32_t* in, uint32_t n, const uint32_t* sums, uint32_t nb, uint32_t* out,
+                  uint32_t* copy) {
   __shared__ uint32_t sm[MSM_NT];
   const uint32_t base = blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_ITEMS;
   uint32_t v[SCAN_ITEMS], s = 0;
@@ -799,10 +857,82 @@ scan_apply_kernel(const uint32_t* in, uint32_t n, const uint32_t* sums, uint32_t
   uint32_t tot;
   uint32_t run = block_excl_scan(s, sm, &tot) + sums[blockIdx.x];
   for (uint32_t q = 0; q < SCAN_ITEMS; q++) {
-    if (base + q < n) out[base + q] = run;
+    if (base + q < n) {
+      out[base + q] = run;
+      if (copy) copy[base + q] = run;
+    }
     run += v[q];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums[nb];
+}
+
+// Whole scan in one workgroup for n <= SMALL_SCAN_MAX (each thread a run of
+// at most 4 consecutive values).
+constexpr uint32_t SMALL_SCAN_NT = 1024;
+constexpr uint32_t SMALL_SCAN_MAX = 4 * SMALL_SCAN_NT;
+__global__ void __launch_bounds__(SMALL_SCAN_NT)
+scan_small_kernel(const uint32_t* in, uint32_t n, uint32_t* out, uint32_t* copy) {
+  __shared__ uint32_t sm[SMALL_SCAN_NT];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t per = (n + SMALL_SCAN_NT - 1) / SMALL_SCAN_NT;
+  const uint32_t base = tid * per;
+  uint32_t v = 0;
+  for (uint32_t q = 0; q < per; q++)
+    if (base + q < n) v += in[base + q];
+  sm[tid] = v;
+  __syncthreads();
+  for (uint32_t d = 1; d < SMALL_SCAN_NT; d <<= 1) {
+    const uint32_t t = tid >= d ? sm[tid - d] : 0u;
+    __syncthreads();
+    sm[tid] += t;
+    __syncthreads();
+  }
+  uint32_t run = sm[tid] - v;
+  for (uint32_t q = 0; q < per; q++) {
+    if (base + q < n) {
+      const uint32_t x = in[base + q];
+      out[base + q] = run;
+      if (copy) copy[base + q] = run;
+      run += x;
+    }
+  }
+  if (tid == SMALL_SCAN_NT - 1) out[n] = sm[tid];
+}
+
+// scan_apply for nb <= SCAN_BLOCK block sums that are not yet scanned: each
+// block adds up the sums before its own (one block reduction) instead of a
+// separate launch scanning them.
+__global__ void __launch_bounds__(MSM_NT)
+scan_apply_raw_kernel(const uint32_t* in, uint32_t n, const uint32_t* sums, uint32_t nb, uint32_t* out,
+                      uint32_t* copy) {
+  __shared__ uint32_t sm[MSM_NT];
+  uint32_t pre = 0;
+  for (uint32_t k = threadIdx.x; k < blockIdx.x; k += MSM_NT) pre += sums[k];
+  uint32_t tot;
+  block_excl_scan(pre, sm, &tot);
+  pre = tot;
+  const uint32_t base = blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_ITEMS;
+  uint32_t v[SCAN_ITEMS], s = 0;
+  for (uint32_t q = 0; q < SCAN_ITEMS; q++) {
+    v[q] = base + q < n ? in[base + q] : 0;
+    s += v[q];
+  }
+  uint32_t run = block_excl_scan(s, sm, &tot) + pre;
+  for (uint32_t q = 0; q < SCAN_ITEMS; q++) {
+    if (base + q < n) {
+      out[base + q] = run;
+      if (copy) copy[base + q] = run;
+    }
+    run += v[q];
+  }
+  if (blockIdx.x == nb - 1 && threadIdx.x == MSM_NT - 1) out[n] = run;
+}
+
+// Zero two arrays in one launch.
+__global__ void fill_zero2_kernel(uint32_t* a, uint32_t na, uint32_t* b, uint32_t nb) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += stride) a[i] = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += stride) b[i] = 0;
 }
 
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -823,6 +953,20 @@ uint32_t msm_default_c(uint32_t n) {
 static void plan_common(MsmPlan& p) {
   p.groups = p.nseg * p.Wb;
   p.nbins = p.groups * p.K;
+  // coarse bins of 2^S bins each, sized for about 32768 entries per coarse
+  // bin when digits are spread evenly: a fine-level block of 4096 entries
+  // then meets one or two coarse bins (few distinct bins, long runs), while
+  // coarse-level blocks still write runs of useful length (measured best of
+  // 8192 / 32768 / 131072 at 2^20; within 3% of the best at 2^22)
+  {
+    const uint64_t ent = (uint64_t)p.n * p.W;
+    uint32_t S = 0;
+    while (S < 8 && S + 1 < p.c && (ent << (S + 1)) <= 32768ull * p.nbins) S++;
+    // a coarse-level block histograms Wb*K >> S coarse bins in LDS (<= 64 KB)
+    while (((p.Wb * p.K) >> S) > 16384u) S++;
+    p.S = S;
+  }
+  p.ncoarse = p.nbins >> p.S;
   const uint64_t entries = (uint64_t)p.n * p.W;
   // enough threads to fill the chip, at most 64 entries each
   uint64_t L = entries / (256ull * 1024);
@@ -855,7 +999,7 @@ MsmPlan msm_plan_generic(uint32_t n, uint32_t c) {
   p.nseg = 1;
   p.Wb = p.W;
   p.tab_stride = 0;
-  p.chunk = 32768;
+  p.chunk = 4096;
   p.nitems = cdiv(n, p.chunk);
   plan_common(p);
   return p;
@@ -871,7 +1015,7 @@ MsmPlan msm_plan_table(const uint64_t* off, uint32_t nmsm, uint32_t c, uint32_t 
   p.nseg = nmsm;
   p.Wb = 1;
   p.tab_stride = tab_stride;
-  p.chunk = 32768;
+  p.chunk = 4096;
   p.nitems = 0;
   for (uint32_t b = 0; b < nmsm; b++) p.nitems += cdiv(off[b + 1] - off[b], p.chunk);
   plan_common(p);
@@ -889,33 +1033,30 @@ size_t scan_tmp_words(uint32_t n) {
   return words + 64;
 }
 
-hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp, hipStream_t s) {
-  const uint32_t nb = cdiv(n, SCAN_BLOCK);
-  if (nb <= 1) {
-    // single block: sums = {0}, total written by the apply kernel from sums[1]
-    hipLaunchKernelGGL(scan_reduce_kernel, dim3(1), dim3(MSM_NT), 0, s, in, n, tmp);
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(MSM_NT), 0, s, tmp, 1u);
-    hipLaunchKernelGGL(scan_apply_kernel, dim3(1), dim3(MSM_NT), 0, s, in, n, tmp, 1u, out);
+hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp, hipStream_t s,
+                          uint32_t* copy) {
+  if (n <= SMALL_SCAN_MAX) {
+    hipLaunchKernelGGL(scan_small_kernel, dim3(1), dim3(SMALL_SCAN_NT), 0, s, in, n, out, copy);
     return hipGetLastError();
   }
+  const uint32_t nb = cdiv(n, SCAN_BLOCK);
   uint32_t* sums = tmp;                 // nb + 1
   uint32_t* scanned = tmp + nb + 1;     // nb + 1
   uint32_t* rest = scanned + nb + 1 + 32;
   hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(MSM_NT), 0, s, in, n, sums);
   hipError_t e;
   if (nb <= SCAN_BLOCK) {
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(MSM_NT), 0, s, sums, nb);
-    hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(MSM_NT), 0, s, in, n, sums, nb, out);
+    hipLaunchKernelGGL(scan_apply_raw_kernel, dim3(nb), dim3(MSM_NT), 0, s, in, n, sums, nb, out, copy);
   } else {
-    if ((e = scan_exclusive(sums, scanned, nb, rest, s))) return e;
-    hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(MSM_NT), 0, s, in, n, scanned, nb, out);
+    if ((e = scan_exclusive(sums, scanned, nb, rest, s, nullptr))) return e;
+    hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(MSM_NT), 0, s, in, n, scanned, nb, out, copy);
   }
   return hipGetLastError();
 }
 
 namespace {
 struct Layout {
-  size_t off[15];
+  size_t off[18];
   size_t total;
 };
 
@@ -929,20 +1070,23 @@ Layout layout(const MsmPlan& p) {
   const size_t ent = (size_t)p.n * p.W;
   const size_t nrec0 = 2 * (size_t)p.acc_blocks * MSM_NT;
   const size_t nrec1 = 2 * (size_t)p.acc_blocks;
-  take(0, ent * 4);                               // digits
-  take(1, (size_t)p.nbins * 4);                   // counts
-  take(2, ((size_t)p.nbins + 1) * 4);             // offsets
-  take(3, (size_t)p.nbins * 4);                   // cursor
-  take(4, scan_tmp_words(p.nbins) * 4);           // scan tmp
-  take(5, ent * 4);                               // entries
-  take(6, (size_t)p.nbins * XYZZ_WORDS * 4);      // buckets
-  take(7, nrec0 * REC_WORDS * 4);                 // records, thread level (and odd levels)
-  take(8, nrec1 * REC_WORDS * 4);                 // records, even levels
-  take(9, (size_t)p.groups * p.J * 2 * XYZZ_WORDS * 4);                // vbuf
-  take(10, (size_t)p.groups * XYZZ_WORDS * 4);                         // wsum
-  take(11, ((size_t)p.nseg + 2) * 4);                                  // seg_off
-  take(12, ((size_t)p.nitems + 1) * 16);                               // items
+  take(0, ent * 8);                                                     // pairs
+  take(1, (size_t)p.nbins * 4);                                         // counts
+  take(2, ((size_t)p.nbins + 1) * 4);                                   // offsets
+  take(3, (size_t)p.nbins * 4);                                         // cursor
+  take(4, scan_tmp_words(p.nbins) * 4);                                 // scan tmp
+  take(5, ent * 4);                                                     // entries
+  take(6, (size_t)p.nbins * XYZZ_WORDS * 4);                            // buckets
+  take(7, nrec0 * REC_WORDS * 4);                                       // records, thread level (and odd levels)
+  take(8, nrec1 * REC_WORDS * 4);                                       // records, even levels
+  take(9, (size_t)p.groups * p.J * 2 * XYZZ_WORDS * 4);                 // vbuf
+  take(10, (size_t)p.groups * XYZZ_WORDS * 4);                          // wsum
+  take(11, ((size_t)p.nseg + 2) * 4);                                   // seg_off
+  take(12, ((size_t)p.nitems + 1) * 16);                                // items
   take(13, (size_t)p.groups * (p.nbits + 1) * p.parts * XYZZ_WORDS * 4); // partial
+  take(14, (size_t)p.ncoarse * 4);                                      // ccounts
+  take(15, ((size_t)p.ncoarse + 1) * 4);                                // coff
+  take(16, (size_t)p.ncoarse * 4);                                      // ccursor
   L.total = o;
   return L;
 }
@@ -954,7 +1098,7 @@ MsmBuffers msm_carve(const MsmPlan& p, void* base) {
   const Layout L = layout(p);
   char* b = static_cast<char*>(base);
   MsmBuffers m;
-  m.digits = reinterpret_cast<uint32_t*>(b + L.off[0]);
+  m.pairs = reinterpret_cast<uint2*>(b + L.off[0]);
   m.counts = reinterpret_cast<uint32_t*>(b + L.off[1]);
   m.offsets = reinterpret_cast<uint32_t*>(b + L.off[2]);
   m.cursor = reinterpret_cast<uint32_t*>(b + L.off[3]);
@@ -968,6 +1112,9 @@ MsmBuffers msm_carve(const MsmPlan& p, void* base) {
   m.seg_off = reinterpret_cast<uint32_t*>(b + L.off[11]);
   m.items = reinterpret_cast<uint4*>(b + L.off[12]);
   m.partial = reinterpret_cast<uint32_t*>(b + L.off[13]);
+  m.ccounts = reinterpret_cast<uint32_t*>(b + L.off[14]);
+  m.coff = reinterpret_cast<uint32_t*>(b + L.off[15]);
+  m.ccursor = reinterpret_cast<uint32_t*>(b + L.off[16]);
   return m;
 }
 
@@ -977,10 +1124,12 @@ static hipError_t set_lds_limits() {
   static bool done = false;
   if (done) return hipSuccess;
   hipError_t e;
-  const int hist_lds = 32768 * 4;
-  if ((e = hipFuncSetAttribute((const void*)hist_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, hist_lds)))
+  const int fine_lds = (int)(FINE_LDS_BINS * 4);
+  if ((e = hipFuncSetAttribute((const void*)fine_count_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               fine_lds)))
     return e;
-  if ((e = hipFuncSetAttribute((const void*)scatter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, hist_lds)))
+  if ((e = hipFuncSetAttribute((const void*)fine_scatter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               fine_lds)))
     return e;
   if ((e = hipFuncSetAttribute((const void*)record_reduce_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)rec_lds_bytes())))
@@ -1027,22 +1176,30 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points
     return hipGetLastError();
   }
   const ProfToken t_sort = prof_begin("msm.sort", s);
-  if ((e = launch_items(p, off, b, s))) return e;
-  hipLaunchKernelGGL(decompose_kernel, dim3(cdiv(p.n, 256)), dim3(256), 0, s, scalars, p.n, p.c, p.W, b.digits);
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(std::min(cdiv(p.nbins, 256), 1024u)), dim3(256), 0, s, b.counts,
-                     p.nbins);
-  const size_t hlds = (size_t)p.K * 4;
+  const bool multi = p.table && p.nseg > 1;
+  if (multi && (e = launch_items(p, off, b, s))) return e;
+  const uint4* items = multi ? b.items : nullptr;
+  hipLaunchKernelGGL(fill_zero2_kernel, dim3(std::min(cdiv(p.nbins, 256), 1024u)), dim3(256), 0, s, b.counts,
+                     p.nbins, b.ccounts, p.ncoarse);
+  const size_t clds = (size_t)((p.Wb * p.K) >> p.S) * 4;
   if (p.nitems) {
-    const dim3 hgrid(p.nitems, p.W);
-    hipLaunchKernelGGL(hist_kernel, hgrid, dim3(MSM_NT), hlds, s, b.digits, p, b.items, b.counts);
+    hipLaunchKernelGGL(coarse_count_kernel, dim3(p.nitems), dim3(MSM_NT), clds, s, scalars, p, items, b.ccounts);
   }
-  if ((e = scan_exclusive(b.counts, b.offsets, p.nbins, b.scan_tmp, s))) return e;
-  hipLaunchKernelGGL(copy_u32_kernel, dim3(std::min(cdiv(p.nbins, 256), 1024u)), dim3(256), 0, s, b.offsets,
-                     b.cursor, p.nbins);
+  if ((e = scan_exclusive(b.ccounts, b.coff, p.ncoarse, b.scan_tmp, s, b.ccursor))) return e;
   if (p.nitems) {
-    const dim3 hgrid(p.nitems, p.W);
-    hipLaunchKernelGGL(scatter_kernel, hgrid, dim3(MSM_NT), hlds, s, b.digits, p, b.items, b.seg_off, b.cursor,
-                       b.entries);
+    hipLaunchKernelGGL(coarse_scatter_kernel, dim3(p.nitems), dim3(MSM_NT), clds, s, scalars, p, items,
+                       b.seg_off, b.ccursor, b.pairs);
+  }
+  const uint32_t fine_blocks = (uint32_t)cdiv((uint64_t)p.n * p.W, FINE_CHUNK);
+  const size_t flds = (size_t)FINE_LDS_BINS * 4;
+  if (fine_blocks) {
+    hipLaunchKernelGGL(fine_count_kernel, dim3(fine_blocks), dim3(MSM_NT), flds, s, b.pairs, b.coff + p.ncoarse, p,
+                       b.counts);
+  }
+  if ((e = scan_exclusive(b.counts, b.offsets, p.nbins, b.scan_tmp, s, b.cursor))) return e;
+  if (fine_blocks) {
+    hipLaunchKernelGGL(fine_scatter_kernel, dim3(fine_blocks), dim3(MSM_NT), flds, s, b.pairs, b.coff + p.ncoarse,
+                       p, b.cursor, b.entries);
   }
   prof_end(t_sort, s);
   const ProfToken t_acc = prof_begin("msm.accumulate", s);
