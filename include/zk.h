@@ -159,6 +159,10 @@ zk_status zk_release_cached_memory(void);
  * the sum of their durations and their count; reset != 0 forgets them. */
 zk_status zk_profile_enable(int on);
 zk_status zk_profile_read(const char* region, double* total_ms, uint64_t* launches, int reset);
+/* Record only the regions called `region` (NULL: every region).  Each
+ * recorded region adds two timestamp events to its stream; timing one
+ * region keeps that cost out of the others. */
+zk_status zk_profile_only(const char* region);
 
 #ifdef __cplusplus
 }

@@ -278,6 +278,8 @@ zk_status run_msm(const MsmPlan& plan, const uint64_t* offsets, const uint32_t* 
 constexpr uint32_t SRS_C = 16;                 // window bits of the main table
 constexpr uint32_t SRS_C_SMALL = 8;            // window bits of the small-MSM table
 constexpr uint32_t SRS_SMALL_MAX = 1u << 15;   // MSMs below this size use the small table
+constexpr uint32_t SRS_C_LARGE = 20;           // window bits of the large-MSM table
+constexpr uint64_t SRS_LARGE_MIN = 1ull << 21; // MSMs from this size use the large table
 
 }  // namespace
 
@@ -291,6 +293,9 @@ struct zk_srs {
   uint32_t c_small;
   uint32_t W_small;
   uint32_t* tab_small;  // W_small * n_small points for small MSMs
+  uint32_t c_large;
+  uint32_t W_large;
+  uint32_t* tab_large;  // W_large * n points for large MSMs (n >= SRS_LARGE_MIN only)
 };
 
 extern "C" {
@@ -316,6 +321,11 @@ zk_status zk_release_cached_memory(void) {
 
 zk_status zk_profile_enable(int on) {
   prof_set_enabled(on != 0);
+  return ZK_OK;
+}
+
+zk_status zk_profile_only(const char* region) {
+  prof_set_filter(region);
   return ZK_OK;
 }
 
@@ -430,17 +440,23 @@ zk_status zk_srs_create(const zk_g1* points, uint64_t n, zk_srs** srs, void* str
   h->c_small = SRS_C_SMALL;
   h->W_small = (254 + SRS_C_SMALL - 1) / SRS_C_SMALL;
   h->tab_small = nullptr;
+  h->c_large = SRS_C_LARGE;
+  h->W_large = (254 + SRS_C_LARGE - 1) / SRS_C_LARGE;
+  h->tab_large = nullptr;
   if (n) {
+    const uint32_t* pts = reinterpret_cast<const uint32_t*>(points);
     hipError_t e = hipMalloc(&h->tab, (size_t)h->W * n * 64);
     if (e == hipSuccess) e = hipMalloc(&h->tab_small, (size_t)h->W_small * h->n_small * 64);
+    if (e == hipSuccess && n >= SRS_LARGE_MIN) e = hipMalloc(&h->tab_large, (size_t)h->W_large * n * 64);
+    if (e == hipSuccess) e = msm_build_table(pts, h->tab, n, h->c, h->W, (hipStream_t)stream);
     if (e == hipSuccess)
-      e = msm_build_table(reinterpret_cast<const uint32_t*>(points), h->tab, n, h->c, h->W, (hipStream_t)stream);
-    if (e == hipSuccess)
-      e = msm_build_table(reinterpret_cast<const uint32_t*>(points), h->tab_small, h->n_small, h->c_small,
-                          h->W_small, (hipStream_t)stream);
+      e = msm_build_table(pts, h->tab_small, h->n_small, h->c_small, h->W_small, (hipStream_t)stream);
+    if (e == hipSuccess && h->tab_large)
+      e = msm_build_table(pts, h->tab_large, n, h->c_large, h->W_large, (hipStream_t)stream);
     if (e != hipSuccess) {
       if (h->tab) (void)hipFree(h->tab);
       if (h->tab_small) (void)hipFree(h->tab_small);
+      if (h->tab_large) (void)hipFree(h->tab_large);
       delete h;
       return hip_fail(e, "zk_srs_create: table build");
     }
@@ -458,6 +474,7 @@ zk_status zk_srs_destroy(zk_srs* srs) {
     (void)hipDeviceSynchronize();
     (void)hipFree(srs->tab);
     if (srs->tab_small) (void)hipFree(srs->tab_small);
+    if (srs->tab_large) (void)hipFree(srs->tab_large);
     (void)hipSetDevice(prev);
   }
   delete srs;
@@ -466,19 +483,38 @@ zk_status zk_srs_destroy(zk_srs* srs) {
 
 uint64_t zk_srs_size(const zk_srs* srs) { return srs ? srs->n : 0; }
 
-static MsmPlan srs_plan(const zk_srs* srs, uint64_t n, const uint64_t off[2]) {
-  if (n < SRS_SMALL_MAX)
-    return msm_plan_table(off, 1, SRS_C_SMALL, srs ? (uint32_t)srs->n_small : (uint32_t)n);
-  return msm_plan_table(off, 1, SRS_C, srs ? (uint32_t)srs->n : (uint32_t)n);
+// One commitment picks a pre-shifted table by size: 8-bit windows below
+// SRS_SMALL_MAX points (short reduction tail), 20-bit windows from
+// SRS_LARGE_MIN (13 windows instead of 16: fewer additions, for 16x the
+// buckets), 16-bit windows between.  Every window of the MSM shares one
+// bucket set.
+enum class SrsTable { small, main, large };
+
+static SrsTable srs_table_for(const zk_srs* srs, uint64_t n) {
+  if (n < SRS_SMALL_MAX) return SrsTable::small;
+  if (n >= SRS_LARGE_MIN && (!srs || srs->tab_large || srs->n >= SRS_LARGE_MIN)) return SrsTable::large;
+  return SrsTable::main;
 }
 
-// One commitment: the small-window table below SRS_SMALL_MAX points, the
-// main table above; either way every window keeps its own buckets.
+static MsmPlan srs_plan(const zk_srs* srs, uint64_t n, const uint64_t off[2]) {
+  const uint32_t stride = srs ? (uint32_t)srs->n : (uint32_t)n;
+  switch (srs_table_for(srs, n)) {
+    case SrsTable::small:
+      return msm_plan_table(off, 1, SRS_C_SMALL, srs ? (uint32_t)srs->n_small : (uint32_t)n);
+    case SrsTable::large:
+      return msm_plan_table(off, 1, SRS_C_LARGE, stride);
+    default:
+      return msm_plan_table(off, 1, SRS_C, stride);
+  }
+}
+
 static zk_status msm_srs_one(const zk_srs* srs, const uint32_t* scalars, uint64_t n, uint32_t* out16,
                              hipStream_t s, hipEvent_t after_accumulate = nullptr) {
   const uint64_t off[2] = {0, n};
   const MsmPlan plan = srs_plan(srs, n, off);
-  return run_msm(plan, off, n < SRS_SMALL_MAX ? srs->tab_small : srs->tab, scalars, out16, s, after_accumulate);
+  const SrsTable t = srs_table_for(srs, n);
+  const uint32_t* tab = t == SrsTable::small ? srs->tab_small : t == SrsTable::large ? srs->tab_large : srs->tab;
+  return run_msm(plan, off, tab, scalars, out16, s, after_accumulate);
 }
 
 uint64_t zk_msm_srs_workspace_bytes(const zk_srs* srs, uint64_t n) {

@@ -632,47 +632,75 @@ bit_sums_kernel(const uint32_t* __restrict__ vbuf, MsmPlan p, uint32_t* __restri
     st_xyzz(partial + ((size_t)(g * (p.nbits + 1) + i) * p.parts + part) * XYZZ_WORDS, ld_xyzz(sm));
 }
 
-// Bucket set g: U_i from the slice partials, V = U_T + sum_i 2^(log2 LB + i) U_i
-// (every slice doubled in its own thread, then a tree), and the result written
-// as canonical affine (table layout: the set is one output) or as XYZZ (the
-// generic layout's window sums, combined by Horner next).
-constexpr uint32_t FIN_SLICES = 16;  // nbits + 1 <= 16
-constexpr uint32_t FIN_NT = 256;     // 16 threads per slice
+// One tree level over slice partials: block (k, i, g) adds partials
+// 64k .. 64k+63 of slice i of set g (fewer partials per slice for the next
+// level or the finishing kernel).
+__global__ void __launch_bounds__(BITS_NT)
+partial_tree_kernel(const uint32_t* __restrict__ in, uint32_t nin, uint32_t nslices, uint32_t* __restrict__ out) {
+  __shared__ uint32_t sm[BITS_NT * XYZZ_WORDS];
+  const uint32_t k = blockIdx.x, i = blockIdx.y, g = blockIdx.z, tid = threadIdx.x;
+  const uint32_t nout = (nin + BITS_NT - 1) / BITS_NT;
+  const uint32_t src = k * BITS_NT + tid;
+  const xyzz a = src < nin ? ld_xyzz(in + ((size_t)(g * nslices + i) * nin + src) * XYZZ_WORDS) : xyzz_inf();
+  st_xyzz(sm + tid * XYZZ_WORDS, a);
+  __syncthreads();
+  for (uint32_t h = BITS_NT / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      const xyzz t = add(ld_xyzz(sm + tid * XYZZ_WORDS), ld_xyzz(sm + (tid + h) * XYZZ_WORDS));
+      st_xyzz(sm + tid * XYZZ_WORDS, t);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) st_xyzz(out + ((size_t)(g * nslices + i) * nout + k) * XYZZ_WORDS, ld_xyzz(sm));
+}
+
+// Bucket set g: U_i from the slice partials (at most 2 per thread),
+// V = U_T + sum_i 2^(log2 LB + i) U_i (every slice doubled in its own
+// thread, then a tree), and the result written as canonical affine (table
+// layout: the set is one output) or as XYZZ (the generic layout's window
+// sums, combined by Horner next).
+constexpr uint32_t FIN_SLICES = 32;  // nbits + 1 <= 32
+constexpr uint32_t FIN_NT = 256;
+// Threads per slice in the finishing kernel: FIN_NT over the slice count
+// rounded up to a power of two; each first sums up to 2 partials.
+inline uint32_t fin_tps(uint32_t nslices) {
+  uint32_t p2 = 1;
+  while (p2 < nslices) p2 <<= 1;
+  return FIN_NT / p2;
+}
 __global__ void __launch_bounds__(FIN_NT)
-bit_finish_kernel(const uint32_t* __restrict__ partial, MsmPlan p, uint32_t* __restrict__ out_affine,
-                  uint32_t* __restrict__ out_xyzz) {
+bit_finish_kernel(const uint32_t* __restrict__ partial, uint32_t nparts, uint32_t tps, MsmPlan p,
+                  uint32_t* __restrict__ out_affine, uint32_t* __restrict__ out_xyzz) {
   __shared__ uint32_t sm[FIN_NT * XYZZ_WORDS];
   const uint32_t g = blockIdx.x, tid = threadIdx.x;
-  const uint32_t i = tid / 16, q = tid % 16;
-  const uint32_t ns = p.nbits + 1;
+  const uint32_t i = tid / tps, q = tid % tps;
+  const uint32_t ns = p.nbits + 1, nsp = FIN_NT / tps;
   xyzz acc = xyzz_inf();
   if (i < ns)
-    for (uint32_t k = q; k < p.parts; k += 16)
-      acc = add(acc, ld_xyzz(partial + ((size_t)(g * ns + i) * p.parts + k) * XYZZ_WORDS));
+    for (uint32_t k = q; k < nparts; k += tps)
+      acc = add(acc, ld_xyzz(partial + ((size_t)(g * ns + i) * nparts + k) * XYZZ_WORDS));
   st_xyzz(sm + tid * XYZZ_WORDS, acc);
   __syncthreads();
-  for (uint32_t h = 8; h > 0; h >>= 1) {
+  for (uint32_t h = tps / 2; h > 0; h >>= 1) {
     if (q < h) {
       const xyzz a = add(ld_xyzz(sm + tid * XYZZ_WORDS), ld_xyzz(sm + (tid + h) * XYZZ_WORDS));
       st_xyzz(sm + tid * XYZZ_WORDS, a);
     }
     __syncthreads();
   }
-  // slice i's sum sits in slot 16 i; scale it into slot i
+  // slice i's sum sits in slot tps i; scale it into slot i
   xyzz u = xyzz_inf();
-  if (tid < FIN_SLICES) {
-    u = ld_xyzz(sm + tid * 16 * XYZZ_WORDS);
+  if (tid < ns) {
+    u = ld_xyzz(sm + tid * tps * XYZZ_WORDS);
     if (tid < p.nbits) {
       const uint32_t e = p.lgLB + tid;
       for (uint32_t k = 0; k < e; k++) u = dbl(u);
-    } else if (tid > p.nbits) {
-      u = xyzz_inf();
     }
   }
   __syncthreads();
-  if (tid < FIN_SLICES) st_xyzz(sm + tid * XYZZ_WORDS, u);
+  if (tid < nsp) st_xyzz(sm + tid * XYZZ_WORDS, u);
   __syncthreads();
-  for (uint32_t h = FIN_SLICES / 2; h > 0; h >>= 1) {
+  for (uint32_t h = nsp / 2; h > 0; h >>= 1) {
     if (tid < h) {
       const xyzz a = add(ld_xyzz(sm + tid * XYZZ_WORDS), ld_xyzz(sm + (tid + h) * XYZZ_WORDS));
       st_xyzz(sm + tid * XYZZ_WORDS, a);
@@ -977,15 +1005,16 @@ static void plan_common(MsmPlan& p) {
   if (p.acc_blocks == 0) p.acc_blocks = 1;
   // chunk length: short chains for one or a few bucket sets (latency), longer
   // ones when many sets already fill the chip (less bit-slice work)
-  uint32_t lb = (uint64_t)p.groups * p.K >= (1u << 20) ? 16 : 4;
+  uint32_t lb = (uint64_t)p.groups * p.K >= (1u << 20) ? 16 : (p.K > (1u << 15) ? 8 : 4);
   if (lb > p.K) lb = p.K;
   p.LB = lb;
   p.lgLB = 31 - __builtin_clz(lb);
   p.J = p.K / p.LB;
   p.nbits = 31 - __builtin_clz(p.J);
-  uint32_t parts = p.J / 256;
+  // slice partials: at most 4 terms per thread of a 64-thread block (the
+  // T slice has J terms, the others J / 2)
+  uint32_t parts = (p.J + 255) / 256;
   if (parts < 1) parts = 1;
-  if (parts > 64) parts = 64;
   p.parts = parts;
 }
 
@@ -1208,6 +1237,10 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points
   prof_end(t_acc, s);
   if (after_accumulate && (e = hipEventRecord(after_accumulate, s))) return e;
   if (p.nbits + 1 > FIN_SLICES) return hipErrorInvalidValue;
+  // partial-tree levels until a slice has at most 2 partials per finishing thread
+  const uint32_t tps = fin_tps(p.nbits + 1);
+  uint32_t levels = 0;
+  for (uint32_t np = p.parts; np > 2 * tps; np = (np + BITS_NT - 1) / BITS_NT) levels++;
   const ProfToken t_red = prof_begin("msm.reduce", s);
   uint32_t nrec = 2 * p.acc_blocks * MSM_NT;
   int cur = 0;
@@ -1224,10 +1257,23 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points
                      b.counts, p, b.vbuf);
   hipLaunchKernelGGL(bit_sums_kernel, dim3(p.parts, p.nbits + 1, p.groups), dim3(BITS_NT), 0, s, b.vbuf, p,
                      b.partial);
+  // tree levels ping-pong between the partial buffer and the (now free) chunk buffer
+  uint32_t* pin = b.partial;
+  uint32_t* pout = b.vbuf;
+  uint32_t np = p.parts;
+  for (uint32_t l = 0; l < levels; l++) {
+    const uint32_t nn = (np + BITS_NT - 1) / BITS_NT;
+    hipLaunchKernelGGL(partial_tree_kernel, dim3(nn, p.nbits + 1, p.groups), dim3(BITS_NT), 0, s, pin, np,
+                       p.nbits + 1, pout);
+    np = nn;
+    uint32_t* t = pin;
+    pin = pout;
+    pout = t;
+  }
   if (p.table) {
-    hipLaunchKernelGGL(bit_finish_kernel, dim3(p.groups), dim3(FIN_NT), 0, s, b.partial, p, out, nullptr);
+    hipLaunchKernelGGL(bit_finish_kernel, dim3(p.groups), dim3(FIN_NT), 0, s, pin, np, tps, p, out, nullptr);
   } else {
-    hipLaunchKernelGGL(bit_finish_kernel, dim3(p.groups), dim3(FIN_NT), 0, s, b.partial, p, nullptr, b.wsum);
+    hipLaunchKernelGGL(bit_finish_kernel, dim3(p.groups), dim3(FIN_NT), 0, s, pin, np, tps, p, nullptr, b.wsum);
     hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, s, b.wsum, p.W, p.c, out);
   }
   prof_end(t_red, s);

@@ -11,6 +11,8 @@ struct ProfToken {
 
 bool prof_enabled();
 void prof_set_enabled(bool on);
+// Record only regions called `name` (nullptr: every region).
+void prof_set_filter(const char* name);
 ProfToken prof_begin(const char* name, hipStream_t s);
 void prof_end(ProfToken t, hipStream_t s);
 // Sum of elapsed times (ms) and count of completed regions called `name`;

@@ -23,6 +23,7 @@ std::mutex g_mu;
 std::map<int, Region> g_regions;
 int g_next = 0;
 std::vector<hipEvent_t> g_pool;
+std::string g_filter;  // empty: record every region
 
 hipEvent_t take_event() {
   if (!g_pool.empty()) {
@@ -41,10 +42,16 @@ bool prof_enabled() { return g_on.load(std::memory_order_relaxed); }
 
 void prof_set_enabled(bool on) { g_on.store(on); }
 
+void prof_set_filter(const char* name) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_filter = name ? name : "";
+}
+
 ProfToken prof_begin(const char* name, hipStream_t s) {
   ProfToken t;
   if (!prof_enabled()) return t;
   std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_filter.empty() && g_filter != name) return t;
   Region r;
   r.name = name;
   r.a = take_event();

@@ -210,6 +210,17 @@ def test_msm_large_commit_workload(zk, tau, srs_big):
     assert got == omsm.srs_msm_closed_form(tau[1], fr_from_host(s))
 
 
+@pytest.mark.parametrize("n", [(1 << 21) + 12345, 1 << 22])
+def test_msm_large_window_table(zk, tau, srs_big, n):
+    # from 2^21 points the commitment runs on the 20-bit-window table
+    # (13 windows, 2^19 shared buckets): uniform scalars, ragged and full size
+    s = gen.uniform_fr(gen.CONFIG_SEEDS["commit"], n, tag=11)
+    _, h = srs_big
+    log("msm large-window table", n)
+    got = points_from_host(_host(zk, zk.msm_srs(h, _dev(zk, s))))[0]
+    assert got == omsm.srs_msm_closed_form(tau[1], fr_from_host(s))
+
+
 def test_msm_quantized_full_size(zk, tau, srs_big):
     n = 1 << 22
     q = gen.quantized_fr(gen.CONFIG_SEEDS["quantized"], n)
