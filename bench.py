@@ -210,20 +210,10 @@ def main():
     com = torch.empty((1, 16), dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
 
-    # the MSM and the coset evaluation both consume the coefficients: the
-    # coset transform runs on a second stream, started when the MSM's
-    # bucket accumulation is done, beside the MSM's latency-bound reduction
-    side = torch.cuda.Stream(device=dev)
-    main_s = torch.cuda.current_stream(dev)
-    acc_done = torch.cuda.Event()
-
+    # one commit job per step: the library runs the coset transform on a
+    # companion stream beside the MSM's latency-bound reduction
     def step():
-        zk.intt(evals, out=coeffs)
-        zk.msm_srs_overlap(srs, coeffs, acc_done, out=com)
-        side.wait_event(acc_done)
-        with torch.cuda.stream(side):
-            zk.coset_ntt(coeffs, 2, out=coset)
-        main_s.wait_stream(side)
+        zk.commit_job(srs, evals, log_blowup=2, coeffs=coeffs, com=com, coset=coset)
 
     log("warmup", args.warmup)
     for _ in range(args.warmup):

@@ -116,6 +116,20 @@ uint64_t zk_srs_size(const zk_srs* srs);
  * the first n points of the prepared SRS (n <= zk_srs_size(srs)). */
 zk_status zk_msm_srs(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream);
 
+/* One commit job on a witness vector (Polynomial Commitment preliminaries;
+ * the vector is its polynomial's evaluations on H, Sec. 4.4.1):
+ *   coeffs     = iNTT(evals)                       (2^log_n elements)
+ *   commitment = sum_i coeffs_i [tau^i]_1          (2^log_n <= zk_srs_size)
+ *   coset      = f(g omega_(2^(log_n+log_blowup))^j), j < 2^(log_n+log_blowup),
+ * as zk_intt, zk_msm_srs and zk_coset_ntt would give (shift_host NULL: g = 5).
+ * The library overlaps the parts on a companion stream of `stream`: the
+ * coset transform runs there beside the MSM's latency-bound reduction (it
+ * starts once the bucket accumulation is enqueued).  All results are ordered
+ * on `stream` when the call's work there completes.  evals and coeffs may alias; the other
+ * buffers must not overlap. */
+zk_status zk_commit_job(const zk_srs* srs, const zk_fr* evals, uint32_t log_n, uint32_t log_blowup,
+                        const zk_fr* shift_host, zk_fr* coeffs, zk_g1* commitment, zk_fr* coset, void* stream);
+
 /* zk_msm_srs that also records `accumulate_done_event` (a hipEvent_t, may be
  * NULL) on `stream` as soon as its bucket-accumulation kernel is enqueued.
  * What follows on the stream is a latency-bound reduction that leaves most

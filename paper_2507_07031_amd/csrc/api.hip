@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -200,14 +201,23 @@ zk_status scratch_alloc(Scratch& sc, size_t bytes, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- NTT driver
-zk_status run_ntt(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t L, bool inverse, const f29* pre_lo,
-                  const f29* pre_hi, uint32_t valid_n, hipStream_t s) {
+// A transform of 2^L points: one LDS pass up to the tile size, else two
+// four-step passes through a scratch buffer.  Prepared first, then launched
+// pass by pass, so a caller can interleave the passes with other work.
+struct NttRun {
+  NttPass a{}, b{};
+  bool two = false;
+  Scratch tmp;  // intermediate of the two-pass form
+};
+
+zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t L, bool inverse, const f29* pre_lo,
+                      const f29* pre_hi, uint32_t valid_n, hipStream_t s, NttRun& r) {
   const uint32_t T = ntt_tile_log();
   const f29* lo = inverse ? c->tw[2] : c->tw[0];
   const f29* hi = inverse ? c->tw[3] : c->tw[1];
   const f29* scale = inverse ? c->ninv + L : nullptr;
   if (L <= T) {
-    NttPass p{};
+    NttPass& p = r.a;
     p.in = in;
     p.out = out;
     p.m = L;
@@ -222,16 +232,15 @@ zk_status run_ntt(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t L, b
     p.pre_lo = pre_lo;
     p.pre_hi = pre_hi;
     p.post_scale = scale;
-    ZK_HIP(ntt_launch_pass(p, s), "ntt pass");
+    r.two = false;
     return ZK_OK;
   }
   const uint32_t mA = L / 2, mB = L - mA;  // pass A transforms have 2^mA points
   const uint32_t N1 = 1u << mB, N2 = 1u << mA;
-  Scratch tmp;
-  zk_status st = scratch_alloc(tmp, (size_t)32 << L, s);
+  zk_status st = scratch_alloc(r.tmp, (size_t)32 << L, s);
   if (st) return st;
-  uint32_t* Y = static_cast<uint32_t*>(tmp.p);
-  NttPass a{};
+  uint32_t* Y = static_cast<uint32_t*>(r.tmp.p);
+  NttPass& a = r.a;
   a.in = in;
   a.out = Y;
   a.m = mA;
@@ -246,8 +255,7 @@ zk_status run_ntt(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t L, b
   a.post_tw_L = L;
   a.pre_lo = pre_lo;
   a.pre_hi = pre_hi;
-  ZK_HIP(ntt_launch_pass(a, s), "ntt pass A");
-  NttPass b{};
+  NttPass& b = r.b;
   b.in = Y;
   b.out = out;
   b.m = mB;
@@ -260,18 +268,84 @@ zk_status run_ntt(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t L, b
   b.tw_lo = lo;
   b.tw_hi = hi;
   b.post_scale = scale;
-  ZK_HIP(ntt_launch_pass(b, s), "ntt pass B");
+  r.two = true;
   return ZK_OK;
+}
+
+zk_status ntt_first(NttRun& r, hipStream_t s) {
+  ZK_HIP(ntt_launch_pass(r.a, s), "ntt pass");
+  return ZK_OK;
+}
+
+zk_status ntt_second(NttRun& r, hipStream_t s) {
+  if (r.two) ZK_HIP(ntt_launch_pass(r.b, s), "ntt pass B");
+  return ZK_OK;
+}
+
+zk_status run_ntt(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t L, bool inverse, const f29* pre_lo,
+                  const f29* pre_hi, uint32_t valid_n, hipStream_t s) {
+  NttRun r;
+  zk_status st = ntt_prepare(c, in, out, L, inverse, pre_lo, pre_hi, valid_n, s, r);
+  if (!st) st = ntt_first(r, s);
+  if (!st) st = ntt_second(r, s);
+  return st;
 }
 
 // ---------------------------------------------------------------- MSM driver
 zk_status run_msm(const MsmPlan& plan, const uint64_t* offsets, const uint32_t* mont_points, const uint32_t* scalars,
-                  uint32_t* out, hipStream_t s, hipEvent_t after_accumulate = nullptr) {
+                  uint32_t* out, hipStream_t s, hipEvent_t after_accumulate = nullptr,
+                  hipEvent_t before_accumulate = nullptr) {
   Scratch ws;
   zk_status st = scratch_alloc(ws, msm_workspace_bytes(plan), s);
   if (st) return st;
   const MsmBuffers b = msm_carve(plan, ws.p);
-  ZK_HIP(msm_run(plan, offsets, mont_points, scalars, b, out, s, after_accumulate), "msm");
+  ZK_HIP(msm_run(plan, offsets, mont_points, scalars, b, out, s, after_accumulate, before_accumulate), "msm");
+  return ZK_OK;
+}
+
+// Companion stream of a caller stream (one each, default priority), for work
+// the library overlaps with the caller's; and a pool of sync-only events.
+std::mutex g_side_mu;
+std::map<std::pair<int, hipStream_t>, hipStream_t> g_side;
+std::vector<hipEvent_t> g_sync_events;
+
+zk_status side_stream(hipStream_t caller, hipStream_t* out) {
+  int dev = 0;
+  ZK_HIP(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  auto it = g_side.find({dev, caller});
+  if (it != g_side.end()) {
+    *out = it->second;
+    return ZK_OK;
+  }
+  hipStream_t s2 = nullptr;
+  ZK_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+  g_side[{dev, caller}] = s2;
+  *out = s2;
+  return ZK_OK;
+}
+
+struct SyncEvents {
+  hipEvent_t e[2] = {nullptr, nullptr};
+  ~SyncEvents() {
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    for (hipEvent_t x : e)
+      if (x) g_sync_events.push_back(x);
+  }
+};
+
+zk_status sync_events(SyncEvents& ev) {
+  for (hipEvent_t& x : ev.e) {
+    {
+      std::lock_guard<std::mutex> lk(g_side_mu);
+      if (!g_sync_events.empty()) {
+        x = g_sync_events.back();
+        g_sync_events.pop_back();
+        continue;
+      }
+    }
+    ZK_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming), "hipEventCreateWithFlags");
+  }
   return ZK_OK;
 }
 
@@ -509,12 +583,13 @@ static MsmPlan srs_plan(const zk_srs* srs, uint64_t n, const uint64_t off[2]) {
 }
 
 static zk_status msm_srs_one(const zk_srs* srs, const uint32_t* scalars, uint64_t n, uint32_t* out16,
-                             hipStream_t s, hipEvent_t after_accumulate = nullptr) {
+                             hipStream_t s, hipEvent_t after_accumulate = nullptr,
+                             hipEvent_t before_accumulate = nullptr) {
   const uint64_t off[2] = {0, n};
   const MsmPlan plan = srs_plan(srs, n, off);
   const SrsTable t = srs_table_for(srs, n);
   const uint32_t* tab = t == SrsTable::small ? srs->tab_small : t == SrsTable::large ? srs->tab_large : srs->tab;
-  return run_msm(plan, off, tab, scalars, out16, s, after_accumulate);
+  return run_msm(plan, off, tab, scalars, out16, s, after_accumulate, before_accumulate);
 }
 
 uint64_t zk_msm_srs_workspace_bytes(const zk_srs* srs, uint64_t n) {
@@ -526,6 +601,63 @@ uint64_t zk_msm_srs_workspace_bytes(const zk_srs* srs, uint64_t n) {
 uint64_t zk_ntt_workspace_bytes(uint32_t log_n) {
   if (log_n > ZK_MAX_LOG_NTT) return 0;
   return log_n <= ntt_tile_log() ? 0 : ((uint64_t)32 << log_n);
+}
+
+zk_status zk_commit_job(const zk_srs* srs, const zk_fr* evals, uint32_t log_n, uint32_t log_blowup,
+                        const zk_fr* shift_host, zk_fr* coeffs, zk_g1* commitment, zk_fr* coset, void* stream) {
+  if (!srs || !evals || !coeffs || !commitment || !coset) return fail(ZK_EINVAL, "zk_commit_job: NULL argument");
+  if (log_n > ZK_MAX_LOG_NTT || log_blowup > ZK_MAX_LOG_NTT || log_n + log_blowup > ZK_MAX_LOG_NTT)
+    return fail(ZK_EUNSUPPORTED, "zk_commit_job: log_n + log_blowup > ZK_MAX_LOG_NTT");
+  const uint64_t n = 1ull << log_n;
+  if (n > srs->n) return fail(ZK_EINVAL, "zk_commit_job: 2^log_n exceeds the SRS size");
+  uint32_t sw[8];
+  if (shift_host) {
+    std::memcpy(sw, shift_host->v, 32);
+    unsigned br = 0;
+    for (int i = 0; i < 8; i++) (void)__builtin_subc(sw[i], FrP::M32[i], br, &br);
+    if (!br) return fail(ZK_EINVAL, "zk_commit_job: shift not canonical (>= r)");
+  }
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  const hipStream_t s = (hipStream_t)stream;
+  hipStream_t side = nullptr;
+  if ((st = side_stream(s, &side))) return st;
+  SyncEvents ev;
+  if ((st = sync_events(ev))) return st;
+  uint32_t* cf = reinterpret_cast<uint32_t*>(coeffs);
+  // coefficients on the caller's stream
+  if ((st = run_ntt(c, reinterpret_cast<const uint32_t*>(evals), cf, log_n, true, nullptr, nullptr, (uint32_t)n, s)))
+    return st;
+  // the commitment; the coset transform starts on the companion stream once
+  // the accumulation kernel is enqueued, so it fills the compute units the
+  // latency-bound reduction leaves idle (measured: running its first pass
+  // beside the sort instead slowed the sort more than it hid)
+  if ((st = msm_srs_one(srs, cf, n, reinterpret_cast<uint32_t*>(commitment), s, ev.e[0]))) return st;
+  ZK_HIP(hipStreamWaitEvent(side, ev.e[0], 0), "hipStreamWaitEvent");
+  const f29* lo = c->coset5[0];
+  const f29* hi = c->coset5[1];
+  Scratch tab;
+  if (shift_host) {
+    const size_t tsz = sizeof(f29) << 14;
+    if ((st = scratch_alloc(tab, 2 * tsz, side))) return st;
+    char* base = static_cast<char*>(tab.p);
+    Words8 w8;
+    std::memcpy(w8.w, sw, 32);
+    ZK_HIP(ntt_make_pow_tables(w8, reinterpret_cast<f29*>(base), reinterpret_cast<f29*>(base + tsz), side),
+           "shift tables");
+    lo = reinterpret_cast<const f29*>(base);
+    hi = reinterpret_cast<const f29*>(base + tsz);
+  }
+  NttRun r;
+  if ((st = ntt_prepare(c, cf, reinterpret_cast<uint32_t*>(coset), log_n + log_blowup, false, lo, hi, (uint32_t)n,
+                        side, r)))
+    return st;
+  if ((st = ntt_first(r, side))) return st;
+  if ((st = ntt_second(r, side))) return st;
+  ZK_HIP(hipEventRecord(ev.e[1], side), "hipEventRecord");
+  ZK_HIP(hipStreamWaitEvent(s, ev.e[1], 0), "hipStreamWaitEvent");
+  return ZK_OK;
 }
 
 zk_status zk_msm_srs_ex(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream,

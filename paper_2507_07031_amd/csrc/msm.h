@@ -76,9 +76,12 @@ MsmBuffers msm_carve(const MsmPlan& p, void* base);
 // or nullptr (generic).  out: 16 words per output (nseg), canonical affine.
 // after_accumulate: if not null, recorded on s right after the accumulation
 // kernel (the rest of the run is latency-bound reduction; work that waits on
-// this event can fill the idle compute units).
+// this event can fill the idle compute units).  before_accumulate: if not
+// null, s waits for it before the accumulation kernel (work overlapped with
+// the sort then does not compete with the accumulation).
 hipError_t msm_run(const MsmPlan& p, const uint64_t* offsets, const uint32_t* points, const uint32_t* scalars,
-                   const MsmBuffers& b, uint32_t* out, hipStream_t s, hipEvent_t after_accumulate = nullptr);
+                   const MsmBuffers& b, uint32_t* out, hipStream_t s, hipEvent_t after_accumulate = nullptr,
+                   hipEvent_t before_accumulate = nullptr);
 
 // Canonical plain affine points -> Montgomery-form affine points (count n).
 hipError_t msm_points_to_mont(const uint32_t* plain, uint32_t* mont, uint64_t n, hipStream_t s);

@@ -1195,12 +1195,14 @@ static hipError_t launch_items(const MsmPlan& p, const uint64_t* off, const MsmB
 }
 
 hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points, const uint32_t* scalars,
-                   const MsmBuffers& b, uint32_t* out, hipStream_t s, hipEvent_t after_accumulate) {
+                   const MsmBuffers& b, uint32_t* out, hipStream_t s, hipEvent_t after_accumulate,
+                   hipEvent_t before_accumulate) {
   hipError_t e;
   if ((e = set_lds_limits())) return e;
   const uint32_t nout = p.nseg;
   if (p.n == 0) {
     for (uint32_t i = 0; i < nout; i++) hipLaunchKernelGGL(zero16_kernel, dim3(1), dim3(64), 0, s, out + 16 * i);
+    if (before_accumulate && (e = hipStreamWaitEvent(s, before_accumulate, 0))) return e;
     if (after_accumulate && (e = hipEventRecord(after_accumulate, s))) return e;
     return hipGetLastError();
   }
@@ -1231,6 +1233,7 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points
                        p, b.cursor, b.entries);
   }
   prof_end(t_sort, s);
+  if (before_accumulate && (e = hipStreamWaitEvent(s, before_accumulate, 0))) return e;
   const ProfToken t_acc = prof_begin("msm.accumulate", s);
   hipLaunchKernelGGL(accumulate_kernel, dim3(p.acc_blocks), dim3(MSM_NT), 0, s, b.entries, b.offsets, p.nbins,
                      points, p.L, b.buckets, b.rec[0]);

@@ -12,7 +12,9 @@ SRS) and the 4x coset evaluation that the quotient by X^N - 1 needs.
   whose footprint exceeds the whole budget is rejected.
 * `GpuExecutor` runs each admitted job on its own HIP stream (all at the
   default priority), so jobs admitted while others are on the GPU overlap
-  with them; completion is detected by polling an event per job.
+  with them; completion is detected by polling an event per job.  A job is
+  one `zk_commit_job` call (the library overlaps its coset transform with
+  the MSM's reduction on a companion stream of the slot's stream).
 * `serve` drives a timed arrival stream through both and records per-job
   arrival, start and finish times (host clock).
 
@@ -111,9 +113,7 @@ class GpuExecutor:
             if job.n < N:
                 ev = torch.cat([self.pool[job.offset:job.offset + job.n],
                                 torch.zeros((N - job.n, 8), dtype=torch.int32, device=ev.device)])
-            coeffs = zk.intt(ev)
-            com = zk.msm_srs(self.srs, coeffs)
-            coset = zk.coset_ntt(coeffs, 2)
+            coeffs, com, coset = zk.commit_job(self.srs, ev, log_blowup=2)
             done = torch.cuda.Event(enable_timing=self.timing)
             done.record(s)
         job.handle = (slot, done, com, coset, coeffs, ev)

@@ -23,7 +23,7 @@ MAX_LOG_NTT = 24
 EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_srs_setup", "zk_srs_create",
            "zk_srs_destroy", "zk_srs_size", "zk_msm_srs", "zk_msm_batch", "zk_fold", "zk_profile_enable",
            "zk_profile_read", "zk_msm_srs_workspace_bytes", "zk_ntt_workspace_bytes", "zk_release_cached_memory",
-           "zk_msm_srs_ex", "zk_profile_only")
+           "zk_msm_srs_ex", "zk_profile_only", "zk_commit_job")
 
 
 class ZkError(RuntimeError):
@@ -50,6 +50,7 @@ def _load():
         "zk_msm_srs": ([P, P, U64, P, P], I),
         "zk_msm_srs_ex": ([P, P, U64, P, P, P], I),
         "zk_profile_only": ([ctypes.c_char_p], I),
+        "zk_commit_job": ([P, P, I, I, P, P, P, P, P], I),
         "zk_msm_batch": ([P, P, P, U32, P, P], I),
         "zk_fold": ([P, P, U32, U32, P, P], I),
         "zk_profile_enable": ([I], I),
@@ -156,6 +157,29 @@ def coset_ntt(coeffs, log_blowup, shift=None, out=None):
 
 
 # ---------------------------------------------------------------- commitments
+
+def commit_job(srs, evals, log_blowup=2, shift=None, coeffs=None, com=None, coset=None):
+    """iNTT -> commitment against the SRS -> coset evaluations, overlapped by
+    the library.  Returns (coeffs, com, coset)."""
+    evals = _dev_words(evals, 8, "evals")
+    n = evals.shape[0]
+    L = n.bit_length() - 1
+    if (1 << L) != n:
+        raise ValueError("length must be a power of two")
+    torch = _torch()
+    if coeffs is None:
+        coeffs = torch.empty_like(evals)
+    if com is None:
+        com = torch.empty((1, 16), dtype=torch.int32, device=evals.device)
+    if coset is None:
+        coset = torch.empty((n << log_blowup, 8), dtype=torch.int32, device=evals.device)
+    sp = None
+    if shift is not None:
+        sa, sp = _host_fr(shift)
+    _check(lib.zk_commit_job(srs.handle, _ptr(evals), L, int(log_blowup), sp, _ptr(coeffs), _ptr(com), _ptr(coset),
+                             _stream(evals)))
+    return coeffs, com, coset
+
 
 def msm(bases, scalars, n=None, out=None):
     bases = _dev_words(bases, 16, "bases")

@@ -48,6 +48,10 @@ def test_argument_errors_return_before_device_work(zk):
     assert L.zk_msm_batch(null, dummy, dummy, 1, dummy, null) == zk.ZK_EINVAL
     assert L.zk_fold(dummy, null, 3, 1, dummy, null) == zk.ZK_EINVAL
     assert L.zk_fold(dummy, dummy, 0, 1, dummy, null) == zk.ZK_EINVAL
+    assert L.zk_msm_srs_ex(null, dummy, 4, dummy, null, null) == zk.ZK_EINVAL
+    assert L.zk_commit_job(null, dummy, 4, 2, null, dummy, dummy, dummy, null) == zk.ZK_EINVAL
+    assert L.zk_commit_job(dummy, dummy, 4, 2, null, dummy, null, dummy, null) == zk.ZK_EINVAL
+    assert L.zk_commit_job(dummy, dummy, 20, 5, null, dummy, dummy, dummy, null) == zk.ZK_EUNSUPPORTED
     assert L.zk_srs_size(null) == 0
     assert L.zk_srs_destroy(null) == zk.ZK_OK
     # tau >= r is rejected

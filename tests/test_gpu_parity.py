@@ -300,6 +300,39 @@ def test_commit_step_overlapped(zk, tau, srs_big, logn):
         assert Ev[j] == ontt.coset_eval_at(cv, 2, j, 5), j
 
 
+@pytest.mark.parametrize("logn,logb,custom", [(0, 2, False), (3, 0, False), (12, 2, False), (13, 2, True),
+                                               (16, 2, False), (20, 2, False)])
+def test_commit_job(zk, tau, srs_big, logn, logb, custom):
+    # the fused commit job (iNTT, commitment, coset evaluations overlapped on
+    # a companion stream) equals the three separate calls and the oracle
+    n = 1 << logn
+    _, h = srs_big
+    ev = _dev(zk, gen.uniform_fr(gen.CONFIG_SEEDS["commit"], n, tag=50 + logn))
+    shift = None
+    g = 5
+    if custom:
+        g = 7
+        shift = np.zeros(8, dtype=np.uint32)
+        shift[0] = g
+    log("commit job", logn, logb, custom)
+    coeffs, com, coset = zk.commit_job(h, ev, log_blowup=logb, shift=shift)
+    cf_ref = zk.intt(ev)
+    com_h, cos_h, cf_h = _host(zk, com), _host(zk, coset), _host(zk, coeffs)
+    assert np.array_equal(cf_h, _host(zk, cf_ref))
+    assert np.array_equal(com_h, _host(zk, zk.msm_srs(h, cf_ref)))
+    assert np.array_equal(cos_h, _host(zk, zk.coset_ntt(cf_ref, logb, shift=shift)))
+    cv = fr_from_host(cf_h)
+    assert points_from_host(com_h)[0] == omsm.srs_msm_closed_form(tau[1], cv)
+    Ev = fr_from_host(cos_h)
+    m = n << logb
+    for j in sorted({0, 1, m - 1, (7 * m) // 3 % m}):
+        assert Ev[j] == ontt.coset_eval_at(cv, logb, j, g), j
+    # in-place: evals and coeffs alias
+    ev2 = ev.clone()
+    zk.commit_job(h, ev2, log_blowup=logb, shift=shift, coeffs=ev2)
+    assert np.array_equal(_host(zk, ev2), cf_h)
+
+
 def test_msm_empty(zk, srs_big):
     import torch
     pts, h = srs_big
