@@ -237,6 +237,8 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   }
   const uint32_t mA = L / 2, mB = L - mA;  // pass A transforms have 2^mA points
   const uint32_t N1 = 1u << mB, N2 = 1u << mA;
+  // tiles of 2048 points where both passes fit (two workgroups per CU), else 4096
+  const uint32_t tile = mB <= T - 1 ? (1u << (T - 1)) : (1u << T);
   zk_status st = scratch_alloc(r.tmp, (size_t)32 << L, s);
   if (st) return st;
   uint32_t* Y = static_cast<uint32_t*>(r.tmp.p);
@@ -245,7 +247,7 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   a.out = Y;
   a.m = mA;
   a.nbatch = N1;
-  a.G = std::min((1u << T) / N2, N1);
+  a.G = std::min(tile / N2, N1);
   a.s_in = N1;
   a.s_out = 1;
   a.b_out = N2;
@@ -260,7 +262,7 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   b.out = out;
   b.m = mB;
   b.nbatch = N2;
-  b.G = std::min((1u << T) / N1, N2);
+  b.G = std::min(tile / N1, N2);
   b.s_in = N2;
   b.s_out = N2;
   b.b_out = 1;

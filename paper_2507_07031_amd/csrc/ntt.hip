@@ -30,8 +30,8 @@ namespace zk {
 namespace {
 
 constexpr uint32_t TILE_LOG = 12;
-constexpr uint32_t TILE = 1u << TILE_LOG;    // elements per workgroup
-constexpr uint32_t NTT_THREADS = 512;
+constexpr uint32_t TILE = 1u << TILE_LOG;    // elements per workgroup, at most
+constexpr uint32_t NTT_THREADS = 512;        // threads per workgroup, at most (one 8-point unit each)
 
 __device__ __forceinline__ void ld8(const uint32_t* p, uint32_t w[8]) {
   const uint4 a = reinterpret_cast<const uint4*>(p)[0];
@@ -47,12 +47,51 @@ __device__ __forceinline__ void st8(uint32_t* p, const uint32_t w[8]) {
 
 __device__ __forceinline__ f29 ldf29(const f29* t, uint32_t i) { return t[i]; }
 
+// LDS slot of tile point e: one 32-byte pad after every 8 points.  Units of
+// the first stages read points 8 (or 64) apart; unpadded, those 256-byte
+// strides put the lanes of an access on the same banks.
+__device__ __forceinline__ uint32_t* lds_at(uint32_t* lds, uint32_t e) { return lds + (e + (e >> 3)) * 8; }
+
 // omega^(e) of the 2^28-th root for e < 2^28, from the split tables.
 __device__ __forceinline__ f29 pow28(const f29* lo, const f29* hi, uint32_t E) {
   const uint32_t a = E & 0x3fffu, b = E >> 14;
   if (b == 0) return ldf29(lo, a);
   if (a == 0) return ldf29(hi, b);
   return mont_mul<FrP>(ldf29(lo, a), ldf29(hi, b));
+}
+
+// Inside a tile values are kept in [0, 2q) (2q < 2^255), not canonical: a
+// twiddle product of such a value is < 2q without a final correction, and a
+// sum or difference needs one conditional correction by 2q.  The store makes
+// every value canonical.
+__device__ __forceinline__ uint32_t q2_word(int i) {
+  return (FrP::M32[i] << 1) | (i ? FrP::M32[i - 1] >> 31 : 0u);
+}
+
+__device__ __forceinline__ void add_2q(const uint32_t a[8], const uint32_t b[8], uint32_t r[8]) {
+  uint32_t sum[8], d[8];
+  unsigned c = 0, br = 0;
+#pragma unroll
+  for (int i = 0; i < 8; i++) sum[i] = __builtin_addc(a[i], b[i], c, &c);
+#pragma unroll
+  for (int i = 0; i < 8; i++) d[i] = __builtin_subc(sum[i], q2_word(i), br, &br);
+#pragma unroll
+  for (int i = 0; i < 8; i++) r[i] = br ? sum[i] : d[i];
+}
+
+__device__ __forceinline__ void sub_2q(const uint32_t a[8], const uint32_t b[8], uint32_t r[8]) {
+  uint32_t d[8];
+  unsigned br = 0, c = 0;
+#pragma unroll
+  for (int i = 0; i < 8; i++) d[i] = __builtin_subc(a[i], b[i], br, &br);
+  const uint32_t mask = 0u - br;
+#pragma unroll
+  for (int i = 0; i < 8; i++) r[i] = __builtin_addc(d[i], q2_word(i) & mask, c, &c);
+}
+
+// a * w (w a Montgomery-form twiddle) for a < 2q: < a q / 2^261 + q < 2q.
+__device__ __forceinline__ void mul_tw_2q(const uint32_t a[8], const f29& w, uint32_t r[8]) {
+  pack(mont_mul<FrP>(unpack(a), w), r);
 }
 
 // One butterfly of stage s+T on registers x[q], x[q + 2^T] of a unit (q with
@@ -71,10 +110,10 @@ __device__ __forceinline__ void dit_butterflies(uint32_t (&x)[Q][8], uint32_t s,
   } else {
     // omega_(2^(s+T))^jt = omega_(2^28)^(jt * 2^(28-s-T)): a "hi" table entry
     const uint32_t jt = j + qlow * h;
-    mul_plain_by_mont<FrP>(x[r], ldf29(tw_hi, jt << (14 - s - T)), tv);
+    mul_tw_2q(x[r], ldf29(tw_hi, jt << (14 - s - T)), tv);
   }
-  add_mod32<FrP>(x[q], tv, x[r]);
-  sub_mod32<FrP>(x[q], tv, tv);
+  add_2q(x[q], tv, x[r]);
+  sub_2q(x[q], tv, tv);
 #pragma unroll
   for (int w = 0; w < 8; w++) {
     const uint32_t sum = x[r][w];
@@ -101,16 +140,16 @@ __device__ __forceinline__ void dit_stages(uint32_t* lds, uint32_t s, uint32_t m
   constexpr int Q = 1 << R;
   const uint32_t h = 1u << (s - 1);
   const uint32_t units_per_tr = 1u << (m - R);
-  for (uint32_t u = threadIdx.x; u < TE / Q; u += NTT_THREADS) {
+  for (uint32_t u = threadIdx.x; u < TE / Q; u += blockDim.x) {
     const uint32_t b = u >> (m - R), ul = u & (units_per_tr - 1);
     const uint32_t j = ul & (h - 1), grp = ul >> (s - 1);
     const uint32_t base = (b << m) + (grp << (s + R - 1)) + j;
     uint32_t x[Q][8];
 #pragma unroll
-    for (int q = 0; q < Q; q++) ld8(lds + (base + q * h) * 8, x[q]);
+    for (int q = 0; q < Q; q++) ld8(lds_at(lds, base + q * h), x[q]);
     dit_levels<Q, 0, R>(x, s, j, h, tw_hi);
 #pragma unroll
-    for (int q = 0; q < Q; q++) st8(lds + (base + q * h) * 8, x[q]);
+    for (int q = 0; q < Q; q++) st8(lds_at(lds, base + q * h), x[q]);
   }
 }
 
@@ -124,7 +163,7 @@ ntt_pass_kernel(NttPass a) {
   const uint32_t tid = threadIdx.x;
 
   // ---- load (bit-reversed into LDS), coset pre-scale, zero padding
-  for (uint32_t e = tid; e < TE; e += NTT_THREADS) {
+  for (uint32_t e = tid; e < TE; e += blockDim.x) {
     const uint32_t b = e % G, i = e / G;
     const uint32_t gi = (g0 + b) + i * a.s_in;
     uint32_t w[8];
@@ -139,7 +178,7 @@ ntt_pass_kernel(NttPass a) {
       for (int q = 0; q < 8; q++) w[q] = 0;
     }
     const uint32_t slot = b * M + (a.m ? (__brev(i) >> (32 - a.m)) : 0);
-    st8(lds + slot * 8, w);
+    st8(lds_at(lds, slot), w);
   }
   __syncthreads();
 
@@ -163,16 +202,17 @@ ntt_pass_kernel(NttPass a) {
 
   // ---- store with optional four-step twiddle and final scale
   const bool row_out = (a.s_out == 1);
-  for (uint32_t e = tid; e < TE; e += NTT_THREADS) {
+  for (uint32_t e = tid; e < TE; e += blockDim.x) {
     const uint32_t b = row_out ? e / M : e % G;
     const uint32_t k = row_out ? e % M : e / G;
     uint32_t w[8];
-    ld8(lds + (b * M + k) * 8, w);
+    ld8(lds_at(lds, b * M + k), w);
     if (a.post_tw_L) {
       const uint32_t ex = ((g0 + b) * k) & ((1u << a.post_tw_L) - 1);
-      if (ex) mul_plain_by_mont<FrP>(w, pow28(a.tw_lo, a.tw_hi, ex << (28 - a.post_tw_L)), w);
+      if (ex) mul_tw_2q(w, pow28(a.tw_lo, a.tw_hi, ex << (28 - a.post_tw_L)), w);
     }
-    if (a.post_scale) mul_plain_by_mont<FrP>(w, *a.post_scale, w);
+    if (a.post_scale) mul_tw_2q(w, *a.post_scale, w);
+    canon32<FrP>(w);
     st8(a.out + ((size_t)(g0 + b) * a.b_out + (size_t)k * a.s_out) * 8, w);
   }
 }
@@ -190,12 +230,19 @@ __global__ void pow_tables_kernel(Words8 bw, f29* lo, f29* hi) {
 
 }  // namespace
 
-size_t ntt_pass_lds_bytes() { return (size_t)TILE * 32; }
+size_t ntt_pass_lds_bytes() { return (size_t)(TILE + TILE / 8 + 1) * 32; }
 
 hipError_t ntt_launch_pass(const NttPass& p, hipStream_t s) {
   const uint32_t blocks = (p.nbatch + p.G - 1) / p.G;
+  // LDS and threads sized to the tile: 2048-point tiles (64 KB) let two
+  // workgroups share a CU, so one's loads and stores overlap the other's
+  // butterflies
+  const uint32_t te = (1u << p.m) * p.G;
+  uint32_t threads = te / 8;
+  if (threads < 64) threads = 64;
+  if (threads > NTT_THREADS) threads = NTT_THREADS;
   const ProfToken t = prof_begin("ntt.pass", s);
-  hipLaunchKernelGGL(ntt_pass_kernel, dim3(blocks), dim3(NTT_THREADS), ntt_pass_lds_bytes(), s, p);
+  hipLaunchKernelGGL(ntt_pass_kernel, dim3(blocks), dim3(threads), (size_t)(te + te / 8 + 1) * 32, s, p);
   prof_end(t, s);
   return hipGetLastError();
 }
