@@ -45,8 +45,8 @@ MONT_PER_MADD = 10
 # HBM bytes of one accumulate dispatch of this workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE scaled by a plain-copy calibration (x2.0 / x1.0);
 # valid only for the kernel sources whose hash is recorded with it.
-ACCUMULATE_TRAFFIC = {"sources_sha256_16": "faca7cd74a3fa1e3", "bytes": 2952448828}
-TRAFFIC_SOURCES = ("msm.h", "msm.hip", "curve.h", "field.h", "field_constants.h")
+ACCUMULATE_TRAFFIC = {"sources_sha256_16": "9669405be7e0d1a3", "bytes": 4229645907}
+TRAFFIC_SOURCES = ("msm_accumulate.hip", "msm_store.h", "msm.h", "curve.h", "field.h", "field_constants.h")
 
 
 def kernel_sources_hash():

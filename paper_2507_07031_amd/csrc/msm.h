@@ -83,6 +83,10 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* offsets, const uint32_t* po
                    const MsmBuffers& b, uint32_t* out, hipStream_t s, hipEvent_t after_accumulate = nullptr,
                    hipEvent_t before_accumulate = nullptr);
 
+// The bucket-accumulation kernel of msm_run (msm_accumulate.hip): sorted
+// entries -> complete buckets and two boundary records per thread.
+hipError_t msm_launch_accumulate(const MsmPlan& p, const MsmBuffers& b, const uint32_t* points, hipStream_t s);
+
 // Canonical plain affine points -> Montgomery-form affine points (count n).
 hipError_t msm_points_to_mont(const uint32_t* plain, uint32_t* mont, uint64_t n, hipStream_t s);
 

@@ -35,6 +35,8 @@
 #include <algorithm>
 
 #include "curve.h"
+#include "curve_quad.h"
+#include "msm_store.h"
 #include "msm.h"
 #include "prof.h"
 
@@ -60,41 +62,6 @@ __device__ __forceinline__ void ldw(const uint32_t* p, uint32_t* w, int n4) {
 
 __device__ __forceinline__ void stw(uint32_t* p, const uint32_t* w, int n4) {
   for (int q = 0; q < n4; q++)
-    reinterpret_cast<uint4*>(p)[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
-}
-
-__device__ __forceinline__ xyzz ld_xyzz(const uint32_t* p) {
-  uint32_t w[36];
-#pragma unroll
-  for (int q = 0; q < 9; q++) {
-    const uint4 v = reinterpret_cast<const uint4*>(p)[q];
-    w[4 * q] = v.x;
-    w[4 * q + 1] = v.y;
-    w[4 * q + 2] = v.z;
-    w[4 * q + 3] = v.w;
-  }
-  xyzz a;
-#pragma unroll
-  for (int i = 0; i < 9; i++) {
-    a.X.l[i] = w[i];
-    a.Y.l[i] = w[9 + i];
-    a.ZZ.l[i] = w[18 + i];
-    a.ZZZ.l[i] = w[27 + i];
-  }
-  return a;
-}
-
-__device__ __forceinline__ void st_xyzz(uint32_t* p, const xyzz& a) {
-  uint32_t w[36];
-#pragma unroll
-  for (int i = 0; i < 9; i++) {
-    w[i] = a.X.l[i];
-    w[9 + i] = a.Y.l[i];
-    w[18 + i] = a.ZZ.l[i];
-    w[27 + i] = a.ZZZ.l[i];
-  }
-#pragma unroll
-  for (int q = 0; q < 9; q++)
     reinterpret_cast<uint4*>(p)[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
 }
 
@@ -448,102 +415,6 @@ __device__ void combine_and_emit(RecLds& r, bool left_open, bool right_open, uin
   }
 }
 
-// ---------------------------------------------------------------- accumulate
-__device__ __forceinline__ void ld_pt_words(const uint32_t* __restrict__ points, uint32_t v, uint4 q[4]) {
-  const uint4* src = reinterpret_cast<const uint4*>(points + (size_t)(v & 0x7fffffffu) * 16);
-#pragma unroll
-  for (int k = 0; k < 4; k++) q[k] = src[k];
-}
-
-__device__ __forceinline__ void st_rec_xyzz(uint32_t* rec, uint32_t key, uint32_t flag, const xyzz& a) {
-  reinterpret_cast<uint4*>(rec)[0] = make_uint4(key, flag, 0, 0);
-  st_xyzz(rec + 4, a);
-}
-
-// Each thread sums L consecutive sorted entries.  An entry is only its point
-// index and sign; its bucket is the one whose offset range contains the
-// entry's position (found once by binary search, then followed).  Runs of
-// one bucket strictly inside the range are complete and go straight to HBM;
-// the first and last run of the range become the thread's two records,
-// finished by the record levels.  The next point is loaded one step ahead.
-__global__ void __launch_bounds__(MSM_NT) __attribute__((amdgpu_waves_per_eu(3, 3)))
-accumulate_kernel(const uint32_t* __restrict__ entries, const uint32_t* __restrict__ offsets, uint32_t nbins,
-                  const uint32_t* __restrict__ points, uint32_t L, uint32_t* __restrict__ buckets,
-                  uint32_t* __restrict__ rec) {
-  const uint64_t t = (uint64_t)blockIdx.x * MSM_NT + threadIdx.x;
-  const uint32_t total = offsets[nbins];
-  const uint64_t tb = t * L;
-  uint32_t* r0 = rec + (2 * t) * REC_WORDS;
-  uint32_t* r1 = r0 + REC_WORDS;
-  if (tb >= total) {
-    st_rec_xyzz(r0, KEY_SENTINEL, 0, xyzz_inf());
-    st_rec_xyzz(r1, KEY_SENTINEL, 0, xyzz_inf());
-    return;
-  }
-  const uint32_t te = (uint32_t)min(tb + L, (uint64_t)total);
-  // bucket of entry tb: the largest b with offsets[b] <= tb
-  uint32_t lo = 0, hi = nbins;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi + 1) >> 1;
-    if (offsets[mid] <= (uint32_t)tb) lo = mid; else hi = mid - 1;
-  }
-  uint32_t cur = lo;
-  uint32_t bend = offsets[cur + 1];
-  uint32_t v = entries[tb];
-  uint4 q[4];
-  ld_pt_words(points, v, q);
-  bool first_done = false;
-  xyzz acc = xyzz_inf();
-  for (uint32_t e = (uint32_t)tb; e < te; e++) {
-    uint32_t nv = v;
-    uint4 nq[4] = {q[0], q[1], q[2], q[3]};
-    if (e + 1 < te) {
-      nv = entries[e + 1];
-      ld_pt_words(points, nv, nq);
-    }
-    if (e == bend) {
-      if (!first_done) {
-        st_rec_xyzz(r0, cur, 1, acc);
-        first_done = true;
-      } else {
-        st_xyzz(buckets + (size_t)cur * XYZZ_WORDS, acc);
-      }
-      do {
-        cur++;
-        bend = offsets[cur + 1];
-      } while (bend == e);
-      acc = xyzz_inf();
-    }
-    uint32_t w[16];
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-      w[4 * k] = q[k].x;
-      w[4 * k + 1] = q[k].y;
-      w[4 * k + 2] = q[k].z;
-      w[4 * k + 3] = q[k].w;
-    }
-    uint32_t o = 0;
-#pragma unroll
-    for (int k = 0; k < 16; k++) o |= w[k];
-    if (o) {
-      aff pt;
-      pt.x = unpack(w);
-      pt.y = unpack(w + 8);
-      if (v >> 31) pt = aff_neg(pt);
-      acc = madd(acc, pt);
-    }
-    v = nv;
-#pragma unroll
-    for (int k = 0; k < 4; k++) q[k] = nq[k];
-  }
-  if (!first_done) {
-    st_rec_xyzz(r0, cur, 1, acc);
-    st_rec_xyzz(r1, cur, 0, xyzz_inf());
-  } else {
-    st_rec_xyzz(r1, cur, 1, acc);
-  }
-}
-
 // Level of the record reduction: 2*MSM_NT records per workgroup.
 __global__ void __launch_bounds__(MSM_NT)
 record_reduce_kernel(const uint32_t* __restrict__ in_rec, uint32_t nrec, uint32_t* __restrict__ buckets,
@@ -601,6 +472,24 @@ chunk_sums_kernel(const uint32_t* __restrict__ buckets, const uint32_t* __restri
   st_xyzz(vbuf + ((size_t)id * 2 + 1) * XYZZ_WORDS, sum);
 }
 
+// The same with each chunk on a quad (four lanes per point operation): for
+// few chunks, where the sums' latency matters more than their total work.
+__global__ void __launch_bounds__(64)
+chunk_sums_quad_kernel(const uint32_t* __restrict__ buckets, const uint32_t* __restrict__ counts, MsmPlan p,
+                       uint32_t* __restrict__ vbuf) {
+  const uint32_t id = (blockIdx.x * blockDim.x + threadIdx.x) >> 2, c = threadIdx.x & 3u;
+  if (id >= p.groups * p.J) return;  // whole quads
+  const uint32_t g = id / p.J, j = id % p.J;
+  const uint32_t base = g * p.K + j * p.LB;
+  f29 acc = f29_zero(), sum = f29_zero();
+  for (int m = (int)p.LB - 1; m >= 0; --m) {
+    if (counts[base + m]) acc = quad_add(acc, ldq(buckets + (size_t)(base + m) * XYZZ_WORDS, c));
+    sum = quad_add(sum, acc);
+  }
+  stq(vbuf + (size_t)id * 2 * XYZZ_WORDS, c, acc);
+  stq(vbuf + ((size_t)id * 2 + 1) * XYZZ_WORDS, c, sum);
+}
+
 // Partial sums of one bit slice: block (part, i, g) adds its share of the
 // terms of slice i of bucket set g -- the S_j with bit i of j set (i < nbits)
 // or every T_j (i = nbits) -- sequentially per thread, then by a tree in LDS.
@@ -654,88 +543,87 @@ partial_tree_kernel(const uint32_t* __restrict__ in, uint32_t nin, uint32_t nsli
   if (tid == 0) st_xyzz(out + ((size_t)(g * nslices + i) * nout + k) * XYZZ_WORDS, ld_xyzz(sm));
 }
 
-// Bucket set g: U_i from the slice partials (at most 2 per thread),
-// V = U_T + sum_i 2^(log2 LB + i) U_i (every slice doubled in its own
-// thread, then a tree), and the result written as canonical affine (table
-// layout: the set is one output) or as XYZZ (the generic layout's window
-// sums, combined by Horner next).
+// Bucket set g: U_i from the slice partials, V = U_T + sum_i 2^(log2 LB + i) U_i,
+// and the result written as canonical affine (table layout: the set is one
+// output) or as XYZZ (the generic layout's window sums, combined by Horner
+// next).  Every point operation runs on a quad (see curve_quad.h): this
+// kernel is one dependent chain per set.  qps quads share a slice's
+// partials, then the slice sums are doubled into place (one quad per slice)
+// and added by a tree.
 constexpr uint32_t FIN_SLICES = 32;  // nbits + 1 <= 32
-constexpr uint32_t FIN_NT = 256;
-// Threads per slice in the finishing kernel: FIN_NT over the slice count
-// rounded up to a power of two; each first sums up to 2 partials.
-inline uint32_t fin_tps(uint32_t nslices) {
+constexpr uint32_t FIN_NT = 256;     // 64 quads
+constexpr uint32_t FIN_QUADS = FIN_NT / 4;
+// Quads per slice: FIN_QUADS over the slice count rounded up to a power of two.
+inline uint32_t fin_qps(uint32_t nslices) {
   uint32_t p2 = 1;
   while (p2 < nslices) p2 <<= 1;
-  return FIN_NT / p2;
+  return FIN_QUADS / p2;
 }
 __global__ void __launch_bounds__(FIN_NT)
-bit_finish_kernel(const uint32_t* __restrict__ partial, uint32_t nparts, uint32_t tps, MsmPlan p,
+bit_finish_kernel(const uint32_t* __restrict__ partial, uint32_t nparts, uint32_t qps, MsmPlan p,
                   uint32_t* __restrict__ out_affine, uint32_t* __restrict__ out_xyzz) {
-  __shared__ uint32_t sm[FIN_NT * XYZZ_WORDS];
-  const uint32_t g = blockIdx.x, tid = threadIdx.x;
-  const uint32_t i = tid / tps, q = tid % tps;
-  const uint32_t ns = p.nbits + 1, nsp = FIN_NT / tps;
-  xyzz acc = xyzz_inf();
+  __shared__ uint32_t sm[FIN_QUADS * XYZZ_WORDS];
+  const uint32_t g = blockIdx.x, tid = threadIdx.x, quad = tid >> 2, c = tid & 3u;
+  const uint32_t i = quad / qps, k0 = quad % qps;
+  const uint32_t ns = p.nbits + 1, nsp = FIN_QUADS / qps;
+  f29 acc = f29_zero();
   if (i < ns)
-    for (uint32_t k = q; k < nparts; k += tps)
-      acc = add(acc, ld_xyzz(partial + ((size_t)(g * ns + i) * nparts + k) * XYZZ_WORDS));
-  st_xyzz(sm + tid * XYZZ_WORDS, acc);
+    for (uint32_t k = k0; k < nparts; k += qps)
+      acc = quad_add(acc, ldq(partial + ((size_t)(g * ns + i) * nparts + k) * XYZZ_WORDS, c));
+  stq(sm + quad * XYZZ_WORDS, c, acc);
   __syncthreads();
-  for (uint32_t h = tps / 2; h > 0; h >>= 1) {
-    if (q < h) {
-      const xyzz a = add(ld_xyzz(sm + tid * XYZZ_WORDS), ld_xyzz(sm + (tid + h) * XYZZ_WORDS));
-      st_xyzz(sm + tid * XYZZ_WORDS, a);
+  for (uint32_t h = qps / 2; h > 0; h >>= 1) {
+    if (k0 < h) {
+      acc = quad_add(acc, ldq(sm + (quad + h) * XYZZ_WORDS, c));
+      stq(sm + quad * XYZZ_WORDS, c, acc);
     }
     __syncthreads();
   }
-  // slice i's sum sits in slot tps i; scale it into slot i
-  xyzz u = xyzz_inf();
-  if (tid < ns) {
-    u = ld_xyzz(sm + tid * tps * XYZZ_WORDS);
-    if (tid < p.nbits) {
-      const uint32_t e = p.lgLB + tid;
-      for (uint32_t k = 0; k < e; k++) u = dbl(u);
-    }
+  // slice i's sum is in quad i*qps; scale it and move it to slot i
+  if (k0 == 0 && i < p.nbits) {
+    const uint32_t e = p.lgLB + i;
+    for (uint32_t k = 0; k < e; k++) acc = quad_dbl(acc);
   }
   __syncthreads();
-  if (tid < nsp) st_xyzz(sm + tid * XYZZ_WORDS, u);
+  if (k0 == 0) stq(sm + i * XYZZ_WORDS, c, i < ns ? acc : f29_zero());
   __syncthreads();
+  f29 v = quad < nsp ? ldq(sm + quad * XYZZ_WORDS, c) : f29_zero();
   for (uint32_t h = nsp / 2; h > 0; h >>= 1) {
-    if (tid < h) {
-      const xyzz a = add(ld_xyzz(sm + tid * XYZZ_WORDS), ld_xyzz(sm + (tid + h) * XYZZ_WORDS));
-      st_xyzz(sm + tid * XYZZ_WORDS, a);
+    if (quad < h) {
+      v = quad_add(v, ldq(sm + (quad + h) * XYZZ_WORDS, c));
+      stq(sm + quad * XYZZ_WORDS, c, v);
     }
     __syncthreads();
   }
-  if (tid != 0) return;
-  xyzz v = ld_xyzz(sm);
-  force_vgpr(v);
+  if (quad != 0) return;
   if (out_xyzz) {
-    st_xyzz(out_xyzz + (size_t)g * XYZZ_WORDS, v);
-  } else {
-    uint32_t o[16];
-    to_affine_words(v, o);
-    stw(out_affine + (size_t)g * 16, o, 4);
+    stq(out_xyzz + (size_t)g * XYZZ_WORDS, c, v);
+    return;
   }
+  xyzz r = quad_gather(v);
+  if (c != 0) return;
+  force_vgpr(r);
+  uint32_t o[16];
+  to_affine_words(r, o);
+  stw(out_affine + (size_t)g * 16, o, 4);
 }
 
-// Generic layout: Q = sum_w 2^(c w) S_w by Horner, then canonical affine.
+// Generic layout: Q = sum_w 2^(c w) S_w by Horner (on one quad), then
+// canonical affine.
 __global__ void __launch_bounds__(64) combine_kernel(const uint32_t* __restrict__ wsum, uint32_t nwin, uint32_t c,
                                uint32_t* __restrict__ out16) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  xyzz q = ld_xyzz(wsum + (size_t)(nwin - 1) * XYZZ_WORDS);
+  if (blockIdx.x != 0 || threadIdx.x >= 4) return;
+  const uint32_t ln = threadIdx.x;
+  f29 q = ldq(wsum + (size_t)(nwin - 1) * XYZZ_WORDS, ln);
   for (int w = (int)nwin - 2; w >= 0; --w) {
-    for (uint32_t t = 0; t < c; t++) {
-      force_vgpr(q);
-      q = dbl(q);
-    }
-    xyzz s = ld_xyzz(wsum + (size_t)w * XYZZ_WORDS);
-    force_vgpr(s);
-    q = add(q, s);
+    for (uint32_t t = 0; t < c; t++) q = quad_dbl(q);
+    q = quad_add(q, ldq(wsum + (size_t)w * XYZZ_WORDS, ln));
   }
-  force_vgpr(q);
+  xyzz r = quad_gather(q);
+  if (ln != 0) return;
+  force_vgpr(r);
   uint32_t o[16];
-  to_affine_words(q, o);
+  to_affine_words(r, o);
   stw(out16, o, 4);
 }
 
@@ -1235,15 +1123,14 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points
   prof_end(t_sort, s);
   if (before_accumulate && (e = hipStreamWaitEvent(s, before_accumulate, 0))) return e;
   const ProfToken t_acc = prof_begin("msm.accumulate", s);
-  hipLaunchKernelGGL(accumulate_kernel, dim3(p.acc_blocks), dim3(MSM_NT), 0, s, b.entries, b.offsets, p.nbins,
-                     points, p.L, b.buckets, b.rec[0]);
+  if ((e = msm_launch_accumulate(p, b, points, s))) return e;
   prof_end(t_acc, s);
   if (after_accumulate && (e = hipEventRecord(after_accumulate, s))) return e;
   if (p.nbits + 1 > FIN_SLICES) return hipErrorInvalidValue;
-  // partial-tree levels until a slice has at most 2 partials per finishing thread
-  const uint32_t tps = fin_tps(p.nbits + 1);
+  // partial-tree levels until a slice has at most 8 partials per finishing quad
+  const uint32_t qps = fin_qps(p.nbits + 1);
   uint32_t levels = 0;
-  for (uint32_t np = p.parts; np > 2 * tps; np = (np + BITS_NT - 1) / BITS_NT) levels++;
+  for (uint32_t np = p.parts; np > 8 * qps; np = (np + BITS_NT - 1) / BITS_NT) levels++;
   const ProfToken t_red = prof_begin("msm.reduce", s);
   uint32_t nrec = 2 * p.acc_blocks * MSM_NT;
   int cur = 0;
@@ -1256,8 +1143,14 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points
     nrec = 2 * g2;
     cur ^= 1;
   }
-  hipLaunchKernelGGL(chunk_sums_kernel, dim3(cdiv((uint64_t)p.groups * p.J, 64)), dim3(64), 0, s, b.buckets,
-                     b.counts, p, b.vbuf);
+  // chunk sums on quads while they fill at most about two waves per SIMD
+  if ((uint64_t)p.groups * p.J * 4 <= (1u << 17)) {
+    hipLaunchKernelGGL(chunk_sums_quad_kernel, dim3(cdiv((uint64_t)p.groups * p.J * 4, 64)), dim3(64), 0, s,
+                       b.buckets, b.counts, p, b.vbuf);
+  } else {
+    hipLaunchKernelGGL(chunk_sums_kernel, dim3(cdiv((uint64_t)p.groups * p.J, 64)), dim3(64), 0, s, b.buckets,
+                       b.counts, p, b.vbuf);
+  }
   hipLaunchKernelGGL(bit_sums_kernel, dim3(p.parts, p.nbits + 1, p.groups), dim3(BITS_NT), 0, s, b.vbuf, p,
                      b.partial);
   // tree levels ping-pong between the partial buffer and the (now free) chunk buffer
@@ -1274,9 +1167,9 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points
     pout = t;
   }
   if (p.table) {
-    hipLaunchKernelGGL(bit_finish_kernel, dim3(p.groups), dim3(FIN_NT), 0, s, pin, np, tps, p, out, nullptr);
+    hipLaunchKernelGGL(bit_finish_kernel, dim3(p.groups), dim3(FIN_NT), 0, s, pin, np, qps, p, out, nullptr);
   } else {
-    hipLaunchKernelGGL(bit_finish_kernel, dim3(p.groups), dim3(FIN_NT), 0, s, pin, np, tps, p, nullptr, b.wsum);
+    hipLaunchKernelGGL(bit_finish_kernel, dim3(p.groups), dim3(FIN_NT), 0, s, pin, np, qps, p, nullptr, b.wsum);
     hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, s, b.wsum, p.W, p.c, out);
   }
   prof_end(t_red, s);

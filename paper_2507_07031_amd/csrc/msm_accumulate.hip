@@ -1,0 +1,114 @@
+// Bucket accumulation of the multi-scalar multiplication (see msm.hip for
+// the whole pipeline): the dominant kernel, kept in a file of its own so that
+// its measured memory traffic is tied to exactly this code.
+#include "msm.h"
+#include "msm_store.h"
+
+namespace zk {
+
+namespace {
+
+__device__ __forceinline__ void ld_pt_words(const uint32_t* __restrict__ points, uint32_t v, uint4 q[4]) {
+  const uint4* src = reinterpret_cast<const uint4*>(points + (size_t)(v & 0x7fffffffu) * 16);
+#pragma unroll
+  for (int k = 0; k < 4; k++) q[k] = src[k];
+}
+
+__device__ __forceinline__ void st_rec_xyzz(uint32_t* rec, uint32_t key, uint32_t flag, const xyzz& a) {
+  reinterpret_cast<uint4*>(rec)[0] = make_uint4(key, flag, 0, 0);
+  st_xyzz(rec + 4, a);
+}
+
+// Each thread sums L consecutive sorted entries.  An entry is only its point
+// index and sign; its bucket is the one whose offset range contains the
+// entry's position (found once by binary search, then followed).  Runs of
+// one bucket strictly inside the range are complete and go straight to HBM;
+// the first and last run of the range become the thread's two records,
+// finished by the record levels.  The next point is loaded one step ahead.
+__global__ void __launch_bounds__(MSM_NT) __attribute__((amdgpu_waves_per_eu(3, 3)))
+accumulate_kernel(const uint32_t* __restrict__ entries, const uint32_t* __restrict__ offsets, uint32_t nbins,
+                  const uint32_t* __restrict__ points, uint32_t L, uint32_t* __restrict__ buckets,
+                  uint32_t* __restrict__ rec) {
+  const uint64_t t = (uint64_t)blockIdx.x * MSM_NT + threadIdx.x;
+  const uint32_t total = offsets[nbins];
+  const uint64_t tb = t * L;
+  uint32_t* r0 = rec + (2 * t) * REC_WORDS;
+  uint32_t* r1 = r0 + REC_WORDS;
+  if (tb >= total) {
+    st_rec_xyzz(r0, KEY_SENTINEL, 0, xyzz_inf());
+    st_rec_xyzz(r1, KEY_SENTINEL, 0, xyzz_inf());
+    return;
+  }
+  const uint32_t te = (uint32_t)min(tb + L, (uint64_t)total);
+  // bucket of entry tb: the largest b with offsets[b] <= tb
+  uint32_t lo = 0, hi = nbins;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (offsets[mid] <= (uint32_t)tb) lo = mid; else hi = mid - 1;
+  }
+  uint32_t cur = lo;
+  uint32_t bend = offsets[cur + 1];
+  uint32_t v = entries[tb];
+  uint4 q[4];
+  ld_pt_words(points, v, q);
+  bool first_done = false;
+  xyzz acc = xyzz_inf();
+  for (uint32_t e = (uint32_t)tb; e < te; e++) {
+    uint32_t nv = v;
+    uint4 nq[4] = {q[0], q[1], q[2], q[3]};
+    if (e + 1 < te) {
+      nv = entries[e + 1];
+      ld_pt_words(points, nv, nq);
+    }
+    if (e == bend) {
+      if (!first_done) {
+        st_rec_xyzz(r0, cur, 1, acc);
+        first_done = true;
+      } else {
+        st_xyzz(buckets + (size_t)cur * XYZZ_WORDS, acc);
+      }
+      do {
+        cur++;
+        bend = offsets[cur + 1];
+      } while (bend == e);
+      acc = xyzz_inf();
+    }
+    uint32_t w[16];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      w[4 * k] = q[k].x;
+      w[4 * k + 1] = q[k].y;
+      w[4 * k + 2] = q[k].z;
+      w[4 * k + 3] = q[k].w;
+    }
+    uint32_t o = 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) o |= w[k];
+    if (o) {
+      aff pt;
+      pt.x = unpack(w);
+      pt.y = unpack(w + 8);
+      if (v >> 31) pt = aff_neg(pt);
+      acc = madd(acc, pt);
+    }
+    v = nv;
+#pragma unroll
+    for (int k = 0; k < 4; k++) q[k] = nq[k];
+  }
+  if (!first_done) {
+    st_rec_xyzz(r0, cur, 1, acc);
+    st_rec_xyzz(r1, cur, 0, xyzz_inf());
+  } else {
+    st_rec_xyzz(r1, cur, 1, acc);
+  }
+}
+
+}  // namespace
+
+hipError_t msm_launch_accumulate(const MsmPlan& p, const MsmBuffers& b, const uint32_t* points, hipStream_t s) {
+  hipLaunchKernelGGL(accumulate_kernel, dim3(p.acc_blocks), dim3(MSM_NT), 0, s, b.entries, b.offsets, p.nbins,
+                     points, p.L, b.buckets, b.rec[0]);
+  return hipGetLastError();
+}
+
+}  // namespace zk
