@@ -297,6 +297,37 @@ def main():
             "msm_points_per_s": n / (t_msm / 1e3), "ntt_elems_per_s": n / (t_ntt / 1e3),
             "intt_elems_per_s": n / (t_intt / 1e3), "coset_out_elems_per_s": 4 * n / (t_coset / 1e3),
             "ntt_hbm_frac_2pass": round(2 * 2 * 32 * n / (t_ntt / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+        # both roofs of the transforms: algorithmic HBM bytes (two passes, each
+        # reading and writing the data once) and algorithmic word products
+        # ((N/2) log2 N butterflies, one Fr product of MADS_PER_MONT each)
+        roofs = {}
+        for name, t_ms, N_in, N_out in (("ntt_2^20", t_ntt, n, n), ("intt_2^20", t_intt, n, n),
+                                        ("coset_2^20->2^22", t_coset, n, 4 * n)):
+            lg = N_out.bit_length() - 1
+            hbm_bytes = 32 * (N_in + N_out) + 2 * 32 * N_out
+            mads = (N_out // 2) * lg * MADS_PER_MONT
+            roofs[name] = {"ms": round(t_ms, 4),
+                           "hbm_gbs": round(hbm_bytes / (t_ms / 1e3) / 1e9, 1),
+                           "hbm_frac": round(hbm_bytes / (t_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+                           "int_tops": round(mads / (t_ms / 1e3) / 1e12, 3),
+                           "int_frac": round(mads / (t_ms / 1e3) / 1e12 / PEAK_MAD_TOPS, 4),
+                           "bound": "alu"}
+        extras["ntt_rooflines"] = roofs
+
+        # per-step latency distribution of the commit job (each step bracketed
+        # by its own events; separate from the timed throughput run)
+        lat = []
+        for _ in range(max(20, args.steps)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            step()
+            e1.record()
+            torch.cuda.synchronize()
+            lat.append(e0.elapsed_time(e1))
+        lat = np.array(lat)
+        extras["step_latency_ms"] = {"median": round(float(np.median(lat)), 4),
+                                     "p90": round(float(np.percentile(lat, 90)), 4),
+                                     "min": round(float(lat.min()), 4), "reps": int(lat.size)}
 
         log("quantized 2^22")
         N22 = 1 << 22

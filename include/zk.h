@@ -160,6 +160,13 @@ zk_status zk_msm_batch(const zk_srs* srs, const zk_fr* scalars, const uint64_t* 
  * inst[k + j].  out: k points.  m >= 1. */
 zk_status zk_fold(const zk_g1* inst, const zk_fr* gammas, uint32_t m, uint32_t k, zk_g1* out, void* stream);
 
+/* Input validation (off by default).  When on, every call checks on the
+ * device, before any other work, that its Fr inputs are canonical (< r) and
+ * its G1 inputs are (0, 0) or canonical affine points on y^2 = x^3 + 3, and
+ * returns ZK_EINVAL (message in zk_last_error) if one is not.  The check
+ * waits for the call's stream, so validated calls are synchronous. */
+zk_status zk_set_validate(int on);
+
 /* Wait for and free every cached scratch block of the current device. */
 zk_status zk_release_cached_memory(void);
 

@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -15,6 +17,7 @@
 #include "msm.h"
 #include "ntt.h"
 #include "prof.h"
+#include "validate.h"
 
 using namespace zk;
 
@@ -32,6 +35,18 @@ zk_status hip_fail(hipError_t e, const char* where) {
               std::string(where) + ": " + hipGetErrorString(e));
 }
 
+// zk_set_validate: when on, calls check their Fr and G1 inputs on the device
+// before any work and return ZK_EINVAL if one is out of range (the check
+// waits for the stream: validated calls are synchronous).
+std::atomic<bool> g_validate{false};
+
+struct InputCheck {
+  const void* p;
+  uint64_t n;
+  bool g1;
+};
+
+
 #define ZK_HIP(call, where)                 \
   do {                                      \
     hipError_t _e = (call);                 \
@@ -45,6 +60,7 @@ struct DeviceCtx {
   f29* coset5[2] = {nullptr, nullptr};                  // 5^e lo / hi
   f29* ninv = nullptr;                                  // 2^-L, L = 0..28
   uint32_t* gtab = nullptr;                             // 2^j G table for the setup
+  uint32_t* vflag = nullptr;                            // input-check findings (zk_set_validate)
 };
 
 std::mutex g_mu;
@@ -73,6 +89,7 @@ zk_status ctx_get(DeviceCtx** out) {
   for (int i = 0; i < 2; i++) ZK_HIP(hipMalloc(&c.coset5[i], tsz), "hipMalloc(coset)");
   ZK_HIP(hipMalloc(&c.ninv, sizeof(f29) * 29), "hipMalloc(ninv)");
   ZK_HIP(hipMalloc(&c.gtab, srs_gtab_words() * 4), "hipMalloc(gtab)");
+  ZK_HIP(hipMalloc(&c.vflag, 4), "hipMalloc(vflag)");
   // roots omega_(2^28), its inverse, and the coset shift 5 (host arithmetic, same field code)
   Words8 wf, wi, w5;
   std::memcpy(wf.w, FR_OMEGA_2_28, 32);
@@ -193,6 +210,22 @@ struct Scratch {
   void* p = nullptr;
   ~Scratch() { block_free(blk); }
 };
+
+zk_status check_inputs(DeviceCtx* c, hipStream_t s, std::initializer_list<InputCheck> checks, const char* who) {
+  if (!g_validate.load(std::memory_order_relaxed)) return ZK_OK;
+  ZK_HIP(hipMemsetAsync(c->vflag, 0, 4, s), "hipMemsetAsync");
+  for (const InputCheck& k : checks) {
+    const uint32_t* w = static_cast<const uint32_t*>(k.p);
+    ZK_HIP(k.g1 ? validate_g1(w, k.n, c->vflag, s) : validate_fr(w, k.n, c->vflag, s), "input check");
+  }
+  uint32_t found = 0;
+  ZK_HIP(hipMemcpyAsync(&found, c->vflag, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  ZK_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (found & VALIDATE_FR) return fail(ZK_EINVAL, std::string(who) + ": an Fr input is not canonical (>= r)");
+  if (found & VALIDATE_G1)
+    return fail(ZK_EINVAL, std::string(who) + ": a G1 input is not (0, 0) or a canonical point on the curve");
+  return ZK_OK;
+}
 
 zk_status scratch_alloc(Scratch& sc, size_t bytes, hipStream_t s) {
   zk_status st = block_alloc(sc.blk, bytes, s);
@@ -395,6 +428,11 @@ zk_status zk_release_cached_memory(void) {
   return ZK_OK;
 }
 
+zk_status zk_set_validate(int on) {
+  g_validate.store(on != 0);
+  return ZK_OK;
+}
+
 zk_status zk_profile_enable(int on) {
   prof_set_enabled(on != 0);
   return ZK_OK;
@@ -419,6 +457,7 @@ zk_status zk_ntt(const zk_fr* in, zk_fr* out, uint32_t log_n, void* stream) {
   DeviceCtx* c;
   zk_status st = ctx_get(&c);
   if (st) return st;
+  if ((st = check_inputs(c, (hipStream_t)stream, {{in, 1ull << log_n, false}}, "zk_ntt"))) return st;
   return run_ntt(c, reinterpret_cast<const uint32_t*>(in), reinterpret_cast<uint32_t*>(out), log_n, false,
                  nullptr, nullptr, 1u << log_n, (hipStream_t)stream);
 }
@@ -429,6 +468,7 @@ zk_status zk_intt(const zk_fr* in, zk_fr* out, uint32_t log_n, void* stream) {
   DeviceCtx* c;
   zk_status st = ctx_get(&c);
   if (st) return st;
+  if ((st = check_inputs(c, (hipStream_t)stream, {{in, 1ull << log_n, false}}, "zk_intt"))) return st;
   return run_ntt(c, reinterpret_cast<const uint32_t*>(in), reinterpret_cast<uint32_t*>(out), log_n, true,
                  nullptr, nullptr, 1u << log_n, (hipStream_t)stream);
 }
@@ -442,6 +482,7 @@ zk_status zk_coset_ntt(const zk_fr* coeffs, uint32_t log_n, uint32_t log_blowup,
   zk_status st = ctx_get(&c);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
+  if ((st = check_inputs(c, s, {{coeffs, 1ull << log_n, false}}, "zk_coset_ntt"))) return st;
   const f29* lo = c->coset5[0];
   const f29* hi = c->coset5[1];
   Scratch tab;
@@ -474,6 +515,7 @@ zk_status zk_msm(const zk_g1* bases, const zk_fr* scalars, uint64_t n, zk_g1* ou
   zk_status st = ctx_get(&c);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
+  if ((st = check_inputs(c, s, {{bases, n, true}, {scalars, n, false}}, "zk_msm"))) return st;
   const MsmPlan plan = msm_plan_generic((uint32_t)n, msm_default_c((uint32_t)n));
   Scratch pts;
   st = scratch_alloc(pts, (size_t)n * 64, s);
@@ -506,6 +548,7 @@ zk_status zk_srs_create(const zk_g1* points, uint64_t n, zk_srs** srs, void* str
   DeviceCtx* c;
   zk_status st = ctx_get(&c);
   if (st) return st;
+  if ((st = check_inputs(c, (hipStream_t)stream, {{points, n, true}}, "zk_srs_create"))) return st;
   zk_srs* h = new zk_srs();
   ZK_HIP(hipGetDevice(&h->device), "hipGetDevice");
   h->n = n;
@@ -623,6 +666,7 @@ zk_status zk_commit_job(const zk_srs* srs, const zk_fr* evals, uint32_t log_n, u
   zk_status st = ctx_get(&c);
   if (st) return st;
   const hipStream_t s = (hipStream_t)stream;
+  if ((st = check_inputs(c, s, {{evals, n, false}}, "zk_commit_job"))) return st;
   hipStream_t side = nullptr;
   if ((st = side_stream(s, &side))) return st;
   SyncEvents ev;
@@ -669,6 +713,7 @@ zk_status zk_msm_srs_ex(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_
   DeviceCtx* c;
   zk_status st = ctx_get(&c);
   if (st) return st;
+  if ((st = check_inputs(c, (hipStream_t)stream, {{scalars, n, false}}, "zk_msm_srs_ex"))) return st;
   return msm_srs_one(srs, reinterpret_cast<const uint32_t*>(scalars), n, reinterpret_cast<uint32_t*>(out),
                      (hipStream_t)stream, (hipEvent_t)accumulate_done_event);
 }
@@ -679,6 +724,7 @@ zk_status zk_msm_srs(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1*
   DeviceCtx* c;
   zk_status st = ctx_get(&c);
   if (st) return st;
+  if ((st = check_inputs(c, (hipStream_t)stream, {{scalars, n, false}}, "zk_msm_srs"))) return st;
   return msm_srs_one(srs, reinterpret_cast<const uint32_t*>(scalars), n, reinterpret_cast<uint32_t*>(out),
                      (hipStream_t)stream);
 }
@@ -696,6 +742,8 @@ zk_status zk_msm_batch(const zk_srs* srs, const zk_fr* scalars, const uint64_t* 
   if (st) return st;
   if (batch == 0) return ZK_OK;
   if (offsets_host[batch] >= (1ull << 31) / 16) return fail(ZK_EUNSUPPORTED, "zk_msm_batch: too many scalars");
+  if ((st = check_inputs(c, (hipStream_t)stream, {{scalars, offsets_host[batch], false}}, "zk_msm_batch")))
+    return st;
   // one Pippenger run over every MSM: digits of all scalars sorted into
   // per-MSM buckets, one accumulation, one reduction, one output per MSM
   const MsmPlan plan = msm_plan_table(offsets_host, batch, srs->c, (uint32_t)srs->n);
@@ -711,6 +759,7 @@ zk_status zk_fold(const zk_g1* inst, const zk_fr* gammas, uint32_t m, uint32_t k
   zk_status st = ctx_get(&c);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
+  if ((st = check_inputs(c, s, {{inst, (uint64_t)m * k, true}, {gammas, m - 1ull, false}}, "zk_fold"))) return st;
   Scratch ws;
   st = scratch_alloc(ws, (size_t)m * (32 + 64 + 64) + 512, s);
   if (st) return st;

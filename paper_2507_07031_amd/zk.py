@@ -23,7 +23,7 @@ MAX_LOG_NTT = 24
 EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_srs_setup", "zk_srs_create",
            "zk_srs_destroy", "zk_srs_size", "zk_msm_srs", "zk_msm_batch", "zk_fold", "zk_profile_enable",
            "zk_profile_read", "zk_msm_srs_workspace_bytes", "zk_ntt_workspace_bytes", "zk_release_cached_memory",
-           "zk_msm_srs_ex", "zk_profile_only", "zk_commit_job")
+           "zk_msm_srs_ex", "zk_profile_only", "zk_commit_job", "zk_set_validate")
 
 
 class ZkError(RuntimeError):
@@ -50,6 +50,7 @@ def _load():
         "zk_msm_srs": ([P, P, U64, P, P], I),
         "zk_msm_srs_ex": ([P, P, U64, P, P, P], I),
         "zk_profile_only": ([ctypes.c_char_p], I),
+        "zk_set_validate": ([I], I),
         "zk_commit_job": ([P, P, I, I, P, P, P, P, P], I),
         "zk_msm_batch": ([P, P, P, U32, P, P], I),
         "zk_fold": ([P, P, U32, U32, P, P], I),
@@ -299,6 +300,11 @@ def release_cached_memory():
 
 def profile_enable(on=True):
     _check(lib.zk_profile_enable(1 if on else 0))
+
+
+def set_validate(on=True):
+    """Check inputs (canonical Fr, on-curve G1) on the device before every call."""
+    _check(lib.zk_set_validate(1 if on else 0))
 
 
 def profile_only(region=None):

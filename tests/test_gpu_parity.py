@@ -409,6 +409,47 @@ def test_fold_matches_tree(zk, tau, srs_big, m, k):
         assert out == ofold.tree_fold(inst_pts, gv)
 
 
+# ------------------------------------------------------------------ input validation
+
+def test_validation_rejects_out_of_range_inputs(zk, tau, srs_big):
+    # zk_set_validate: non-canonical scalars and off-curve bases are refused
+    # with ZK_EINVAL before any work; valid inputs give unchanged results
+    pts, h = srs_big
+    n = 64
+    s = gen.uniform_fr(gen.CONFIG_SEEDS["tiny"], n, tag=90)
+    base = pts[:n].contiguous()
+    ref = _host(zk, zk.msm(base, _dev(zk, s)))
+    bad_s = s.copy()
+    bad_s[5] = gen.ints_to_limbs([R])[0]            # r itself: not canonical
+    host_pts = _host(zk, base).copy()
+    bad_p = host_pts.copy()
+    bad_p[7, 8] ^= 1                                 # y changed: off the curve
+    zk.set_validate(True)
+    try:
+        assert np.array_equal(_host(zk, zk.msm(base, _dev(zk, s))), ref)
+        assert np.array_equal(_host(zk, zk.msm_srs(h, _dev(zk, s))), _host(zk, zk.msm_srs(h, _dev(zk, s))))
+        for call in (lambda: zk.msm(base, _dev(zk, bad_s)),
+                     lambda: zk.msm(_dev(zk, bad_p), _dev(zk, s)),
+                     lambda: zk.msm_srs(h, _dev(zk, bad_s)),
+                     lambda: zk.ntt(_dev(zk, bad_s)),
+                     lambda: zk.intt(_dev(zk, bad_s)),
+                     lambda: zk.coset_ntt(_dev(zk, bad_s), 2),
+                     lambda: zk.commit_job(h, _dev(zk, bad_s)),
+                     lambda: zk.msm_batch(h, _dev(zk, bad_s), np.array([0, 10, n], dtype=np.uint64)),
+                     lambda: zk.SRS(_dev(zk, bad_p))):
+            with pytest.raises(zk.ZkError) as ei:
+                call()
+            assert ei.value.code == zk.ZK_EINVAL
+        # infinity (0, 0) is a valid base
+        inf_p = host_pts.copy()
+        inf_p[3] = 0
+        zk.msm(_dev(zk, inf_p), _dev(zk, s))
+    finally:
+        zk.set_validate(False)
+    # off again: the same non-canonical input is not checked
+    zk.ntt(_dev(zk, bad_s))
+
+
 # ------------------------------------------------------------------ serving
 
 def test_serving_mix_equals_alone(zk, tau, srs_big):
