@@ -8,8 +8,9 @@ import random
 
 import pytest
 
-from oracle import field, fold, g1, msm, ntt, srs
+from oracle import field, fold, g1, kzg, msm, ntt, srs
 from tests import test_oracle_g1 as tg
+from tests import test_oracle_kzg as tk
 from tests import test_oracle_msm_fold as tm
 from tests import test_oracle_ntt as tn
 
@@ -96,3 +97,47 @@ def test_barycentric_missing_scale_is_caught(monkeypatch):
 def test_srs_generator_off_by_one_is_caught(monkeypatch):
     monkeypatch.setattr(srs, "srs", lambda tau, n: [g1.gen_mul(pow(tau, i + 1, R)) for i in range(n)])
     _fails(tm.test_srs_points, random.Random(7))
+
+
+def test_synthetic_division_sign_is_caught(monkeypatch):
+    def bad(coeffs, x):
+        f = [int(c) % R for c in coeffs]
+        if not f:
+            return [], 0
+        q, carry = [0] * (len(f) - 1), f[-1]
+        for i in range(len(f) - 2, -1, -1):
+            q[i] = carry
+            carry = (f[i] - x * carry) % R
+        return q, carry
+    monkeypatch.setattr(kzg, "divide_by_linear", bad)
+    _fails(tk.test_division_multiplies_back, random.Random(8))
+
+
+def test_quotient_index_shift_is_caught(monkeypatch):
+    def bad(coeffs, x):
+        f = [int(c) % R for c in coeffs]
+        if not f:
+            return [], 0
+        q, carry = [0] * (len(f) - 1), f[-1]
+        for i in range(len(f) - 2, -1, -1):
+            carry = (f[i] + x * carry) % R
+            q[i] = carry
+        return q, carry
+    monkeypatch.setattr(kzg, "divide_by_linear", bad)
+    _fails(tk.test_hand_worked_example)
+
+
+def test_batch_gamma_power_shift_is_caught(monkeypatch):
+    good = kzg.batch_open_at
+
+    def bad(polys, x, gamma):
+        ys, h = good(polys, x, gamma)
+        return ys, [c * gamma % R for c in h]  # gamma^(i+1) instead of gamma^i
+    monkeypatch.setattr(kzg, "batch_open_at", bad)
+    _fails(tk.test_batch_is_gamma_combination_of_single_quotients, random.Random(10))
+
+
+def test_verifier_sign_slip_is_caught(monkeypatch):
+    monkeypatch.setattr(kzg, "verify_with_trapdoor",
+                        lambda tau, com, x, y, pi: g1.add(com, g1.gen_mul(y % R)) == g1.mul((tau - x) % R, pi))
+    _fails(tk.test_verifier_equation_with_trapdoor, random.Random(11))
