@@ -153,6 +153,37 @@ uint64_t zk_ntt_workspace_bytes(uint32_t log_n);
 zk_status zk_msm_batch(const zk_srs* srs, const zk_fr* scalars, const uint64_t* offsets_host, uint32_t batch,
                        zk_g1* out, void* stream);
 
+/* KZG opening (Preliminaries, Polynomial Commitment: open): for the
+ * polynomial f with n coefficients `coeffs` (lowest degree first) and the
+ * point x,
+ *   *y     = f(x),
+ *   q(X)   = (f(X) - y) / (X - x)            (n - 1 coefficients),
+ *   *proof = [q(tau)]_1 = sum_i q_i [tau^i]_1 over the prepared SRS,
+ * so that the verifier's pairing check e(proof, [tau - x]_2) =
+ * e(com - [y]_1, [1]_2) holds for com = [f(tau)]_1.
+ *   x_host:   host zk_fr (canonical; any value, also one in a domain H).
+ *   y:        one device zk_fr.          proof: one device zk_g1.
+ *   quotient: device array of n - 1 zk_fr that receives q, or NULL (the
+ *             quotient then lives in library scratch only).
+ * Requires n - 1 <= zk_srs_size(srs).  n = 0 (the zero polynomial) gives
+ * y = 0 and proof = (0, 0); n = 1 gives y = coeffs[0] and proof = (0, 0).
+ * No buffer may overlap another. */
+zk_status zk_kzg_open(const zk_srs* srs, const zk_fr* coeffs, uint64_t n, const zk_fr* x_host, zk_fr* y,
+                      zk_fr* quotient, zk_g1* proof, void* stream);
+
+/* Batched KZG opening at one point (same passage: the prover sends every
+ * f_i(x), then one proof for the verifier's challenge gamma):
+ *   ys[i]  = f_i(x),  i < m,
+ *   h(X)   = sum_i gamma^i (f_i(X) - ys[i]) / (X - x)   (n - 1 coefficients),
+ *   *proof = [h(tau)]_1.
+ * polys: m polynomials of n coefficients each, polys[i * n + j] (pad a
+ * shorter polynomial with zero high coefficients).  gamma_host: host zk_fr,
+ * ignored (may be NULL) when m = 1.  ys: m device zk_fr.  quotient: as for
+ * zk_kzg_open (receives h).  The verifier's check is
+ * e(proof, [tau - x]_2) = e(sum_i gamma^i (com_i - [ys[i]]_1), [1]_2). */
+zk_status zk_kzg_open_batch(const zk_srs* srs, const zk_fr* polys, uint32_t m, uint64_t n, const zk_fr* x_host,
+                            const zk_fr* gamma_host, zk_fr* ys, zk_fr* quotient, zk_g1* proof, void* stream);
+
 /* Fold m instances of k G1 commitments each (inst[i*k + j]) into one:
  * the tree of pairwise folds gamma * left + right (adjacent pairs per level,
  * an odd last instance carried up, challenges consumed level by level, left

@@ -16,6 +16,7 @@
 #include "field.h"
 #include "msm.h"
 #include "ntt.h"
+#include "open.h"
 #include "prof.h"
 #include "validate.h"
 
@@ -749,6 +750,44 @@ zk_status zk_msm_batch(const zk_srs* srs, const zk_fr* scalars, const uint64_t* 
   const MsmPlan plan = msm_plan_table(offsets_host, batch, srs->c, (uint32_t)srs->n);
   return run_msm(plan, offsets_host, srs->tab, reinterpret_cast<const uint32_t*>(scalars),
                  reinterpret_cast<uint32_t*>(out), (hipStream_t)stream);
+}
+
+zk_status zk_kzg_open_batch(const zk_srs* srs, const zk_fr* polys, uint32_t m, uint64_t n, const zk_fr* x_host,
+                            const zk_fr* gamma_host, zk_fr* ys, zk_fr* quotient, zk_g1* proof, void* stream) {
+  if (!srs || !x_host || !ys || !proof || m == 0 || (n && !polys) || (m > 1 && !gamma_host))
+    return fail(ZK_EINVAL, "zk_kzg_open_batch: bad argument");
+  const uint64_t qn = n ? n - 1 : 0;
+  if (qn > srs->n) return fail(ZK_EINVAL, "zk_kzg_open_batch: n - 1 exceeds the SRS size");
+  if (n >= (1ull << 31) / 16) return fail(ZK_EUNSUPPORTED, "zk_kzg_open_batch: n too large");
+  if ((uint64_t)m * n >= (1ull << 40)) return fail(ZK_EUNSUPPORTED, "zk_kzg_open_batch: m * n too large");
+  uint32_t xw[8], gw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  std::memcpy(xw, x_host->v, 32);
+  if (m > 1) std::memcpy(gw, gamma_host->v, 32);
+  for (const uint32_t* w : {xw, gw}) {
+    unsigned br = 0;
+    for (int i = 0; i < 8; i++) (void)__builtin_subc(w[i], FrP::M32[i], br, &br);
+    if (!br) return fail(ZK_EINVAL, "zk_kzg_open_batch: x or gamma not canonical (>= r)");
+  }
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  const hipStream_t s = (hipStream_t)stream;
+  if ((st = check_inputs(c, s, {{polys, (uint64_t)m * n, false}}, "zk_kzg_open_batch"))) return st;
+  const size_t sb = open_scratch_bytes(m, n);
+  const size_t qb = quotient ? 0 : (size_t)qn * 32;
+  Scratch ws;
+  if ((st = scratch_alloc(ws, sb + qb, s))) return st;
+  uint32_t* q = quotient ? reinterpret_cast<uint32_t*>(quotient)
+                         : reinterpret_cast<uint32_t*>(static_cast<char*>(ws.p) + sb);
+  ZK_HIP(open_quotient(reinterpret_cast<const uint32_t*>(polys), m, n, xw, gw, reinterpret_cast<uint32_t*>(ys), q,
+                       ws.p, s),
+         "kzg open");
+  return msm_srs_one(srs, q, qn, reinterpret_cast<uint32_t*>(proof), s);
+}
+
+zk_status zk_kzg_open(const zk_srs* srs, const zk_fr* coeffs, uint64_t n, const zk_fr* x_host, zk_fr* y,
+                      zk_fr* quotient, zk_g1* proof, void* stream) {
+  return zk_kzg_open_batch(srs, coeffs, 1, n, x_host, nullptr, y, quotient, proof, stream);
 }
 
 zk_status zk_fold(const zk_g1* inst, const zk_fr* gammas, uint32_t m, uint32_t k, zk_g1* out, void* stream) {

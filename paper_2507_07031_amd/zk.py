@@ -23,7 +23,8 @@ MAX_LOG_NTT = 24
 EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_srs_setup", "zk_srs_create",
            "zk_srs_destroy", "zk_srs_size", "zk_msm_srs", "zk_msm_batch", "zk_fold", "zk_profile_enable",
            "zk_profile_read", "zk_msm_srs_workspace_bytes", "zk_ntt_workspace_bytes", "zk_release_cached_memory",
-           "zk_msm_srs_ex", "zk_profile_only", "zk_commit_job", "zk_set_validate")
+           "zk_msm_srs_ex", "zk_profile_only", "zk_commit_job", "zk_set_validate", "zk_kzg_open",
+           "zk_kzg_open_batch")
 
 
 class ZkError(RuntimeError):
@@ -53,6 +54,8 @@ def _load():
         "zk_set_validate": ([I], I),
         "zk_commit_job": ([P, P, I, I, P, P, P, P, P], I),
         "zk_msm_batch": ([P, P, P, U32, P, P], I),
+        "zk_kzg_open": ([P, P, U64, P, P, P, P, P], I),
+        "zk_kzg_open_batch": ([P, P, U32, U64, P, P, P, P, P, P], I),
         "zk_fold": ([P, P, U32, U32, P, P], I),
         "zk_profile_enable": ([I], I),
         "zk_release_cached_memory": ([], I),
@@ -261,6 +264,50 @@ def msm_batch(srs, scalars, offsets, out=None):
     _check(lib.zk_msm_batch(srs.handle, _ptr(scalars), off.ctypes.data_as(ctypes.c_void_p), batch, _ptr(out),
                             _stream(scalars)))
     return out
+
+
+def kzg_open(srs, coeffs, x, n=None, y=None, quotient=None, proof=None, want_quotient=False):
+    """KZG opening of the polynomial with coefficients `coeffs` (n, 8) at the
+    host Fr value x (8 words).  Returns (y, quotient or None, proof)."""
+    coeffs = _dev_words(coeffs, 8, "coeffs")
+    n = int(n if n is not None else coeffs.shape[0])
+    if n > coeffs.shape[0]:
+        raise ValueError("n exceeds the coefficients")
+    torch = _torch()
+    dev = coeffs.device
+    if y is None:
+        y = torch.empty((1, 8), dtype=torch.int32, device=dev)
+    if quotient is None and want_quotient:
+        quotient = torch.empty((max(n - 1, 0), 8), dtype=torch.int32, device=dev)
+    if proof is None:
+        proof = torch.empty((1, 16), dtype=torch.int32, device=dev)
+    xa, xp = _host_fr(x)
+    qp = _ptr(quotient) if quotient is not None else None
+    _check(lib.zk_kzg_open(srs.handle, _ptr(coeffs), n, xp, _ptr(y), qp, _ptr(proof), _stream(coeffs)))
+    return y, quotient, proof
+
+
+def kzg_open_batch(srs, polys, x, gamma, ys=None, quotient=None, proof=None, want_quotient=False):
+    """Batched opening of m polynomials polys (m, n, 8) at x with challenge
+    gamma (host Fr values).  Returns (ys (m, 8), quotient or None, proof)."""
+    torch = _torch()
+    if (not isinstance(polys, torch.Tensor) or not polys.is_cuda or polys.dim() != 3 or polys.shape[2] != 8
+            or polys.dtype != torch.int32 or not polys.is_contiguous()):
+        raise TypeError("polys must be a contiguous int32 device tensor of shape (m, n, 8)")
+    m, n = int(polys.shape[0]), int(polys.shape[1])
+    dev = polys.device
+    if ys is None:
+        ys = torch.empty((m, 8), dtype=torch.int32, device=dev)
+    if quotient is None and want_quotient:
+        quotient = torch.empty((max(n - 1, 0), 8), dtype=torch.int32, device=dev)
+    if proof is None:
+        proof = torch.empty((1, 16), dtype=torch.int32, device=dev)
+    xa, xp = _host_fr(x)
+    ga, gp = _host_fr(gamma)
+    qp = _ptr(quotient) if quotient is not None else None
+    _check(lib.zk_kzg_open_batch(srs.handle, _ptr(polys), m, n, xp, gp, _ptr(ys), qp, _ptr(proof),
+                                 _stream(polys)))
+    return ys, quotient, proof
 
 
 def fold(inst, gammas, out=None):
