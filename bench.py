@@ -329,6 +329,53 @@ def main():
                                      "p90": round(float(np.percentile(lat, 90)), 4),
                                      "min": round(float(lat.min()), 4), "reps": int(lat.size)}
 
+        log("kzg opening 2^20")
+        # KZG opening of the committed polynomial at a point (quotient by
+        # X - x, then its MSM), and a batched opening of 8 polynomials at one
+        # point; the division scan is HBM-bound: 32 B per coefficient read per
+        # polynomial plus 32 B per quotient coefficient written
+        xw = gen.uniform_fr(gen.CONFIG_SEEDS["commit"], 1, tag=11)[0]
+        gw = gen.uniform_fr(gen.CONFIG_SEEDS["commit"], 1, tag=12)[0]
+        y1 = torch.empty((1, 8), dtype=torch.int32, device=dev)
+        pi = torch.empty((1, 16), dtype=torch.int32, device=dev)
+        zk.intt(evals, out=coeffs)
+        torch.cuda.synchronize()
+        kzg = {}
+        for m_open in (1, 8):
+            if m_open == 1:
+                def run_open():
+                    zk.kzg_open(srs, coeffs, xw, y=y1, proof=pi)
+            else:
+                polys = torch.stack([zk.to_device(gen.uniform_fr(gen.CONFIG_SEEDS["commit"], n, tag=20 + i))
+                                     for i in range(m_open)])
+                ys8 = torch.empty((m_open, 8), dtype=torch.int32, device=dev)
+
+                def run_open():
+                    zk.kzg_open_batch(srs, polys, xw, gw, ys=ys8, proof=pi)
+            t_open = timed(run_open, reps=10)
+            for reg in ("open.scan", "msm.sort", "msm.accumulate", "msm.reduce"):
+                zk.profile_read(reg)
+            zk.profile_enable(True)
+            for _ in range(10):
+                run_open()
+            torch.cuda.synchronize()
+            zk.profile_enable(False)
+            scan_ms, scan_n = zk.profile_read("open.scan")
+            scan_ms /= max(scan_n, 1)
+            msm_ms = sum(zk.profile_read(reg)[0] for reg in ("msm.sort", "msm.accumulate", "msm.reduce")) / 10
+            alg_bytes = 32 * m_open * n + 32 * (n - 1)
+            products = (2 * m_open - 1) * n
+            kzg["open_m%d" % m_open] = {
+                "polys": m_open, "coeffs": n, "ms": round(t_open, 4), "openings_per_s": round(1e3 / t_open, 2),
+                "scan_ms": round(scan_ms, 4), "msm_ms_profiled": round(msm_ms, 4),
+                "scan_hbm_gbs": round(alg_bytes / (scan_ms / 1e3) / 1e9, 1),
+                "scan_hbm_frac": round(alg_bytes / (scan_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+                "scan_int_frac": round(products * MADS_PER_MONT / (scan_ms / 1e3) / 1e12 / PEAK_MAD_TOPS, 4),
+                "scan_alg_bytes": alg_bytes, "scan_min_fr_products": products}
+            if m_open > 1:
+                del polys, ys8
+        extras["kzg_open_2^20"] = kzg
+
         log("quantized 2^22")
         N22 = 1 << 22
         q = zk.to_device(gen.quantized_fr(gen.CONFIG_SEEDS["quantized"], N22))

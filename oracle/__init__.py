@@ -22,6 +22,9 @@ Accumulation"):
 * ``fold``  -- the random linear combination gamma*v + v' of the accumulation
   prover (Parallel Accumulation, prover step 5) and its tree schedule.
 * ``srs``   -- [tau^i]_1 for a known test trapdoor (Polynomial Commitment: srs).
+* ``kzg``   -- opening y = f(x), q = (f - y)/(X - x), pi = [q(tau)]_1, and the
+  batched opening at one point with challenge powers gamma^i (Polynomial
+  Commitment: open, batching), plus the verifier equation with tau known.
 
 Every function here is pinned by a CPU test against something other than
 itself (closed forms, invariants, brute force); see ``tests/test_oracle_*``.
