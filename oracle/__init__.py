@@ -25,6 +25,8 @@ Accumulation"):
 * ``kzg``   -- opening y = f(x), q = (f - y)/(X - x), pi = [q(tau)]_1, and the
   batched opening at one point with challenge powers gamma^i (Polynomial
   Commitment: open, batching), plus the verifier equation with tau known.
+* ``quotient`` -- the Mul block's quotient t = (f h - g) / (X^n - 1) from the
+  witness vectors, by transform-based product and long division (Mul).
 
 Every function here is pinned by a CPU test against something other than
 itself (closed forms, invariants, brute force); see ``tests/test_oracle_*``.

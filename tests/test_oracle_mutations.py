@@ -8,9 +8,10 @@ import random
 
 import pytest
 
-from oracle import field, fold, g1, kzg, msm, ntt, srs
+from oracle import field, fold, g1, kzg, msm, ntt, quotient, srs
 from tests import test_oracle_g1 as tg
 from tests import test_oracle_kzg as tk
+from tests import test_oracle_quotient as tq
 from tests import test_oracle_msm_fold as tm
 from tests import test_oracle_ntt as tn
 
@@ -141,3 +142,29 @@ def test_verifier_sign_slip_is_caught(monkeypatch):
     monkeypatch.setattr(kzg, "verify_with_trapdoor",
                         lambda tau, com, x, y, pi: g1.add(com, g1.gen_mul(y % R)) == g1.mul((tau - x) % R, pi))
     _fails(tk.test_verifier_equation_with_trapdoor, random.Random(11))
+
+
+def test_vanishing_division_sign_is_caught(monkeypatch):
+    def bad(p, n):
+        work = [int(c) % R for c in p]
+        if len(work) <= n:
+            return [], work + [0] * (n - len(work))
+        t = [0] * (len(work) - n)
+        for i in range(len(work) - 1, n - 1, -1):
+            c = work[i]
+            t[i - n] = (t[i - n] + c) % R
+            work[i - n] = (work[i - n] - c) % R
+            work[i] = 0
+        return t, work[:n]
+    monkeypatch.setattr(quotient, "divide_by_vanishing", bad)
+    _fails(tq.test_division_multiplies_back, random.Random(12))
+
+
+def test_cyclic_product_is_caught(monkeypatch):
+    def bad(f, h):
+        size = max(len(f), len(h))
+        F = ntt.fft(list(f) + [0] * (size - len(f)))
+        H = ntt.fft(list(h) + [0] * (size - len(h)))
+        return ntt.ifft([x * y % R for x, y in zip(F, H)]) + [0] * (len(f) + len(h) - 1 - size)
+    monkeypatch.setattr(quotient, "poly_mul_fft", bad)
+    _fails(tq.test_two_point_domain_by_hand, random.Random(13))
