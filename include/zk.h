@@ -184,6 +184,25 @@ zk_status zk_kzg_open(const zk_srs* srs, const zk_fr* coeffs, uint64_t n, const 
 zk_status zk_kzg_open_batch(const zk_srs* srs, const zk_fr* polys, uint32_t m, uint64_t n, const zk_fr* x_host,
                             const zk_fr* gamma_host, zk_fr* ys, zk_fr* quotient, zk_g1* proof, void* stream);
 
+/* Quotient of the Mul basic block (Foldable basic blocks, Mul): for witness
+ * vectors a, b, c on H (n = 2^log_n elements each, c_i = a_i b_i) with
+ * interpolants f, h, g (element i = value at omega^i),
+ *   t(X) = (f(X) h(X) - g(X)) / (X^n - 1)          (degree <= n - 2),
+ *   t_coeffs[i] = t_i, i < n (t_coeffs[n - 1] = 0),
+ *   *t_commit   = [t(tau)]_1 over the first n SRS points.
+ * Computed on the coset s H_(B n), B = 2^log_blowup (1 <= log_blowup <= 4;
+ * B = 2 is enough for this degree): the coset evaluations of f, h, g, the
+ * pointwise (f h - g) / (X^n - 1) (B distinct divisor values), the inverse
+ * coset transform, then the commitment.  shift_host: s as a host zk_fr, or
+ * NULL for s = 5; a shift whose coset meets a root of X^n - 1 is rejected.
+ * If c is not the entrywise product of a and b there is no such quotient:
+ * the result is then the interpolant of (f h - g) / (X^n - 1) on the coset.
+ * Requires n <= zk_srs_size(srs) and log_n + log_blowup <= ZK_MAX_LOG_NTT.
+ * Scratch: 32 (n + 3 B n) bytes from the library cache. */
+zk_status zk_quotient_mul(const zk_srs* srs, const zk_fr* a, const zk_fr* b, const zk_fr* c, uint32_t log_n,
+                          uint32_t log_blowup, const zk_fr* shift_host, zk_fr* t_coeffs, zk_g1* t_commit,
+                          void* stream);
+
 /* Fold m instances of k G1 commitments each (inst[i*k + j]) into one:
  * the tree of pairwise folds gamma * left + right (adjacent pairs per level,
  * an odd last instance carried up, challenges consumed level by level, left

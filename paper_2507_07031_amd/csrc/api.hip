@@ -18,6 +18,7 @@
 #include "ntt.h"
 #include "open.h"
 #include "prof.h"
+#include "quotient.h"
 #include "validate.h"
 
 using namespace zk;
@@ -59,6 +60,7 @@ struct DeviceCtx {
   bool ready = false;
   f29* tw[4] = {nullptr, nullptr, nullptr, nullptr};   // fwd lo, fwd hi, inv lo, inv hi
   f29* coset5[2] = {nullptr, nullptr};                  // 5^e lo / hi
+  f29* coset5inv[2] = {nullptr, nullptr};               // 5^-e lo / hi
   f29* ninv = nullptr;                                  // 2^-L, L = 0..28
   uint32_t* gtab = nullptr;                             // 2^j G table for the setup
   uint32_t* vflag = nullptr;                            // input-check findings (zk_set_validate)
@@ -88,6 +90,7 @@ zk_status ctx_get(DeviceCtx** out) {
   const size_t tsz = sizeof(f29) << 14;
   for (int i = 0; i < 4; i++) ZK_HIP(hipMalloc(&c.tw[i], tsz), "hipMalloc(twiddles)");
   for (int i = 0; i < 2; i++) ZK_HIP(hipMalloc(&c.coset5[i], tsz), "hipMalloc(coset)");
+  for (int i = 0; i < 2; i++) ZK_HIP(hipMalloc(&c.coset5inv[i], tsz), "hipMalloc(coset)");
   ZK_HIP(hipMalloc(&c.ninv, sizeof(f29) * 29), "hipMalloc(ninv)");
   ZK_HIP(hipMalloc(&c.gtab, srs_gtab_words() * 4), "hipMalloc(gtab)");
   ZK_HIP(hipMalloc(&c.vflag, 4), "hipMalloc(vflag)");
@@ -103,6 +106,11 @@ zk_status ctx_get(DeviceCtx** out) {
   ZK_HIP(ntt_make_pow_tables(wf, c.tw[0], c.tw[1], 0), "twiddle tables");
   ZK_HIP(ntt_make_pow_tables(wi, c.tw[2], c.tw[3], 0), "twiddle tables");
   ZK_HIP(ntt_make_pow_tables(w5, c.coset5[0], c.coset5[1], 0), "coset tables");
+  {
+    Words8 w5i;
+    host_words(from_mont<FrP>(mont_inv<FrP>(reduce_full<FrP>(to_mont<FrP>(unpack(w5.w))))), w5i.w);
+    ZK_HIP(ntt_make_pow_tables(w5i, c.coset5inv[0], c.coset5inv[1], 0), "coset tables");
+  }
   // 2^-L in Montgomery form; 2^-1 = (r + 1) / 2
   f29 ninv[29];
   {
@@ -788,6 +796,82 @@ zk_status zk_kzg_open_batch(const zk_srs* srs, const zk_fr* polys, uint32_t m, u
 zk_status zk_kzg_open(const zk_srs* srs, const zk_fr* coeffs, uint64_t n, const zk_fr* x_host, zk_fr* y,
                       zk_fr* quotient, zk_g1* proof, void* stream) {
   return zk_kzg_open_batch(srs, coeffs, 1, n, x_host, nullptr, y, quotient, proof, stream);
+}
+
+zk_status zk_quotient_mul(const zk_srs* srs, const zk_fr* a, const zk_fr* b, const zk_fr* c_evals, uint32_t log_n,
+                          uint32_t log_blowup, const zk_fr* shift_host, zk_fr* t_coeffs, zk_g1* t_commit,
+                          void* stream) {
+  if (!srs || !a || !b || !c_evals || !t_coeffs || !t_commit) return fail(ZK_EINVAL, "zk_quotient_mul: NULL argument");
+  if (log_blowup < 1 || log_blowup > QUOT_MAX_LOG_BLOWUP)
+    return fail(ZK_EINVAL, "zk_quotient_mul: log_blowup must be 1..4");
+  if (log_n > ZK_MAX_LOG_NTT || log_n + log_blowup > ZK_MAX_LOG_NTT)
+    return fail(ZK_EUNSUPPORTED, "zk_quotient_mul: log_n + log_blowup > ZK_MAX_LOG_NTT");
+  const uint64_t n = 1ull << log_n;
+  if (n > srs->n) return fail(ZK_EINVAL, "zk_quotient_mul: 2^log_n exceeds the SRS size");
+  // shift s (Montgomery form) and the B values s^n omega_B^k - 1 of the vanishing polynomial
+  uint32_t sw[8] = {5, 0, 0, 0, 0, 0, 0, 0};
+  if (shift_host) {
+    std::memcpy(sw, shift_host->v, 32);
+    unsigned br = 0;
+    for (int i = 0; i < 8; i++) (void)__builtin_subc(sw[i], FrP::M32[i], br, &br);
+    if (!br) return fail(ZK_EINVAL, "zk_quotient_mul: shift not canonical (>= r)");
+  }
+  const f29 one = f29_from(FrP::ONE);
+  const f29 sm = reduce_full<FrP>(to_mont<FrP>(unpack(sw)));
+  if (f29_is_zero_limbs(sm)) return fail(ZK_EINVAL, "zk_quotient_mul: shift is zero");
+  f29 sn = sm;  // s^n by log_n squarings
+  for (uint32_t i = 0; i < log_n; i++) sn = reduce_full<FrP>(mont_mul<FrP>(sn, sn));
+  f29 wb = reduce_full<FrP>(to_mont<FrP>(unpack(FR_OMEGA_2_28)));  // omega_B = omega_(2^28)^(2^(28 - log_b))
+  for (uint32_t i = 0; i < 28 - log_blowup; i++) wb = reduce_full<FrP>(mont_mul<FrP>(wb, wb));
+  QuotZinv zi;
+  {
+    f29 pk = sn;
+    for (uint32_t k = 0; k < (1u << log_blowup); k++) {
+      const f29 z = reduce_full<FrP>(sub_k(pk, one, FrP::K2));
+      if (f29_is_zero_limbs(z)) return fail(ZK_EINVAL, "zk_quotient_mul: X^n - 1 vanishes on the coset (bad shift)");
+      zi.zinv_r2[k] = reduce_full<FrP>(mont_mul<FrP>(mont_inv<FrP>(z), f29_from(FrP::R2)));
+      pk = reduce_full<FrP>(mont_mul<FrP>(pk, wb));
+    }
+    for (uint32_t k = 1u << log_blowup; k < (1u << QUOT_MAX_LOG_BLOWUP); k++) zi.zinv_r2[k] = f29_zero();
+  }
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  const hipStream_t s = (hipStream_t)stream;
+  if ((st = check_inputs(c, s, {{a, n, false}, {b, n, false}, {c_evals, n, false}}, "zk_quotient_mul"))) return st;
+  const uint32_t L = log_n + log_blowup;
+  const uint64_t big = 1ull << L;
+  const size_t tsz = sizeof(f29) << 14;
+  Scratch ws;
+  if ((st = scratch_alloc(ws, (size_t)32 * (n + 3 * big) + (shift_host ? 4 * tsz : 0), s))) return st;
+  uint32_t* coef = static_cast<uint32_t*>(ws.p);
+  uint32_t* E[3] = {coef + 8 * n, coef + 8 * (n + big), coef + 8 * (n + 2 * big)};
+  const f29 *lo = c->coset5[0], *hi = c->coset5[1], *ilo = c->coset5inv[0], *ihi = c->coset5inv[1];
+  if (shift_host) {
+    f29* t = reinterpret_cast<f29*>(coef + 8 * (n + 3 * big));
+    Words8 fw, iw;
+    std::memcpy(fw.w, sw, 32);
+    host_words(from_mont<FrP>(mont_inv<FrP>(sm)), iw.w);
+    ZK_HIP(ntt_make_pow_tables(fw, t, t + (1u << 14), s), "shift tables");
+    ZK_HIP(ntt_make_pow_tables(iw, t + (2u << 14), t + (3u << 14), s), "shift tables");
+    lo = t;
+    hi = t + (1u << 14);
+    ilo = t + (2u << 14);
+    ihi = t + (3u << 14);
+  }
+  // f, h, g on the coset: coefficients, then the coset transform of each
+  const zk_fr* in[3] = {a, b, c_evals};
+  for (int k = 0; k < 3; k++) {
+    if ((st = run_ntt(c, reinterpret_cast<const uint32_t*>(in[k]), coef, log_n, true, nullptr, nullptr, (uint32_t)n,
+                      s)))
+      return st;
+    if ((st = run_ntt(c, coef, E[k], L, false, lo, hi, (uint32_t)n, s))) return st;
+  }
+  // t on the coset, then its coefficients: inverse transform, times s^-i
+  ZK_HIP(quot_mul_pointwise(E[0], E[1], E[2], big, log_blowup, zi, s), "quotient pointwise");
+  if ((st = run_ntt(c, E[0], E[0], L, true, nullptr, nullptr, (uint32_t)big, s))) return st;
+  ZK_HIP(quot_scale_powers(E[0], n, ilo, ihi, reinterpret_cast<uint32_t*>(t_coeffs), s), "quotient scale");
+  return msm_srs_one(srs, reinterpret_cast<const uint32_t*>(t_coeffs), n, reinterpret_cast<uint32_t*>(t_commit), s);
 }
 
 zk_status zk_fold(const zk_g1* inst, const zk_fr* gammas, uint32_t m, uint32_t k, zk_g1* out, void* stream) {

@@ -24,7 +24,7 @@ EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_s
            "zk_srs_destroy", "zk_srs_size", "zk_msm_srs", "zk_msm_batch", "zk_fold", "zk_profile_enable",
            "zk_profile_read", "zk_msm_srs_workspace_bytes", "zk_ntt_workspace_bytes", "zk_release_cached_memory",
            "zk_msm_srs_ex", "zk_profile_only", "zk_commit_job", "zk_set_validate", "zk_kzg_open",
-           "zk_kzg_open_batch")
+           "zk_kzg_open_batch", "zk_quotient_mul")
 
 
 class ZkError(RuntimeError):
@@ -55,6 +55,7 @@ def _load():
         "zk_commit_job": ([P, P, I, I, P, P, P, P, P], I),
         "zk_msm_batch": ([P, P, P, U32, P, P], I),
         "zk_kzg_open": ([P, P, U64, P, P, P, P, P], I),
+        "zk_quotient_mul": ([P, P, P, P, U32, U32, P, P, P, P], I),
         "zk_kzg_open_batch": ([P, P, U32, U64, P, P, P, P, P, P], I),
         "zk_fold": ([P, P, U32, U32, P, P], I),
         "zk_profile_enable": ([I], I),
@@ -308,6 +309,29 @@ def kzg_open_batch(srs, polys, x, gamma, ys=None, quotient=None, proof=None, wan
     _check(lib.zk_kzg_open_batch(srs.handle, _ptr(polys), m, n, xp, gp, _ptr(ys), qp, _ptr(proof),
                                  _stream(polys)))
     return ys, quotient, proof
+
+
+def quotient_mul(srs, a, b, c, log_blowup=1, shift=None, t=None, com=None):
+    """Mul-block quotient t = (f h - g) / (X^n - 1) of witness vectors a, b, c
+    (each (n, 8), n a power of two) and its commitment.  Returns (t, com)."""
+    a = _dev_words(a, 8, "a")
+    b = _dev_words(b, 8, "b")
+    c = _dev_words(c, 8, "c")
+    n = a.shape[0]
+    L = n.bit_length() - 1
+    if (1 << L) != n or b.shape[0] != n or c.shape[0] != n:
+        raise ValueError("a, b, c must have one power-of-two length")
+    torch = _torch()
+    if t is None:
+        t = torch.empty_like(a)
+    if com is None:
+        com = torch.empty((1, 16), dtype=torch.int32, device=a.device)
+    sp = None
+    if shift is not None:
+        sa, sp = _host_fr(shift)
+    _check(lib.zk_quotient_mul(srs.handle, _ptr(a), _ptr(b), _ptr(c), L, int(log_blowup), sp, _ptr(t), _ptr(com),
+                               _stream(a)))
+    return t, com
 
 
 def fold(inst, gammas, out=None):

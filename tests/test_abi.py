@@ -54,6 +54,8 @@ def test_argument_errors_return_before_device_work(zk):
     assert L.zk_commit_job(dummy, dummy, 20, 5, null, dummy, dummy, dummy, null) == zk.ZK_EUNSUPPORTED
     assert L.zk_set_validate(0) == zk.ZK_OK
     assert L.zk_kzg_open(null, dummy, 4, dummy, dummy, null, dummy, null) == zk.ZK_EINVAL
+    assert L.zk_quotient_mul(null, dummy, dummy, dummy, 4, 1, null, dummy, dummy, null) == zk.ZK_EINVAL
+    assert L.zk_quotient_mul(dummy, dummy, dummy, dummy, 4, 0, null, dummy, dummy, null) == zk.ZK_EINVAL
     assert L.zk_kzg_open_batch(dummy, dummy, 0, 4, dummy, dummy, dummy, null, dummy, null) == zk.ZK_EINVAL
     assert L.zk_kzg_open_batch(dummy, dummy, 2, 4, dummy, null, dummy, null, dummy, null) == zk.ZK_EINVAL
     assert L.zk_srs_size(null) == 0
