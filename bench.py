@@ -376,6 +376,38 @@ def main():
                 del polys, ys8
         extras["kzg_open_2^20"] = kzg
 
+        log("quotient 2^20")
+        # Mul-block quotient t = (f h - g)/(X^n - 1) from three 2^20 witness
+        # vectors (c = a*b), on cosets of 2x and 4x the domain, and its commitment
+        qa_h = gen.uniform_fr(gen.CONFIG_SEEDS["commit"], n, tag=31)
+        qb_h = gen.uniform_fr(gen.CONFIG_SEEDS["commit"], n, tag=32)
+        qc_h = gen.ints_to_limbs([x * y % gen.FR_MODULUS for x, y in
+                                  zip(gen.limbs_to_ints(qa_h), gen.limbs_to_ints(qb_h))]).reshape(n, 8)
+        qa, qb, qc = zk.to_device(qa_h), zk.to_device(qb_h), zk.to_device(qc_h)
+        qt = torch.empty_like(qa)
+        quot = {}
+        for lb in (1, 2):
+            t_q = timed(lambda: zk.quotient_mul(srs, qa, qb, qc, log_blowup=lb, t=qt, com=com), reps=5)
+            for reg in ("quot.pointwise", "ntt.pass", "msm.sort", "msm.accumulate", "msm.reduce"):
+                zk.profile_read(reg)
+            zk.profile_enable(True)
+            for _ in range(5):
+                zk.quotient_mul(srs, qa, qb, qc, log_blowup=lb, t=qt, com=com)
+            torch.cuda.synchronize()
+            zk.profile_enable(False)
+            pw_ms = zk.profile_read("quot.pointwise")[0] / 5
+            ntt_ms = zk.profile_read("ntt.pass")[0] / 5
+            msm_q = sum(zk.profile_read(reg)[0] for reg in ("msm.sort", "msm.accumulate", "msm.reduce")) / 5
+            big = n << lb
+            quot["blowup_%d" % (1 << lb)] = {
+                "ms": round(t_q, 4), "quotients_per_s": round(1e3 / t_q, 2),
+                "transforms_ms": round(ntt_ms, 4), "msm_ms": round(msm_q, 4),
+                "pointwise_ms": round(pw_ms, 4),
+                "pointwise_hbm_frac": round(4 * 32 * big / (pw_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+                "pointwise_int_frac": round(3 * big * MADS_PER_MONT / (pw_ms / 1e3) / 1e12 / PEAK_MAD_TOPS, 4)}
+        extras["quotient_mul_2^20"] = quot
+        del qa, qb, qc, qt
+
         log("quantized 2^22")
         N22 = 1 << 22
         q = zk.to_device(gen.quantized_fr(gen.CONFIG_SEEDS["quantized"], N22))
