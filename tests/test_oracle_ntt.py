@@ -113,3 +113,22 @@ def test_barycentric_matches_interpolation(rng):
         v = _vec(rng, n)
         x = rng.randrange(R)
         assert ntt.barycentric_eval(v, x) == ntt.horner(ntt.ifft(v), x)
+
+
+def test_lagrange_basis_pins(rng):
+    from oracle import srs as osrs
+    n = 16
+    w = ntt.root_of_unity(n)
+    tau = rng.randrange(R)
+    lj = [osrs.lagrange_basis_at(tau, n, j) for j in range(n)]
+    # partition of unity, and the basis reproduces every monomial X^k, k < n
+    assert sum(lj) % R == 1
+    for k in (1, 5, n - 1):
+        assert sum(l * pow(w, j * k, R) for j, l in enumerate(lj)) % R == pow(tau, k, R)
+    # l_j is the interpolant of the j-th unit vector (inverse transform, Horner)
+    for j in (0, 3):
+        e = [0] * n
+        e[j] = 1
+        assert lj[j] == ntt.horner(ntt.idft(e), tau)
+    # tau on H: the basis is a unit vector
+    assert [osrs.lagrange_basis_at(pow(w, 5, R), n, j) for j in range(n)] == [int(j == 5) for j in range(n)]
