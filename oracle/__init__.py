@@ -20,7 +20,11 @@ Accumulation"):
   plain recursive FFT, coset evaluation for the X^n - 1 quotients (Mul,
   Poly-IOP), barycentric commit-from-evaluations.
 * ``fold``  -- the random linear combination gamma*v + v' of the accumulation
-  prover (Parallel Accumulation, prover step 5) and its tree schedule.
+  prover (Parallel Accumulation, prover step 5) and its tree schedule, and
+  the full step: E'' = E' + sum_j gamma^j E_j + gamma^d E, the Fr parts and
+  the error vectors.
+* ``transcript`` -- the challenge hash (the paper's random oracles, read as
+  SHA-256 to the field).
 * ``srs``   -- [tau^i]_1 for a known test trapdoor (Polynomial Commitment: srs).
 * ``kzg``   -- opening y = f(x), q = (f - y)/(X - x), pi = [q(tau)]_1, and the
   batched opening at one point with challenge powers gamma^i (Polynomial

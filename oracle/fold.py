@@ -74,3 +74,31 @@ def flat_fold(instances, gammas):
             acc = g1.add(acc, g1.mul(sig[i], instances[i][c]))
         out.append(acc)
     return out
+
+
+def fold_errors_g1(gamma: int, E, E2, Ej):
+    """E'' = E' + sum_(j=1)^(d-1) gamma^j E_j + gamma^d E (prover step 5),
+    d = len(Ej) + 1: the committed error polynomial evaluated at gamma."""
+    terms = [E2] + list(Ej) + [E]
+    acc = None
+    for j, pt in enumerate(terms):
+        acc = g1.add(acc, g1.mul(pow(gamma, j, R), pt))
+    return acc
+
+
+def fold_errors_fr(gamma: int, e, e2, ej):
+    """e'' = e' + sum_j gamma^j e_j + gamma^d e, elementwise over Fr vectors."""
+    vecs = [e2] + list(ej) + [e]
+    return [sum(pow(gamma, j, R) * int(v[i]) for j, v in enumerate(vecs)) % R for i in range(len(e))]
+
+
+def fold_fr(gamma: int, v, v2):
+    """v'' = gamma v + v' over the Fr parts (mu, pi, r_i, m_i)."""
+    return [(gamma * int(a) + int(b)) % R for a, b in zip(v, v2)]
+
+
+def acc_fold(gamma: int, C, C2, E, E2, Ej, v, v2, e, e2, ej):
+    """One accumulation step on two accumulators (C, E, v, e) and
+    (C2, E2, v2, e2): (C'', E'', v'', e'')."""
+    return (fold_pair(gamma, C, C2), fold_errors_g1(gamma, E, E2, Ej), fold_fr(gamma, v, v2),
+            fold_errors_fr(gamma, e, e2, ej))

@@ -12,6 +12,7 @@ from oracle import field, fold, g1, kzg, msm, ntt, quotient, srs
 from tests import test_oracle_g1 as tg
 from tests import test_oracle_kzg as tk
 from tests import test_oracle_quotient as tq
+from tests import test_oracle_accum as ta
 from tests import test_oracle_msm_fold as tm
 from tests import test_oracle_ntt as tn
 
@@ -168,3 +169,22 @@ def test_cyclic_product_is_caught(monkeypatch):
         return ntt.ifft([x * y % R for x, y in zip(F, H)]) + [0] * (len(f) + len(h) - 1 - size)
     monkeypatch.setattr(quotient, "poly_mul_fft", bad)
     _fails(tq.test_two_point_domain_by_hand, random.Random(13))
+
+
+def test_error_fold_roles_swapped_is_caught(monkeypatch):
+    good = fold.fold_errors_g1
+    monkeypatch.setattr(fold, "fold_errors_g1", lambda gam, E, E2, Ej: good(gam, E2, E, Ej))
+    _fails(ta.test_two_term_case, random.Random(14))
+
+
+def test_fr_fold_operands_swapped_is_caught(monkeypatch):
+    monkeypatch.setattr(fold, "fold_fr", lambda gam, v, v2: [(gam * b + a) % R for a, b in zip(v, v2)])
+    _fails(ta.test_commitment_homomorphism, random.Random(15))
+
+
+def test_error_power_off_by_one_is_caught(monkeypatch):
+    def bad(gam, e, e2, ej):
+        vecs = [e2] + list(ej) + [e]
+        return [sum(pow(gam, j + (j > 0), R) * int(v[i]) for j, v in enumerate(vecs)) % R for i in range(len(e))]
+    monkeypatch.setattr(fold, "fold_errors_fr", bad)
+    _fails(ta.test_error_polynomial_extraction, random.Random(16))
