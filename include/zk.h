@@ -99,6 +99,20 @@ zk_status zk_msm(const zk_g1* bases, const zk_fr* scalars, uint64_t n, zk_g1* ou
  * G = (1, 2).  tau_host: host zk_fr. */
 zk_status zk_srs_setup(const zk_fr* tau_host, uint64_t n, zk_g1* out, void* stream);
 
+/* KZG setup in the Lagrange basis of H = {omega^j : j < n}, n = 2^log_n, for
+ * a known trapdoor (Polynomial Commitment: srs; the vector encoding of
+ * Foldable basic blocks): out[j] = [l_j(tau)]_1, where l_j is the polynomial
+ * of degree < n with l_j(omega^i) = 1 if i = j and 0 otherwise.  A vector v
+ * of evaluations on H then commits as sum_j v_j out[j] = [f(tau)]_1 for the
+ * interpolant f of v: zk_msm_srs over an SRS prepared from these points
+ * commits evaluations directly, without the inverse NTT, and small entries
+ * (quantized activations) stay small scalars.  A prefix of m < n points is
+ * not a Lagrange basis of a smaller domain: commit vectors of length n
+ * (shorter vectors are read as zero-padded to n).  out: n zk_g1.  Test and
+ * benchmark use; deployments load a ceremony's Lagrange-form points and call
+ * zk_srs_create. */
+zk_status zk_srs_lagrange_setup(const zk_fr* tau_host, uint32_t log_n, zk_g1* out, void* stream);
+
 /* Prepare an SRS (any n affine points, e.g. from zk_srs_setup or a
  * ceremony) for commitments.  Allocates 16 * 64 * n bytes (the points times
  * 2^(16 w), w < 16) plus 32 * 64 * min(n, 2^15) bytes (times 2^(8 w), for
@@ -202,6 +216,35 @@ zk_status zk_kzg_open_batch(const zk_srs* srs, const zk_fr* polys, uint32_t m, u
 zk_status zk_quotient_mul(const zk_srs* srs, const zk_fr* a, const zk_fr* b, const zk_fr* c, uint32_t log_n,
                           uint32_t log_blowup, const zk_fr* shift_host, zk_fr* t_coeffs, zk_g1* t_commit,
                           void* stream);
+
+/* Fiat-Shamir challenge from a transcript (the random oracles rho_acc and
+ * rho_NARK of Parallel Accumulation, which the paper leaves unspecified):
+ *   *challenge = (SHA-256(0x00 || data) || SHA-256(0x01 || data)) mod r,
+ * the two 32-byte digests read as one 512-bit little-endian integer (SHA-256
+ * as FIPS 180-4 defines it).  data: `bytes` bytes of device memory (e.g.
+ * the instances' commitments, E terms and Fr parts, as stored); challenge:
+ * one device zk_fr, usable directly as zk_acc_fold's gamma.  One workgroup;
+ * meant for transcripts of kilobytes. */
+zk_status zk_transcript_challenge(const void* data, uint64_t bytes, zk_fr* challenge, void* stream);
+
+/* One step of the accumulation prover (Parallel Accumulation, prover steps
+ * 5-6) on the device parts of two accumulators: acc = (C, E, v, e), weighted
+ * by gamma, and acc' = (C2, E2, v2, e2), with the correction terms E_j and
+ * the error vectors e_j of the relation of degree d (1 <= d <= 15):
+ *   C_out[i] = gamma C[i] + C2[i],                         i < k
+ *   *E_out   = E2 + sum_(j=1)^(d-1) gamma^j Ej[j-1] + gamma^d E
+ *   v_out[i] = gamma v[i] + v2[i],                         i < len_v
+ *              (the Fr parts mu, pi, r_i, m_i, concatenated by the caller)
+ *   e_out[i] = e2[i] + sum_(j=1)^(d-1) gamma^j ej[(j-1) len_e + i] + gamma^d e[i]
+ * G1 arguments are zk_g1 arrays ((0, 0) = infinity), Fr arguments zk_fr
+ * arrays, gamma one device zk_fr (e.g. from zk_transcript_challenge).  Ej
+ * and ej may be NULL when d = 1; Fr parts of length 0 may be NULL.  The
+ * new mu'' = gamma mu + mu' is the first element of v_out when mu leads v.
+ * Outputs must not overlap inputs. */
+zk_status zk_acc_fold(uint32_t k, const zk_g1* C, const zk_g1* C2, uint32_t d, const zk_g1* E, const zk_g1* E2,
+                      const zk_g1* Ej, uint64_t len_v, const zk_fr* v, const zk_fr* v2, uint64_t len_e,
+                      const zk_fr* e, const zk_fr* e2, const zk_fr* ej, const zk_fr* gamma, zk_g1* C_out,
+                      zk_g1* E_out, zk_fr* v_out, zk_fr* e_out, void* stream);
 
 /* Fold m instances of k G1 commitments each (inst[i*k + j]) into one:
  * the tree of pairwise folds gamma * left + right (adjacent pairs per level,

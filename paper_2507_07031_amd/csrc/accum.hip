@@ -1,0 +1,276 @@
+// One step of the accumulation prover (Parallel Accumulation, prover steps
+// 4-6) on the device parts of two accumulators acc (weighted by gamma) and
+// acc':
+//   C''_i = gamma C_i + C'_i                       (the k G1 commitments)
+//   E''   = E' + sum_(j=1)^(d-1) gamma^j E_j + gamma^d E    (committed errors)
+//   v''   = gamma v + v'                           (Fr parts: mu, pi, r_i, m_i)
+//   e''   = e' + sum_j gamma^j e_j + gamma^d e     (Fr error vectors)
+// and the challenge gamma derived from a transcript by hashing.
+//
+// The G1 outputs are short sums of scalar multiples by powers of one
+// challenge, all independent: each runs in one quad (curve_quad.h) by
+// Straus's method with 4-bit windows, the table of 1..15 times every point
+// kept in scratch memory, 64 window steps of four doublings and one
+// addition per nonzero digit.  The Fr parts are elementwise Horner
+// combinations streamed through HBM.
+#include "accum.h"
+#include "curve.h"
+#include "curve_quad.h"
+#include "msm_store.h"
+#include "prof.h"
+
+namespace zk {
+
+namespace {
+
+constexpr uint32_t ACC_NT = 64;        // threads per workgroup: 16 quads
+constexpr uint32_t TAB_WORDS = 16 * 36;  // one term's table: multiples 0..15, 36 words each
+constexpr uint32_t RLC_NT = 256;
+
+__device__ __forceinline__ void ld8w(const uint32_t* p, uint32_t w[8]) {
+  const uint4 a = reinterpret_cast<const uint4*>(p)[0];
+  const uint4 b = reinterpret_cast<const uint4*>(p)[1];
+  w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+  w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+}
+
+__device__ __forceinline__ void st8w(uint32_t* p, const uint32_t w[8]) {
+  reinterpret_cast<uint4*>(p)[0] = make_uint4(w[0], w[1], w[2], w[3]);
+  reinterpret_cast<uint4*>(p)[1] = make_uint4(w[4], w[5], w[6], w[7]);
+}
+
+// Term t of output o: its point (scalar gamma^t).  Output o < k is
+// gamma C[o] + C2[o] (terms C2[o], C[o]); output k is E'' (terms E2, Ej..., E).
+__device__ __forceinline__ const uint32_t* term_point(const uint32_t* C, const uint32_t* C2, const uint32_t* E,
+                                                      const uint32_t* E2, const uint32_t* Ej, uint32_t k,
+                                                      uint32_t d, uint32_t o, uint32_t t) {
+  if (o < k) return t == 0 ? C2 + (size_t)o * 16 : C + (size_t)o * 16;
+  if (t == 0) return E2;
+  if (t == d) return E;
+  return Ej + (size_t)(t - 1) * 16;
+}
+
+__global__ __launch_bounds__(ACC_NT) void acc_fold_g1_kernel(const uint32_t* __restrict__ C,
+                                                             const uint32_t* __restrict__ C2, uint32_t k,
+                                                             const uint32_t* __restrict__ E,
+                                                             const uint32_t* __restrict__ E2,
+                                                             const uint32_t* __restrict__ Ej, uint32_t d,
+                                                             const uint32_t* __restrict__ gamma,
+                                                             uint32_t* __restrict__ C_out,
+                                                             uint32_t* __restrict__ E_out,
+                                                             uint32_t* __restrict__ scratch) {
+  const uint32_t o = (blockIdx.x * ACC_NT + threadIdx.x) >> 2;  // output of this quad
+  if (o > k) return;                                              // whole quads leave together
+  const uint32_t c = quad_lane();
+  const uint32_t nterm = o < k ? 2u : d + 1;
+  uint32_t* tab = scratch + (size_t)o * (ACC_MAX_D + 1) * (TAB_WORDS + 8);
+  uint32_t* sc = tab + (size_t)(ACC_MAX_D + 1) * TAB_WORDS;  // scalars gamma^t, 8 words each
+  // scalars gamma^t, canonical: every lane of the quad computes and stores
+  // the same words, so each lane later reads back its own stores
+  {
+    uint32_t gw[8];
+    ld8w(gamma, gw);
+    const f29 gm = reduce_full<FrP>(to_mont<FrP>(unpack(gw)));
+    f29 p = f29_from(FrP::ONE);
+    for (uint32_t t = 0; t < nterm; t++) {
+      uint32_t w[8];
+      pack(from_mont<FrP>(p), w);
+      st8w(sc + t * 8, w);
+      p = reduce_full<FrP>(mont_mul<FrP>(p, gm));
+    }
+  }
+  // tables: multiple m of term t's point at tab[t][m] (m = 1..15)
+  for (uint32_t t = 0; t < nterm; t++) {
+    uint32_t w[16];
+    const uint32_t* P = term_point(C, C2, E, E2, Ej, k, d, o, t);
+    ld8w(P, w);
+    ld8w(P + 8, w + 8);
+    aff a;
+    const bool fin = aff_from_plain_words(w, a);
+    const xyzz p1 = fin ? from_aff(a) : xyzz_inf();
+    const f29 base = quad_coord(p1, c);
+    uint32_t* tt = tab + (size_t)t * TAB_WORDS;
+    stq(tt + 36, c, base);
+    f29 cur = quad_dbl(base);
+    stq(tt + 2 * 36, c, cur);
+    for (uint32_t m = 3; m < 16; m++) {
+      cur = quad_add(cur, base);
+      stq(tt + m * 36, c, cur);
+    }
+  }
+  // Straus: 64 windows of 4 bits from the top
+  f29 acc = f29_zero();
+  for (int32_t win = 63; win >= 0; --win) {
+    if (win != 63) {
+      acc = quad_dbl(acc);
+      acc = quad_dbl(acc);
+      acc = quad_dbl(acc);
+      acc = quad_dbl(acc);
+    }
+    for (uint32_t t = 0; t < nterm; t++) {
+      const uint32_t digit = (sc[t * 8 + (win >> 3)] >> ((win & 7) * 4)) & 15u;
+      if (digit) acc = quad_add(acc, ldq(tab + (size_t)t * TAB_WORDS + digit * 36, c));
+    }
+  }
+  xyzz r = quad_gather(acc);
+  if (c == 0) {
+    force_vgpr(r);
+    uint32_t out[16];
+    to_affine_words(r, out);
+    uint32_t* dst = o < k ? C_out + (size_t)o * 16 : E_out;
+    st8w(dst, out);
+    st8w(dst + 8, out + 8);
+  }
+}
+
+__global__ __launch_bounds__(RLC_NT) void fr_rlc_kernel(const uint32_t* __restrict__ v0,
+                                                        const uint32_t* __restrict__ vmid,
+                                                        const uint32_t* __restrict__ vlast, uint32_t d,
+                                                        uint64_t len, const uint32_t* __restrict__ gamma,
+                                                        uint32_t* __restrict__ out) {
+  const uint64_t i = (uint64_t)blockIdx.x * RLC_NT + threadIdx.x;
+  if (i >= len) return;
+  uint32_t w[8];
+  ld8w(gamma, w);
+  const f29 gm = reduce_full<FrP>(to_mont<FrP>(unpack(w)));
+  ld8w(vlast + i * 8, w);
+  f29 acc = unpack(w);
+  for (int32_t t = (int32_t)d - 1; t >= 1; --t) {
+    ld8w(vmid + ((uint64_t)(t - 1) * len + i) * 8, w);
+    acc = add_n(unpack(w), mont_mul<FrP>(acc, gm));
+  }
+  ld8w(v0 + i * 8, w);
+  acc = add_n(unpack(w), mont_mul<FrP>(acc, gm));
+  pack(reduce_full<FrP>(acc), w);
+  st8w(out + i * 8, w);
+}
+
+// ---- SHA-256 (FIPS 180-4) ---------------------------------------------------
+// Round constants: the first 32 bits of the fractional parts of the cube
+// roots of the first 64 primes; initial value: the same of the square roots
+// of the first 8 primes (FIPS 180-4, 4.2.2 and 5.3.3).
+__constant__ uint32_t SHA_K[64] = {
+    0x428a2f98u, 0x71374491u, 0xb5c0fbcfu, 0xe9b5dba5u, 0x3956c25bu, 0x59f111f1u, 0x923f82a4u, 0xab1c5ed5u,
+    0xd807aa98u, 0x12835b01u, 0x243185beu, 0x550c7dc3u, 0x72be5d74u, 0x80deb1feu, 0x9bdc06a7u, 0xc19bf174u,
+    0xe49b69c1u, 0xefbe4786u, 0x0fc19dc6u, 0x240ca1ccu, 0x2de92c6fu, 0x4a7484aau, 0x5cb0a9dcu, 0x76f988dau,
+    0x983e5152u, 0xa831c66du, 0xb00327c8u, 0xbf597fc7u, 0xc6e00bf3u, 0xd5a79147u, 0x06ca6351u, 0x14292967u,
+    0x27b70a85u, 0x2e1b2138u, 0x4d2c6dfcu, 0x53380d13u, 0x650a7354u, 0x766a0abbu, 0x81c2c92eu, 0x92722c85u,
+    0xa2bfe8a1u, 0xa81a664bu, 0xc24b8b70u, 0xc76c51a3u, 0xd192e819u, 0xd6990624u, 0xf40e3585u, 0x106aa070u,
+    0x19a4c116u, 0x1e376c08u, 0x2748774cu, 0x34b0bcb5u, 0x391c0cb3u, 0x4ed8aa4au, 0x5b9cca4fu, 0x682e6ff3u,
+    0x748f82eeu, 0x78a5636fu, 0x84c87814u, 0x8cc70208u, 0x90befffau, 0xa4506cebu, 0xbef9a3f7u, 0xc67178f2u};
+__constant__ uint32_t SHA_H0[8] = {0x6a09e667u, 0xbb67ae85u, 0x3c6ef372u, 0xa54ff53au,
+                                   0x510e527fu, 0x9b05688cu, 0x1f83d9abu, 0x5be0cd19u};
+
+__device__ __forceinline__ uint32_t rotr(uint32_t x, uint32_t n) { return (x >> n) | (x << (32 - n)); }
+
+// Byte b of the message prefix || data || padding || 64-bit bit length.
+__device__ __forceinline__ uint32_t msg_byte(const uint8_t* data, uint64_t bytes, uint8_t prefix, uint64_t total,
+                                             uint64_t b) {
+  const uint64_t L = bytes + 1;
+  if (b == 0) return prefix;
+  if (b < L) return data[b - 1];
+  if (b == L) return 0x80u;
+  if (b >= total - 8) {
+    const uint64_t bits = L * 8;
+    return (uint32_t)(bits >> (8 * (total - 1 - b))) & 0xffu;
+  }
+  return 0;
+}
+
+__device__ void sha256_prefixed(const uint8_t* data, uint64_t bytes, uint8_t prefix, uint32_t h[8]) {
+  const uint64_t L = bytes + 1;
+  const uint64_t total = ((L + 8) / 64 + 1) * 64;
+  for (int i = 0; i < 8; i++) h[i] = SHA_H0[i];
+  for (uint64_t blk = 0; blk < total; blk += 64) {
+    uint32_t W[64];
+    for (int t = 0; t < 16; t++) {
+      uint32_t v = 0;
+      for (int q = 0; q < 4; q++) v = (v << 8) | msg_byte(data, bytes, prefix, total, blk + 4 * t + q);
+      W[t] = v;
+    }
+    for (int t = 16; t < 64; t++) {
+      const uint32_t s0 = rotr(W[t - 15], 7) ^ rotr(W[t - 15], 18) ^ (W[t - 15] >> 3);
+      const uint32_t s1 = rotr(W[t - 2], 17) ^ rotr(W[t - 2], 19) ^ (W[t - 2] >> 10);
+      W[t] = W[t - 16] + s0 + W[t - 7] + s1;
+    }
+    uint32_t a = h[0], b = h[1], c = h[2], d = h[3], e = h[4], f = h[5], g = h[6], hh = h[7];
+    for (int t = 0; t < 64; t++) {
+      const uint32_t S1 = rotr(e, 6) ^ rotr(e, 11) ^ rotr(e, 25);
+      const uint32_t ch = (e & f) ^ (~e & g);
+      const uint32_t t1 = hh + S1 + ch + SHA_K[t] + W[t];
+      const uint32_t S0 = rotr(a, 2) ^ rotr(a, 13) ^ rotr(a, 22);
+      const uint32_t mj = (a & b) ^ (a & c) ^ (b & c);
+      const uint32_t t2 = S0 + mj;
+      hh = g;
+      g = f;
+      f = e;
+      e = d + t1;
+      d = c;
+      c = b;
+      b = a;
+      a = t1 + t2;
+    }
+    h[0] += a; h[1] += b; h[2] += c; h[3] += d; h[4] += e; h[5] += f; h[6] += g; h[7] += hh;
+  }
+}
+
+// Lanes 0 and 1 hash with prefixes 0 and 1; lane 0 reduces the 512-bit
+// little-endian concatenation of the two digests modulo r.
+__global__ void transcript_kernel(const uint8_t* __restrict__ data, uint64_t bytes, f29 c_2_256,
+                                  uint32_t* __restrict__ out) {
+  __shared__ uint32_t dig[2][8];
+  const uint32_t lane = threadIdx.x;
+  if (lane < 2) {
+    uint32_t h[8];
+    sha256_prefixed(data, bytes, (uint8_t)lane, h);
+    // digest bytes are h[0] big-endian first; as a little-endian integer,
+    // 32-bit word i is the byte-reversed h[i]
+    for (int i = 0; i < 8; i++) dig[lane][i] = __builtin_bswap32(h[i]);
+  }
+  __syncthreads();
+  if (lane == 0) {
+    const f29 lo = unpack(dig[0]);
+    const f29 hi = unpack(dig[1]);
+    // lo + hi 2^256 mod r: hi times 2^256 2^261 by a Montgomery product
+    const f29 v = add_n(lo, mont_mul<FrP>(hi, c_2_256));
+    uint32_t w[8];
+    pack(reduce_full<FrP>(v), w);
+    st8w(out, w);
+  }
+}
+
+}  // namespace
+
+size_t acc_fold_g1_scratch_bytes(uint32_t k, uint32_t d) {
+  (void)d;
+  return (size_t)(k + 1) * (ACC_MAX_D + 1) * (TAB_WORDS + 8) * 4;
+}
+
+hipError_t acc_fold_g1(const uint32_t* C, const uint32_t* C2, uint32_t k, const uint32_t* E, const uint32_t* E2,
+                       const uint32_t* Ej, uint32_t d, const uint32_t* gamma, uint32_t* C_out, uint32_t* E_out,
+                       void* scratch, hipStream_t s) {
+  const uint32_t threads = (k + 1) * 4;
+  const ProfToken tok = prof_begin("acc.fold_g1", s);
+  hipLaunchKernelGGL(acc_fold_g1_kernel, dim3((threads + ACC_NT - 1) / ACC_NT), dim3(ACC_NT), 0, s, C, C2, k, E,
+                     E2, Ej, d, gamma, C_out, E_out, static_cast<uint32_t*>(scratch));
+  prof_end(tok, s);
+  return hipGetLastError();
+}
+
+hipError_t fr_rlc(const uint32_t* v0, const uint32_t* vmid, const uint32_t* vlast, uint32_t d, uint64_t len,
+                  const uint32_t* gamma, uint32_t* out, hipStream_t s) {
+  if (len == 0) return hipSuccess;
+  const ProfToken tok = prof_begin("acc.fr_rlc", s);
+  hipLaunchKernelGGL(fr_rlc_kernel, dim3((uint32_t)((len + RLC_NT - 1) / RLC_NT)), dim3(RLC_NT), 0, s, v0, vmid,
+                     vlast, d, len, gamma, out);
+  prof_end(tok, s);
+  return hipGetLastError();
+}
+
+hipError_t transcript_challenge(const uint8_t* data, uint64_t bytes, const f29& c_2_256, uint32_t* out,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(transcript_kernel, dim3(1), dim3(64), 0, s, data, bytes, c_2_256, out);
+  return hipGetLastError();
+}
+
+}  // namespace zk

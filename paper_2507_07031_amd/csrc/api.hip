@@ -13,12 +13,14 @@
 #include <vector>
 
 #include "../../include/zk.h"
+#include "accum.h"
 #include "field.h"
 #include "msm.h"
 #include "ntt.h"
 #include "open.h"
 #include "prof.h"
 #include "quotient.h"
+#include "setup.h"
 #include "validate.h"
 
 using namespace zk;
@@ -551,6 +553,35 @@ zk_status zk_srs_setup(const zk_fr* tau_host, uint64_t n, zk_g1* out, void* stre
   return ZK_OK;
 }
 
+zk_status zk_srs_lagrange_setup(const zk_fr* tau_host, uint32_t log_n, zk_g1* out, void* stream) {
+  if (!tau_host || !out) return fail(ZK_EINVAL, "zk_srs_lagrange_setup: NULL argument");
+  if (log_n > ZK_MAX_LOG_NTT) return fail(ZK_EUNSUPPORTED, "zk_srs_lagrange_setup: log_n > ZK_MAX_LOG_NTT");
+  uint32_t w[8];
+  std::memcpy(w, tau_host->v, 32);
+  unsigned br = 0;
+  for (int i = 0; i < 8; i++) (void)__builtin_subc(w[i], FrP::M32[i], br, &br);
+  if (!br) return fail(ZK_EINVAL, "zk_srs_lagrange_setup: tau not canonical (>= r)");
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  // c = (tau^n - 1) / n; tau^n = 1 exactly when tau lies in H
+  const f29 one = f29_from(FrP::ONE);
+  f29 tn = reduce_full<FrP>(to_mont<FrP>(unpack(w)));
+  for (uint32_t i = 0; i < log_n; i++) tn = reduce_full<FrP>(mont_mul<FrP>(tn, tn));
+  const f29 num = reduce_full<FrP>(sub_k(tn, one, FrP::K2));
+  const bool in_h = f29_is_zero_limbs(num);
+  uint32_t nw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  nw[log_n >> 5] = 1u << (log_n & 31);
+  const f29 ninv = mont_inv<FrP>(reduce_full<FrP>(to_mont<FrP>(unpack(nw))));
+  const f29 cm = in_h ? f29_zero() : reduce_full<FrP>(mont_mul<FrP>(num, ninv));
+  Tau8 t;
+  std::memcpy(t.w, w, 32);
+  ZK_HIP(srs_lagrange_from_tau(t, log_n, cm, in_h, c->tw[0], c->tw[1], reinterpret_cast<uint32_t*>(out), c->gtab,
+                               (hipStream_t)stream),
+         "lagrange setup");
+  return ZK_OK;
+}
+
 zk_status zk_srs_create(const zk_g1* points, uint64_t n, zk_srs** srs, void* stream) {
   if (!srs || (n && !points)) return fail(ZK_EINVAL, "zk_srs_create: NULL argument");
   if (n >= (1ull << 31) / 16) return fail(ZK_EUNSUPPORTED, "zk_srs_create: n too large");
@@ -872,6 +903,58 @@ zk_status zk_quotient_mul(const zk_srs* srs, const zk_fr* a, const zk_fr* b, con
   if ((st = run_ntt(c, E[0], E[0], L, true, nullptr, nullptr, (uint32_t)big, s))) return st;
   ZK_HIP(quot_scale_powers(E[0], n, ilo, ihi, reinterpret_cast<uint32_t*>(t_coeffs), s), "quotient scale");
   return msm_srs_one(srs, reinterpret_cast<const uint32_t*>(t_coeffs), n, reinterpret_cast<uint32_t*>(t_commit), s);
+}
+
+zk_status zk_transcript_challenge(const void* data, uint64_t bytes, zk_fr* challenge, void* stream) {
+  if (!challenge || (bytes && !data)) return fail(ZK_EINVAL, "zk_transcript_challenge: NULL argument");
+  if (bytes >= (1ull << 40)) return fail(ZK_EUNSUPPORTED, "zk_transcript_challenge: input too long");
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  // 2^256 in Montgomery form: twice the Montgomery form of 2^255
+  uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0x80000000u};
+  const f29 h = reduce_full<FrP>(to_mont<FrP>(unpack(w)));
+  const f29 c256 = reduce_full<FrP>(add_n(h, h));
+  ZK_HIP(transcript_challenge(static_cast<const uint8_t*>(data), bytes, c256, reinterpret_cast<uint32_t*>(challenge),
+                              (hipStream_t)stream),
+         "transcript");
+  return ZK_OK;
+}
+
+zk_status zk_acc_fold(uint32_t k, const zk_g1* C, const zk_g1* C2, uint32_t d, const zk_g1* E, const zk_g1* E2,
+                      const zk_g1* Ej, uint64_t len_v, const zk_fr* v, const zk_fr* v2, uint64_t len_e,
+                      const zk_fr* e, const zk_fr* e2, const zk_fr* ej, const zk_fr* gamma, zk_g1* C_out,
+                      zk_g1* E_out, zk_fr* v_out, zk_fr* e_out, void* stream) {
+  if (!gamma || !E || !E2 || !E_out || (d > 1 && !Ej) || (k && (!C || !C2 || !C_out)) ||
+      (len_v && (!v || !v2 || !v_out)) || (len_e && (!e || !e2 || !e_out || (d > 1 && !ej))))
+    return fail(ZK_EINVAL, "zk_acc_fold: NULL argument");
+  if (d < 1 || d > ACC_MAX_D) return fail(ZK_EINVAL, "zk_acc_fold: d must be 1..15");
+  if (k >= (1u << 20)) return fail(ZK_EUNSUPPORTED, "zk_acc_fold: k too large");
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  const hipStream_t s = (hipStream_t)stream;
+  if ((st = check_inputs(c, s,
+                         {{C, k, true}, {C2, k, true}, {E, 1, true}, {E2, 1, true}, {Ej, d - 1ull, true},
+                          {gamma, 1, false}, {v, len_v, false}, {v2, len_v, false}, {e, len_e, false},
+                          {e2, len_e, false}, {ej, (d - 1ull) * len_e, false}},
+                         "zk_acc_fold")))
+    return st;
+  Scratch ws;
+  if ((st = scratch_alloc(ws, acc_fold_g1_scratch_bytes(k, d), s))) return st;
+  const uint32_t* gw = reinterpret_cast<const uint32_t*>(gamma);
+  ZK_HIP(acc_fold_g1(reinterpret_cast<const uint32_t*>(C), reinterpret_cast<const uint32_t*>(C2), k,
+                     reinterpret_cast<const uint32_t*>(E), reinterpret_cast<const uint32_t*>(E2),
+                     reinterpret_cast<const uint32_t*>(Ej), d, gw, reinterpret_cast<uint32_t*>(C_out),
+                     reinterpret_cast<uint32_t*>(E_out), ws.p, s),
+         "acc fold g1");
+  ZK_HIP(fr_rlc(reinterpret_cast<const uint32_t*>(v2), nullptr, reinterpret_cast<const uint32_t*>(v), 1, len_v, gw,
+                reinterpret_cast<uint32_t*>(v_out), s),
+         "acc fold fr");
+  ZK_HIP(fr_rlc(reinterpret_cast<const uint32_t*>(e2), reinterpret_cast<const uint32_t*>(ej),
+                reinterpret_cast<const uint32_t*>(e), d, len_e, gw, reinterpret_cast<uint32_t*>(e_out), s),
+         "acc fold errors");
+  return ZK_OK;
 }
 
 zk_status zk_fold(const zk_g1* inst, const zk_fr* gammas, uint32_t m, uint32_t k, zk_g1* out, void* stream) {

@@ -39,6 +39,7 @@
 #include "msm_store.h"
 #include "msm.h"
 #include "prof.h"
+#include "setup.h"
 
 namespace zk {
 
@@ -698,6 +699,45 @@ __global__ void srs_kernel(Tau8 tw, const uint32_t* __restrict__ gtab, uint32_t*
   stw(out + i * 16, o, 4);
 }
 
+// [s] G by double-and-add over the table 2^b G, canonical plain affine words.
+__device__ __forceinline__ void gen_mul_words(const uint32_t s[8], const uint32_t* __restrict__ gtab, uint32_t o[16]) {
+  xyzz acc = xyzz_inf();
+  for (int b = 0; b < 254; b++) {
+    if ((s[b >> 5] >> (b & 31)) & 1u) {
+      aff g;
+      ld_aff(gtab + (size_t)b * 16, g);
+      acc = madd(acc, g);
+    }
+  }
+  to_affine_words(acc, o);
+}
+
+__global__ void lagrange_kernel(Tau8 tw, uint32_t L, f29 c_mont, uint32_t tau_in_h, const f29* __restrict__ lo,
+                                const f29* __restrict__ hi, const uint32_t* __restrict__ gtab,
+                                uint32_t* __restrict__ out, uint64_t n) {
+  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const f29 tau = reduce_full<FrP>(to_mont<FrP>(unpack(tw.w)));
+  // omega_(2^L)^j = omega_(2^28)^(j 2^(28 - L)), exponent split over the two tables
+  const uint32_t E = (uint32_t)j << (28 - L);
+  const uint32_t ea = E & 0x3fffu, eb = E >> 14;
+  const f29 wj = reduce_full<FrP>(mont_mul<FrP>(lo[ea], hi[eb]));
+  f29 lm;
+  if (tau_in_h) {
+    uint32_t diff = 0;
+#pragma unroll
+    for (int i = 0; i < 9; i++) diff |= wj.l[i] ^ tau.l[i];
+    lm = diff == 0 ? f29_from(FrP::ONE) : f29_zero();
+  } else {
+    const f29 d = reduce_full<FrP>(sub_k(tau, wj, FrP::K2));
+    lm = mont_mul<FrP>(mont_mul<FrP>(c_mont, wj), mont_inv<FrP>(d));
+  }
+  uint32_t s[8], o[16];
+  pack(from_mont<FrP>(lm), s);
+  gen_mul_words(s, gtab, o);
+  stw(out + j * 16, o, 4);
+}
+
 // sigma_i = product of the challenges of the folds where instance i is the
 // left operand (adjacent pairs per level, odd last carried, BFS order).
 __global__ void fold_sigma_kernel(const uint32_t* __restrict__ gammas, uint32_t m, uint32_t* __restrict__ sigma) {
@@ -1195,6 +1235,15 @@ hipError_t srs_from_tau(Tau8 tau, uint32_t* out, uint64_t n, uint32_t* gtab, hip
   hipLaunchKernelGGL(gen_table_kernel, dim3(4), dim3(64), 0, s, gtab);
   if (n == 0) return hipGetLastError();
   hipLaunchKernelGGL(srs_kernel, dim3(cdiv(n, 128)), dim3(128), 0, s, tau, gtab, out, n);
+  return hipGetLastError();
+}
+
+hipError_t srs_lagrange_from_tau(Tau8 tau, uint32_t L, f29 c_mont, bool tau_in_h, const f29* tw_lo,
+                                 const f29* tw_hi, uint32_t* out, uint32_t* gtab, hipStream_t s) {
+  hipLaunchKernelGGL(gen_table_kernel, dim3(4), dim3(64), 0, s, gtab);
+  const uint64_t n = 1ull << L;
+  hipLaunchKernelGGL(lagrange_kernel, dim3(cdiv(n, 128)), dim3(128), 0, s, tau, L, c_mont, tau_in_h ? 1u : 0u, tw_lo,
+                     tw_hi, gtab, out, n);
   return hipGetLastError();
 }
 

@@ -24,7 +24,8 @@ EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_s
            "zk_srs_destroy", "zk_srs_size", "zk_msm_srs", "zk_msm_batch", "zk_fold", "zk_profile_enable",
            "zk_profile_read", "zk_msm_srs_workspace_bytes", "zk_ntt_workspace_bytes", "zk_release_cached_memory",
            "zk_msm_srs_ex", "zk_profile_only", "zk_commit_job", "zk_set_validate", "zk_kzg_open",
-           "zk_kzg_open_batch", "zk_quotient_mul")
+           "zk_kzg_open_batch", "zk_quotient_mul",
+           "zk_srs_lagrange_setup", "zk_transcript_challenge", "zk_acc_fold")
 
 
 class ZkError(RuntimeError):
@@ -45,6 +46,7 @@ def _load():
         "zk_coset_ntt": ([P, U32, U32, P, P, P], I),
         "zk_msm": ([P, P, U64, P, P], I),
         "zk_srs_setup": ([P, U64, P, P], I),
+        "zk_srs_lagrange_setup": ([P, U32, P, P], I),
         "zk_srs_create": ([P, U64, ctypes.POINTER(ctypes.c_void_p), P], I),
         "zk_srs_destroy": ([P], I),
         "zk_srs_size": ([P], U64),
@@ -56,6 +58,8 @@ def _load():
         "zk_msm_batch": ([P, P, P, U32, P, P], I),
         "zk_kzg_open": ([P, P, U64, P, P, P, P, P], I),
         "zk_quotient_mul": ([P, P, P, P, U32, U32, P, P, P, P], I),
+        "zk_transcript_challenge": ([P, U64, P, P], I),
+        "zk_acc_fold": ([U32, P, P, U32, P, P, P, U64, P, P, U64, P, P, P, P, P, P, P, P, P], I),
         "zk_kzg_open_batch": ([P, P, U32, U64, P, P, P, P, P, P], I),
         "zk_fold": ([P, P, U32, U32, P, P], I),
         "zk_profile_enable": ([I], I),
@@ -206,6 +210,15 @@ def srs_setup(tau, n, device="cuda"):
     return out
 
 
+def srs_lagrange_setup(tau, log_n, device="cuda"):
+    """[l_j(tau)]_1 for the Lagrange basis of the 2^log_n-th roots of unity."""
+    torch = _torch()
+    out = torch.empty((1 << int(log_n), 16), dtype=torch.int32, device=device)
+    ta, tp = _host_fr(tau)
+    _check(lib.zk_srs_lagrange_setup(tp, int(log_n), _ptr(out), _stream(out)))
+    return out
+
+
 class SRS:
     """A prepared SRS (zk_srs handle) built from device points (n, 16)."""
 
@@ -332,6 +345,62 @@ def quotient_mul(srs, a, b, c, log_blowup=1, shift=None, t=None, com=None):
     _check(lib.zk_quotient_mul(srs.handle, _ptr(a), _ptr(b), _ptr(c), L, int(log_blowup), sp, _ptr(t), _ptr(com),
                                _stream(a)))
     return t, com
+
+
+def transcript_challenge(data, out=None):
+    """Challenge (SHA-256(0||data) || SHA-256(1||data)) mod r of the bytes of
+    the contiguous device tensor `data`.  Returns a (1, 8) device tensor."""
+    torch = _torch()
+    if not isinstance(data, torch.Tensor) or not data.is_cuda or not data.is_contiguous():
+        raise TypeError("data must be a contiguous device tensor")
+    if out is None:
+        out = torch.empty((1, 8), dtype=torch.int32, device=data.device)
+    nbytes = data.numel() * data.element_size()
+    _check(lib.zk_transcript_challenge(_ptr(data) if nbytes else None, nbytes, _ptr(out), _stream(data)))
+    return out
+
+
+def acc_fold(gamma, C, C2, E, E2, Ej=None, v=None, v2=None, e=None, e2=None, ej=None):
+    """One accumulation step: returns (C_out, E_out, v_out, e_out) for
+    acc = (C, E, v, e) weighted by gamma and acc' = (C2, E2, v2, e2).
+    C, C2: (k, 16); E, E2: (1, 16); Ej: (d - 1, 16) or None; v, v2: (len_v, 8)
+    or None; e, e2: (len_e, 8) or None; ej: (d - 1, len_e, 8) or None;
+    gamma: (1, 8) device Fr."""
+    torch = _torch()
+    gamma = _dev_words(gamma, 8, "gamma")
+    C, C2 = _dev_words(C, 16, "C"), _dev_words(C2, 16, "C2")
+    E, E2 = _dev_words(E, 16, "E"), _dev_words(E2, 16, "E2")
+    k = C.shape[0]
+    if C2.shape[0] != k:
+        raise ValueError("C and C2 differ in length")
+    d = 1 + (0 if Ej is None else int(Ej.shape[0]))
+    ejp = None
+    if Ej is not None and d > 1:
+        Ej = _dev_words(Ej, 16, "Ej")
+    dev = C.device
+    C_out = torch.empty_like(C)
+    E_out = torch.empty((1, 16), dtype=torch.int32, device=dev)
+    len_v = 0 if v is None else int(v.shape[0])
+    v_out = None
+    if len_v:
+        v, v2 = _dev_words(v, 8, "v"), _dev_words(v2, 8, "v2")
+        v_out = torch.empty_like(v)
+    len_e = 0 if e is None else int(e.shape[0])
+    e_out = None
+    if len_e:
+        e, e2 = _dev_words(e, 8, "e"), _dev_words(e2, 8, "e2")
+        e_out = torch.empty_like(e)
+        if d > 1:
+            if ej is None or tuple(ej.shape) != (d - 1, len_e, 8) or not ej.is_contiguous():
+                raise ValueError("ej must be a contiguous (d - 1, len_e, 8) tensor")
+            ejp = _ptr(ej)
+
+    def p(t):
+        return _ptr(t) if t is not None and t.numel() else None
+    _check(lib.zk_acc_fold(k, p(C), p(C2), d, _ptr(E), _ptr(E2), p(Ej) if d > 1 else None, len_v, p(v), p(v2),
+                           len_e, p(e), p(e2), ejp, _ptr(gamma), p(C_out), _ptr(E_out), p(v_out), p(e_out),
+                           _stream(E)))
+    return C_out, E_out, v_out, e_out
 
 
 def fold(inst, gammas, out=None):

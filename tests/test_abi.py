@@ -64,3 +64,5 @@ def test_argument_errors_return_before_device_work(zk):
     bad = (ctypes.c_uint32 * 8)(*([0xFFFFFFFF] * 8))
     assert L.zk_srs_setup(ctypes.cast(bad, ctypes.c_void_p), 4, dummy, null) == zk.ZK_EINVAL
     assert "canonical" in L.zk_last_error().decode()
+    assert L.zk_srs_lagrange_setup(ctypes.cast(bad, ctypes.c_void_p), 4, dummy, null) == zk.ZK_EINVAL
+    assert L.zk_srs_lagrange_setup(null, 4, dummy, null) == zk.ZK_EINVAL
