@@ -14,6 +14,8 @@ Accumulation"):
   fixes BN254 (Experimental Setup) and writes p for the group order
   (Preliminaries), which this code calls r.
 * ``g1``    -- affine short-Weierstrass group G1, [x]_1 = xG (Preliminaries).
+* ``g2``    -- G2 over Fq2 (the sextic twist), [x]_2 = x H, its MSM and SRS
+  (commitments in G2 of MulScalar, Mul and MatMul).
 * ``msm``   -- KZG commit com = [f(tau)]_1 = sum_i f_i [tau^i]_1 as a naive sum of
   scalar multiples, and its closed form (Polynomial Commitment).
 * ``ntt``   -- evaluations on H = {omega^i} (Foldable basic blocks), O(n^2) DFT,

@@ -8,11 +8,12 @@ import random
 
 import pytest
 
-from oracle import field, fold, g1, kzg, msm, ntt, quotient, srs
+from oracle import field, fold, g1, g2, kzg, msm, ntt, quotient, srs
 from tests import test_oracle_g1 as tg
 from tests import test_oracle_kzg as tk
 from tests import test_oracle_quotient as tq
 from tests import test_oracle_accum as ta
+from tests import test_oracle_g2 as tg2
 from tests import test_oracle_msm_fold as tm
 from tests import test_oracle_ntt as tn
 
@@ -188,3 +189,19 @@ def test_error_power_off_by_one_is_caught(monkeypatch):
         return [sum(pow(gam, j + (j > 0), R) * int(v[i]) for j, v in enumerate(vecs)) % R for i in range(len(e))]
     monkeypatch.setattr(fold, "fold_errors_fr", bad)
     _fails(ta.test_error_polynomial_extraction, random.Random(16))
+
+
+def test_fq2_sign_of_u_squared_is_caught(monkeypatch):
+    monkeypatch.setattr(g2, "f2_mul", lambda a, b: ((a[0] * b[0] + a[1] * b[1]) % field.P,
+                                                    (a[0] * b[1] + a[1] * b[0]) % field.P))
+    _fails(tg2.test_fq2_definition, random.Random(17))
+
+
+def test_g2_doubling_slip_is_caught(monkeypatch):
+    good = g2.double
+
+    def bad(pt):
+        r = good(pt)
+        return None if r is None else (r[0], g2.f2_neg(r[1]))
+    monkeypatch.setattr(g2, "double", bad)
+    _fails(tg2.test_generator_order_r)
