@@ -408,6 +408,77 @@ def main():
         extras["quotient_mul_2^20"] = quot
         del qa, qb, qc, qt
 
+        log("lagrange commit 2^20")
+        # commitments to a 2^20 vector of quantized activations as evaluations
+        # on H: against the Lagrange-basis SRS (the vector's entries are the
+        # MSM scalars, small) and through the monomial SRS (iNTT first, full
+        # size coefficients)
+        lag = zk.SRS(zk.srs_lagrange_setup(tau, 20))
+        qv = zk.to_device(gen.quantized_fr(gen.CONFIG_SEEDS["quantized"], n, tag=3))
+        qcoef = torch.empty_like(qv)
+        t_lag = timed(lambda: zk.msm_srs(lag, qv, out=com), reps=10)
+
+        def mono_commit():
+            zk.intt(qv, out=qcoef)
+            zk.msm_srs(srs, qcoef, out=com)
+        t_mono = timed(mono_commit, reps=10)
+        extras["lagrange_commit_2^20"] = {
+            "vector": "quantized activations (int16, 30% zeros)", "lagrange_ms": round(t_lag, 4),
+            "monomial_intt_msm_ms": round(t_mono, 4), "speedup": round(t_mono / t_lag, 3),
+            "lagrange_points_per_s": n / (t_lag / 1e3)}
+        lag.close()
+        del qv, qcoef
+
+        log("accumulation step")
+        # one full fold of two accumulators: 64 commitments, a degree-2
+        # relation (one correction term E_1), 2^20-element Fr parts and error
+        # vectors; the challenge from the device transcript of the instances
+        ka, la = 64, n
+        Cs = [zk.srs_setup(gen.uniform_fr(gen.CONFIG_SEEDS["batched"], 1, tag=40 + i)[0], ka) for i in range(2)]
+        Es = [zk.srs_setup(gen.uniform_fr(gen.CONFIG_SEEDS["batched"], 1, tag=50 + i)[0], 1) for i in range(3)]
+        vs = [zk.to_device(gen.uniform_fr(gen.CONFIG_SEEDS["batched"], la, tag=60 + i)) for i in range(5)]
+        tr = torch.cat([Cs[0].flatten(), Es[0].flatten(), Cs[1].flatten(), Es[1].flatten(), Es[2].flatten()])
+        gam = torch.empty((1, 8), dtype=torch.int32, device=dev)
+        t_tr = timed(lambda: zk.transcript_challenge(tr, out=gam), reps=10)
+
+        def acc_step():
+            zk.transcript_challenge(tr, out=gam)
+            zk.acc_fold(gam, Cs[0], Cs[1], Es[0], Es[1], Es[2], vs[0], vs[1], vs[2], vs[3],
+                        vs[4].reshape(1, la, 8))
+        t_acc = timed(acc_step, reps=5)
+        for reg in ("acc.fold_g1", "acc.fr_rlc"):
+            zk.profile_read(reg)
+        zk.profile_enable(True)
+        for _ in range(5):
+            acc_step()
+        torch.cuda.synchronize()
+        zk.profile_enable(False)
+        g1_ms = zk.profile_read("acc.fold_g1")[0] / 5
+        rlc_ms, rlc_n = zk.profile_read("acc.fr_rlc")
+        # fr_rlc launches per step: v'' (2 vectors in, 1 out) and e'' (3 in, 1 out)
+        rlc_bytes = 32 * la * (3 + 4)
+        extras["acc_fold_step"] = {
+            "commitments": ka, "degree": 2, "fr_len": la, "ms": round(t_acc, 4), "transcript_ms": round(t_tr, 4),
+            "g1_fold_ms": round(g1_ms, 4), "fr_rlc_ms": round(rlc_ms / 5, 4),
+            "fr_rlc_hbm_frac": round(rlc_bytes / (rlc_ms / 5 / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+        del Cs, Es, vs, tr
+
+        log("g2 msm")
+        # G2 commitments (MulScalar / Mul / MatMul send G2 commitments beside
+        # the G1 ones): MSMs over a prepared 2^20-point G2 SRS
+        g2pts = zk.srs_g2_setup(tau, n)
+        g2srs = zk.SRSG2(g2pts)
+        g2out = torch.empty((1, 32), dtype=torch.int32, device=dev)
+        g2 = {}
+        for lg in (16, 20):
+            sc2 = zk.to_device(gen.uniform_fr(gen.CONFIG_SEEDS["commit"], 1 << lg, tag=70 + lg))
+            t_g2 = timed(lambda: zk.msm_g2_srs(g2srs, sc2, out=g2out), reps=3)
+            g2["msm_2^%d" % lg] = {"ms": round(t_g2, 4), "points_per_s": (1 << lg) / (t_g2 / 1e3)}
+            del sc2
+        extras["g2_msm"] = g2
+        g2srs.close()
+        del g2pts
+
         log("quantized 2^22")
         N22 = 1 << 22
         q = zk.to_device(gen.quantized_fr(gen.CONFIG_SEEDS["quantized"], N22))

@@ -56,6 +56,16 @@ typedef struct zk_g1 {
   uint32_t y[8];
 } zk_g1;
 
+/* An affine G2 point: x = x0 + x1 u, y = y0 + y1 u in Fq2 = Fq[u]/(u^2 + 1),
+ * each component 8 little-endian words, canonical (< p).  The point at
+ * infinity is all zeros. */
+typedef struct zk_g2 {
+  uint32_t x0[8];
+  uint32_t x1[8];
+  uint32_t y0[8];
+  uint32_t y1[8];
+} zk_g2;
+
 typedef int zk_status;
 #define ZK_OK 0
 #define ZK_EINVAL (-1)      /* bad argument (NULL, size out of range, ...)   */
@@ -245,6 +255,24 @@ zk_status zk_acc_fold(uint32_t k, const zk_g1* C, const zk_g1* C2, uint32_t d, c
                       const zk_g1* Ej, uint64_t len_v, const zk_fr* v, const zk_fr* v2, uint64_t len_e,
                       const zk_fr* e, const zk_fr* e2, const zk_fr* ej, const zk_fr* gamma, zk_g1* C_out,
                       zk_g1* E_out, zk_fr* v_out, zk_fr* e_out, void* stream);
+
+/* Commitments in G2 (Preliminaries: [x]_2 = x H; MulScalar's s', Mul's h',
+ * MatMul's B' and D' are G2 commitments): G2 is the order-r subgroup of the
+ * BN254 twist y^2 = x^3 + 3/(9 + u) over Fq2, H its usual generator
+ * (x = 0x1800deef...c2 + 0x198e9393...ed u as in Ethereum's precompiles).
+ *
+ * zk_srs_g2_setup: out[i] = [tau^i]_2 = tau^i H, i < n, for a known trapdoor
+ * (test and benchmark use).  zk_srs_g2_create prepares n points (any G2
+ * points: they are not checked, also not by zk_set_validate) with
+ * 32 * 128 * n bytes of pre-shifted table owned by the handle;
+ * zk_msm_g2_srs: *out = sum_{i<n} scalars[i] P_i over the first n prepared
+ * points (n <= zk_srs_g2_size), n = 0 gives infinity.  n < 2^26. */
+typedef struct zk_srs_g2 zk_srs_g2;
+zk_status zk_srs_g2_setup(const zk_fr* tau_host, uint64_t n, zk_g2* out, void* stream);
+zk_status zk_srs_g2_create(const zk_g2* points, uint64_t n, zk_srs_g2** srs, void* stream);
+zk_status zk_srs_g2_destroy(zk_srs_g2* srs);
+uint64_t zk_srs_g2_size(const zk_srs_g2* srs);
+zk_status zk_msm_g2_srs(const zk_srs_g2* srs, const zk_fr* scalars, uint64_t n, zk_g2* out, void* stream);
 
 /* Fold m instances of k G1 commitments each (inst[i*k + j]) into one:
  * the tree of pairwise folds gamma * left + right (adjacent pairs per level,

@@ -15,6 +15,7 @@
 #include "../../include/zk.h"
 #include "accum.h"
 #include "field.h"
+#include "g2msm.h"
 #include "msm.h"
 #include "ntt.h"
 #include "open.h"
@@ -416,6 +417,12 @@ struct zk_srs {
   uint32_t c_large;
   uint32_t W_large;
   uint32_t* tab_large;  // W_large * n points for large MSMs (n >= SRS_LARGE_MIN only)
+};
+
+struct zk_srs_g2 {
+  int device;
+  uint64_t n;
+  uint32_t* tab;  // G2_W * n Montgomery affine points, row w = 2^(8 w) P_i
 };
 
 extern "C" {
@@ -954,6 +961,80 @@ zk_status zk_acc_fold(uint32_t k, const zk_g1* C, const zk_g1* C2, uint32_t d, c
   ZK_HIP(fr_rlc(reinterpret_cast<const uint32_t*>(e2), reinterpret_cast<const uint32_t*>(ej),
                 reinterpret_cast<const uint32_t*>(e), d, len_e, gw, reinterpret_cast<uint32_t*>(e_out), s),
          "acc fold errors");
+  return ZK_OK;
+}
+
+zk_status zk_srs_g2_setup(const zk_fr* tau_host, uint64_t n, zk_g2* out, void* stream) {
+  if (!tau_host || (n && !out)) return fail(ZK_EINVAL, "zk_srs_g2_setup: NULL argument");
+  if (n >= (1ull << 26)) return fail(ZK_EUNSUPPORTED, "zk_srs_g2_setup: n too large");
+  uint32_t w[8];
+  std::memcpy(w, tau_host->v, 32);
+  unsigned br = 0;
+  for (int i = 0; i < 8; i++) (void)__builtin_subc(w[i], FrP::M32[i], br, &br);
+  if (!br) return fail(ZK_EINVAL, "zk_srs_g2_setup: tau not canonical (>= r)");
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  const hipStream_t s = (hipStream_t)stream;
+  Scratch gt;
+  if ((st = scratch_alloc(gt, (size_t)254 * G2_AFF_WORDS * 4, s))) return st;
+  ZK_HIP(g2_srs_from_tau(w, reinterpret_cast<uint32_t*>(out), n, static_cast<uint32_t*>(gt.p), s), "g2 srs setup");
+  return ZK_OK;
+}
+
+zk_status zk_srs_g2_create(const zk_g2* points, uint64_t n, zk_srs_g2** srs, void* stream) {
+  if (!srs || (n && !points)) return fail(ZK_EINVAL, "zk_srs_g2_create: NULL argument");
+  if (n >= (1ull << 26)) return fail(ZK_EUNSUPPORTED, "zk_srs_g2_create: n too large");
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  zk_srs_g2* h = new zk_srs_g2();
+  ZK_HIP(hipGetDevice(&h->device), "hipGetDevice");
+  h->n = n;
+  h->tab = nullptr;
+  if (n) {
+    hipError_t e = hipMalloc(&h->tab, (size_t)G2_W * n * G2_AFF_WORDS * 4);
+    if (e == hipSuccess)
+      e = g2_build_table(reinterpret_cast<const uint32_t*>(points), h->tab, n, (hipStream_t)stream);
+    if (e != hipSuccess) {
+      if (h->tab) (void)hipFree(h->tab);
+      delete h;
+      return hip_fail(e, "zk_srs_g2_create: table build");
+    }
+  }
+  *srs = h;
+  return ZK_OK;
+}
+
+zk_status zk_srs_g2_destroy(zk_srs_g2* srs) {
+  if (!srs) return ZK_OK;
+  if (srs->tab) {
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(srs->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(srs->tab);
+    (void)hipSetDevice(prev);
+  }
+  delete srs;
+  return ZK_OK;
+}
+
+uint64_t zk_srs_g2_size(const zk_srs_g2* srs) { return srs ? srs->n : 0; }
+
+zk_status zk_msm_g2_srs(const zk_srs_g2* srs, const zk_fr* scalars, uint64_t n, zk_g2* out, void* stream) {
+  if (!srs || !out || (n && !scalars)) return fail(ZK_EINVAL, "zk_msm_g2_srs: NULL argument");
+  if (n > srs->n) return fail(ZK_EINVAL, "zk_msm_g2_srs: n exceeds the SRS size");
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  const hipStream_t s = (hipStream_t)stream;
+  if ((st = check_inputs(c, s, {{scalars, n, false}}, "zk_msm_g2_srs"))) return st;
+  Scratch ws;
+  if ((st = scratch_alloc(ws, g2_msm_scratch_bytes(n), s))) return st;
+  ZK_HIP(g2_msm(srs->tab, srs->n, reinterpret_cast<const uint32_t*>(scalars), n, reinterpret_cast<uint32_t*>(out),
+                ws.p, s),
+         "g2 msm");
   return ZK_OK;
 }
 

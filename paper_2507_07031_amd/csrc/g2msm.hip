@@ -1,0 +1,380 @@
+// Multi-scalar multiplication over BN254 G2, sum_i s_i P_i, for the G2
+// commitments [f(tau)]_2 = sum_i f_i [tau^i]_2 that MulScalar, Mul and
+// MatMul send beside their G1 ones.
+//
+// Pippenger with signed 8-bit digits over a pre-shifted table, as for G1:
+// tab[w n + i] = 2^(8 w) P_i, so digit w of s_i selects table point (w, i)
+// and every window shares one set of 128 buckets (|digit| = 1..128); the
+// window sums need no doubling chain.
+//   count    per workgroup, a histogram of the digits' buckets (LDS atomics)
+//   offsets  one workgroup: every workgroup's base in every bucket, bucket
+//            offsets, and the accumulation threads of every bucket
+//   scatter  digits recomputed, entries (table index, sign) written at the
+//            workgroup's reserved positions
+//   accumulate  each thread adds up to G2_L consecutive entries of one
+//            bucket (mixed additions of table points), one partial each
+//   buckets  one workgroup per bucket: its partials summed (LDS tree)
+//   final    sum_b (b + 1) B_b by running sums over 16 chunks of 8, affine
+// Field and point arithmetic: g2.h.
+#include "g2.h"
+#include "g2msm.h"
+#include "prof.h"
+
+namespace zk {
+
+namespace {
+
+constexpr uint32_t G2_NT = 256;
+constexpr uint32_t G2_L = 32;               // entries per accumulation thread
+constexpr uint32_t G2_XYZZ_WORDS = 72;      // four Fq2 coordinates, 9 limbs per component
+constexpr uint32_t G2_BUCKET_NT = 128;      // threads of a bucket workgroup
+
+struct Words8x {
+  uint32_t w[8];
+};
+
+uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+__device__ __forceinline__ void ldw(const uint32_t* p, uint32_t* w, int n4) {
+  for (int i = 0; i < n4; i++) {
+    const uint4 v = reinterpret_cast<const uint4*>(p)[i];
+    w[4 * i] = v.x;
+    w[4 * i + 1] = v.y;
+    w[4 * i + 2] = v.z;
+    w[4 * i + 3] = v.w;
+  }
+}
+
+__device__ __forceinline__ void stw(uint32_t* p, const uint32_t* w, int n4) {
+  for (int i = 0; i < n4; i++) reinterpret_cast<uint4*>(p)[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
+}
+
+// Montgomery affine point <-> packed words (x0 x1 y0 y1, 8 words each, canonical).
+__device__ __forceinline__ void st_aff(uint32_t* p, const g2aff& a) {
+  uint32_t w[32];
+  pack(a.x.c0, w);
+  pack(a.x.c1, w + 8);
+  pack(a.y.c0, w + 16);
+  pack(a.y.c1, w + 24);
+  stw(p, w, 8);
+}
+
+__device__ __forceinline__ bool ld_aff(const uint32_t* p, g2aff& a) {
+  uint32_t w[32];
+  ldw(p, w, 8);
+  uint32_t o = 0;
+  for (int i = 0; i < 32; i++) o |= w[i];
+  a.x.c0 = unpack(w);
+  a.x.c1 = unpack(w + 8);
+  a.y.c0 = unpack(w + 16);
+  a.y.c1 = unpack(w + 24);
+  return o != 0;
+}
+
+__device__ __forceinline__ void st_xyzz(uint32_t* p, const g2xyzz& a) {
+  const f29* c[8] = {&a.X.c0, &a.X.c1, &a.Y.c0, &a.Y.c1, &a.ZZ.c0, &a.ZZ.c1, &a.ZZZ.c0, &a.ZZZ.c1};
+  for (int k = 0; k < 8; k++)
+    for (int i = 0; i < 9; i++) p[9 * k + i] = c[k]->l[i];
+}
+
+__device__ __forceinline__ g2xyzz ld_xyzz(const uint32_t* p) {
+  g2xyzz a;
+  f29* c[8] = {&a.X.c0, &a.X.c1, &a.Y.c0, &a.Y.c1, &a.ZZ.c0, &a.ZZ.c1, &a.ZZZ.c0, &a.ZZZ.c1};
+  for (int k = 0; k < 8; k++)
+    for (int i = 0; i < 9; i++) c[k]->l[i] = p[9 * k + i];
+  return a;
+}
+
+// Signed 8-bit digit of window w (carry from the lower windows): the caller
+// walks w = 0, 1, ... keeping `carry`.
+__device__ __forceinline__ int32_t next_digit(const uint32_t s[8], uint32_t w, uint32_t& carry) {
+  const uint32_t v = ((s[w >> 2] >> (8 * (w & 3))) & 255u) + carry;
+  if (v > 128u) {
+    carry = 1;
+    return (int32_t)v - 256;
+  }
+  carry = 0;
+  return (int32_t)v;
+}
+
+// ---- setup ---------------------------------------------------------------------
+
+// gtab[b] = 2^b H, b < 254
+__global__ void g2_gen_table_kernel(uint32_t* gtab) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= 254) return;
+  uint32_t w[32];
+  for (int i = 0; i < 32; i++) w[i] = G2_GEN[i];
+  g2aff h;
+  g2_from_words(w, h);
+  g2xyzz acc = g2_from_aff(h);
+  for (uint32_t t = 0; t < b; t++) acc = g2_dbl(acc);
+  g2aff a;
+  g2_to_aff(acc, a);
+  st_aff(gtab + (size_t)b * G2_AFF_WORDS, a);
+}
+
+__global__ void g2_srs_kernel(Words8x tw, const uint32_t* __restrict__ gtab, uint32_t* __restrict__ out,
+                              uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const f29 tau = reduce_full<FrP>(to_mont<FrP>(unpack(tw.w)));
+  uint32_t e[8] = {(uint32_t)i, (uint32_t)(i >> 32), 0, 0, 0, 0, 0, 0};
+  const f29 ti = (i == 0) ? f29_from(FrP::ONE) : mont_pow<FrP>(tau, e);
+  uint32_t s[8];
+  pack(from_mont<FrP>(ti), s);
+  g2xyzz acc = g2_inf();
+  for (int b = 0; b < 254; b++) {
+    if ((s[b >> 5] >> (b & 31)) & 1u) {
+      g2aff g;
+      ld_aff(gtab + (size_t)b * G2_AFF_WORDS, g);
+      acc = g2_madd(acc, g);
+    }
+  }
+  uint32_t o[32];
+  g2_to_words(acc, o);
+  stw(out + i * 32, o, 8);
+}
+
+__global__ void g2_table_kernel(const uint32_t* __restrict__ points, uint32_t* __restrict__ tab, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t w[32];
+  ldw(points + i * 32, w, 8);
+  g2aff p;
+  const bool fin = g2_from_words(w, p);
+  g2xyzz acc = fin ? g2_from_aff(p) : g2_inf();
+  for (uint32_t win = 0; win < G2_W; win++) {
+    g2aff a;
+    if (g2_to_aff(acc, a)) {
+      st_aff(tab + ((uint64_t)win * n + i) * G2_AFF_WORDS, a);
+    } else {
+      for (int k = 0; k < 32; k++) w[k] = 0;
+      stw(tab + ((uint64_t)win * n + i) * G2_AFF_WORDS, w, 8);
+    }
+    if (win + 1 < G2_W)
+      for (uint32_t t = 0; t < G2_C; t++) acc = g2_dbl(acc);
+  }
+}
+
+// ---- MSM -------------------------------------------------------------------------
+
+__global__ __launch_bounds__(G2_NT) void g2_count_kernel(const uint32_t* __restrict__ scalars, uint64_t n,
+                                                         uint32_t* __restrict__ blockhist) {
+  __shared__ uint32_t hist[G2_K];
+  for (uint32_t b = threadIdx.x; b < G2_K; b += G2_NT) hist[b] = 0;
+  __syncthreads();
+  const uint64_t i = (uint64_t)blockIdx.x * G2_NT + threadIdx.x;
+  if (i < n) {
+    uint32_t s[8];
+    ldw(scalars + i * 8, s, 2);
+    uint32_t carry = 0;
+    for (uint32_t w = 0; w < G2_W; w++) {
+      const int32_t d = next_digit(s, w, carry);
+      if (d) atomicAdd(&hist[(d < 0 ? -d : d) - 1], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < G2_K; b += G2_NT) blockhist[(size_t)blockIdx.x * G2_K + b] = hist[b];
+}
+
+// One workgroup of G2_K threads.  blockhist becomes every workgroup's
+// position in every bucket; off[b] = first entry of bucket b (off[G2_K] =
+// total); tp[b] = first accumulation thread of bucket b (tp[G2_K] = total).
+__global__ __launch_bounds__(G2_K) void g2_offsets_kernel(uint32_t* __restrict__ blockhist, uint32_t nblk,
+                                                          uint32_t* __restrict__ off, uint32_t* __restrict__ tp) {
+  __shared__ uint32_t tot[G2_K], thr[G2_K];
+  const uint32_t b = threadIdx.x;
+  uint32_t run = 0;
+  for (uint32_t k = 0; k < nblk; k++) {
+    const uint32_t c = blockhist[(size_t)k * G2_K + b];
+    blockhist[(size_t)k * G2_K + b] = run;
+    run += c;
+  }
+  tot[b] = run;
+  thr[b] = (run + G2_L - 1) / G2_L;
+  __syncthreads();
+  if (b == 0) {
+    uint32_t a = 0, t = 0;
+    for (uint32_t k = 0; k < G2_K; k++) {
+      const uint32_t ca = tot[k], ct = thr[k];
+      tot[k] = a;
+      thr[k] = t;
+      a += ca;
+      t += ct;
+    }
+    off[G2_K] = a;
+    tp[G2_K] = t;
+  }
+  __syncthreads();
+  off[b] = tot[b];
+  tp[b] = thr[b];
+  for (uint32_t k = 0; k < nblk; k++) blockhist[(size_t)k * G2_K + b] += tot[b];
+}
+
+__global__ __launch_bounds__(G2_NT) void g2_scatter_kernel(const uint32_t* __restrict__ scalars, uint64_t n,
+                                                           uint64_t n_tab, const uint32_t* __restrict__ base,
+                                                           uint32_t* __restrict__ entries) {
+  __shared__ uint32_t cur[G2_K];
+  for (uint32_t b = threadIdx.x; b < G2_K; b += G2_NT) cur[b] = base[(size_t)blockIdx.x * G2_K + b];
+  __syncthreads();
+  const uint64_t i = (uint64_t)blockIdx.x * G2_NT + threadIdx.x;
+  if (i < n) {
+    uint32_t s[8];
+    ldw(scalars + i * 8, s, 2);
+    uint32_t carry = 0;
+    for (uint32_t w = 0; w < G2_W; w++) {
+      const int32_t d = next_digit(s, w, carry);
+      if (d) {
+        const uint32_t pos = atomicAdd(&cur[(d < 0 ? -d : d) - 1], 1u);
+        entries[pos] = (uint32_t)((uint64_t)w * n_tab + i) | (d < 0 ? 0x80000000u : 0u);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(G2_NT) void g2_accumulate_kernel(const uint32_t* __restrict__ tab,
+                                                              const uint32_t* __restrict__ entries,
+                                                              const uint32_t* __restrict__ off,
+                                                              const uint32_t* __restrict__ tp,
+                                                              uint32_t* __restrict__ partial) {
+  __shared__ uint32_t t0[G2_K + 1];
+  for (uint32_t b = threadIdx.x; b <= G2_K; b += G2_NT) t0[b] = tp[b];
+  __syncthreads();
+  const uint32_t t = blockIdx.x * G2_NT + threadIdx.x;
+  if (t >= t0[G2_K]) return;
+  // bucket of thread t: the last b with t0[b] <= t
+  uint32_t lo = 0, hi = G2_K;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (t0[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  const uint32_t b = lo;
+  const uint32_t beg = off[b] + (t - t0[b]) * G2_L;
+  const uint32_t end = min(beg + G2_L, off[b + 1]);
+  g2xyzz acc = g2_inf();
+  for (uint32_t e = beg; e < end; e++) {
+    const uint32_t en = entries[e];
+    g2aff p;
+    if (!ld_aff(tab + (size_t)(en & 0x7fffffffu) * G2_AFF_WORDS, p)) continue;
+    if (en >> 31) p = g2_aff_neg(p);
+    acc = g2_madd(acc, p);
+  }
+  st_xyzz(partial + (size_t)t * G2_XYZZ_WORDS, acc);
+}
+
+// One workgroup per bucket: B_b = sum of the bucket's partials.
+__global__ __launch_bounds__(G2_BUCKET_NT) void g2_bucket_kernel(const uint32_t* __restrict__ partial,
+                                                                 const uint32_t* __restrict__ tp,
+                                                                 uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t lds[G2_BUCKET_NT * G2_XYZZ_WORDS];
+  const uint32_t b = blockIdx.x;
+  const uint32_t first = tp[b], last = tp[b + 1];
+  g2xyzz acc = g2_inf();
+  for (uint32_t t = first + threadIdx.x; t < last; t += G2_BUCKET_NT)
+    acc = g2_add(acc, ld_xyzz(partial + (size_t)t * G2_XYZZ_WORDS));
+  st_xyzz(lds + threadIdx.x * G2_XYZZ_WORDS, acc);
+  __syncthreads();
+  for (uint32_t h = G2_BUCKET_NT / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      const g2xyzz o = ld_xyzz(lds + (threadIdx.x + h) * G2_XYZZ_WORDS);
+      acc = g2_add(acc, o);
+      st_xyzz(lds + threadIdx.x * G2_XYZZ_WORDS, acc);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) st_xyzz(bsum + (size_t)b * G2_XYZZ_WORDS, acc);
+}
+
+// sum_b (b + 1) B_b: 16 threads take 8 buckets each (running sums give the
+// chunk total S_j and T_j = sum_m (m + 1) B_(8j+m)); thread 0 adds
+// sum_j T_j + 8 sum_j j S_j and writes the affine result.
+__global__ void g2_final_kernel(const uint32_t* __restrict__ bsum, uint32_t* __restrict__ out) {
+  __shared__ uint32_t S[16 * G2_XYZZ_WORDS], T[16 * G2_XYZZ_WORDS];
+  const uint32_t j = threadIdx.x;
+  if (j < 16) {
+    g2xyzz run = g2_inf(), tot = g2_inf();
+    for (int m = 7; m >= 0; --m) {
+      run = g2_add(run, ld_xyzz(bsum + (size_t)(8 * j + m) * G2_XYZZ_WORDS));
+      tot = g2_add(tot, run);
+    }
+    st_xyzz(S + j * G2_XYZZ_WORDS, run);
+    st_xyzz(T + j * G2_XYZZ_WORDS, tot);
+  }
+  __syncthreads();
+  if (j == 0) {
+    g2xyzz a = g2_inf(), run = g2_inf(), js = g2_inf();
+    for (int k = 15; k >= 0; --k) {
+      a = g2_add(a, ld_xyzz(T + k * G2_XYZZ_WORDS));
+      if (k >= 1) {
+        run = g2_add(run, ld_xyzz(S + k * G2_XYZZ_WORDS));
+        js = g2_add(js, run);  // after the loop: sum_k k S_k
+      }
+    }
+    for (int d = 0; d < 3; d++) js = g2_dbl(js);
+    const g2xyzz r = g2_add(a, js);
+    uint32_t o[32];
+    g2_to_words(r, o);
+    stw(out, o, 8);
+  }
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+hipError_t g2_srs_from_tau(const uint32_t tau[8], uint32_t* out, uint64_t n, uint32_t* gtab, hipStream_t s) {
+  hipLaunchKernelGGL(g2_gen_table_kernel, dim3(4), dim3(64), 0, s, gtab);
+  if (n == 0) return hipGetLastError();
+  Words8x t;
+  for (int i = 0; i < 8; i++) t.w[i] = tau[i];
+  hipLaunchKernelGGL(g2_srs_kernel, dim3(cdiv(n, 64)), dim3(64), 0, s, t, gtab, out, n);
+  return hipGetLastError();
+}
+
+hipError_t g2_build_table(const uint32_t* points, uint32_t* tab, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(g2_table_kernel, dim3(cdiv(n, 64)), dim3(64), 0, s, points, tab, n);
+  return hipGetLastError();
+}
+
+size_t g2_msm_scratch_bytes(uint64_t n) {
+  const uint64_t nblk = cdiv(n ? n : 1, G2_NT);
+  const uint64_t ent = (uint64_t)G2_W * n;
+  const uint64_t thr = ent / G2_L + G2_K + 1;
+  return align256(nblk * G2_K * 4) + 2 * align256((G2_K + 1) * 4) + align256(ent * 4) +
+         align256(thr * G2_XYZZ_WORDS * 4) + align256((size_t)G2_K * G2_XYZZ_WORDS * 4);
+}
+
+hipError_t g2_msm(const uint32_t* tab, uint64_t n_tab, const uint32_t* scalars, uint64_t n, uint32_t* out,
+                  void* scratch, hipStream_t s) {
+  const uint32_t nblk = cdiv(n ? n : 1, G2_NT);
+  const uint64_t ent = (uint64_t)G2_W * n;
+  const uint64_t thr = ent / G2_L + G2_K + 1;
+  char* p = static_cast<char*>(scratch);
+  uint32_t* blockhist = reinterpret_cast<uint32_t*>(p);
+  p += align256((size_t)nblk * G2_K * 4);
+  uint32_t* off = reinterpret_cast<uint32_t*>(p);
+  p += align256((G2_K + 1) * 4);
+  uint32_t* tp = reinterpret_cast<uint32_t*>(p);
+  p += align256((G2_K + 1) * 4);
+  uint32_t* entries = reinterpret_cast<uint32_t*>(p);
+  p += align256(ent * 4);
+  uint32_t* partial = reinterpret_cast<uint32_t*>(p);
+  p += align256(thr * G2_XYZZ_WORDS * 4);
+  uint32_t* bsum = reinterpret_cast<uint32_t*>(p);
+
+  const ProfToken tok = prof_begin("g2.msm", s);
+  hipLaunchKernelGGL(g2_count_kernel, dim3(nblk), dim3(G2_NT), 0, s, scalars, n, blockhist);
+  hipLaunchKernelGGL(g2_offsets_kernel, dim3(1), dim3(G2_K), 0, s, blockhist, nblk, off, tp);
+  hipLaunchKernelGGL(g2_scatter_kernel, dim3(nblk), dim3(G2_NT), 0, s, scalars, n, n_tab, blockhist, entries);
+  hipLaunchKernelGGL(g2_accumulate_kernel, dim3(cdiv(thr, G2_NT)), dim3(G2_NT), 0, s, tab, entries, off, tp,
+                     partial);
+  hipLaunchKernelGGL(g2_bucket_kernel, dim3(G2_K), dim3(G2_BUCKET_NT), 0, s, partial, tp, bsum);
+  hipLaunchKernelGGL(g2_final_kernel, dim3(1), dim3(64), 0, s, bsum, out);
+  prof_end(tok, s);
+  return hipGetLastError();
+}
+
+}  // namespace zk

@@ -25,7 +25,8 @@ EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_s
            "zk_profile_read", "zk_msm_srs_workspace_bytes", "zk_ntt_workspace_bytes", "zk_release_cached_memory",
            "zk_msm_srs_ex", "zk_profile_only", "zk_commit_job", "zk_set_validate", "zk_kzg_open",
            "zk_kzg_open_batch", "zk_quotient_mul",
-           "zk_srs_lagrange_setup", "zk_transcript_challenge", "zk_acc_fold")
+           "zk_srs_lagrange_setup", "zk_transcript_challenge", "zk_acc_fold",
+           "zk_srs_g2_setup", "zk_srs_g2_create", "zk_srs_g2_destroy", "zk_srs_g2_size", "zk_msm_g2_srs")
 
 
 class ZkError(RuntimeError):
@@ -59,6 +60,11 @@ def _load():
         "zk_kzg_open": ([P, P, U64, P, P, P, P, P], I),
         "zk_quotient_mul": ([P, P, P, P, U32, U32, P, P, P, P], I),
         "zk_transcript_challenge": ([P, U64, P, P], I),
+        "zk_srs_g2_setup": ([P, U64, P, P], I),
+        "zk_srs_g2_create": ([P, U64, ctypes.POINTER(ctypes.c_void_p), P], I),
+        "zk_srs_g2_destroy": ([P], I),
+        "zk_srs_g2_size": ([P], U64),
+        "zk_msm_g2_srs": ([P, P, U64, P, P], I),
         "zk_acc_fold": ([U32, P, P, U32, P, P, P, U64, P, P, U64, P, P, P, P, P, P, P, P, P], I),
         "zk_kzg_open_batch": ([P, P, U32, U64, P, P, P, P, P, P], I),
         "zk_fold": ([P, P, U32, U32, P, P], I),
@@ -401,6 +407,48 @@ def acc_fold(gamma, C, C2, E, E2, Ej=None, v=None, v2=None, e=None, e2=None, ej=
                            len_e, p(e), p(e2), ejp, _ptr(gamma), p(C_out), _ptr(E_out), p(v_out), p(e_out),
                            _stream(E)))
     return C_out, E_out, v_out, e_out
+
+
+def srs_g2_setup(tau, n, device="cuda"):
+    """[tau^i]_2 for i < n: (n, 32) device tensor (x0 x1 y0 y1 words)."""
+    torch = _torch()
+    out = torch.empty((int(n), 32), dtype=torch.int32, device=device)
+    ta, tp = _host_fr(tau)
+    _check(lib.zk_srs_g2_setup(tp, int(n), _ptr(out), _stream(out)))
+    return out
+
+
+class SRSG2:
+    """A prepared G2 SRS (zk_srs_g2 handle) built from device points (n, 32)."""
+
+    def __init__(self, points):
+        points = _dev_words(points, 32, "points")
+        h = ctypes.c_void_p()
+        _check(lib.zk_srs_g2_create(_ptr(points), points.shape[0], ctypes.byref(h), _stream(points)))
+        self.handle = h
+        self.n = int(lib.zk_srs_g2_size(h))
+
+    def close(self):
+        if self.handle:
+            _check(lib.zk_srs_g2_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def msm_g2_srs(srs, scalars, n=None, out=None):
+    scalars = _dev_words(scalars, 8, "scalars")
+    n = int(n if n is not None else scalars.shape[0])
+    if n > scalars.shape[0]:
+        raise ValueError("n exceeds the scalars")
+    if out is None:
+        out = _torch().empty((1, 32), dtype=_torch().int32, device=scalars.device)
+    _check(lib.zk_msm_g2_srs(srs.handle, _ptr(scalars), n, _ptr(out), _stream(scalars)))
+    return out
 
 
 def fold(inst, gammas, out=None):
