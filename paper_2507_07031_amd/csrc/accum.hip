@@ -177,56 +177,73 @@ __device__ __forceinline__ uint32_t msg_byte(const uint8_t* data, uint64_t bytes
   return 0;
 }
 
-__device__ void sha256_prefixed(const uint8_t* data, uint64_t bytes, uint8_t prefix, uint32_t h[8]) {
-  const uint64_t L = bytes + 1;
-  const uint64_t total = ((L + 8) / 64 + 1) * 64;
-  for (int i = 0; i < 8; i++) h[i] = SHA_H0[i];
-  for (uint64_t blk = 0; blk < total; blk += 64) {
-    uint32_t W[64];
-    for (int t = 0; t < 16; t++) {
-      uint32_t v = 0;
-      for (int q = 0; q < 4; q++) v = (v << 8) | msg_byte(data, bytes, prefix, total, blk + 4 * t + q);
-      W[t] = v;
+// One compression of a 64-byte block (FIPS 180-4, 6.2.2), schedule kept in a
+// rolling window of 16 registers.
+__device__ __forceinline__ void sha256_block(uint32_t h[8], const uint32_t blk[16]) {
+  uint32_t W[16];
+#pragma unroll
+  for (int t = 0; t < 16; t++) W[t] = blk[t];
+  uint32_t a = h[0], b = h[1], c = h[2], d = h[3], e = h[4], f = h[5], g = h[6], hh = h[7];
+#pragma unroll
+  for (int t = 0; t < 64; t++) {
+    uint32_t wt;
+    if (t < 16) {
+      wt = W[t];
+    } else {
+      const uint32_t w15 = W[(t - 15) & 15], w2 = W[(t - 2) & 15];
+      const uint32_t s0 = rotr(w15, 7) ^ rotr(w15, 18) ^ (w15 >> 3);
+      const uint32_t s1 = rotr(w2, 17) ^ rotr(w2, 19) ^ (w2 >> 10);
+      wt = W[t & 15] + s0 + W[(t - 7) & 15] + s1;
+      W[t & 15] = wt;
     }
-    for (int t = 16; t < 64; t++) {
-      const uint32_t s0 = rotr(W[t - 15], 7) ^ rotr(W[t - 15], 18) ^ (W[t - 15] >> 3);
-      const uint32_t s1 = rotr(W[t - 2], 17) ^ rotr(W[t - 2], 19) ^ (W[t - 2] >> 10);
-      W[t] = W[t - 16] + s0 + W[t - 7] + s1;
-    }
-    uint32_t a = h[0], b = h[1], c = h[2], d = h[3], e = h[4], f = h[5], g = h[6], hh = h[7];
-    for (int t = 0; t < 64; t++) {
-      const uint32_t S1 = rotr(e, 6) ^ rotr(e, 11) ^ rotr(e, 25);
-      const uint32_t ch = (e & f) ^ (~e & g);
-      const uint32_t t1 = hh + S1 + ch + SHA_K[t] + W[t];
-      const uint32_t S0 = rotr(a, 2) ^ rotr(a, 13) ^ rotr(a, 22);
-      const uint32_t mj = (a & b) ^ (a & c) ^ (b & c);
-      const uint32_t t2 = S0 + mj;
-      hh = g;
-      g = f;
-      f = e;
-      e = d + t1;
-      d = c;
-      c = b;
-      b = a;
-      a = t1 + t2;
-    }
-    h[0] += a; h[1] += b; h[2] += c; h[3] += d; h[4] += e; h[5] += f; h[6] += g; h[7] += hh;
+    const uint32_t S1 = rotr(e, 6) ^ rotr(e, 11) ^ rotr(e, 25);
+    const uint32_t ch = (e & f) ^ (~e & g);
+    const uint32_t t1 = hh + S1 + ch + SHA_K[t] + wt;
+    const uint32_t S0 = rotr(a, 2) ^ rotr(a, 13) ^ rotr(a, 22);
+    const uint32_t mj = (a & b) ^ (a & c) ^ (b & c);
+    hh = g;
+    g = f;
+    f = e;
+    e = d + t1;
+    d = c;
+    c = b;
+    b = a;
+    a = t1 + S0 + mj;
   }
+  h[0] += a; h[1] += b; h[2] += c; h[3] += d; h[4] += e; h[5] += f; h[6] += g; h[7] += hh;
 }
 
-// Lanes 0 and 1 hash with prefixes 0 and 1; lane 0 reduces the 512-bit
-// little-endian concatenation of the two digests modulo r.
+// Both messages 0x00 || data and 0x01 || data have the same padded layout;
+// per 64-byte block, lanes 0..15 assemble the big-endian words in LDS and
+// lanes 0 and 1 compress them for prefix 0 and 1 (lane 1 patches the prefix
+// byte of the first word).  Lane 0 then reduces the 512-bit little-endian
+// concatenation of the two digests modulo r.
 __global__ void transcript_kernel(const uint8_t* __restrict__ data, uint64_t bytes, f29 c_2_256,
                                   uint32_t* __restrict__ out) {
+  __shared__ uint32_t blk[16];
   __shared__ uint32_t dig[2][8];
   const uint32_t lane = threadIdx.x;
-  if (lane < 2) {
-    uint32_t h[8];
-    sha256_prefixed(data, bytes, (uint8_t)lane, h);
-    // digest bytes are h[0] big-endian first; as a little-endian integer,
-    // 32-bit word i is the byte-reversed h[i]
-    for (int i = 0; i < 8; i++) dig[lane][i] = __builtin_bswap32(h[i]);
+  const uint64_t L = bytes + 1;
+  const uint64_t total = ((L + 8) / 64 + 1) * 64;
+  uint32_t h[8];
+  for (int i = 0; i < 8; i++) h[i] = SHA_H0[i];
+  for (uint64_t base = 0; base < total; base += 64) {
+    if (lane < 16) {
+      uint32_t v = 0;
+      for (int q = 0; q < 4; q++) v = (v << 8) | msg_byte(data, bytes, 0, total, base + 4 * lane + q);
+      blk[lane] = v;
+    }
+    __syncthreads();
+    if (lane < 2) {
+      uint32_t w[16];
+      for (int t = 0; t < 16; t++) w[t] = blk[t];
+      if (base == 0) w[0] = (w[0] & 0x00ffffffu) | (lane << 24);
+      sha256_block(h, w);
+    }
+    __syncthreads();
   }
+  if (lane < 2)
+    for (int i = 0; i < 8; i++) dig[lane][i] = __builtin_bswap32(h[i]);  // digest bytes as little-endian words
   __syncthreads();
   if (lane == 0) {
     const f29 lo = unpack(dig[0]);
