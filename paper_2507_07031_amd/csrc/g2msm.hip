@@ -7,14 +7,14 @@
 // and every window shares one set of 128 buckets (|digit| = 1..128); the
 // window sums need no doubling chain.
 //   count    per workgroup, a histogram of the digits' buckets (LDS atomics)
-//   offsets  one workgroup: every workgroup's base in every bucket, bucket
-//            offsets, and the accumulation threads of every bucket
+//   offsets  one workgroup per bucket scans the workgroups' counts; one more
+//            forms the bucket offsets and the accumulation threads per bucket
 //   scatter  digits recomputed, entries (table index, sign) written at the
 //            workgroup's reserved positions
-//   accumulate  each thread adds up to G2_L consecutive entries of one
+//   accumulate  each thread adds up to L consecutive entries of one
 //            bucket (mixed additions of table points), one partial each
 //   buckets  one workgroup per bucket: its partials summed (LDS tree)
-//   final    sum_b (b + 1) B_b by running sums over 16 chunks of 8, affine
+//   final    sum_b (b + 1) B_b as the sum of the buckets' suffix sums, affine
 // Field and point arithmetic: g2.h.
 #include "g2.h"
 #include "g2msm.h"
@@ -25,7 +25,7 @@ namespace zk {
 namespace {
 
 constexpr uint32_t G2_NT = 256;
-constexpr uint32_t G2_L = 32;               // entries per accumulation thread
+constexpr uint32_t G2_L = 32;               // entries per accumulation thread, at least
 constexpr uint32_t G2_XYZZ_WORDS = 72;      // four Fq2 coordinates, 9 limbs per component
 constexpr uint32_t G2_BUCKET_NT = 128;      // threads of a bucket workgroup
 
@@ -178,45 +178,61 @@ __global__ __launch_bounds__(G2_NT) void g2_count_kernel(const uint32_t* __restr
   for (uint32_t b = threadIdx.x; b < G2_K; b += G2_NT) blockhist[(size_t)blockIdx.x * G2_K + b] = hist[b];
 }
 
-// One workgroup of G2_K threads.  blockhist becomes every workgroup's
-// position in every bucket; off[b] = first entry of bucket b (off[G2_K] =
-// total); tp[b] = first accumulation thread of bucket b (tp[G2_K] = total).
-__global__ __launch_bounds__(G2_K) void g2_offsets_kernel(uint32_t* __restrict__ blockhist, uint32_t nblk,
-                                                          uint32_t* __restrict__ off, uint32_t* __restrict__ tp) {
-  __shared__ uint32_t tot[G2_K], thr[G2_K];
-  const uint32_t b = threadIdx.x;
-  uint32_t run = 0;
-  for (uint32_t k = 0; k < nblk; k++) {
+// One workgroup per bucket b: blockhist[k][b] becomes workgroup k's position
+// inside bucket b (an exclusive scan over the workgroups); tot[b] = the
+// bucket's entry count.
+__global__ __launch_bounds__(G2_NT) void g2_bucket_scan_kernel(uint32_t* __restrict__ blockhist, uint32_t nblk,
+                                                               uint32_t* __restrict__ tot) {
+  __shared__ uint32_t part[G2_NT];
+  const uint32_t b = blockIdx.x;
+  const uint32_t per = (nblk + G2_NT - 1) / G2_NT;
+  const uint32_t k0 = threadIdx.x * per;
+  uint32_t sum = 0;
+  for (uint32_t k = k0; k < min(k0 + per, nblk); k++) sum += blockhist[(size_t)k * G2_K + b];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (uint32_t t = 0; t < G2_NT; t++) {
+      const uint32_t c = part[t];
+      part[t] = run;
+      run += c;
+    }
+    tot[b] = run;
+  }
+  __syncthreads();
+  uint32_t run = part[threadIdx.x];
+  for (uint32_t k = k0; k < min(k0 + per, nblk); k++) {
     const uint32_t c = blockhist[(size_t)k * G2_K + b];
     blockhist[(size_t)k * G2_K + b] = run;
     run += c;
   }
-  tot[b] = run;
-  thr[b] = (run + G2_L - 1) / G2_L;
-  __syncthreads();
-  if (b == 0) {
+}
+
+// One workgroup of G2_K threads: off[b] = first entry of bucket b (off[G2_K]
+// = total); tp[b] = first accumulation thread of bucket b (tp[G2_K] = total).
+__global__ __launch_bounds__(G2_K) void g2_offsets_kernel(const uint32_t* __restrict__ tot, uint32_t L,
+                                                          uint32_t* __restrict__ off, uint32_t* __restrict__ tp) {
+  if (threadIdx.x == 0) {
     uint32_t a = 0, t = 0;
     for (uint32_t k = 0; k < G2_K; k++) {
-      const uint32_t ca = tot[k], ct = thr[k];
-      tot[k] = a;
-      thr[k] = t;
-      a += ca;
-      t += ct;
+      const uint32_t c = tot[k];
+      off[k] = a;
+      tp[k] = t;
+      a += c;
+      t += (c + L - 1) / L;
     }
     off[G2_K] = a;
     tp[G2_K] = t;
   }
-  __syncthreads();
-  off[b] = tot[b];
-  tp[b] = thr[b];
-  for (uint32_t k = 0; k < nblk; k++) blockhist[(size_t)k * G2_K + b] += tot[b];
 }
 
 __global__ __launch_bounds__(G2_NT) void g2_scatter_kernel(const uint32_t* __restrict__ scalars, uint64_t n,
                                                            uint64_t n_tab, const uint32_t* __restrict__ base,
+                                                           const uint32_t* __restrict__ off,
                                                            uint32_t* __restrict__ entries) {
   __shared__ uint32_t cur[G2_K];
-  for (uint32_t b = threadIdx.x; b < G2_K; b += G2_NT) cur[b] = base[(size_t)blockIdx.x * G2_K + b];
+  for (uint32_t b = threadIdx.x; b < G2_K; b += G2_NT) cur[b] = off[b] + base[(size_t)blockIdx.x * G2_K + b];
   __syncthreads();
   const uint64_t i = (uint64_t)blockIdx.x * G2_NT + threadIdx.x;
   if (i < n) {
@@ -236,7 +252,7 @@ __global__ __launch_bounds__(G2_NT) void g2_scatter_kernel(const uint32_t* __res
 __global__ __launch_bounds__(G2_NT) void g2_accumulate_kernel(const uint32_t* __restrict__ tab,
                                                               const uint32_t* __restrict__ entries,
                                                               const uint32_t* __restrict__ off,
-                                                              const uint32_t* __restrict__ tp,
+                                                              const uint32_t* __restrict__ tp, uint32_t L,
                                                               uint32_t* __restrict__ partial) {
   __shared__ uint32_t t0[G2_K + 1];
   for (uint32_t b = threadIdx.x; b <= G2_K; b += G2_NT) t0[b] = tp[b];
@@ -251,8 +267,8 @@ __global__ __launch_bounds__(G2_NT) void g2_accumulate_kernel(const uint32_t* __
     else hi = mid;
   }
   const uint32_t b = lo;
-  const uint32_t beg = off[b] + (t - t0[b]) * G2_L;
-  const uint32_t end = min(beg + G2_L, off[b + 1]);
+  const uint32_t beg = off[b] + (t - t0[b]) * L;
+  const uint32_t end = min(beg + L, off[b + 1]);
   g2xyzz acc = g2_inf();
   for (uint32_t e = beg; e < end; e++) {
     const uint32_t en = entries[e];
@@ -287,35 +303,32 @@ __global__ __launch_bounds__(G2_BUCKET_NT) void g2_bucket_kernel(const uint32_t*
   if (threadIdx.x == 0) st_xyzz(bsum + (size_t)b * G2_XYZZ_WORDS, acc);
 }
 
-// sum_b (b + 1) B_b: 16 threads take 8 buckets each (running sums give the
-// chunk total S_j and T_j = sum_m (m + 1) B_(8j+m)); thread 0 adds
-// sum_j T_j + 8 sum_j j S_j and writes the affine result.
-__global__ void g2_final_kernel(const uint32_t* __restrict__ bsum, uint32_t* __restrict__ out) {
-  __shared__ uint32_t S[16 * G2_XYZZ_WORDS], T[16 * G2_XYZZ_WORDS];
-  const uint32_t j = threadIdx.x;
-  if (j < 16) {
-    g2xyzz run = g2_inf(), tot = g2_inf();
-    for (int m = 7; m >= 0; --m) {
-      run = g2_add(run, ld_xyzz(bsum + (size_t)(8 * j + m) * G2_XYZZ_WORDS));
-      tot = g2_add(tot, run);
-    }
-    st_xyzz(S + j * G2_XYZZ_WORDS, run);
-    st_xyzz(T + j * G2_XYZZ_WORDS, tot);
-  }
+// sum_b (b + 1) B_b = sum_b S_b with S_b = sum_(b' >= b) B_b': one thread per
+// bucket, an inclusive suffix scan (7 Hillis-Steele levels, two LDS buffers)
+// and a tree sum (7 levels), then the affine result.
+__global__ __launch_bounds__(G2_K) void g2_final_kernel(const uint32_t* __restrict__ bsum, uint32_t* __restrict__ out) {
+  __shared__ uint32_t buf[2][G2_K * G2_XYZZ_WORDS];
+  const uint32_t b = threadIdx.x;
+  g2xyzz v = ld_xyzz(bsum + (size_t)b * G2_XYZZ_WORDS);
+  st_xyzz(buf[0] + b * G2_XYZZ_WORDS, v);
   __syncthreads();
-  if (j == 0) {
-    g2xyzz a = g2_inf(), run = g2_inf(), js = g2_inf();
-    for (int k = 15; k >= 0; --k) {
-      a = g2_add(a, ld_xyzz(T + k * G2_XYZZ_WORDS));
-      if (k >= 1) {
-        run = g2_add(run, ld_xyzz(S + k * G2_XYZZ_WORDS));
-        js = g2_add(js, run);  // after the loop: sum_k k S_k
-      }
+  uint32_t cur = 0;
+  for (uint32_t d = 1; d < G2_K; d <<= 1) {
+    if (b + d < G2_K) v = g2_add(v, ld_xyzz(buf[cur] + (b + d) * G2_XYZZ_WORDS));
+    st_xyzz(buf[cur ^ 1] + b * G2_XYZZ_WORDS, v);
+    cur ^= 1;
+    __syncthreads();
+  }
+  for (uint32_t h = G2_K / 2; h > 0; h >>= 1) {
+    if (b < h) {
+      v = g2_add(v, ld_xyzz(buf[cur] + (b + h) * G2_XYZZ_WORDS));
+      st_xyzz(buf[cur] + b * G2_XYZZ_WORDS, v);
     }
-    for (int d = 0; d < 3; d++) js = g2_dbl(js);
-    const g2xyzz r = g2_add(a, js);
+    __syncthreads();
+  }
+  if (b == 0) {
     uint32_t o[32];
-    g2_to_words(r, o);
+    g2_to_words(v, o);
     stw(out, o, 8);
   }
 }
@@ -339,11 +352,20 @@ hipError_t g2_build_table(const uint32_t* points, uint32_t* tab, uint64_t n, hip
   return hipGetLastError();
 }
 
+// Entries per accumulation thread: at least G2_L, more once the threads
+// exceed about 2^17 (enough waves), which keeps the partial sums per bucket
+// (summed by one workgroup each) few.
+uint32_t g2_entries_per_thread(uint64_t ent) {
+  uint64_t L = ent >> 17;
+  if (L < G2_L) L = G2_L;
+  return (uint32_t)L;
+}
+
 size_t g2_msm_scratch_bytes(uint64_t n) {
   const uint64_t nblk = cdiv(n ? n : 1, G2_NT);
   const uint64_t ent = (uint64_t)G2_W * n;
-  const uint64_t thr = ent / G2_L + G2_K + 1;
-  return align256(nblk * G2_K * 4) + 2 * align256((G2_K + 1) * 4) + align256(ent * 4) +
+  const uint64_t thr = ent / g2_entries_per_thread(ent) + G2_K + 1;
+  return align256(nblk * G2_K * 4) + 3 * align256((G2_K + 1) * 4) + align256(ent * 4) +
          align256(thr * G2_XYZZ_WORDS * 4) + align256((size_t)G2_K * G2_XYZZ_WORDS * 4);
 }
 
@@ -351,10 +373,13 @@ hipError_t g2_msm(const uint32_t* tab, uint64_t n_tab, const uint32_t* scalars, 
                   void* scratch, hipStream_t s) {
   const uint32_t nblk = cdiv(n ? n : 1, G2_NT);
   const uint64_t ent = (uint64_t)G2_W * n;
-  const uint64_t thr = ent / G2_L + G2_K + 1;
+  const uint32_t L = g2_entries_per_thread(ent);
+  const uint64_t thr = ent / L + G2_K + 1;
   char* p = static_cast<char*>(scratch);
   uint32_t* blockhist = reinterpret_cast<uint32_t*>(p);
   p += align256((size_t)nblk * G2_K * 4);
+  uint32_t* tot = reinterpret_cast<uint32_t*>(p);
+  p += align256((G2_K + 1) * 4);
   uint32_t* off = reinterpret_cast<uint32_t*>(p);
   p += align256((G2_K + 1) * 4);
   uint32_t* tp = reinterpret_cast<uint32_t*>(p);
@@ -367,12 +392,13 @@ hipError_t g2_msm(const uint32_t* tab, uint64_t n_tab, const uint32_t* scalars, 
 
   const ProfToken tok = prof_begin("g2.msm", s);
   hipLaunchKernelGGL(g2_count_kernel, dim3(nblk), dim3(G2_NT), 0, s, scalars, n, blockhist);
-  hipLaunchKernelGGL(g2_offsets_kernel, dim3(1), dim3(G2_K), 0, s, blockhist, nblk, off, tp);
-  hipLaunchKernelGGL(g2_scatter_kernel, dim3(nblk), dim3(G2_NT), 0, s, scalars, n, n_tab, blockhist, entries);
-  hipLaunchKernelGGL(g2_accumulate_kernel, dim3(cdiv(thr, G2_NT)), dim3(G2_NT), 0, s, tab, entries, off, tp,
+  hipLaunchKernelGGL(g2_bucket_scan_kernel, dim3(G2_K), dim3(G2_NT), 0, s, blockhist, nblk, tot);
+  hipLaunchKernelGGL(g2_offsets_kernel, dim3(1), dim3(G2_K), 0, s, tot, L, off, tp);
+  hipLaunchKernelGGL(g2_scatter_kernel, dim3(nblk), dim3(G2_NT), 0, s, scalars, n, n_tab, blockhist, off, entries);
+  hipLaunchKernelGGL(g2_accumulate_kernel, dim3(cdiv(thr, G2_NT)), dim3(G2_NT), 0, s, tab, entries, off, tp, L,
                      partial);
   hipLaunchKernelGGL(g2_bucket_kernel, dim3(G2_K), dim3(G2_BUCKET_NT), 0, s, partial, tp, bsum);
-  hipLaunchKernelGGL(g2_final_kernel, dim3(1), dim3(64), 0, s, bsum, out);
+  hipLaunchKernelGGL(g2_final_kernel, dim3(1), dim3(G2_K), 0, s, bsum, out);
   prof_end(tok, s);
   return hipGetLastError();
 }

@@ -14,7 +14,8 @@
 //   2. carries one workgroup per polynomial turns the tile values into
 //              y_i = sum_b L_b x^(T b); one more (the only one for a single
 //              polynomial) scans the tile values of g into the carry into
-//              every tile, C_(b+1) = Q_((b+1) T);
+//              every tile, C_(b+1) = Q_((b+1) T), and tabulates the 64 lane
+//              powers the apply launch's in-tile scan needs;
 //   3. apply   every tile re-evaluates its chunks, combines them with its
 //              carry, and runs the recurrence down through its coefficients,
 //              writing the quotient.
@@ -60,8 +61,8 @@ struct OpenArgs {
 
 struct CarryArgs {
   f29 X;       // x^OPEN_T: tile-to-tile multiplier
-  f29 gamma;
   f29 pw[7];   // X^(G 2^l)
+  f29 xe[6];   // x^(OPEN_E 2^l): for the lane powers of the in-tile scan
   uint32_t G;  // tiles per thread
 };
 
@@ -101,8 +102,11 @@ struct ScanOut {
 // Returns the workgroup total (every thread) and, if CARRY, each thread's
 // carry: the sum over later chunks and the tail, scaled to its chunk's end.
 // lds: 4 elements, free on entry; the caller synchronises before reusing it.
+// lane_pow (CARRY): b^(per (63 - lane)) for every lane, or nullptr to form
+// it here from pw.
 template <bool CARRY>
-__device__ __forceinline__ ScanOut block_suffix(const f29& h, const f29 (&pw)[7], const f29& tail, f29* lds) {
+__device__ __forceinline__ ScanOut block_suffix(const f29& h, const f29 (&pw)[7], const f29& tail, f29* lds,
+                                                const f29* lane_pow = nullptr) {
   const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
   // inclusive suffix scan across the wave: S_t = sum_(k >= t) h_k b^(per (k - t))
   f29 S = h;
@@ -127,12 +131,17 @@ __device__ __forceinline__ ScanOut block_suffix(const f29& h, const f29 (&pw)[7]
   if (CARRY) {
     f29 nxt = shfl_down_f29(S, 1);
     if (lane == 63) nxt = f29_zero();
-    // b^(per (63 - lane)) from the bits of 63 - lane
-    const f29 one = f29_from(FrP::ONE);
-    const uint32_t e = 63u - lane;
-    f29 p = one;
+    f29 p;
+    if (lane_pow) {
+      p = lane_pow[lane];
+    } else {
+      // b^(per (63 - lane)) from the bits of 63 - lane
+      const f29 one = f29_from(FrP::ONE);
+      const uint32_t e = 63u - lane;
+      p = one;
 #pragma unroll
-    for (int l = 0; l < 6; l++) p = mont_mul<FrP>(p, ((e >> l) & 1u) ? pw[l] : one);
+      for (int l = 0; l < 6; l++) p = mont_mul<FrP>(p, ((e >> l) & 1u) ? pw[l] : one);
+    }
     r.carry = mac(nxt, Kw, p);
   } else {
     r.carry = f29_zero();
@@ -148,7 +157,8 @@ __device__ __forceinline__ f29 ld_coeff(const uint32_t* f, uint64_t j, uint64_t 
 }
 
 // Launch 1.  Grid: one workgroup per tile.  tile_vals[i * nt + b] = L_b of
-// polynomial i (canonical); g (BATCH, m > 1): the gamma combination, canonical.
+// polynomial i (canonical); BATCH (m > 1): g, the gamma combination of the
+// coefficients, and its tile values sum_i gamma^i L_(i,b) in row m.
 template <bool BATCH>
 __global__ __launch_bounds__(OPEN_NT) void open_tiles_kernel(const uint32_t* __restrict__ polys, uint32_t m,
                                                              uint64_t n, OpenArgs a, f29* __restrict__ tile_vals,
@@ -156,6 +166,7 @@ __global__ __launch_bounds__(OPEN_NT) void open_tiles_kernel(const uint32_t* __r
   __shared__ f29 lds[2][4];
   const uint64_t s = (uint64_t)blockIdx.x * OPEN_T + (uint64_t)threadIdx.x * OPEN_E;
   f29 acc[OPEN_E];
+  f29 lg = f29_zero();
   for (int32_t i = (int32_t)m - 1; i >= 0; --i) {
     const uint32_t* f = polys + (uint64_t)i * n * 8;
     f29 v[OPEN_E];
@@ -164,7 +175,11 @@ __global__ __launch_bounds__(OPEN_NT) void open_tiles_kernel(const uint32_t* __r
     f29 h = v[OPEN_E - 1];
     static_for<OPEN_E - 1>([&](auto c) { h = mac(v[OPEN_E - 2 - c], h, a.x); });
     const ScanOut r = block_suffix<false>(h, a.pw, f29_zero(), lds[i & 1]);
-    if (threadIdx.x == 0) tile_vals[(uint64_t)i * nt + blockIdx.x] = reduce_full<FrP>(r.total);
+    if (threadIdx.x == 0) {
+      const f29 li = reduce_full<FrP>(r.total);
+      tile_vals[(uint64_t)i * nt + blockIdx.x] = li;
+      if (BATCH) lg = (uint32_t)i == m - 1 ? li : mac(li, lg, a.gamma);
+    }
     if (BATCH) {
       const bool first = (uint32_t)i == m - 1;
       static_for<OPEN_E>([&](auto k) { acc[k] = first ? v[k] : mac(v[k], acc[k], a.gamma); });
@@ -174,25 +189,23 @@ __global__ __launch_bounds__(OPEN_NT) void open_tiles_kernel(const uint32_t* __r
 #pragma unroll
     for (uint32_t k = 0; k < OPEN_E; k++)
       if (s + k < n) st_canon(g + (s + k) * 8, acc[k]);
+    if (threadIdx.x == 0) tile_vals[(uint64_t)m * nt + blockIdx.x] = reduce_full<FrP>(lg);
   }
 }
 
-// Tile value b of the scanned sequence: polynomial `poly`'s, or (poly == m)
-// the gamma combination sum_i gamma^i L_(i,b).
-__device__ __forceinline__ f29 tile_value(const f29* tile_vals, uint32_t m, uint32_t nt, uint32_t poly, uint32_t b,
-                                          const f29& gamma) {
+// Tile value b of row `row` of tile_vals (zero past the last tile).
+__device__ __forceinline__ f29 tile_value(const f29* tile_vals, uint32_t nt, uint32_t row, uint32_t b) {
   if (b >= nt) return f29_zero();
-  if (poly < m) return tile_vals[(uint64_t)poly * nt + b];
-  f29 L = tile_vals[(uint64_t)(m - 1) * nt + b];
-  for (int32_t i = (int32_t)m - 2; i >= 0; --i) L = mac(tile_vals[(uint64_t)i * nt + b], L, gamma);
-  return L;
+  return tile_vals[(uint64_t)row * nt + b];
 }
 
 // Launch 2.  Grid: m workgroups (y of each polynomial) plus, for m > 1, one
-// for the carries of g; with m == 1 workgroup 0 does both.  Thread t owns
-// tiles [t G, t G + G).
+// for the carries of g (row m); with m == 1 workgroup 0 does both.  Thread t
+// owns tiles [t G, t G + G).  The carry workgroup also writes lane_pow[t] =
+// x^(OPEN_E (63 - t)), t < 64, for the apply launch's in-tile scan.
 __global__ __launch_bounds__(CARRY_NT) void open_carry_kernel(const f29* __restrict__ tile_vals, uint32_t m,
                                                               uint32_t nt, CarryArgs a, f29* __restrict__ carry_in,
+                                                              f29* __restrict__ lane_pow,
                                                               uint32_t* __restrict__ ys) {
   __shared__ f29 lds[4];
   const uint32_t poly = blockIdx.x;
@@ -200,7 +213,7 @@ __global__ __launch_bounds__(CARRY_NT) void open_carry_kernel(const f29* __restr
   const bool carries = (m == 1) || poly == m;
   const uint32_t b0 = threadIdx.x * a.G;
   f29 h = f29_zero();
-  for (int32_t k = (int32_t)a.G - 1; k >= 0; --k) h = mac(tile_value(tile_vals, m, nt, src, b0 + k, a.gamma), h, a.X);
+  for (int32_t k = (int32_t)a.G - 1; k >= 0; --k) h = mac(tile_value(tile_vals, nt, src, b0 + k), h, a.X);
   ScanOut r;
   if (carries)
     r = block_suffix<true>(h, a.pw, f29_zero(), lds);
@@ -213,8 +226,15 @@ __global__ __launch_bounds__(CARRY_NT) void open_carry_kernel(const f29* __restr
       const uint32_t b = b0 + k;
       if (b < nt) {
         carry_in[b] = reduce_full<FrP>(Q);
-        Q = mac(tile_value(tile_vals, m, nt, src, b, a.gamma), Q, a.X);
+        Q = mac(tile_value(tile_vals, nt, src, b), Q, a.X);
       }
+    }
+    if (threadIdx.x < 64) {
+      const f29 one = f29_from(FrP::ONE);
+      const uint32_t e = 63u - threadIdx.x;
+      f29 p = one;
+      for (int l = 0; l < 6; l++) p = mont_mul<FrP>(p, ((e >> l) & 1u) ? a.xe[l] : one);
+      lane_pow[threadIdx.x] = reduce_full<FrP>(p);
     }
   }
 }
@@ -222,6 +242,7 @@ __global__ __launch_bounds__(CARRY_NT) void open_carry_kernel(const f29* __restr
 // Launch 3.  Grid: one workgroup per tile.  q[j - 1] = Q_j for 1 <= j < n.
 __global__ __launch_bounds__(OPEN_NT) void open_apply_kernel(const uint32_t* __restrict__ f, uint64_t n, OpenArgs a,
                                                              const f29* __restrict__ carry_in,
+                                                             const f29* __restrict__ lane_pow,
                                                              uint32_t* __restrict__ q) {
   __shared__ f29 lds[4];
   const uint64_t s = (uint64_t)blockIdx.x * OPEN_T + (uint64_t)threadIdx.x * OPEN_E;
@@ -230,7 +251,7 @@ __global__ __launch_bounds__(OPEN_NT) void open_apply_kernel(const uint32_t* __r
   for (uint32_t k = 0; k < OPEN_E; k++) v[k] = ld_coeff(f, s + k, n);
   f29 h = v[OPEN_E - 1];
   static_for<OPEN_E - 1>([&](auto c) { h = mac(v[OPEN_E - 2 - c], h, a.x); });
-  const ScanOut r = block_suffix<true>(h, a.pw, carry_in[blockIdx.x], lds);
+  const ScanOut r = block_suffix<true>(h, a.pw, carry_in[blockIdx.x], lds, lane_pow);
   f29 Q = r.carry;
   static_for<OPEN_E>([&](auto c) {
     constexpr int k = OPEN_E - 1 - decltype(c)::value;
@@ -263,7 +284,8 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t open_scratch_bytes(uint32_t m, uint64_t n) {
   const uint64_t nt = tiles_of(n);
-  size_t b = align256(sizeof(f29) * (size_t)m * nt) + align256(sizeof(f29) * (nt + 1));
+  const uint64_t rows = m + (m > 1 ? 1 : 0);
+  size_t b = align256(sizeof(f29) * (size_t)rows * nt) + align256(sizeof(f29) * (nt + 1)) + align256(sizeof(f29) * 64);
   if (m > 1) b += align256((size_t)n * 32);
   return b;
 }
@@ -272,10 +294,13 @@ hipError_t open_quotient(const uint32_t* polys, uint32_t m, uint64_t n, const ui
                          const uint32_t gamma[8], uint32_t* ys, uint32_t* q, void* scratch, hipStream_t s) {
   const uint32_t nt = tiles_of(n);
   char* p = static_cast<char*>(scratch);
+  const uint64_t rows = m + (m > 1 ? 1 : 0);
   f29* tile_vals = reinterpret_cast<f29*>(p);
-  p += align256(sizeof(f29) * (size_t)m * nt);
+  p += align256(sizeof(f29) * (size_t)rows * nt);
   f29* carry_in = reinterpret_cast<f29*>(p);
   p += align256(sizeof(f29) * (nt + 1));
+  f29* lane_pow = reinterpret_cast<f29*>(p);
+  p += align256(sizeof(f29) * 64);
   uint32_t* g = m > 1 ? reinterpret_cast<uint32_t*>(p) : nullptr;
 
   OpenArgs a;
@@ -285,7 +310,7 @@ hipError_t open_quotient(const uint32_t* polys, uint32_t m, uint64_t n, const ui
   for (int l = 1; l < 7; l++) a.pw[l] = host_sq(a.pw[l - 1]);
   CarryArgs c;
   c.X = host_pow(a.x, OPEN_T);
-  c.gamma = a.gamma;
+  for (int l = 0; l < 6; l++) c.xe[l] = a.pw[l];
   c.G = nt ? (nt + CARRY_NT - 1) / CARRY_NT : 1;
   c.pw[0] = host_pow(c.X, c.G);
   for (int l = 1; l < 7; l++) c.pw[l] = host_sq(c.pw[l - 1]);
@@ -300,11 +325,12 @@ hipError_t open_quotient(const uint32_t* polys, uint32_t m, uint64_t n, const ui
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(open_carry_kernel, dim3(m + (m > 1 ? 1 : 0)), dim3(CARRY_NT), 0, s, tile_vals, m, nt, c,
-                     carry_in, ys);
+                     carry_in, lane_pow, ys);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (nt && n > 1) {
-    hipLaunchKernelGGL(open_apply_kernel, dim3(nt), dim3(OPEN_NT), 0, s, m > 1 ? g : polys, n, a, carry_in, q);
+    hipLaunchKernelGGL(open_apply_kernel, dim3(nt), dim3(OPEN_NT), 0, s, m > 1 ? g : polys, n, a, carry_in,
+                       lane_pow, q);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
