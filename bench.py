@@ -42,6 +42,8 @@ PEAK_MAD_TOPS = 256 * 64 * 2.4e9 / 1e12
 MADS_PER_MONT = 136
 # Fq products of a mixed XYZZ addition (8M + 2S)
 MONT_PER_MADD = 10
+# Fq products of a mixed G2 XYZZ addition: 8 Fq2 products x 3 + 2 Fq2 squares x 2
+G2_FQ_PER_MADD = 28
 # HBM bytes of one accumulate dispatch of this workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE scaled by a plain-copy calibration (x2.0 / x1.0);
 # valid only for the kernel sources whose hash is recorded with it.
@@ -93,6 +95,20 @@ def nonzero_digits(scalars_u32, c):
         mag = np.where(big, (1 << c) - d, d)
         carry = big.astype(np.int64)
         count += int(np.count_nonzero(mag))
+    return count
+
+
+def g2_nonzero_digits(scalars_u32):
+    """Nonzero signed 8-bit digits of the G2 MSM's recoding (32 windows, no
+    negation trick): the number of mixed G2 additions it performs."""
+    b = np.ascontiguousarray(np.asarray(scalars_u32, dtype=np.uint32)).view(np.uint8).reshape(-1, 32)
+    carry = np.zeros(b.shape[0], dtype=np.int64)
+    count = 0
+    for w in range(32):
+        v = b[:, w].astype(np.int64) + carry
+        big = v > 128
+        carry = big.astype(np.int64)
+        count += int(np.count_nonzero(np.where(big, v - 256, v)))
     return count
 
 
@@ -471,9 +487,24 @@ def main():
         g2out = torch.empty((1, 32), dtype=torch.int32, device=dev)
         g2 = {}
         for lg in (16, 20):
-            sc2 = zk.to_device(gen.uniform_fr(gen.CONFIG_SEEDS["commit"], 1 << lg, tag=70 + lg))
+            sc2_h = gen.uniform_fr(gen.CONFIG_SEEDS["commit"], 1 << lg, tag=70 + lg)
+            sc2 = zk.to_device(sc2_h)
             t_g2 = timed(lambda: zk.msm_g2_srs(g2srs, sc2, out=g2out), reps=3)
-            g2["msm_2^%d" % lg] = {"ms": round(t_g2, 4), "points_per_s": (1 << lg) / (t_g2 / 1e3)}
+            zk.profile_read("g2.accumulate")
+            zk.profile_enable(True)
+            for _ in range(3):
+                zk.msm_g2_srs(g2srs, sc2, out=g2out)
+            torch.cuda.synchronize()
+            zk.profile_enable(False)
+            acc_ms, acc_n = zk.profile_read("g2.accumulate")
+            acc_ms /= max(acc_n, 1)
+            # one mixed G2 addition per nonzero signed 8-bit digit: 8 Fq2
+            # products (3 Fq products each) and 2 Fq2 squares (2 each)
+            g2_madds = g2_nonzero_digits(sc2_h)
+            g2_tops = g2_madds * G2_FQ_PER_MADD * MADS_PER_MONT / (acc_ms / 1e3) / 1e12
+            g2["msm_2^%d" % lg] = {"ms": round(t_g2, 4), "points_per_s": (1 << lg) / (t_g2 / 1e3),
+                                   "accumulate_ms": round(acc_ms, 4), "mixed_additions": g2_madds,
+                                   "accumulate_int_frac": round(g2_tops / PEAK_MAD_TOPS, 4)}
             del sc2
         extras["g2_msm"] = g2
         g2srs.close()

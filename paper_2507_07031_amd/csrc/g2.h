@@ -4,8 +4,9 @@
 // Every Fq2 operation returns both components reduced below 2q with
 // normalised limbs, so inputs of every Montgomery product stay below 4q (sums
 // of two reduced values), comfortably inside the product's 16q input bound;
-// this spends three conditional subtractions per component instead of an
-// interval analysis of lazy reduction.  Coordinates are in Montgomery form.
+// a product of two values below 4q is below 1.1q.  Each operation then needs
+// only the conditional subtractions its own output bound calls for (stated
+// at each one).  Coordinates are in Montgomery form.
 // The point formulas are the XYZZ ones of curve.h with Fq2 coefficients.
 #pragma once
 #include "curve.h"
@@ -31,12 +32,11 @@ __constant__ static const uint32_t G2_GEN[32] = {
     0x66fa7daau, 0x4ce6cc01u, 0x0c43d37bu, 0xe3d1e769u, 0x8dcb408fu, 0x4aab7180u, 0xdb8c6debu, 0x12c85ea5u,
     0xd122975bu, 0x55acdadcu, 0x70b38ef3u, 0xbc4b3133u, 0x690c3395u, 0xec9e99adu, 0x585ff075u, 0x090689d0u};
 
-// normalised value < 16q -> < 2q
-ZK_HD f29 red2(f29 a) {
-  a = cond_sub(a, Fq::C8);
-  a = cond_sub(a, Fq::C4);
-  return cond_sub(a, Fq::C2);
-}
+// normalised value < 4q -> < 2q
+ZK_HD f29 red_lt4(const f29& a) { return cond_sub(a, Fq::C2); }
+
+// normalised value < 8q -> < 2q
+ZK_HD f29 red_lt8(const f29& a) { return cond_sub(cond_sub(a, Fq::C4), Fq::C2); }
 
 ZK_HD fp2 fp2_zero() { return fp2{f29_zero(), f29_zero()}; }
 
@@ -44,27 +44,31 @@ ZK_HD bool fp2_is_zero_limbs(const fp2& a) { return f29_is_zero_limbs(a.c0) && f
 
 ZK_HD bool fp2_is_zero_mod(const fp2& a) { return is_zero_mod<Fq>(a.c0) && is_zero_mod<Fq>(a.c1); }
 
-ZK_HD fp2 fp2_add(const fp2& a, const fp2& b) { return fp2{red2(add_n(a.c0, b.c0)), red2(add_n(a.c1, b.c1))}; }
+// a + b < 4q
+ZK_HD fp2 fp2_add(const fp2& a, const fp2& b) { return fp2{red_lt4(add_n(a.c0, b.c0)), red_lt4(add_n(a.c1, b.c1))}; }
 
+// a - b + 2q < 4q
 ZK_HD fp2 fp2_sub(const fp2& a, const fp2& b) {
-  return fp2{red2(sub_k(a.c0, b.c0, Fq::K2)), red2(sub_k(a.c1, b.c1, Fq::K2))};
+  return fp2{red_lt4(sub_k(a.c0, b.c0, Fq::K2)), red_lt4(sub_k(a.c1, b.c1, Fq::K2))};
 }
 
 ZK_HD fp2 fp2_neg(const fp2& a) { return fp2_sub(fp2_zero(), a); }
 
 // (a0 + a1 u)(b0 + b1 u) = (a0 b0 - a1 b1) + ((a0 + a1)(b0 + b1) - a0 b0 - a1 b1) u
+// m0, m1 < 1.03q, m2 < 1.1q: c0 = m0 - m1 + 2q < 4q, c1 = m2 - (m0 + m1) + 4q < 8q.
 ZK_HD fp2 fp2_mul(const fp2& a, const fp2& b) {
   const f29 m0 = mont_mul<Fq>(a.c0, b.c0);
   const f29 m1 = mont_mul<Fq>(a.c1, b.c1);
   const f29 m2 = mont_mul<Fq>(add_n(a.c0, a.c1), add_n(b.c0, b.c1));
-  return fp2{red2(sub_k(m0, m1, Fq::K2)), red2(sub_k(m2, add_n(m0, m1), Fq::K4))};
+  return fp2{red_lt4(sub_k(m0, m1, Fq::K2)), red_lt8(sub_k(m2, add_n(m0, m1), Fq::K4))};
 }
 
 // (a0 + a1 u)^2 = (a0 + a1)(a0 - a1) + 2 a0 a1 u
+// both factors of s below 4q, so s < 1.1q; 2 t < 2.1q.
 ZK_HD fp2 fp2_sqr(const fp2& a) {
   const f29 s = mont_mul<Fq>(add_n(a.c0, a.c1), sub_k(a.c0, a.c1, Fq::K2));
   const f29 t = mont_mul<Fq>(a.c0, a.c1);
-  return fp2{red2(s), red2(add_n(t, t))};
+  return fp2{s, red_lt4(add_n(t, t))};
 }
 
 ZK_HD fp2 fp2_from_mont_one() { return fp2{f29_from(Fq::ONE), f29_zero()}; }
@@ -73,8 +77,8 @@ ZK_HD fp2 fp2_from_mont_one() { return fp2{f29_from(Fq::ONE), f29_zero()}; }
 ZK_HD fp2 fp2_inv(const fp2& a) {
   const f29 nrm = reduce_full<Fq>(add_n(mont_mul<Fq>(a.c0, a.c0), mont_mul<Fq>(a.c1, a.c1)));
   const f29 ni = mont_inv<Fq>(nrm);
-  const fp2 conj{a.c0, red2(sub_k(f29_zero(), a.c1, Fq::K2))};
-  return fp2{red2(mont_mul<Fq>(conj.c0, ni)), red2(mont_mul<Fq>(conj.c1, ni))};
+  const fp2 conj{a.c0, red_lt4(sub_k(f29_zero(), a.c1, Fq::K2))};
+  return fp2{red_lt4(mont_mul<Fq>(conj.c0, ni)), red_lt4(mont_mul<Fq>(conj.c1, ni))};
 }
 
 ZK_HD bool g2_is_inf(const g2xyzz& a) { return fp2_is_zero_limbs(a.ZZ); }

@@ -395,8 +395,10 @@ hipError_t g2_msm(const uint32_t* tab, uint64_t n_tab, const uint32_t* scalars, 
   hipLaunchKernelGGL(g2_bucket_scan_kernel, dim3(G2_K), dim3(G2_NT), 0, s, blockhist, nblk, tot);
   hipLaunchKernelGGL(g2_offsets_kernel, dim3(1), dim3(G2_K), 0, s, tot, L, off, tp);
   hipLaunchKernelGGL(g2_scatter_kernel, dim3(nblk), dim3(G2_NT), 0, s, scalars, n, n_tab, blockhist, off, entries);
+  const ProfToken acc = prof_begin("g2.accumulate", s);
   hipLaunchKernelGGL(g2_accumulate_kernel, dim3(cdiv(thr, G2_NT)), dim3(G2_NT), 0, s, tab, entries, off, tp, L,
                      partial);
+  prof_end(acc, s);
   hipLaunchKernelGGL(g2_bucket_kernel, dim3(G2_K), dim3(G2_BUCKET_NT), 0, s, partial, tp, bsum);
   hipLaunchKernelGGL(g2_final_kernel, dim3(1), dim3(G2_K), 0, s, bsum, out);
   prof_end(tok, s);

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "../../paper_2507_07031_amd/csrc/curve.h"
+#include "../../paper_2507_07031_amd/csrc/g2.h"
 
 using namespace zk;
 
@@ -149,6 +150,77 @@ void host_xyzz_dbl_raw(const uint32_t* a, uint32_t* out) {
 
 void host_xyzz_to_affine(const uint32_t* a, uint32_t* out) {
   to_affine_words(load_xyzz_raw(a), out);
+}
+
+}  // extern "C"
+
+// ---- G2 (Fq2 and twist points) ----------------------------------------------
+
+static fp2 load_fp2_raw(const uint32_t* w) {
+  fp2 a;
+  for (int i = 0; i < 9; i++) {
+    a.c0.l[i] = w[i];
+    a.c1.l[i] = w[9 + i];
+  }
+  return a;
+}
+
+static void store_fp2_raw(const fp2& a, uint32_t* w) {
+  for (int i = 0; i < 9; i++) {
+    w[i] = a.c0.l[i];
+    w[9 + i] = a.c1.l[i];
+  }
+}
+
+extern "C" {
+
+// op: 0 add, 1 sub, 2 mul, 3 sqr, 4 inv (Montgomery components as raw
+// 29-bit limbs, 18 words per element).
+void host_fq2_op_raw(int op, const uint32_t* a, const uint32_t* b, uint32_t* out) {
+  const fp2 x = load_fp2_raw(a), y = load_fp2_raw(b);
+  fp2 r;
+  switch (op) {
+    case 0: r = fp2_add(x, y); break;
+    case 1: r = fp2_sub(x, y); break;
+    case 2: r = fp2_mul(x, y); break;
+    case 3: r = fp2_sqr(x); break;
+    default: r = fp2_inv(x); break;
+  }
+  store_fp2_raw(r, out);
+}
+
+// sum of affine G2 points (32 words each, (0,0,0,0) = infinity).
+void host_g2_sum_madd(const uint32_t* pts, uint64_t n, uint32_t* out) {
+  g2xyzz acc = g2_inf();
+  for (uint64_t i = 0; i < n; i++) {
+    g2aff p;
+    if (g2_from_words(pts + 32 * i, p)) acc = g2_madd(acc, p);
+  }
+  g2_to_words(acc, out);
+}
+
+void host_g2_sum_add(const uint32_t* pts, uint64_t n, uint32_t* out) {
+  g2xyzz acc = g2_inf();
+  for (uint64_t i = 0; i < n; i++) {
+    g2aff p;
+    if (g2_from_words(pts + 32 * i, p)) acc = g2_add(acc, g2_from_aff(p));
+  }
+  g2_to_words(acc, out);
+}
+
+void host_g2_dbl(const uint32_t* pt, uint32_t* out) {
+  g2aff p;
+  const g2xyzz a = g2_from_words(pt, p) ? g2_from_aff(p) : g2_inf();
+  g2_to_words(g2_dbl(a), out);
+}
+
+void host_g2_neg(const uint32_t* pt, uint32_t* out) {
+  g2aff p;
+  if (!g2_from_words(pt, p)) {
+    for (int i = 0; i < 32; i++) out[i] = 0;
+    return;
+  }
+  g2_to_words(g2_from_aff(g2_aff_neg(p)), out);
 }
 
 }  // extern "C"

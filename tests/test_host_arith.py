@@ -13,7 +13,7 @@ import subprocess
 import numpy as np
 import pytest
 
-from oracle import field, g1
+from oracle import field, g1, g2
 from workloads import ints_to_limbs, limbs_to_ints
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -43,7 +43,7 @@ def lib():
 
 def _sources():
     csrc = os.path.join(os.path.dirname(HERE), "paper_2507_07031_amd", "csrc")
-    return [SRC] + [os.path.join(csrc, f) for f in ("field.h", "curve.h", "field_constants.h")]
+    return [SRC] + [os.path.join(csrc, f) for f in ("field.h", "curve.h", "field_constants.h", "g2.h")]
 
 
 def _w(vals):
@@ -254,3 +254,76 @@ def test_formulas_at_edge_of_bound_box(lib):
         oa = np.zeros(16, dtype=np.uint32)
         lib.host_xyzz_to_affine(ptr(wa), ptr(oa))
         assert _read_pt(oa) == a
+
+
+# ---- G2 -----------------------------------------------------------------------
+
+def _fp2_raw(c0, c1):
+    return np.array(_limbs29(c0) + _limbs29(c1), dtype=np.uint32)
+
+
+def _fp2_val(arr):
+    return (_from_limbs29(arr[:9]), _from_limbs29(arr[9:]))
+
+
+def test_fq2_ops_bounds_and_values(lib):
+    """Fq2 add, sub, mul, sqr, inv on Montgomery components anywhere in [0, 2q):
+    results below 2q and equal to the oracle's values (times 2^261)."""
+    rng = np.random.default_rng(21)
+    Rm = MONT % P
+    Rinv = pow(MONT, -1, P)
+    edge = [0, 1, P - 1, P, 2 * P - 1]
+    for t in range(400):
+        vals = [int(rng.integers(0, 2 ** 62)) * (2 ** 192) % (2 * P) for _ in range(4)]
+        if t < 25:
+            vals = [edge[(t + k) % 5] for k in range(4)]
+        a, b = (vals[0], vals[1]), (vals[2], vals[3])
+        pa = ((a[0] * Rinv) % P, (a[1] * Rinv) % P)  # plain values represented
+        pb = ((b[0] * Rinv) % P, (b[1] * Rinv) % P)
+        want = {0: g2.f2_add(pa, pb), 1: g2.f2_sub(pa, pb), 2: g2.f2_mul(pa, pb), 3: g2.f2_mul(pa, pa)}
+        if pa != (0, 0):
+            want[4] = g2.f2_inv(pa)
+        for op, w in want.items():
+            out = np.zeros(18, dtype=np.uint32)
+            lib.host_fq2_op_raw(op, _fp2_raw(*a).ctypes.data_as(ctypes.c_void_p),
+                                _fp2_raw(*b).ctypes.data_as(ctypes.c_void_p),
+                                out.ctypes.data_as(ctypes.c_void_p))
+            r = _fp2_val(out)
+            assert r[0] < 2 * P and r[1] < 2 * P, (op, t)
+            assert all(x < (1 << 29) for x in out[:8]) and all(x < (1 << 29) for x in out[9:17]), (op, t)
+            assert ((r[0] * Rinv) % P, (r[1] * Rinv) % P) == w, (op, t)
+    assert Rm != 0
+
+
+def _g2_words(pts):
+    vals = []
+    for p in pts:
+        vals += list(g2.encode(p))
+    return _w(vals)
+
+
+def _read_g2(arr):
+    return g2.decode(tuple(limbs_to_ints(arr.reshape(4, 8))))
+
+
+def test_g2_point_sums_and_special_cases(lib):
+    rng = np.random.default_rng(22)
+    ks = [int(rng.integers(1, 2 ** 62)) for _ in range(5)]
+    pts = [g2.gen_mul(k) for k in ks]
+    cases = [pts, [pts[0], pts[0]], [pts[1], g2.neg(pts[1])], [None, pts[2], None], [pts[3], pts[3], pts[3]],
+             [pts[0], pts[1], g2.neg(pts[0])], []]
+    for case in cases:
+        want = None
+        for p in case:
+            want = g2.add(want, p)
+        for fn in (lib.host_g2_sum_madd, lib.host_g2_sum_add):
+            arr, ptr = _g2_words(case) if case else _w([0])
+            out, optr = _out(32)
+            fn(ptr, len(case), optr)
+            assert _read_g2(out) == want
+    out, optr = _out(32)
+    arr, ptr = _g2_words([pts[4]])
+    lib.host_g2_dbl(ptr, optr)
+    assert _read_g2(out) == g2.double(pts[4])
+    lib.host_g2_neg(ptr, optr)
+    assert _read_g2(out) == g2.neg(pts[4])
