@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <initializer_list>
 #include <atomic>
@@ -179,6 +180,16 @@ zk_status block_alloc(Block& out, size_t bytes, hipStream_t s) {
     if (out.stream != s) ZK_HIP(hipStreamWaitEvent(s, out.done, 0), "hipStreamWaitEvent(scratch)");
     out.stream = s;
     return ZK_OK;
+  }
+  static const bool log_alloc = std::getenv("ZK_LOG_ALLOC") != nullptr;
+  if (log_alloc) {
+    size_t cached = 0;
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      for (const Block& b : g_free_blocks) cached += b.size;
+    }
+    std::fprintf(stderr, "[zk] scratch hipMalloc %zu bytes (cached %zu bytes in %zu blocks)\n", bytes, cached,
+                 g_free_blocks.size());
   }
   hipError_t e = hipMalloc(&out.p, bytes);
   if (e != hipSuccess) {

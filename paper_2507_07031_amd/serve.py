@@ -9,14 +9,17 @@ SRS) and the 4x coset evaluation that the quotient by X^N - 1 needs.
   arrival order; the head job starts as soon as a stream slot is free and its
   HBM footprint fits the budget next to the jobs already running (strict
   FIFO, so a large job is never starved by small ones behind it).  A job
-  whose footprint exceeds the whole budget is rejected.
+  whose footprint exceeds the whole budget is rejected, and so is a job that
+  arrives while `max_queue` jobs already wait (back-pressure).
 * `GpuExecutor` runs each admitted job on its own HIP stream (all at the
   default priority), so jobs admitted while others are on the GPU overlap
   with them; completion is detected by polling an event per job.  A job is
   one `zk_commit_job` call (the library overlaps its coset transform with
   the MSM's reduction on a companion stream of the slot's stream).
 * `serve` drives a timed arrival stream through both and records per-job
-  arrival, start and finish times (host clock).
+  arrival, start and finish times (host clock).  A job whose start or
+  completion raises (a library error such as ZK_EDEVICE) is finished with
+  `error` set and its slot and bytes released; the other jobs go on.
 
 The executor is pluggable; the tests use a mock that only models durations
 and bytes to check the admission logic on the CPU.
@@ -28,7 +31,7 @@ import numpy as np
 
 
 class Job:
-    __slots__ = ("jid", "n", "N", "arrival", "offset", "start", "finish", "footprint", "handle", "result")
+    __slots__ = ("jid", "n", "N", "arrival", "offset", "start", "finish", "footprint", "handle", "result", "error")
 
     def __init__(self, jid, n, arrival, offset=0):
         self.jid = int(jid)
@@ -41,15 +44,17 @@ class Job:
         self.footprint = 0
         self.handle = None
         self.result = None
+        self.error = None
 
 
 class Admission:
     """FIFO admission under a byte budget and a number of concurrent slots."""
 
-    def __init__(self, budget_bytes, slots, footprint):
+    def __init__(self, budget_bytes, slots, footprint, max_queue=None):
         self.budget = int(budget_bytes)
         self.slots = int(slots)
         self.footprint = footprint
+        self.max_queue = max_queue
         self.queue = collections.deque()
         self.running = []
         self.used = 0
@@ -58,6 +63,11 @@ class Admission:
     def submit(self, job):
         job.footprint = int(self.footprint(job))
         if job.footprint > self.budget:
+            job.error = "rejected: footprint exceeds the budget"
+            self.rejected.append(job)
+            return False
+        if self.max_queue is not None and len(self.queue) >= self.max_queue:
+            job.error = "rejected: queue full"
             self.rejected.append(job)
             return False
         self.queue.append(job)
@@ -107,15 +117,19 @@ class GpuExecutor:
         torch, zk = self.torch, self.zk
         slot = self.free.pop()
         s = self.streams[slot]
-        with torch.cuda.stream(s):
-            N = job.N
-            ev = self.pool[job.offset:job.offset + N]
-            if job.n < N:
-                ev = torch.cat([self.pool[job.offset:job.offset + job.n],
-                                torch.zeros((N - job.n, 8), dtype=torch.int32, device=ev.device)])
-            coeffs, com, coset = zk.commit_job(self.srs, ev, log_blowup=2)
-            done = torch.cuda.Event(enable_timing=self.timing)
-            done.record(s)
+        try:
+            with torch.cuda.stream(s):
+                N = job.N
+                ev = self.pool[job.offset:job.offset + N]
+                if job.n < N:
+                    ev = torch.cat([self.pool[job.offset:job.offset + job.n],
+                                    torch.zeros((N - job.n, 8), dtype=torch.int32, device=ev.device)])
+                coeffs, com, coset = zk.commit_job(self.srs, ev, log_blowup=2)
+                done = torch.cuda.Event(enable_timing=self.timing)
+                done.record(s)
+        except Exception:
+            self.free.append(slot)
+            raise
         job.handle = (slot, done, com, coset, coeffs, ev)
 
     def poll(self, job):
@@ -129,10 +143,11 @@ class GpuExecutor:
         return True
 
 
-def serve(jobs, executor, budget_bytes, slots, clock=time.perf_counter, sleep=None):
+def serve(jobs, executor, budget_bytes, slots, clock=time.perf_counter, sleep=None, max_queue=None):
     """Feed `jobs` (sorted by arrival, seconds from start) through admission
-    and the executor.  Returns (finished jobs, rejected jobs, wall seconds)."""
-    adm = Admission(budget_bytes, slots, executor.footprint)
+    and the executor.  Returns (finished jobs, rejected jobs, wall seconds);
+    finished jobs whose `error` is set failed on the device."""
+    adm = Admission(budget_bytes, slots, executor.footprint, max_queue)
     pending = collections.deque(sorted(jobs, key=lambda j: j.arrival))
     finished = []
     t0 = clock()
@@ -141,22 +156,35 @@ def serve(jobs, executor, budget_bytes, slots, clock=time.perf_counter, sleep=No
         while pending and pending[0].arrival <= now:
             adm.submit(pending.popleft())
         for job in list(adm.running):
-            if job.start is not None and executor.poll(job):
+            if job.start is None:
+                continue
+            try:
+                done = executor.poll(job)
+            except Exception as e:  # completion reported a device error
+                job.error, done = repr(e), True
+            if done:
                 job.finish = clock() - t0
                 adm.release(job)
                 finished.append(job)
         for job in adm.admissible():
             job.start = clock() - t0
-            executor.start(job)
+            try:
+                executor.start(job)
+            except Exception as e:  # the call failed before running: no slot held
+                job.error = repr(e)
+                job.finish = clock() - t0
+                adm.release(job)
+                finished.append(job)
         if sleep is not None:
             sleep()
     return finished, adm.rejected, clock() - t0
 
 
 def summarize(finished, wall):
-    lat = np.array([j.finish - j.arrival for j in finished]) * 1e3
+    ok = [j for j in finished if j.error is None]
+    lat = np.array([j.finish - j.arrival for j in ok]) * 1e3
     if lat.size == 0:
-        return {"jobs": 0}
+        return {"jobs": 0, "failed": len(finished)}
     return {"jobs": int(lat.size), "jobs_per_s": lat.size / wall, "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
-            "max_ms": float(lat.max())}
+            "max_ms": float(lat.max()), "failed": len(finished) - len(ok)}

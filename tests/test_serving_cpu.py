@@ -106,3 +106,50 @@ def test_admission_queue_unit():
     adm.release(a)
     assert adm.admissible() == [b, c]
     assert adm.used == 60 and np.isclose(adm.used, 60)
+
+
+def test_queue_full_back_pressure():
+    clock = FakeClock()
+    ex = MockExecutor(clock, 10 ** 12, 1, per_point=1e-6)
+    jobs = [Job(i, 1 << 12, 0.0) for i in range(6)]
+    fin, rej, _ = serve(jobs, ex, 10 ** 12, 1, clock=clock, sleep=clock.tick, max_queue=2)
+    # all six arrive together: two wait, the rest are refused
+    assert sorted(j.jid for j in fin) == [0, 1]
+    assert sorted(j.jid for j in rej) == [2, 3, 4, 5]
+    assert all(j.error == "rejected: queue full" for j in rej)
+    fin2, rej2, _ = serve([Job(i, 1 << 12, i * 0.01) for i in range(6)], MockExecutor(clock, 10 ** 12, 1),
+                          10 ** 12, 1, clock=clock, sleep=clock.tick, max_queue=2)
+    assert len(fin2) == 6 and not rej2
+
+
+class FailingExecutor(MockExecutor):
+    """Raises for chosen jobs at start (before any work) or at completion."""
+
+    def __init__(self, clock, budget, slots, fail_start=(), fail_poll=()):
+        super().__init__(clock, budget, slots)
+        self.fail_start, self.fail_poll = set(fail_start), set(fail_poll)
+
+    def start(self, job):
+        if job.jid in self.fail_start:
+            raise RuntimeError("zk error -3: injected device failure")
+        super().start(job)
+
+    def poll(self, job):
+        done = super().poll(job)
+        if done and job.jid in self.fail_poll:
+            raise RuntimeError("zk error -3: injected completion failure")
+        return done
+
+
+def test_failed_jobs_are_isolated():
+    clock = FakeClock()
+    jobs = _jobs(40, seed=9)
+    ex = FailingExecutor(clock, 10 ** 9, 3, fail_start=(3, 17), fail_poll=(8,))
+    fin, rej, wall = serve(jobs, ex, 10 ** 9, 3, clock=clock, sleep=clock.tick)
+    assert not rej and len(fin) == 40
+    failed = {j.jid for j in fin if j.error is not None}
+    assert failed == {3, 8, 17}
+    assert all(j.finish >= j.start >= j.arrival for j in fin)
+    s = summarize(fin, wall)
+    assert s["jobs"] == 37 and s["failed"] == 3
+    assert not ex.live  # every slot and byte released
