@@ -136,6 +136,21 @@ zk_status zk_srs_destroy(zk_srs* srs);
 /* Number of points of a prepared SRS (0 for NULL). */
 uint64_t zk_srs_size(const zk_srs* srs);
 
+/* Table policy of a prepared SRS (which pre-shifted table, hence which
+ * window size, serves an n-point commitment): n < small_max uses the 8-bit
+ * windows of the first 2^15 points, n >= large_min the 20-bit windows (only
+ * when that table was built, i.e. zk_srs_size >= 2^21), anything else the
+ * 16-bit windows.  Defaults: 0 and 2^21, the autotuner's measurement on
+ * MI355X (paper_2507_07031_amd/autotune.py times each table per size on the
+ * running device and sets measured thresholds).  The result of a
+ * commitment does not depend on the policy.  small_max <= 2^15, else
+ * ZK_EINVAL.  Set it while no call on this SRS is being enqueued. */
+zk_status zk_srs_set_table_policy(zk_srs* srs, uint64_t small_max, uint64_t large_min);
+
+/* Window bits (8, 16 or 20) the policy picks for an n-point commitment, or 0
+ * for NULL / n > zk_srs_size. */
+uint32_t zk_srs_window_bits(const zk_srs* srs, uint64_t n);
+
 /* KZG commitment to coefficients: *out = sum_{i<n} scalars[i] [tau^i]_1 over
  * the first n points of the prepared SRS (n <= zk_srs_size(srs)). */
 zk_status zk_msm_srs(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream);

@@ -409,9 +409,14 @@ zk_status sync_events(SyncEvents& ev) {
 
 constexpr uint32_t SRS_C = 16;                 // window bits of the main table
 constexpr uint32_t SRS_C_SMALL = 8;            // window bits of the small-MSM table
-constexpr uint32_t SRS_SMALL_MAX = 1u << 15;   // MSMs below this size use the small table
+constexpr uint32_t SRS_SMALL_MAX = 1u << 15;   // points covered by the small table
 constexpr uint32_t SRS_C_LARGE = 20;           // window bits of the large-MSM table
 constexpr uint64_t SRS_LARGE_MIN = 1ull << 21; // MSMs from this size use the large table
+// Default table policy, as the autotuner measured it on MI355X: the 16-bit
+// table beats the 8-bit one at every size from 2^10 (its reduction tail is no
+// longer the bottleneck), so the 8-bit table serves no size unless a policy
+// asks for it; the 20-bit table wins from 2^21.
+constexpr uint64_t SRS_SMALL_POLICY = 0;
 
 }  // namespace
 
@@ -428,6 +433,8 @@ struct zk_srs {
   uint32_t c_large;
   uint32_t W_large;
   uint32_t* tab_large;  // W_large * n points for large MSMs (n >= SRS_LARGE_MIN only)
+  uint64_t small_max;   // table policy: n < small_max -> small table,
+  uint64_t large_min;   //               n >= large_min -> large table (if built), else main
 };
 
 struct zk_srs_g2 {
@@ -620,6 +627,8 @@ zk_status zk_srs_create(const zk_g1* points, uint64_t n, zk_srs** srs, void* str
   h->c_large = SRS_C_LARGE;
   h->W_large = (254 + SRS_C_LARGE - 1) / SRS_C_LARGE;
   h->tab_large = nullptr;
+  h->small_max = SRS_SMALL_POLICY;
+  h->large_min = SRS_LARGE_MIN;
   if (n) {
     const uint32_t* pts = reinterpret_cast<const uint32_t*>(points);
     hipError_t e = hipMalloc(&h->tab, (size_t)h->W * n * 64);
@@ -660,16 +669,18 @@ zk_status zk_srs_destroy(zk_srs* srs) {
 
 uint64_t zk_srs_size(const zk_srs* srs) { return srs ? srs->n : 0; }
 
-// One commitment picks a pre-shifted table by size: 8-bit windows below
-// SRS_SMALL_MAX points (short reduction tail), 20-bit windows from
-// SRS_LARGE_MIN (13 windows instead of 16: fewer additions, for 16x the
-// buckets), 16-bit windows between.  Every window of the MSM shares one
-// bucket set.
+// One commitment picks a pre-shifted table by size, by the SRS's policy:
+// 8-bit windows below small_max points (short reduction tail, twice the
+// windows), 20-bit windows from large_min (13 windows instead of 16: fewer
+// additions, for 16x the buckets), 16-bit windows between.  Every window of
+// the MSM shares one bucket set.
 enum class SrsTable { small, main, large };
 
 static SrsTable srs_table_for(const zk_srs* srs, uint64_t n) {
-  if (n < SRS_SMALL_MAX) return SrsTable::small;
-  if (n >= SRS_LARGE_MIN && (!srs || srs->tab_large || srs->n >= SRS_LARGE_MIN)) return SrsTable::large;
+  const uint64_t small_max = srs ? srs->small_max : SRS_SMALL_POLICY;
+  const uint64_t large_min = srs ? srs->large_min : SRS_LARGE_MIN;
+  if (n < small_max) return SrsTable::small;
+  if (n >= large_min && (!srs || srs->tab_large)) return SrsTable::large;
   return SrsTable::main;
 }
 
@@ -693,6 +704,23 @@ static zk_status msm_srs_one(const zk_srs* srs, const uint32_t* scalars, uint64_
   const SrsTable t = srs_table_for(srs, n);
   const uint32_t* tab = t == SrsTable::small ? srs->tab_small : t == SrsTable::large ? srs->tab_large : srs->tab;
   return run_msm(plan, off, tab, scalars, out16, s, after_accumulate, before_accumulate);
+}
+
+zk_status zk_srs_set_table_policy(zk_srs* srs, uint64_t small_max, uint64_t large_min) {
+  if (!srs) return fail(ZK_EINVAL, "zk_srs_set_table_policy: NULL srs");
+  if (small_max > SRS_SMALL_MAX) return fail(ZK_EINVAL, "zk_srs_set_table_policy: small_max above 2^15");
+  srs->small_max = small_max;
+  srs->large_min = large_min;
+  return ZK_OK;
+}
+
+uint32_t zk_srs_window_bits(const zk_srs* srs, uint64_t n) {
+  if (!srs || n > srs->n) return 0;
+  switch (srs_table_for(srs, n)) {
+    case SrsTable::small: return SRS_C_SMALL;
+    case SrsTable::large: return SRS_C_LARGE;
+    default: return SRS_C;
+  }
 }
 
 uint64_t zk_msm_srs_workspace_bytes(const zk_srs* srs, uint64_t n) {

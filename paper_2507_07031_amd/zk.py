@@ -26,7 +26,8 @@ EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_s
            "zk_msm_srs_ex", "zk_profile_only", "zk_commit_job", "zk_set_validate", "zk_kzg_open",
            "zk_kzg_open_batch", "zk_quotient_mul",
            "zk_srs_lagrange_setup", "zk_transcript_challenge", "zk_acc_fold",
-           "zk_srs_g2_setup", "zk_srs_g2_create", "zk_srs_g2_destroy", "zk_srs_g2_size", "zk_msm_g2_srs")
+           "zk_srs_g2_setup", "zk_srs_g2_create", "zk_srs_g2_destroy", "zk_srs_g2_size", "zk_msm_g2_srs",
+           "zk_srs_set_table_policy", "zk_srs_window_bits")
 
 
 class ZkError(RuntimeError):
@@ -65,6 +66,8 @@ def _load():
         "zk_srs_g2_destroy": ([P], I),
         "zk_srs_g2_size": ([P], U64),
         "zk_msm_g2_srs": ([P, P, U64, P, P], I),
+        "zk_srs_set_table_policy": ([P, U64, U64], I),
+        "zk_srs_window_bits": ([P, U64], U32),
         "zk_acc_fold": ([U32, P, P, U32, P, P, P, U64, P, P, U64, P, P, P, P, P, P, P, P, P], I),
         "zk_kzg_open_batch": ([P, P, U32, U64, P, P, P, P, P, P], I),
         "zk_fold": ([P, P, U32, U32, P, P], I),
@@ -246,6 +249,15 @@ class SRS:
             self.close()
         except Exception:
             pass
+
+
+def srs_set_table_policy(srs, small_max, large_min):
+    """n < small_max: 8-bit-window table; n >= large_min: 20-bit (if built)."""
+    _check(lib.zk_srs_set_table_policy(srs.handle, int(small_max), int(large_min)))
+
+
+def srs_window_bits(srs, n):
+    return int(lib.zk_srs_window_bits(srs.handle, int(n)))
 
 
 def msm_srs(srs, scalars, n=None, out=None):

@@ -12,7 +12,7 @@ HEADER = os.path.join(ROOT, "include", "zk.h")
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:zk_status|const char\*|uint64_t)\s+(zk_\w+)\(", text, re.M)))
+    return sorted(set(re.findall(r"^(?:zk_status|const char\*|uint64_t|uint32_t)\s+(zk_\w+)\(", text, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -66,3 +66,8 @@ def test_argument_errors_return_before_device_work(zk):
     assert "canonical" in L.zk_last_error().decode()
     assert L.zk_srs_lagrange_setup(ctypes.cast(bad, ctypes.c_void_p), 4, dummy, null) == zk.ZK_EINVAL
     assert L.zk_srs_lagrange_setup(null, 4, dummy, null) == zk.ZK_EINVAL
+    assert L.zk_transcript_challenge(null, 4, dummy, null) == zk.ZK_EINVAL
+    assert L.zk_acc_fold(1, dummy, dummy, 0, dummy, dummy, null, 0, null, null, 0, null, null, null, dummy, dummy,
+                         dummy, null, null, null) == zk.ZK_EINVAL
+    assert L.zk_acc_fold(1, dummy, dummy, 2, dummy, dummy, null, 0, null, null, 0, null, null, null, dummy, dummy,
+                         dummy, null, null, null) == zk.ZK_EINVAL

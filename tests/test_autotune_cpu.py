@@ -1,0 +1,38 @@
+"""The autotuner's threshold derivation and cache on the CPU (timings given)."""
+import json
+
+from paper_2507_07031_amd import autotune
+
+
+class FakeZk:
+    def __init__(self):
+        self.policy = None
+
+    def srs_set_table_policy(self, srs, small_max, large_min):
+        self.policy = (small_max, large_min)
+
+
+def test_save_load_roundtrip(tmp_path):
+    p = tmp_path / "tune.json"
+    autotune.save({"small_max": 100, "large_min": 5}, str(p), "devA")
+    autotune.save({"small_max": 7, "large_min": 9}, str(p), "devB")
+    assert autotune.load(str(p), "devA") == {"small_max": 100, "large_min": 5}
+    assert json.load(open(p))["devB"]["large_min"] == 9
+
+
+def test_apply_sets_policy():
+    z = FakeZk()
+    autotune.apply(z, object(), {"small_max": 1024, "large_min": 1 << 20})
+    assert z.policy == (1024, 1 << 20)
+
+
+def test_derive_policy_follows_timings():
+    t = {1024: {8: 0.1, 16: 0.2}, 2048: {8: 0.15, 16: 0.2}, 4096: {8: 0.3, 16: 0.25},
+         1 << 16: {16: 1.0, 20: 1.2}, 1 << 20: {16: 2.0, 20: 1.9}, 1 << 21: {16: 4.0, 20: 3.1}}
+    assert autotune.derive_policy(t) == {"small_max": 2049, "large_min": 1 << 20}
+    # 20-bit never fastest at the top: no large threshold; 8-bit never fastest: 0
+    t2 = {1024: {8: 0.3, 16: 0.2}, 1 << 21: {16: 3.0, 20: 3.1}}
+    assert autotune.derive_policy(t2) == {"small_max": 0, "large_min": autotune.NEVER}
+    # the 8-bit threshold never passes the table's 2^15 points
+    t3 = {1 << 15: {8: 0.1, 16: 0.2}}
+    assert autotune.derive_policy(t3)["small_max"] == 1 << 15
