@@ -125,9 +125,10 @@ zk_status zk_srs_lagrange_setup(const zk_fr* tau_host, uint32_t log_n, zk_g1* ou
 
 /* Prepare an SRS (any n affine points, e.g. from zk_srs_setup or a
  * ceremony) for commitments.  Allocates 16 * 64 * n bytes (the points times
- * 2^(16 w), w < 16) plus 32 * 64 * min(n, 2^15) bytes (times 2^(8 w), for
- * small commitments) of device memory owned by the handle; the work is
- * enqueued on `stream`.  The handle is bound to the current device. */
+ * 2^(16 w), w < 16), 22 * 64 * min(n, 2^16) bytes (times 2^(12 w), for
+ * small commitments) and, for n >= 2^21, 13 * 64 * n bytes (times 2^(20 w))
+ * of device memory owned by the handle; the work is enqueued on `stream`.
+ * The handle is bound to the current device. */
 zk_status zk_srs_create(const zk_g1* points, uint64_t n, zk_srs** srs, void* stream);
 
 /* Release a prepared SRS (synchronises the device first). */
@@ -137,17 +138,17 @@ zk_status zk_srs_destroy(zk_srs* srs);
 uint64_t zk_srs_size(const zk_srs* srs);
 
 /* Table policy of a prepared SRS (which pre-shifted table, hence which
- * window size, serves an n-point commitment): n < small_max uses the 8-bit
- * windows of the first 2^15 points, n >= large_min the 20-bit windows (only
+ * window size, serves an n-point commitment): n < small_max uses the 12-bit
+ * windows of the first 2^16 points, n >= large_min the 20-bit windows (only
  * when that table was built, i.e. zk_srs_size >= 2^21), anything else the
  * 16-bit windows.  Defaults: 0 and 2^21, the autotuner's measurement on
  * MI355X (paper_2507_07031_amd/autotune.py times each table per size on the
  * running device and sets measured thresholds).  The result of a
- * commitment does not depend on the policy.  small_max <= 2^15, else
+ * commitment does not depend on the policy.  small_max <= 2^16, else
  * ZK_EINVAL.  Set it while no call on this SRS is being enqueued. */
 zk_status zk_srs_set_table_policy(zk_srs* srs, uint64_t small_max, uint64_t large_min);
 
-/* Window bits (8, 16 or 20) the policy picks for an n-point commitment, or 0
+/* Window bits (12, 16 or 20) the policy picks for an n-point commitment, or 0
  * for NULL / n > zk_srs_size. */
 uint32_t zk_srs_window_bits(const zk_srs* srs, uint64_t n);
 

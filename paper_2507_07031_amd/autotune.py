@@ -1,10 +1,10 @@
 """Autotuner for the commitment MSM's table policy.
 
-A prepared SRS holds three pre-shifted tables (8-, 16- and 20-bit windows);
+A prepared SRS holds three pre-shifted tables (12-, 16- and 20-bit windows);
 which one serves an n-point commitment is a per-SRS threshold policy
 (`zk_srs_set_table_policy`).  The best thresholds depend on the device: the
-8-bit table has a short reduction tail but twice the windows, the 20-bit one
-fewer additions but 16 times the buckets.  `tune` times every feasible table
+12-bit table has a short reduction (2048 buckets) but more windows, the
+20-bit one fewer additions but 16 times the buckets.  `tune` times every feasible table
 on the running GPU for power-of-two sizes, picks the thresholds that follow
 the measurements, and `apply` installs them; `save` / `load` keep them as a
 JSON cache keyed by the device name.  The policy never changes a result, only
@@ -15,7 +15,8 @@ its time (the GPU tests check this).
 import argparse
 import json
 
-SMALL_CAP = 1 << 15      # the 8-bit table covers the first 2^15 points
+SMALL_CAP = 1 << 16      # the small table covers the first 2^16 points
+SMALL, MAIN, LARGE = 12, 16, 20   # window bits of the three tables
 NEVER = 1 << 62
 
 
@@ -41,7 +42,7 @@ def tune(zk, srs, scalars, min_log=10, max_log=22, reps=5):
     Returns {"small_max", "large_min", "timings": {n: {window_bits: ms}}}."""
     import torch
     out = torch.empty((1, 16), dtype=torch.int32, device=scalars.device)
-    forced = {8: (NEVER // 2, NEVER), 16: (0, NEVER), 20: (0, 0)}
+    forced = {SMALL: (SMALL_CAP, NEVER), MAIN: (0, NEVER), LARGE: (0, 0)}
     timings = {}
     for lg in range(min_log, max_log + 1):
         n = 1 << lg
@@ -49,9 +50,9 @@ def tune(zk, srs, scalars, min_log=10, max_log=22, reps=5):
             break
         row = {}
         for bits, (small_max, large_min) in forced.items():
-            if bits == 8 and n > SMALL_CAP:
+            if bits == SMALL and n >= SMALL_CAP:
                 continue
-            zk.srs_set_table_policy(srs, min(small_max, SMALL_CAP) if bits == 8 else small_max, large_min)
+            zk.srs_set_table_policy(srs, small_max, large_min)
             if zk.srs_window_bits(srs, n) != bits:
                 continue  # table not built for this SRS
             row[bits] = _time_ms(zk, srs, scalars, n, out, reps)
@@ -63,20 +64,20 @@ def tune(zk, srs, scalars, min_log=10, max_log=22, reps=5):
 
 
 def derive_policy(timings):
-    """Thresholds from {n: {window_bits: ms}}: the 8-bit table up to the first
+    """Thresholds from {n: {window_bits: ms}}: the small table up to the first
     size where it stops being fastest; the 20-bit table from the first size
     after which it stays fastest."""
     small_max = 0
     for n in sorted(timings):
         row = timings[n]
-        if 8 in row and row[8] <= min(row.values()):
+        if SMALL in row and row[SMALL] <= min(row.values()):
             small_max = n + 1
         else:
             break
     large_min = NEVER
     for n in sorted(timings, reverse=True):
         row = timings[n]
-        if 20 in row and row[20] <= min(row.values()):
+        if LARGE in row and row[LARGE] <= min(row.values()):
             large_min = n
         else:
             break

@@ -408,8 +408,8 @@ zk_status sync_events(SyncEvents& ev) {
 }
 
 constexpr uint32_t SRS_C = 16;                 // window bits of the main table
-constexpr uint32_t SRS_C_SMALL = 8;            // window bits of the small-MSM table
-constexpr uint32_t SRS_SMALL_MAX = 1u << 15;   // points covered by the small table
+constexpr uint32_t SRS_C_SMALL = 12;           // window bits of the small-MSM table
+constexpr uint32_t SRS_SMALL_MAX = 1u << 16;   // points covered by the small table
 constexpr uint32_t SRS_C_LARGE = 20;           // window bits of the large-MSM table
 constexpr uint64_t SRS_LARGE_MIN = 1ull << 21; // MSMs from this size use the large table
 // Default table policy, as the autotuner measured it on MI355X: the 16-bit
@@ -670,9 +670,9 @@ zk_status zk_srs_destroy(zk_srs* srs) {
 uint64_t zk_srs_size(const zk_srs* srs) { return srs ? srs->n : 0; }
 
 // One commitment picks a pre-shifted table by size, by the SRS's policy:
-// 8-bit windows below small_max points (short reduction tail, twice the
-// windows), 20-bit windows from large_min (13 windows instead of 16: fewer
-// additions, for 16x the buckets), 16-bit windows between.  Every window of
+// 12-bit windows below small_max points (2048 buckets: a short reduction,
+// for 22 windows instead of 16), 20-bit windows from large_min (13 windows:
+// fewer additions, for 16x the buckets), 16-bit windows between.  Every window of
 // the MSM shares one bucket set.
 enum class SrsTable { small, main, large };
 
@@ -708,7 +708,7 @@ static zk_status msm_srs_one(const zk_srs* srs, const uint32_t* scalars, uint64_
 
 zk_status zk_srs_set_table_policy(zk_srs* srs, uint64_t small_max, uint64_t large_min) {
   if (!srs) return fail(ZK_EINVAL, "zk_srs_set_table_policy: NULL srs");
-  if (small_max > SRS_SMALL_MAX) return fail(ZK_EINVAL, "zk_srs_set_table_policy: small_max above 2^15");
+  if (small_max > SRS_SMALL_MAX) return fail(ZK_EINVAL, "zk_srs_set_table_policy: small_max above 2^16");
   srs->small_max = small_max;
   srs->large_min = large_min;
   return ZK_OK;

@@ -27,12 +27,12 @@ def test_apply_sets_policy():
 
 
 def test_derive_policy_follows_timings():
-    t = {1024: {8: 0.1, 16: 0.2}, 2048: {8: 0.15, 16: 0.2}, 4096: {8: 0.3, 16: 0.25},
+    t = {1024: {12: 0.1, 16: 0.2}, 2048: {12: 0.15, 16: 0.2}, 4096: {12: 0.3, 16: 0.25},
          1 << 16: {16: 1.0, 20: 1.2}, 1 << 20: {16: 2.0, 20: 1.9}, 1 << 21: {16: 4.0, 20: 3.1}}
     assert autotune.derive_policy(t) == {"small_max": 2049, "large_min": 1 << 20}
-    # 20-bit never fastest at the top: no large threshold; 8-bit never fastest: 0
-    t2 = {1024: {8: 0.3, 16: 0.2}, 1 << 21: {16: 3.0, 20: 3.1}}
+    # 20-bit never fastest at the top: no large threshold; 12-bit never fastest: 0
+    t2 = {1024: {12: 0.3, 16: 0.2}, 1 << 21: {16: 3.0, 20: 3.1}}
     assert autotune.derive_policy(t2) == {"small_max": 0, "large_min": autotune.NEVER}
-    # the 8-bit threshold never passes the table's 2^15 points
-    t3 = {1 << 15: {8: 0.1, 16: 0.2}}
-    assert autotune.derive_policy(t3)["small_max"] == 1 << 15
+    # the small-table threshold never passes the table's 2^16 points
+    t3 = {1 << 16: {12: 0.1, 16: 0.2}}
+    assert autotune.derive_policy(t3)["small_max"] == 1 << 16

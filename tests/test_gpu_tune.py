@@ -1,5 +1,5 @@
 """The commitment does not depend on the table policy (window size), and the
-autotuner produces a valid policy: commitments under forced 8-, 16- and
+autotuner produces a valid policy: commitments under forced 12-, 16- and
 20-bit-window tables equal each other and the closed form [f(tau)]_1."""
 import pytest
 
@@ -44,20 +44,20 @@ def _commit(zk, srs, s, n):
     return points_from_host(zk.to_host(out))[0]
 
 
-@pytest.mark.parametrize("n", [1, 777, 5000, (1 << 14) + 3, (1 << 21) - 1])
+@pytest.mark.parametrize("n", [1, 777, 5000, (1 << 14) + 3, (1 << 16) - 1, (1 << 21) - 1])
 def test_result_independent_of_window_size(zk, tau, srs, n):
     s_h = gen.uniform_fr(9300 + n, n)
     s = zk.to_device(s_h)
     want = omsm.srs_msm_closed_form(tau[1], fr_from_host(s_h))
     seen = []
-    for bits, (small_max, large_min) in {8: (1 << 15, NEVER), 16: (0, NEVER), 20: (0, 0)}.items():
+    for bits, (small_max, large_min) in {12: (1 << 16, NEVER), 16: (0, NEVER), 20: (0, 0)}.items():
         zk.srs_set_table_policy(srs, small_max, large_min)
         if zk.srs_window_bits(srs, n) != bits:
             continue
         log("msm n=%d window bits %d" % (n, bits))
         assert _commit(zk, srs, s, n) == want, bits
         seen.append(bits)
-    zk.srs_set_table_policy(srs, 1 << 15, 1 << 21)
+    zk.srs_set_table_policy(srs, 0, 1 << 21)
     assert len(seen) >= 2
 
 
@@ -67,10 +67,10 @@ def test_autotuner_policy(zk, tau, srs):
     s = zk.to_device(s_h)
     log("autotune 2^10..2^16")
     policy = autotune.tune(zk, srs, s, min_log=10, max_log=16, reps=2)
-    assert 0 <= policy["small_max"] <= 1 << 15
+    assert 0 <= policy["small_max"] <= 1 << 16
     assert set(policy["timings"]) == {str(1 << k) for k in range(10, 17)}
     for n in (1 << 12, (1 << 16) - 5):
         assert _commit(zk, srs, s, n) == omsm.srs_msm_closed_form(tau[1], fr_from_host(s_h[:n]))
     with pytest.raises(zk.ZkError):
-        zk.srs_set_table_policy(srs, (1 << 15) + 1, NEVER)
-    zk.srs_set_table_policy(srs, 1 << 15, 1 << 21)
+        zk.srs_set_table_policy(srs, (1 << 16) + 1, NEVER)
+    zk.srs_set_table_policy(srs, 0, 1 << 21)
