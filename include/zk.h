@@ -278,8 +278,8 @@ zk_status zk_acc_fold(uint32_t k, const zk_g1* C, const zk_g1* C2, uint32_t d, c
  * (x = 0x1800deef...c2 + 0x198e9393...ed u as in Ethereum's precompiles).
  *
  * zk_srs_g2_setup: out[i] = [tau^i]_2 = tau^i H, i < n, for a known trapdoor
- * (test and benchmark use).  zk_srs_g2_create prepares n points (any G2
- * points: they are not checked, also not by zk_set_validate) with
+ * (test and benchmark use).  zk_srs_g2_create prepares n G2 points (with
+ * zk_set_validate on: checked canonical, on the twist and of order r) with
  * 32 * 128 * n bytes of pre-shifted table owned by the handle;
  * zk_msm_g2_srs: *out = sum_{i<n} scalars[i] P_i over the first n prepared
  * points (n <= zk_srs_g2_size), n = 0 gives infinity.  n < 2^26. */
@@ -300,7 +300,8 @@ zk_status zk_fold(const zk_g1* inst, const zk_fr* gammas, uint32_t m, uint32_t k
 /* Input validation (off by default).  When on, every call checks on the
  * device, before any other work, that its Fr inputs are canonical (< r) and
  * its G1 inputs are (0, 0) or canonical affine points on y^2 = x^3 + 3, and
- * returns ZK_EINVAL (message in zk_last_error) if one is not.  The check
+ * returns ZK_EINVAL (message in zk_last_error) if one is not; G2 inputs
+ * must be all zeros or canonical points of order r on the twist.  The check
  * waits for the call's stream, so validated calls are synchronous. */
 zk_status zk_set_validate(int on);
 

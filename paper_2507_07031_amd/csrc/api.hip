@@ -49,7 +49,7 @@ std::atomic<bool> g_validate{false};
 struct InputCheck {
   const void* p;
   uint64_t n;
-  bool g1;
+  int kind;  // 0: Fr, 1: G1, 2: G2
 };
 
 
@@ -239,7 +239,10 @@ zk_status check_inputs(DeviceCtx* c, hipStream_t s, std::initializer_list<InputC
   ZK_HIP(hipMemsetAsync(c->vflag, 0, 4, s), "hipMemsetAsync");
   for (const InputCheck& k : checks) {
     const uint32_t* w = static_cast<const uint32_t*>(k.p);
-    ZK_HIP(k.g1 ? validate_g1(w, k.n, c->vflag, s) : validate_fr(w, k.n, c->vflag, s), "input check");
+    ZK_HIP(k.kind == 2   ? validate_g2(w, k.n, c->vflag, s)
+           : k.kind == 1 ? validate_g1(w, k.n, c->vflag, s)
+                         : validate_fr(w, k.n, c->vflag, s),
+           "input check");
   }
   uint32_t found = 0;
   ZK_HIP(hipMemcpyAsync(&found, c->vflag, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
@@ -247,6 +250,8 @@ zk_status check_inputs(DeviceCtx* c, hipStream_t s, std::initializer_list<InputC
   if (found & VALIDATE_FR) return fail(ZK_EINVAL, std::string(who) + ": an Fr input is not canonical (>= r)");
   if (found & VALIDATE_G1)
     return fail(ZK_EINVAL, std::string(who) + ": a G1 input is not (0, 0) or a canonical point on the curve");
+  if (found & VALIDATE_G2)
+    return fail(ZK_EINVAL, std::string(who) + ": a G2 input is not zero or a canonical point of order r on the twist");
   return ZK_OK;
 }
 
@@ -1027,6 +1032,7 @@ zk_status zk_srs_g2_create(const zk_g2* points, uint64_t n, zk_srs_g2** srs, voi
   DeviceCtx* c;
   zk_status st = ctx_get(&c);
   if (st) return st;
+  if ((st = check_inputs(c, (hipStream_t)stream, {{points, n, 2}}, "zk_srs_g2_create"))) return st;
   zk_srs_g2* h = new zk_srs_g2();
   ZK_HIP(hipGetDevice(&h->device), "hipGetDevice");
   h->n = n;

@@ -32,6 +32,11 @@ __constant__ static const uint32_t G2_GEN[32] = {
     0x66fa7daau, 0x4ce6cc01u, 0x0c43d37bu, 0xe3d1e769u, 0x8dcb408fu, 0x4aab7180u, 0xdb8c6debu, 0x12c85ea5u,
     0xd122975bu, 0x55acdadcu, 0x70b38ef3u, 0xbc4b3133u, 0x690c3395u, 0xec9e99adu, 0x585ff075u, 0x090689d0u};
 
+// The twist's constant 3 / (9 + u) (plain canonical words: c0, c1).
+static constexpr uint32_t G2_TWIST_B[16] = {
+    0x24a138e5u, 0x3267e6dcu, 0x59dbefa3u, 0xb5b4c5e5u, 0x1be06ac3u, 0x81be1899u, 0xceb8aaaeu, 0x2b149d40u,
+    0x85c315d2u, 0xe4a2bd06u, 0xe52d1852u, 0xa74fa084u, 0xeed8fdf4u, 0xcd2cafadu, 0x3af0fed4u, 0x009713b0u};
+
 // normalised value < 4q -> < 2q
 ZK_HD f29 red_lt4(const f29& a) { return cond_sub(a, Fq::C2); }
 
@@ -187,6 +192,41 @@ ZK_HD bool g2_from_words(const uint32_t w[32], g2aff& p) {
   p.y.c0 = reduce_full<Fq>(to_mont<Fq>(unpack(w + 16)));
   p.y.c1 = reduce_full<Fq>(to_mont<Fq>(unpack(w + 24)));
   return o != 0;
+}
+
+ZK_HD bool words_below(const uint32_t* w, const uint32_t (&m)[8]) {
+  unsigned br = 0;
+  for (int i = 0; i < 8; i++) (void)__builtin_subc(w[i], m[i], br, &br);
+  return br != 0;
+}
+
+ZK_HD bool fp2_equal(const fp2& a, const fp2& b) {
+  const f29 a0 = reduce_full<Fq>(a.c0), a1 = reduce_full<Fq>(a.c1);
+  const f29 b0 = reduce_full<Fq>(b.c0), b1 = reduce_full<Fq>(b.c1);
+  uint32_t d = 0;
+  for (int k = 0; k < 9; k++) d |= (a0.l[k] ^ b0.l[k]) | (a1.l[k] ^ b1.l[k]);
+  return d == 0;
+}
+
+// Is w (x0 x1 y0 y1, plain words) all zeros or a canonical point of order r
+// on the twist?  G2 has cofactor > 1, so on top of the curve equation the
+// point must satisfy r P = O (double-and-add over the bits of r).
+ZK_HD bool g2_words_valid(const uint32_t w[32]) {
+  uint32_t o = 0;
+  for (int k = 0; k < 32; k++) o |= w[k];
+  if (o == 0) return true;
+  for (int c = 0; c < 4; c++)
+    if (!words_below(w + 8 * c, Fq::M32)) return false;
+  g2aff p;
+  g2_from_words(w, p);
+  const fp2 b{reduce_full<Fq>(to_mont<Fq>(unpack(G2_TWIST_B))), reduce_full<Fq>(to_mont<Fq>(unpack(G2_TWIST_B + 8)))};
+  if (!fp2_equal(fp2_sqr(p.y), fp2_add(fp2_mul(fp2_sqr(p.x), p.x), b))) return false;
+  g2xyzz acc = g2_inf();
+  for (int bit = 253; bit >= 0; --bit) {
+    acc = g2_dbl(acc);
+    if ((FrP::M32[bit >> 5] >> (bit & 31)) & 1u) acc = g2_madd(acc, p);
+  }
+  return g2_is_inf(acc);
 }
 
 }  // namespace zk

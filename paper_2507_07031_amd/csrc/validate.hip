@@ -1,7 +1,8 @@
 // Input checks behind zk_set_validate: Fr inputs are canonical (< r), G1
-// inputs are canonical affine points on y^2 = x^3 + 3 or (0, 0).  Each
-// launch ORs its findings into a device flag word.
-#include "curve.h"
+// inputs are canonical affine points on y^2 = x^3 + 3 or (0, 0), G2 inputs
+// canonical points of order r on the twist y^2 = x^3 + 3/(9 + u) or all
+// zeros.  Each launch ORs its findings into a device flag word.
+#include "g2.h"
 #include "validate.h"
 
 namespace zk {
@@ -52,6 +53,14 @@ __global__ void check_g1_kernel(const uint32_t* __restrict__ pts, uint64_t n, ui
   if (d) atomicOr(flag, VALIDATE_G1);
 }
 
+__global__ void check_g2_kernel(const uint32_t* __restrict__ pts, uint64_t n, uint32_t* flag) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t w[32];
+  for (int k = 0; k < 32; k++) w[k] = pts[i * 32 + k];
+  if (!g2_words_valid(w)) atomicOr(flag, VALIDATE_G2);
+}
+
 inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + 255) / 256); }
 
 }  // namespace
@@ -65,6 +74,12 @@ hipError_t validate_fr(const uint32_t* v, uint64_t n, uint32_t* flag, hipStream_
 hipError_t validate_g1(const uint32_t* pts, uint64_t n, uint32_t* flag, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(check_g1_kernel, dim3(blocks_for(n)), dim3(256), 0, s, pts, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t validate_g2(const uint32_t* pts, uint64_t n, uint32_t* flag, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(check_g2_kernel, dim3((uint32_t)((n + 63) / 64)), dim3(64), 0, s, pts, n, flag);
   return hipGetLastError();
 }
 

@@ -223,4 +223,6 @@ void host_g2_neg(const uint32_t* pt, uint32_t* out) {
   g2_to_words(g2_from_aff(g2_aff_neg(p)), out);
 }
 
+int host_g2_valid(const uint32_t* pt) { return g2_words_valid(pt) ? 1 : 0; }
+
 }  // extern "C"

@@ -110,3 +110,30 @@ def test_g2_msm_rejects_oversize(zk, srs):
     with pytest.raises(zk.ZkError) as ei:
         zk.msm_g2_srs(h, zk.to_device(s))
     assert ei.value.code == zk.ZK_EINVAL
+
+
+def test_g2_validation_mode(zk):
+    from tests.test_host_arith import _fq2_sqrt
+    good = [og2.gen_mul(k) for k in (3, 5, 7)] + [None]
+    q = good[0]
+    off_curve = (q[0], og2.f2_add(q[1], (1, 0)))
+    outside = None
+    for t in range(1, 60):
+        x = (t, 1)
+        y = _fq2_sqrt(og2.f2_add(og2.f2_mul(og2.f2_mul(x, x), x), og2.B2))
+        if y is not None and og2.mul(R, (x, y)) is not None:
+            outside = (x, y)
+            break
+    assert outside is not None and og2.on_curve(outside)
+    zk.set_validate(True)
+    try:
+        log("g2 validation: valid points")
+        h = zk.SRSG2(zk.to_device(_g2_to_host(good)))
+        h.close()
+        for bad in (off_curve, outside):
+            log("g2 validation: rejected point")
+            with pytest.raises(zk.ZkError) as ei:
+                zk.SRSG2(zk.to_device(_g2_to_host(good + [bad])))
+            assert ei.value.code == zk.ZK_EINVAL
+    finally:
+        zk.set_validate(False)

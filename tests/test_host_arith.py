@@ -327,3 +327,59 @@ def test_g2_point_sums_and_special_cases(lib):
     assert _read_g2(out) == g2.double(pts[4])
     lib.host_g2_neg(ptr, optr)
     assert _read_g2(out) == g2.neg(pts[4])
+
+
+def _fq2_sqrt(a):
+    """A square root in Fq2 (p = 3 mod 4; Adj and Rodriguez-Henriquez, Alg. 9), or None."""
+    def pw(x, e):
+        r = (1, 0)
+        while e:
+            if e & 1:
+                r = g2.f2_mul(r, x)
+            x = g2.f2_mul(x, x)
+            e >>= 1
+        return r
+    a1 = pw(a, (P - 3) // 4)
+    alpha = g2.f2_mul(a1, g2.f2_mul(a1, a))
+    a0 = g2.f2_mul(pw(alpha, P), alpha)
+    if a0 == (P - 1, 0):
+        return None
+    x0 = g2.f2_mul(a1, a)
+    if alpha == (P - 1, 0):
+        x = g2.f2_mul((0, 1), x0)
+    else:
+        x = g2.f2_mul(pw(g2.f2_add((1, 0), alpha), (P - 1) // 2), x0)
+    return x if g2.f2_mul(x, x) == a else None
+
+
+def test_g2_validity_check(lib):
+    rng = np.random.default_rng(23)
+    good = [g2.gen_mul(int(rng.integers(1, 2 ** 62))) for _ in range(3)] + [None]
+    for p in good:
+        arr, ptr = _g2_words([p])
+        assert lib.host_g2_valid(ptr) == 1
+    # off the curve: y perturbed
+    q = good[0]
+    arr, ptr = _g2_words([(q[0], g2.f2_add(q[1], (1, 0)))])
+    assert lib.host_g2_valid(ptr) == 0
+    # non-canonical coordinate
+    vals = list(g2.encode(q))
+    vals[1] += P
+    arr, ptr = _w(vals)
+    assert lib.host_g2_valid(ptr) == 0
+    # on the twist but outside the order-r subgroup (the twist has cofactor 2p - r)
+    found = 0
+    for t in range(1, 60):
+        x = (t, 1)
+        y = _fq2_sqrt(g2.f2_add(g2.f2_mul(g2.f2_mul(x, x), x), g2.B2))
+        if y is None:
+            continue
+        pt = (x, y)
+        assert g2.on_curve(pt)
+        arr, ptr = _g2_words([pt])
+        in_g2 = g2.mul(R, pt) is None
+        assert lib.host_g2_valid(ptr) == (1 if in_g2 else 0)
+        found += 0 if in_g2 else 1
+        if found >= 2:
+            break
+    assert found >= 2
