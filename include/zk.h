@@ -74,7 +74,7 @@ typedef int zk_status;
 #define ZK_EUNSUPPORTED (-5) /* valid request outside this build's limits    */
 
 /* Largest transform: log_n (+ log_blowup) <= ZK_MAX_LOG_NTT. */
-#define ZK_MAX_LOG_NTT 24
+#define ZK_MAX_LOG_NTT 28
 
 /* Prepared SRS: the points in the kernels' Montgomery form plus, for every
  * Pippenger window w, the points multiplied by 2^(c w).  Opaque. */

@@ -118,3 +118,43 @@ def barycentric_eval(evals, x: int) -> int:
         acc = (acc + int(v) * wj * fr_inv(x - wj)) % R
         wj = wj * w % R
     return (pow(x, n, R) - 1) * fr_inv(n) % R * acc % R
+
+
+def sum_runs_at(runs, points, x: int) -> int:
+    """f(x) = sum_i v_i x^i for a vector given as constant runs plus single
+    values: ``runs`` lists (start, length, value) over disjoint index ranges,
+    ``points`` maps an index to the value that replaces its run's value there
+    (indices outside every run hold 0 unless listed).  A run contributes
+    value * x^start * (x^length - 1) / (x - 1), or value * length at x = 1
+    (the geometric sum); each point then adds (v - run value) x^i.  This is the
+    definition of one transform output (x = shift * omega^j, or omega^(-i) for
+    the inverse) evaluated in O(#runs + #points) operations, which makes single
+    outputs of transforms of up to 2^28 points checkable."""
+    x %= R
+    acc = 0
+    for start, length, v in runs:
+        if x == 1:
+            g = length % R
+        else:
+            g = (pow(x, length, R) - 1) * fr_inv(x - 1) % R
+        acc = (acc + int(v) * pow(x, start, R) % R * g) % R
+    for i, v in points.items():
+        base = 0
+        for start, length, rv in runs:
+            if start <= i < start + length:
+                base = int(rv)
+                break
+        acc = (acc + (int(v) - base) * pow(x, i, R)) % R
+    return acc
+
+
+def ntt_runs_at(runs, points, log_domain: int, k: int, inverse: bool = False, shift: int = 1) -> int:
+    """Output k of the forward (shift = 1), coset (shift = g) or inverse
+    transform on the domain of N = 2^log_domain points of a run-structured
+    vector (``sum_runs_at``; a coset input has fewer than N coefficients and is
+    zero-padded): forward/coset sum_i v_i (g w^k)^i, inverse
+    N^(-1) sum_i v_i w^(-ik), w = omega_N."""
+    w = root_of_unity(1 << log_domain)
+    if inverse:
+        return sum_runs_at(runs, points, pow(fr_inv(w), k, R)) * fr_inv(1 << log_domain) % R
+    return sum_runs_at(runs, points, shift * pow(w, k, R) % R)

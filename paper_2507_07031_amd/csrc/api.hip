@@ -262,13 +262,16 @@ zk_status scratch_alloc(Scratch& sc, size_t bytes, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- NTT driver
-// A transform of 2^L points: one LDS pass up to the tile size, else two
-// four-step passes through a scratch buffer.  Prepared first, then launched
-// pass by pass, so a caller can interleave the passes with other work.
+// A transform of 2^L points: one LDS pass up to the tile size, two four-step
+// passes through a scratch buffer up to the square of the tile size, else
+// three (the second factor split once more; its intermediate lives in the
+// output buffer, which every transform of the last pass reads and rewrites
+// at the same positions).  Prepared first, then launched pass by pass, so a
+// caller can interleave the passes with other work.
 struct NttRun {
-  NttPass a{}, b{};
-  bool two = false;
-  Scratch tmp;  // intermediate of the two-pass form
+  NttPass a{}, b{}, c{};
+  int passes = 1;
+  Scratch tmp;  // intermediate of the two- and three-pass forms
 };
 
 zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t L, bool inverse, const f29* pre_lo,
@@ -293,13 +296,17 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
     p.pre_lo = pre_lo;
     p.pre_hi = pre_hi;
     p.post_scale = scale;
-    r.two = false;
+    r.passes = 1;
     return ZK_OK;
   }
-  const uint32_t mA = L / 2, mB = L - mA;  // pass A transforms have 2^mA points
+  const bool three = L > 2 * T;
+  // pass A transforms have 2^mA points; above 2^(2T) the three factors are
+  // near-equal (mA >= mB1 >= mB2), so pass A's workgroups hold several
+  // transforms and its strided reads move more than one element at a time
+  const uint32_t mA = three ? (L + 2) / 3 : L / 2, mB = L - mA;
   const uint32_t N1 = 1u << mB, N2 = 1u << mA;
   // tiles of 2048 points where both passes fit (two workgroups per CU), else 4096
-  const uint32_t tile = mB <= T - 1 ? (1u << (T - 1)) : (1u << T);
+  const uint32_t tile = !three && mB <= T - 1 ? (1u << (T - 1)) : (1u << T);
   zk_status st = scratch_alloc(r.tmp, (size_t)32 << L, s);
   if (st) return st;
   uint32_t* Y = static_cast<uint32_t*>(r.tmp.p);
@@ -331,7 +338,39 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   b.tw_lo = lo;
   b.tw_hi = hi;
   b.post_scale = scale;
-  r.two = true;
+  r.passes = 2;
+  if (!three) return ZK_OK;
+  // pass B of N1 = P1 * P2 points, i1 = j1 + P1 j2: B1 runs the P2-point
+  // transforms over j2 (batch k2 + N2 j1), B2 the P1-point ones over j1
+  // (batch k2 + N2 k1'); see the pass equations at the top of ntt.hip
+  const uint32_t p2 = (mB + 1) / 2, p1 = mB - p2;
+  const uint32_t P1 = 1u << p1, P2 = 1u << p2;
+  b.out = out;
+  b.m = p2;
+  b.nbatch = N2 * P1;
+  b.G = std::min((1u << T) / P2, b.nbatch);
+  b.s_in = N2 * P1;
+  b.s_out = N2;
+  b.b_out = 1;
+  b.b_hi_log = mA;
+  b.b_out_hi = N2 * P2;
+  b.post_tw_L = mB;
+  b.tw_shift = mA;
+  b.post_scale = nullptr;
+  NttPass& c3 = r.c;
+  c3.in = out;
+  c3.out = out;
+  c3.m = p1;
+  c3.nbatch = N2 * P2;
+  c3.G = std::min((1u << T) / P1, c3.nbatch);
+  c3.s_in = N2 * P2;
+  c3.s_out = N2 * P2;
+  c3.b_out = 1;
+  c3.valid_n = 1u << L;
+  c3.tw_lo = lo;
+  c3.tw_hi = hi;
+  c3.post_scale = scale;
+  r.passes = 3;
   return ZK_OK;
 }
 
@@ -341,7 +380,8 @@ zk_status ntt_first(NttRun& r, hipStream_t s) {
 }
 
 zk_status ntt_second(NttRun& r, hipStream_t s) {
-  if (r.two) ZK_HIP(ntt_launch_pass(r.b, s), "ntt pass B");
+  if (r.passes >= 2) ZK_HIP(ntt_launch_pass(r.b, s), "ntt pass B");
+  if (r.passes >= 3) ZK_HIP(ntt_launch_pass(r.c, s), "ntt pass B2");
   return ZK_OK;
 }
 

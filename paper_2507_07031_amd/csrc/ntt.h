@@ -9,7 +9,8 @@ namespace zk {
 
 // One pass: a batch of M = 2^m point transforms held in LDS.
 //   input  element (batch b, point i) at in[(b + i*s_in)]          (words x8)
-//   output element (batch b, point k) at out[(b*b_out + k*s_out)]
+//   output element (batch b, point k) at out[(b*b_out + k*s_out)], or, with
+//   b_hi_log > 0, at out[(b mod 2^b_hi_log)*b_out + (b >> b_hi_log)*b_out_hi + k*s_out]
 // Elements with input index >= valid_n read as zero.
 struct NttPass {
   const uint32_t* in;
@@ -23,7 +24,10 @@ struct NttPass {
   uint32_t valid_n;
   const f29* tw_lo;    // omega^e, e < 2^14 (forward or inverse root)
   const f29* tw_hi;    // omega^(e 2^14)
-  uint32_t post_tw_L;  // 0: none; else multiply (b, k) by omega_(2^L)^(b k)
+  uint32_t post_tw_L;  // 0: none; else multiply (b, k) by omega_(2^L)^((b >> tw_shift) k)
+  uint32_t tw_shift;
+  uint32_t b_hi_log;   // 0: plain batch stride b_out
+  uint32_t b_out_hi;
   const f29* pre_lo;   // coset: multiply input i by g^i (nullptr: none)
   const f29* pre_hi;
   const f29* post_scale;  // multiply every output by this constant (nullptr: none)

@@ -12,6 +12,12 @@
 // transforms of at most 4096 points:
 //   pass A: for every i1 < N1, Y[i1][k2] = omega_N^(i1 k2) * NTT_N2(x[i1 + N1 i2])
 //   pass B: for every k2 < N2, X[k2 + N2 k1] = NTT_N1(Y[i1][k2])
+// Above 2^24 points N1 exceeds a tile and pass B is itself factored,
+// N1 = P1 * P2, i1 = j1 + P1 j2, k1 = k1' + P2 k1'' (three passes in all):
+//   pass B1: Z[k2 + N2 k1' + N2 P2 j1] = omega_N1^(j1 k1') * NTT_P2(Y[j1 + P1 j2][k2])
+//   pass B2: X[k2 + N2 k1' + N2 P2 k1''] = NTT_P1(Z[...j1...])
+// B1's batch index k2 + N2 j1 is split (b_hi_log) so that B2 reads every one
+// of its transforms at a single stride.
 // Inside a tile the points are loaded in bit-reversed order into LDS and run
 // through log2(M) decimation-in-time stages.  A workgroup owns G adjacent
 // transforms so that each strided global access moves G*32 contiguous bytes.
@@ -207,13 +213,16 @@ ntt_pass_kernel(NttPass a) {
     const uint32_t k = row_out ? e % M : e / G;
     uint32_t w[8];
     ld8(lds_at(lds, b * M + k), w);
+    const uint32_t bb = g0 + b;
     if (a.post_tw_L) {
-      const uint32_t ex = ((g0 + b) * k) & ((1u << a.post_tw_L) - 1);
+      const uint32_t ex = ((bb >> a.tw_shift) * k) & ((1u << a.post_tw_L) - 1);
       if (ex) mul_tw_2q(w, pow28(a.tw_lo, a.tw_hi, ex << (28 - a.post_tw_L)), w);
     }
     if (a.post_scale) mul_tw_2q(w, *a.post_scale, w);
     canon32<FrP>(w);
-    st8(a.out + ((size_t)(g0 + b) * a.b_out + (size_t)k * a.s_out) * 8, w);
+    const size_t ob = a.b_hi_log ? (size_t)(bb & ((1u << a.b_hi_log) - 1)) * a.b_out + (size_t)(bb >> a.b_hi_log) * a.b_out_hi
+                                 : (size_t)bb * a.b_out;
+    st8(a.out + (ob + (size_t)k * a.s_out) * 8, w);
   }
 }
 

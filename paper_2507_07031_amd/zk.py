@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libzk.so")
 
 ZK_OK, ZK_EINVAL, ZK_ENOMEM, ZK_EDEVICE, ZK_EUNSUPPORTED = 0, -1, -2, -3, -5
-MAX_LOG_NTT = 24
+MAX_LOG_NTT = 28
 
 EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_srs_setup", "zk_srs_create",
            "zk_srs_destroy", "zk_srs_size", "zk_msm_srs", "zk_msm_batch", "zk_fold", "zk_profile_enable",

@@ -41,8 +41,8 @@ def test_argument_errors_return_before_device_work(zk):
     assert L.zk_intt(null, null, 3, null) == zk.ZK_EINVAL
     assert "NULL" in L.zk_last_error().decode()
     dummy = ctypes.c_void_p(0x1000)
-    assert L.zk_ntt(dummy, dummy, 25, null) == zk.ZK_EUNSUPPORTED
-    assert L.zk_coset_ntt(dummy, 20, 5, null, dummy, null) == zk.ZK_EUNSUPPORTED
+    assert L.zk_ntt(dummy, dummy, 29, null) == zk.ZK_EUNSUPPORTED
+    assert L.zk_coset_ntt(dummy, 24, 5, null, dummy, null) == zk.ZK_EUNSUPPORTED
     assert L.zk_msm(null, null, 4, dummy, null) == zk.ZK_EINVAL
     assert L.zk_msm_srs(null, dummy, 4, dummy, null) == zk.ZK_EINVAL
     assert L.zk_msm_batch(null, dummy, dummy, 1, dummy, null) == zk.ZK_EINVAL
@@ -51,7 +51,7 @@ def test_argument_errors_return_before_device_work(zk):
     assert L.zk_msm_srs_ex(null, dummy, 4, dummy, null, null) == zk.ZK_EINVAL
     assert L.zk_commit_job(null, dummy, 4, 2, null, dummy, dummy, dummy, null) == zk.ZK_EINVAL
     assert L.zk_commit_job(dummy, dummy, 4, 2, null, dummy, null, dummy, null) == zk.ZK_EINVAL
-    assert L.zk_commit_job(dummy, dummy, 20, 5, null, dummy, dummy, dummy, null) == zk.ZK_EUNSUPPORTED
+    assert L.zk_commit_job(dummy, dummy, 24, 5, null, dummy, dummy, dummy, null) == zk.ZK_EUNSUPPORTED
     assert L.zk_set_validate(0) == zk.ZK_OK
     assert L.zk_kzg_open(null, dummy, 4, dummy, dummy, null, dummy, null) == zk.ZK_EINVAL
     assert L.zk_quotient_mul(null, dummy, dummy, dummy, 4, 1, null, dummy, dummy, null) == zk.ZK_EINVAL

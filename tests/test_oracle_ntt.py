@@ -132,3 +132,55 @@ def test_lagrange_basis_pins(rng):
         assert lj[j] == ntt.horner(ntt.idft(e), tau)
     # tau on H: the basis is a unit vector
     assert [osrs.lagrange_basis_at(pow(w, 5, R), n, j) for j in range(n)] == [int(j == 5) for j in range(n)]
+
+
+def _runs_vector(rng, n, nruns, npoints):
+    """A random run-structured vector (with gaps) and its dense form."""
+    cuts = sorted(rng.sample(range(1, n), min(2 * nruns, n - 1)))
+    edges = [0] + cuts + [n]
+    runs, dense = [], [0] * n
+    for t in range(len(edges) - 1):
+        if t % 3 == 2:  # a gap of zeros
+            continue
+        s, e = edges[t], edges[t + 1]
+        v = rng.randrange(R)
+        runs.append((s, e - s, v))
+        dense[s:e] = [v] * (e - s)
+    points = {}
+    for i in rng.sample(range(n), min(npoints, n)):
+        points[i] = rng.randrange(R)
+        dense[i] = points[i]
+    return runs, points, dense
+
+
+@pytest.mark.parametrize("logn", [0, 1, 3, 6, 9])
+def test_run_structured_outputs_match_dense_transforms(rng, logn):
+    # the geometric-sum shortcut against the O(n^2) definitions
+    n = 1 << logn
+    runs, points, dense = _runs_vector(rng, n, 5, 4)
+    A, a = ntt.dft(dense), ntt.idft(dense)
+    for k in range(n):
+        assert ntt.ntt_runs_at(runs, points, logn, k) == A[k]
+        assert ntt.ntt_runs_at(runs, points, logn, k, inverse=True) == a[k]
+
+
+@pytest.mark.parametrize("logn,lb", [(0, 2), (3, 1), (5, 2), (6, 3)])
+def test_run_structured_coset_outputs(rng, logn, lb):
+    n = 1 << logn
+    runs, points, dense = _runs_vector(rng, n, 3, 3)
+    E = ntt.coset_evals(dense, lb)
+    for k in range(n << lb):
+        assert ntt.ntt_runs_at(runs, points, logn + lb, k, shift=field.GENERATOR_FR) == E[k]
+
+
+def test_run_structured_edge_cases(rng):
+    # one run over everything: a constant vector transforms to n*c at 0 and 0 elsewhere
+    c = rng.randrange(R)
+    for k in range(16):
+        assert ntt.ntt_runs_at([(0, 16, c)], {}, 4, k) == (16 * c % R if k == 0 else 0)
+    # only points: a delta at i gives omega^(ik)
+    w = ntt.root_of_unity(1 << 20)
+    for k in (0, 1, 12345, (1 << 20) - 1):
+        assert ntt.ntt_runs_at([], {777: 1}, 20, k) == pow(w, 777 * k, R)
+    # a point inside a run replaces the run's value rather than adding to it
+    assert ntt.sum_runs_at([(0, 4, 5)], {2: 5}, 3) == 5 * (1 + 3 + 9 + 27) % R
