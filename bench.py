@@ -328,6 +328,27 @@ def main():
                            "int_tops": round(mads / (t_ms / 1e3) / 1e12, 3),
                            "int_frac": round(mads / (t_ms / 1e3) / 1e12 / PEAK_MAD_TOPS, 4),
                            "bound": "alu"}
+        # the largest transform, 2^28 points (three LDS passes): a dense input
+        # of canonical values (top word cut to 29 bits, below r's)
+        log("ntt 2^28")
+        N28 = 1 << 28
+        big = torch.randint(-2 ** 31, 2 ** 31 - 1, (N28, 8), dtype=torch.int32, device="cuda")
+        big[:, 7] &= 0x1FFFFFFF
+        big_out = torch.empty_like(big)
+        t28 = timed(lambda: zk.ntt(big, out=big_out), reps=5)
+        t28i = timed(lambda: zk.intt(big_out, out=big), reps=5)
+        for name, t_ms in (("ntt_2^28", t28), ("intt_2^28", t28i)):
+            hbm_bytes = 3 * 2 * 32 * N28
+            mads = (N28 // 2) * 28 * MADS_PER_MONT
+            roofs[name] = {"ms": round(t_ms, 4), "passes": 3,
+                           "hbm_gbs": round(hbm_bytes / (t_ms / 1e3) / 1e9, 1),
+                           "hbm_frac": round(hbm_bytes / (t_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+                           "int_tops": round(mads / (t_ms / 1e3) / 1e12, 3),
+                           "int_frac": round(mads / (t_ms / 1e3) / 1e12 / PEAK_MAD_TOPS, 4),
+                           "bound": "alu"}
+        del big, big_out
+        torch.cuda.empty_cache()
+        zk.release_cached_memory()
         extras["ntt_rooflines"] = roofs
 
         # per-step latency distribution of the commit job (each step bracketed

@@ -63,6 +63,7 @@ struct InputCheck {
 struct DeviceCtx {
   bool ready = false;
   f29* tw[4] = {nullptr, nullptr, nullptr, nullptr};   // fwd lo, fwd hi, inv lo, inv hi
+  f29* ladder[2] = {nullptr, nullptr};                  // in-tile twiddles, fwd / inv
   f29* coset5[2] = {nullptr, nullptr};                  // 5^e lo / hi
   f29* coset5inv[2] = {nullptr, nullptr};               // 5^-e lo / hi
   f29* ninv = nullptr;                                  // 2^-L, L = 0..28
@@ -93,6 +94,7 @@ zk_status ctx_get(DeviceCtx** out) {
   ZK_HIP(ntt_pass_setup(), "ntt setup");
   const size_t tsz = sizeof(f29) << 14;
   for (int i = 0; i < 4; i++) ZK_HIP(hipMalloc(&c.tw[i], tsz), "hipMalloc(twiddles)");
+  for (int i = 0; i < 2; i++) ZK_HIP(hipMalloc(&c.ladder[i], sizeof(f29) * ntt_ladder_entries()), "hipMalloc(ladder)");
   for (int i = 0; i < 2; i++) ZK_HIP(hipMalloc(&c.coset5[i], tsz), "hipMalloc(coset)");
   for (int i = 0; i < 2; i++) ZK_HIP(hipMalloc(&c.coset5inv[i], tsz), "hipMalloc(coset)");
   ZK_HIP(hipMalloc(&c.ninv, sizeof(f29) * 29), "hipMalloc(ninv)");
@@ -109,6 +111,8 @@ zk_status ctx_get(DeviceCtx** out) {
   w5.w[0] = 5;
   ZK_HIP(ntt_make_pow_tables(wf, c.tw[0], c.tw[1], 0), "twiddle tables");
   ZK_HIP(ntt_make_pow_tables(wi, c.tw[2], c.tw[3], 0), "twiddle tables");
+  ZK_HIP(ntt_make_ladder(c.tw[1], c.ladder[0], 0), "twiddle ladder");
+  ZK_HIP(ntt_make_ladder(c.tw[3], c.ladder[1], 0), "twiddle ladder");
   ZK_HIP(ntt_make_pow_tables(w5, c.coset5[0], c.coset5[1], 0), "coset tables");
   {
     Words8 w5i;
@@ -280,6 +284,7 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   const f29* lo = inverse ? c->tw[2] : c->tw[0];
   const f29* hi = inverse ? c->tw[3] : c->tw[1];
   const f29* scale = inverse ? c->ninv + L : nullptr;
+  const f29* ladder = inverse ? c->ladder[1] : c->ladder[0];
   if (L <= T) {
     NttPass& p = r.a;
     p.in = in;
@@ -293,6 +298,7 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
     p.valid_n = valid_n;
     p.tw_lo = lo;
     p.tw_hi = hi;
+    p.ladder = ladder;
     p.pre_lo = pre_lo;
     p.pre_hi = pre_hi;
     p.post_scale = scale;
@@ -322,6 +328,7 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   a.valid_n = valid_n;
   a.tw_lo = lo;
   a.tw_hi = hi;
+  a.ladder = ladder;
   a.post_tw_L = L;
   a.pre_lo = pre_lo;
   a.pre_hi = pre_hi;
@@ -337,6 +344,7 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   b.valid_n = 1u << L;
   b.tw_lo = lo;
   b.tw_hi = hi;
+  b.ladder = ladder;
   b.post_scale = scale;
   r.passes = 2;
   if (!three) return ZK_OK;
@@ -369,6 +377,7 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   c3.valid_n = 1u << L;
   c3.tw_lo = lo;
   c3.tw_hi = hi;
+  c3.ladder = ladder;
   c3.post_scale = scale;
   r.passes = 3;
   return ZK_OK;

@@ -24,6 +24,7 @@ struct NttPass {
   uint32_t valid_n;
   const f29* tw_lo;    // omega^e, e < 2^14 (forward or inverse root)
   const f29* tw_hi;    // omega^(e 2^14)
+  const f29* ladder;   // in-tile twiddles: ladder[2^(k-1) + j] = omega_(2^k)^j
   uint32_t post_tw_L;  // 0: none; else multiply (b, k) by omega_(2^L)^((b >> tw_shift) k)
   uint32_t tw_shift;
   uint32_t b_hi_log;   // 0: plain batch stride b_out
@@ -42,6 +43,9 @@ struct Words8 {
 // lo[e] = base^e, hi[e] = base^(e 2^14), e < 2^14 (Montgomery form); base canonical.
 hipError_t ntt_make_pow_tables(Words8 base, f29* lo, f29* hi, hipStream_t s);
 size_t ntt_pass_lds_bytes();
+// ladder[2^(k-1) + j] = omega_(2^k)^j (k <= tile log) from a "hi" table; entries: ntt_ladder_entries()
+size_t ntt_ladder_entries();
+hipError_t ntt_make_ladder(const f29* hi, f29* ladder, hipStream_t s);
 uint32_t ntt_tile_log();
 
 }  // namespace zk

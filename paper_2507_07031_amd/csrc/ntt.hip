@@ -26,8 +26,9 @@
 // Montgomery-form constants in 29-bit limbs, so one Montgomery product
 // returns the plain product w*v.  Twiddle tables hold omega_(2^28)^e for
 // e < 2^14 ("lo") and e = j*2^14 ("hi"); omega_N^e = lo * hi of the exponent
-// e*2^(28-L) split in two halves, and every in-tile twiddle is a single "hi"
-// entry (tile sizes <= 2^14).
+// e*2^(28-L) split in two halves.  In-tile twiddles come from a "ladder"
+// that stores each stage's roots omega_(2^k)^j contiguously, so the lanes of
+// a wave read adjacent entries rather than one cache line each.
 #include "ntt.h"
 #include "prof.h"
 
@@ -105,7 +106,7 @@ __device__ __forceinline__ void mul_tw_2q(const uint32_t a[8], const f29& w, uin
 // Twiddles that are 1 (j = 0 in the first stage of a tile) are skipped.
 template <int Q, int T, int P>
 __device__ __forceinline__ void dit_butterflies(uint32_t (&x)[Q][8], uint32_t s, uint32_t j, uint32_t h,
-                                                const f29* __restrict__ tw_hi) {
+                                                const f29* __restrict__ ladder) {
   constexpr uint32_t q = ((P >> T) << (T + 1)) | (P & ((1u << T) - 1));
   constexpr uint32_t r = q + (1u << T);
   constexpr uint32_t qlow = q & ((1u << T) - 1);
@@ -114,9 +115,9 @@ __device__ __forceinline__ void dit_butterflies(uint32_t (&x)[Q][8], uint32_t s,
 #pragma unroll
     for (int w = 0; w < 8; w++) tv[w] = x[r][w];
   } else {
-    // omega_(2^(s+T))^jt = omega_(2^28)^(jt * 2^(28-s-T)): a "hi" table entry
+    // omega_(2^(s+T))^jt from the ladder: consecutive jt are adjacent entries
     const uint32_t jt = j + qlow * h;
-    mul_tw_2q(x[r], ldf29(tw_hi, jt << (14 - s - T)), tv);
+    mul_tw_2q(x[r], ldf29(ladder, (1u << (s + T - 1)) + jt), tv);
   }
   add_2q(x[q], tv, x[r]);
   sub_2q(x[q], tv, tv);
@@ -126,14 +127,14 @@ __device__ __forceinline__ void dit_butterflies(uint32_t (&x)[Q][8], uint32_t s,
     x[r][w] = tv[w];
     x[q][w] = sum;
   }
-  if constexpr (P + 1 < Q / 2) dit_butterflies<Q, T, P + 1>(x, s, j, h, tw_hi);
+  if constexpr (P + 1 < Q / 2) dit_butterflies<Q, T, P + 1>(x, s, j, h, ladder);
 }
 
 template <int Q, int T, int R>
 __device__ __forceinline__ void dit_levels(uint32_t (&x)[Q][8], uint32_t s, uint32_t j, uint32_t h,
-                                           const f29* __restrict__ tw_hi) {
-  dit_butterflies<Q, T, 0>(x, s, j, h, tw_hi);
-  if constexpr (T + 1 < R) dit_levels<Q, T + 1, R>(x, s, j, h, tw_hi);
+                                           const f29* __restrict__ ladder) {
+  dit_butterflies<Q, T, 0>(x, s, j, h, ladder);
+  if constexpr (T + 1 < R) dit_levels<Q, T + 1, R>(x, s, j, h, ladder);
 }
 
 // R consecutive decimation-in-time stages s .. s+R-1 on the LDS tile, each
@@ -142,7 +143,7 @@ __device__ __forceinline__ void dit_levels(uint32_t (&x)[Q][8], uint32_t s, uint
 // themselves: stage s+T pairs q with q + 2^T.
 template <int R>
 __device__ __forceinline__ void dit_stages(uint32_t* lds, uint32_t s, uint32_t m, uint32_t TE,
-                                           const f29* __restrict__ tw_hi) {
+                                           const f29* __restrict__ ladder) {
   constexpr int Q = 1 << R;
   const uint32_t h = 1u << (s - 1);
   const uint32_t units_per_tr = 1u << (m - R);
@@ -153,7 +154,7 @@ __device__ __forceinline__ void dit_stages(uint32_t* lds, uint32_t s, uint32_t m
     uint32_t x[Q][8];
 #pragma unroll
     for (int q = 0; q < Q; q++) ld8(lds_at(lds, base + q * h), x[q]);
-    dit_levels<Q, 0, R>(x, s, j, h, tw_hi);
+    dit_levels<Q, 0, R>(x, s, j, h, ladder);
 #pragma unroll
     for (int q = 0; q < Q; q++) st8(lds_at(lds, base + q * h), x[q]);
   }
@@ -193,14 +194,14 @@ ntt_pass_kernel(NttPass a) {
     const uint32_t left = a.m - st + 1;
     if (left >= 3 || left == 1) {
       if (left == 1) {
-        dit_stages<1>(lds, st, a.m, TE, a.tw_hi);
+        dit_stages<1>(lds, st, a.m, TE, a.ladder);
         st += 1;
       } else {
-        dit_stages<3>(lds, st, a.m, TE, a.tw_hi);
+        dit_stages<3>(lds, st, a.m, TE, a.ladder);
         st += 3;
       }
     } else {
-      dit_stages<2>(lds, st, a.m, TE, a.tw_hi);
+      dit_stages<2>(lds, st, a.m, TE, a.ladder);
       st += 2;
     }
     __syncthreads();
@@ -224,6 +225,17 @@ ntt_pass_kernel(NttPass a) {
                                  : (size_t)bb * a.b_out;
     st8(a.out + (ob + (size_t)k * a.s_out) * 8, w);
   }
+}
+
+// Ladder of in-tile twiddles: ladder[2^(k-1) + j] = omega_(2^k)^j for
+// j < 2^(k-1), k = 1 .. TILE_LOG, gathered from a "hi" table
+// (hi[e] = omega_(2^28)^(e 2^14), so omega_(2^k)^j = hi[j 2^(14-k)]).
+__global__ void ladder_kernel(const f29* __restrict__ hi, f29* __restrict__ ladder) {
+  const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx == 0 || idx >= TILE) return;
+  const uint32_t k = 32 - __clz(idx);  // 2^(k-1) <= idx < 2^k
+  const uint32_t j = idx - (1u << (k - 1));
+  ladder[idx] = hi[j << (14 - k)];
 }
 
 // lo[e] = base^e, hi[e] = base^(e * 2^14) for e < 2^14 (Montgomery form).
@@ -267,5 +279,12 @@ hipError_t ntt_make_pow_tables(Words8 base, f29* lo, f29* hi, hipStream_t s) {
 }
 
 uint32_t ntt_tile_log() { return TILE_LOG; }
+
+size_t ntt_ladder_entries() { return TILE; }
+
+hipError_t ntt_make_ladder(const f29* hi, f29* ladder, hipStream_t s) {
+  hipLaunchKernelGGL(ladder_kernel, dim3(TILE / 256), dim3(256), 0, s, hi, ladder);
+  return hipGetLastError();
+}
 
 }  // namespace zk
