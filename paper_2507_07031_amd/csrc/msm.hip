@@ -522,6 +522,37 @@ bit_sums_kernel(const uint32_t* __restrict__ vbuf, MsmPlan p, uint32_t* __restri
     st_xyzz(partial + ((size_t)(g * (p.nbits + 1) + i) * p.parts + part) * XYZZ_WORDS, ld_xyzz(sm));
 }
 
+// The same on quads (four lanes per point operation; block (part, i, g) has
+// BITS_QUADS quads): for few bucket sets, where the sums' latency matters
+// more than their total work.
+constexpr uint32_t BITS_QUADS = 64;
+__global__ void __launch_bounds__(BITS_QUADS * 4)
+bit_sums_quad_kernel(const uint32_t* __restrict__ vbuf, MsmPlan p, uint32_t* __restrict__ partial) {
+  __shared__ uint32_t sm[BITS_QUADS * XYZZ_WORDS];
+  const uint32_t part = blockIdx.x, i = blockIdx.y, g = blockIdx.z;
+  const uint32_t quad = threadIdx.x >> 2, c = threadIdx.x & 3u;
+  const bool tslice = i == p.nbits;
+  const uint32_t count = tslice ? p.J : p.J / 2;
+  const uint32_t per = (count + p.parts - 1) / p.parts;
+  const uint32_t t0 = part * per, t1 = min(t0 + per, count);
+  const uint32_t low = (1u << i) - 1u;
+  f29 acc = f29_zero();
+  for (uint32_t t = t0 + quad; t < t1; t += BITS_QUADS) {  // quad-uniform bounds
+    const uint32_t j = tslice ? t : (((t >> i) << (i + 1)) | (1u << i) | (t & low));
+    acc = quad_add(acc, ldq(vbuf + ((size_t)(g * p.J + j) * 2 + (tslice ? 1 : 0)) * XYZZ_WORDS, c));
+  }
+  stq(sm + quad * XYZZ_WORDS, c, acc);
+  __syncthreads();
+  for (uint32_t h = BITS_QUADS / 2; h > 0; h >>= 1) {
+    if (quad < h) {
+      acc = quad_add(acc, ldq(sm + (quad + h) * XYZZ_WORDS, c));
+      stq(sm + quad * XYZZ_WORDS, c, acc);
+    }
+    __syncthreads();
+  }
+  if (quad == 0) stq(partial + ((size_t)(g * (p.nbits + 1) + i) * p.parts + part) * XYZZ_WORDS, c, acc);
+}
+
 // One tree level over slice partials: block (k, i, g) adds partials
 // 64k .. 64k+63 of slice i of set g (fewer partials per slice for the next
 // level or the finishing kernel).
@@ -580,15 +611,21 @@ bit_finish_kernel(const uint32_t* __restrict__ partial, uint32_t nparts, uint32_
     }
     __syncthreads();
   }
-  // slice i's sum is in quad i*qps; scale it and move it to slot i
-  if (k0 == 0 && i < p.nbits) {
-    const uint32_t e = p.lgLB + i;
-    for (uint32_t k = 0; k < e; k++) acc = quad_dbl(acc);
+  // slice i's sum is in slot i*qps; quad i takes it, scales it and moves it
+  // to slot i.  The doubling chains are the kernel's longest, and they run
+  // as issue-bound single waves: packed into the first wave (or two) they
+  // share no SIMD, where spread over the block's waves two of them would
+  // share each SIMD and take twice as long.
+  f29 v = quad < ns ? ldq(sm + quad * qps * XYZZ_WORDS, c) : f29_zero();
+  __syncthreads();
+  if (quad < nsp) {
+    if (quad < p.nbits) {
+      const uint32_t e = p.lgLB + quad;
+      for (uint32_t k = 0; k < e; k++) v = quad_dbl(v);
+    }
+    stq(sm + quad * XYZZ_WORDS, c, v);
   }
   __syncthreads();
-  if (k0 == 0) stq(sm + i * XYZZ_WORDS, c, i < ns ? acc : f29_zero());
-  __syncthreads();
-  f29 v = quad < nsp ? ldq(sm + quad * XYZZ_WORDS, c) : f29_zero();
   for (uint32_t h = nsp / 2; h > 0; h >>= 1) {
     if (quad < h) {
       v = quad_add(v, ldq(sm + (quad + h) * XYZZ_WORDS, c));
@@ -1191,8 +1228,13 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points
     hipLaunchKernelGGL(chunk_sums_kernel, dim3(cdiv((uint64_t)p.groups * p.J, 64)), dim3(64), 0, s, b.buckets,
                        b.counts, p, b.vbuf);
   }
-  hipLaunchKernelGGL(bit_sums_kernel, dim3(p.parts, p.nbits + 1, p.groups), dim3(BITS_NT), 0, s, b.vbuf, p,
-                     b.partial);
+  if ((uint64_t)p.groups * p.J * 4 <= (1u << 17)) {
+    hipLaunchKernelGGL(bit_sums_quad_kernel, dim3(p.parts, p.nbits + 1, p.groups), dim3(BITS_QUADS * 4), 0, s, b.vbuf,
+                       p, b.partial);
+  } else {
+    hipLaunchKernelGGL(bit_sums_kernel, dim3(p.parts, p.nbits + 1, p.groups), dim3(BITS_NT), 0, s, b.vbuf, p,
+                       b.partial);
+  }
   // tree levels ping-pong between the partial buffer and the (now free) chunk buffer
   uint32_t* pin = b.partial;
   uint32_t* pout = b.vbuf;
