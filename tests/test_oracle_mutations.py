@@ -205,3 +205,43 @@ def test_g2_doubling_slip_is_caught(monkeypatch):
         return None if r is None else (r[0], g2.f2_neg(r[1]))
     monkeypatch.setattr(g2, "double", bad)
     _fails(tg2.test_generator_order_r)
+
+
+def _runs_at_variant(geo_extra=0, start_extra=0, replace=True, one_len_extra=0):
+    """sum_runs_at with one planted slip (geometric length, start exponent,
+    point added instead of replacing its run's value, or the x = 1 case)."""
+    def f(runs, points, x):
+        x %= R
+        acc = 0
+        for start, length, v in runs:
+            if x == 1:
+                g = (length + one_len_extra) % R
+            else:
+                g = (pow(x, length + geo_extra, R) - 1) * field.fr_inv(x - 1) % R
+            acc = (acc + int(v) * pow(x, start + start_extra, R) % R * g) % R
+        for i, v in points.items():
+            base = 0
+            if replace:
+                for start, length, rv in runs:
+                    if start <= i < start + length:
+                        base = int(rv)
+                        break
+            acc = (acc + (int(v) - base) * pow(x, i, R)) % R
+        return acc
+    return f
+
+
+@pytest.mark.parametrize("slip", [dict(geo_extra=1), dict(start_extra=1), dict(replace=False),
+                                  dict(one_len_extra=-1)])
+def test_run_structured_slips_are_caught(monkeypatch, slip):
+    monkeypatch.setattr(ntt, "sum_runs_at", _runs_at_variant(**slip))
+    _fails(tn.test_run_structured_outputs_match_dense_transforms, random.Random(3), 6)
+
+
+def test_run_structured_missing_inverse_scale_is_caught(monkeypatch):
+    def bad(runs, points, log_domain, k, inverse=False, shift=1):
+        w = ntt.root_of_unity(1 << log_domain)
+        base = pow(field.fr_inv(w), k, R) if inverse else shift * pow(w, k, R) % R
+        return ntt.sum_runs_at(runs, points, base)
+    monkeypatch.setattr(ntt, "ntt_runs_at", bad)
+    _fails(tn.test_run_structured_outputs_match_dense_transforms, random.Random(4), 6)
