@@ -71,6 +71,7 @@ typedef int zk_status;
 #define ZK_EINVAL (-1)      /* bad argument (NULL, size out of range, ...)   */
 #define ZK_ENOMEM (-2)      /* device allocation failed                      */
 #define ZK_EDEVICE (-3)     /* HIP runtime / kernel launch error             */
+#define ZK_EBUDGET (-4)     /* scratch would exceed zk_set_scratch_budget    */
 #define ZK_EUNSUPPORTED (-5) /* valid request outside this build's limits    */
 
 /* Largest transform: log_n (+ log_blowup) <= ZK_MAX_LOG_NTT. */
@@ -307,6 +308,23 @@ zk_status zk_set_validate(int on);
 
 /* Wait for and free every cached scratch block of the current device. */
 zk_status zk_release_cached_memory(void);
+
+/* HBM budget for the library's scratch on the current device (for callers
+ * that admit work by memory, such as a serving loop; 0, the default, is no
+ * cap).  The budget covers every scratch block the library holds there,
+ * cached ones included.  When a call needs a new block that would take the
+ * total over the budget, the library first frees the device's cached blocks
+ * (waiting for their last use); if the block still does not fit, the call
+ * returns ZK_EBUDGET.  A call's scratch is taken before its kernels are
+ * enqueued, so a call failing this way has enqueued no work of its own
+ * except, for calls that allocate in stages, stages that precede the
+ * failing allocation (its outputs are then unspecified).  Caller buffers
+ * are not counted.  Lowering the budget frees nothing by itself. */
+zk_status zk_set_scratch_budget(uint64_t bytes);
+
+/* Scratch bytes the library holds on the current device, cached blocks
+ * included (0 if there is no device). */
+uint64_t zk_scratch_held(void);
 
 /* Observability: when enabled, the library brackets named kernel regions
  * with HIP events recorded on the stream the kernels run on.  Regions:

@@ -157,6 +157,28 @@ struct Block {
 
 std::mutex g_cache_mu;
 std::vector<Block> g_free_blocks;
+// Per device: scratch bytes the library holds (cached and in use), and the
+// cap set by zk_set_scratch_budget (0: none).  Guarded by g_cache_mu.
+uint64_t g_held[64] = {};
+uint64_t g_budget[64] = {};
+
+// Free this device's cached blocks (waiting for their last use); the caller
+// holds no lock.
+void drop_cached(int dev) {
+  std::vector<Block> keep, drop;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (Block& b : g_free_blocks) (b.device == dev ? drop : keep).push_back(b);
+    g_free_blocks.swap(keep);
+  }
+  for (Block& b : drop) {
+    (void)hipEventSynchronize(b.done);
+    (void)hipFree(b.p);
+    (void)hipEventDestroy(b.done);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_held[dev] -= b.size;
+  }
+}
 
 size_t round_up(size_t b) {
   const size_t g = b <= (size_t(1) << 20) ? 4096 : (size_t(2) << 20);
@@ -166,6 +188,7 @@ size_t round_up(size_t b) {
 zk_status block_alloc(Block& out, size_t bytes, hipStream_t s) {
   int dev = 0;
   ZK_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= 64) return fail(ZK_EUNSUPPORTED, "device index out of range");
   bytes = round_up(bytes ? bytes : 256);
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
@@ -195,21 +218,29 @@ zk_status block_alloc(Block& out, size_t bytes, hipStream_t s) {
     std::fprintf(stderr, "[zk] scratch hipMalloc %zu bytes (cached %zu bytes in %zu blocks)\n", bytes, cached,
                  g_free_blocks.size());
   }
+  // a budget counts cached blocks too: over it, drop the cache first
+  auto over_budget = [&]() {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    return g_budget[dev] != 0 && g_held[dev] + bytes > g_budget[dev];
+  };
+  if (over_budget()) {
+    drop_cached(dev);
+    if (over_budget()) {
+      uint64_t held, cap;
+      {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        held = g_held[dev];
+        cap = g_budget[dev];
+      }
+      return fail(ZK_EBUDGET, "scratch of " + std::to_string(bytes) + " bytes exceeds the budget (" +
+                                  std::to_string(held) + " of " + std::to_string(cap) + " bytes held)");
+    }
+  }
   hipError_t e = hipMalloc(&out.p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     // drop cached blocks of this device and retry once
-    std::vector<Block> keep, drop;
-    {
-      std::lock_guard<std::mutex> lk(g_cache_mu);
-      for (Block& b : g_free_blocks) (b.device == dev ? drop : keep).push_back(b);
-      g_free_blocks.swap(keep);
-    }
-    for (Block& b : drop) {
-      (void)hipEventSynchronize(b.done);
-      (void)hipFree(b.p);
-      (void)hipEventDestroy(b.done);
-    }
+    drop_cached(dev);
     e = hipMalloc(&out.p, bytes);
     if (e != hipSuccess) {
       out.p = nullptr;
@@ -220,6 +251,10 @@ zk_status block_alloc(Block& out, size_t bytes, hipStream_t s) {
   out.size = bytes;
   out.device = dev;
   out.stream = s;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_held[dev] += bytes;
+  }
   ZK_HIP(hipEventCreateWithFlags(&out.done, hipEventDisableTiming), "hipEventCreate(scratch)");
   return ZK_OK;
 }
@@ -504,18 +539,28 @@ const char* zk_last_error(void) { return g_err.c_str(); }
 zk_status zk_release_cached_memory(void) {
   int dev = 0;
   ZK_HIP(hipGetDevice(&dev), "hipGetDevice");
-  std::vector<Block> keep, drop;
-  {
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    for (Block& b : g_free_blocks) (b.device == dev ? drop : keep).push_back(b);
-    g_free_blocks.swap(keep);
-  }
-  for (Block& b : drop) {
-    ZK_HIP(hipEventSynchronize(b.done), "hipEventSynchronize");
-    ZK_HIP(hipFree(b.p), "hipFree");
-    ZK_HIP(hipEventDestroy(b.done), "hipEventDestroy");
-  }
+  if (dev < 0 || dev >= 64) return fail(ZK_EUNSUPPORTED, "device index out of range");
+  drop_cached(dev);
   return ZK_OK;
+}
+
+zk_status zk_set_scratch_budget(uint64_t bytes) {
+  int dev = 0;
+  ZK_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= 64) return fail(ZK_EUNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_budget[dev] = bytes;
+  return ZK_OK;
+}
+
+uint64_t zk_scratch_held(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  return g_held[dev];
 }
 
 zk_status zk_set_validate(int on) {

@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libzk.so")
 
-ZK_OK, ZK_EINVAL, ZK_ENOMEM, ZK_EDEVICE, ZK_EUNSUPPORTED = 0, -1, -2, -3, -5
+ZK_OK, ZK_EINVAL, ZK_ENOMEM, ZK_EDEVICE, ZK_EBUDGET, ZK_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 MAX_LOG_NTT = 28
 
 EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_srs_setup", "zk_srs_create",
@@ -27,7 +27,7 @@ EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_s
            "zk_kzg_open_batch", "zk_quotient_mul",
            "zk_srs_lagrange_setup", "zk_transcript_challenge", "zk_acc_fold",
            "zk_srs_g2_setup", "zk_srs_g2_create", "zk_srs_g2_destroy", "zk_srs_g2_size", "zk_msm_g2_srs",
-           "zk_srs_set_table_policy", "zk_srs_window_bits")
+           "zk_srs_set_table_policy", "zk_srs_window_bits", "zk_set_scratch_budget", "zk_scratch_held")
 
 
 class ZkError(RuntimeError):
@@ -73,6 +73,8 @@ def _load():
         "zk_fold": ([P, P, U32, U32, P, P], I),
         "zk_profile_enable": ([I], I),
         "zk_release_cached_memory": ([], I),
+        "zk_set_scratch_budget": ([U64], I),
+        "zk_scratch_held": ([], U64),
         "zk_msm_srs_workspace_bytes": ([P, U64], U64),
         "zk_ntt_workspace_bytes": ([U32], U64),
         "zk_profile_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U64), I], I),
@@ -489,6 +491,17 @@ def msm_srs_workspace_bytes(srs, n):
 def ntt_workspace_bytes(log_n):
     """Scratch bytes of one 2^log_n-point transform (host-only query)."""
     return int(lib.zk_ntt_workspace_bytes(int(log_n)))
+
+
+def set_scratch_budget(nbytes):
+    """Cap the library's scratch on the current device (0: no cap); a call
+    whose scratch would exceed it raises ZkError with code ZK_EBUDGET."""
+    _check(lib.zk_set_scratch_budget(int(nbytes)))
+
+
+def scratch_held():
+    """Scratch bytes the library holds on the current device (cache included)."""
+    return int(lib.zk_scratch_held())
 
 
 def release_cached_memory():

@@ -53,6 +53,9 @@ def test_argument_errors_return_before_device_work(zk):
     assert L.zk_commit_job(dummy, dummy, 4, 2, null, dummy, null, dummy, null) == zk.ZK_EINVAL
     assert L.zk_commit_job(dummy, dummy, 24, 5, null, dummy, dummy, dummy, null) == zk.ZK_EUNSUPPORTED
     assert L.zk_set_validate(0) == zk.ZK_OK
+    # the scratch budget is per device: without one the call reports the device error
+    assert L.zk_set_scratch_budget(0) in (zk.ZK_OK, zk.ZK_EDEVICE)
+    assert zk.ZK_EBUDGET == -4
     assert L.zk_kzg_open(null, dummy, 4, dummy, dummy, null, dummy, null) == zk.ZK_EINVAL
     assert L.zk_quotient_mul(null, dummy, dummy, dummy, 4, 1, null, dummy, dummy, null) == zk.ZK_EINVAL
     assert L.zk_quotient_mul(dummy, dummy, dummy, dummy, 4, 0, null, dummy, dummy, null) == zk.ZK_EINVAL
