@@ -33,7 +33,7 @@ struct MsmPlan {
   uint32_t ncoarse;    // nbins >> S
   uint32_t chunk;      // scalars per coarse-sort item
   uint32_t nitems;     // items per window
-  uint32_t L;          // sorted entries per accumulating thread
+  uint32_t L;          // least sorted entries per accumulating thread
   uint32_t acc_blocks; // accumulate workgroups
   uint32_t LB;         // buckets per chunk in the running-sum reduction
   uint32_t lgLB;       // log2 LB

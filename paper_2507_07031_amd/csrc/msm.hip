@@ -943,6 +943,29 @@ uint32_t msm_default_c(uint32_t n) {
   return (uint32_t)c;
 }
 
+constexpr uint32_t ACC_BLOCKS_PER_CU = 2;
+constexpr uint32_t ACC_MIN_L = 4;
+constexpr uint64_t ACC_MAX_L = 256;
+
+// Compute units of the current device (queried once per device).
+static uint32_t compute_units() {
+  static uint32_t cus[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    return 256;
+  }
+  if (!cus[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) {
+      (void)hipGetLastError();
+      n = 256;
+    }
+    cus[dev] = (uint32_t)n;
+  }
+  return cus[dev];
+}
+
 static void plan_common(MsmPlan& p) {
   p.groups = p.nseg * p.Wb;
   p.nbins = p.groups * p.K;
@@ -961,12 +984,16 @@ static void plan_common(MsmPlan& p) {
   }
   p.ncoarse = p.nbins >> p.S;
   const uint64_t entries = (uint64_t)p.n * p.W;
-  // enough threads to fill the chip, at most 64 entries each
-  uint64_t L = entries / (256ull * 1024);
-  if (L < 4) L = 4;
-  if (L > 64) L = 64;
-  p.L = (uint32_t)L;
-  p.acc_blocks = cdiv(cdiv(entries, p.L), MSM_NT);
+  // Accumulation grid: whole rounds of ACC_BLOCKS_PER_CU workgroups per
+  // compute unit (a round is resident at once, so no unit waits on a partial
+  // last one), as few rounds as keep slices within ACC_MAX_L entries, and
+  // fewer workgroups when the n * W bound gives under ACC_MIN_L entries per
+  // thread.  The kernel spreads the sorted total, known only on the device,
+  // over the grid.
+  const uint64_t per_round = (uint64_t)compute_units() * ACC_BLOCKS_PER_CU * MSM_NT;
+  const uint64_t rounds = std::max<uint64_t>(1, (entries + per_round * ACC_MAX_L - 1) / (per_round * ACC_MAX_L));
+  p.L = ACC_MIN_L;
+  p.acc_blocks = (uint32_t)cdiv(std::min<uint64_t>(rounds * per_round, cdiv(entries, ACC_MIN_L)), MSM_NT);
   if (p.acc_blocks == 0) p.acc_blocks = 1;
   // chunk length: short chains for one or a few bucket sets (latency), longer
   // ones when many sets already fill the chip (less bit-slice work)

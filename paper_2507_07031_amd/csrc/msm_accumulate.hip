@@ -19,7 +19,7 @@ __device__ __forceinline__ void st_rec_xyzz(uint32_t* rec, uint32_t key, uint32_
   st_xyzz(rec + 4, a);
 }
 
-// Each thread sums L consecutive sorted entries.  An entry is only its point
+// Each thread sums L consecutive sorted entries (L from the sorted total).  An entry is only its point
 // index and sign; its bucket is the one whose offset range contains the
 // entry's position (found once by binary search, then followed).  Runs of
 // one bucket strictly inside the range are complete and go straight to HBM;
@@ -27,10 +27,16 @@ __device__ __forceinline__ void st_rec_xyzz(uint32_t* rec, uint32_t key, uint32_
 // finished by the record levels.  The next point is loaded one step ahead.
 __global__ void __launch_bounds__(MSM_NT) __attribute__((amdgpu_waves_per_eu(3, 3)))
 accumulate_kernel(const uint32_t* __restrict__ entries, const uint32_t* __restrict__ offsets, uint32_t nbins,
-                  const uint32_t* __restrict__ points, uint32_t L, uint32_t* __restrict__ buckets,
+                  const uint32_t* __restrict__ points, uint32_t lmin, uint32_t* __restrict__ buckets,
                   uint32_t* __restrict__ rec) {
   const uint64_t t = (uint64_t)blockIdx.x * MSM_NT + threadIdx.x;
   const uint32_t total = offsets[nbins];
+  // slice length from the sorted total, which zero digits (skipped) can put
+  // far below the n * W the grid was planned for: the real entries are spread
+  // over the whole grid, at least lmin per thread
+  const uint64_t nthreads = (uint64_t)gridDim.x * MSM_NT;
+  uint64_t L = (total + nthreads - 1) / nthreads;
+  if (L < lmin) L = lmin;
   const uint64_t tb = t * L;
   uint32_t* r0 = rec + (2 * t) * REC_WORDS;
   uint32_t* r1 = r0 + REC_WORDS;
