@@ -36,6 +36,7 @@
 
 #include "curve.h"
 #include "curve_quad.h"
+#include "device.h"
 #include "msm_store.h"
 #include "msm.h"
 #include "prof.h"
@@ -947,25 +948,6 @@ constexpr uint32_t ACC_BLOCKS_PER_CU = 2;
 constexpr uint32_t ACC_MIN_L = 4;
 constexpr uint64_t ACC_MAX_L = 256;
 
-// Compute units of the current device (queried once per device).
-static uint32_t compute_units() {
-  static uint32_t cus[64] = {};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
-    (void)hipGetLastError();
-    return 256;
-  }
-  if (!cus[dev]) {
-    int n = 0;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) {
-      (void)hipGetLastError();
-      n = 256;
-    }
-    cus[dev] = (uint32_t)n;
-  }
-  return cus[dev];
-}
-
 static void plan_common(MsmPlan& p) {
   p.groups = p.nseg * p.Wb;
   p.nbins = p.groups * p.K;
@@ -990,7 +972,7 @@ static void plan_common(MsmPlan& p) {
   // fewer workgroups when the n * W bound gives under ACC_MIN_L entries per
   // thread.  The kernel spreads the sorted total, known only on the device,
   // over the grid.
-  const uint64_t per_round = (uint64_t)compute_units() * ACC_BLOCKS_PER_CU * MSM_NT;
+  const uint64_t per_round = (uint64_t)device_compute_units() * ACC_BLOCKS_PER_CU * MSM_NT;
   const uint64_t rounds = std::max<uint64_t>(1, (entries + per_round * ACC_MAX_L - 1) / (per_round * ACC_MAX_L));
   p.L = ACC_MIN_L;
   p.acc_blocks = (uint32_t)cdiv(std::min<uint64_t>(rounds * per_round, cdiv(entries, ACC_MIN_L)), MSM_NT);
