@@ -8,14 +8,16 @@
 // and the challenge gamma derived from a transcript by hashing.
 //
 // The G1 outputs are short sums of scalar multiples by powers of one
-// challenge, all independent: each runs in one quad (curve_quad.h) by
-// Straus's method with 4-bit windows, the table of 1..15 times every point
-// kept in scratch memory, 64 window steps of four doublings and one
-// addition per nonzero digit.  The Fr parts are elementwise Horner
-// combinations streamed through HBM.
+// challenge, all independent: every scalar multiple other than by 1 runs in
+// its own quad (curve_quad.h), split by the endomorphism into two 128-bit
+// halves (glv.h) and computed by Straus's method with 4-bit windows over
+// tables of 1..15 times the point and its image kept in scratch memory: 32
+// window steps of four doublings and up to two additions.  The Fr parts are
+// elementwise Horner combinations streamed through HBM.
 #include "accum.h"
 #include "curve.h"
 #include "curve_quad.h"
+#include "glv.h"
 #include "msm_store.h"
 #include "prof.h"
 
@@ -50,74 +52,124 @@ __device__ __forceinline__ const uint32_t* term_point(const uint32_t* C, const u
   return Ej + (size_t)(t - 1) * 16;
 }
 
+// Coordinate c of a point held by a quad, negated when neg is set (the y
+// coordinate, lane 1): 4q - Y keeps the coordinate bounds of the formulas.
+__device__ __forceinline__ f29 quad_cneg(const f29& v, uint32_t c, bool neg) {
+  return (neg && c == 1) ? sub_k(f29_zero(), v, Fq::K4) : v;
+}
+
+// One quad per (output, term) whose scalar gamma^t is not 1, all at once:
+// quad q of wave w < nwc computes gamma C[16 w + q] for output 16 w + q < k,
+// and quad q of the last wave gamma^(q+1) P_(q+1) of the error output for
+// q < d.  Each scalar is split by the endomorphism (glv.h),
+// k = +-k1 +- k2 lambda with k1, k2 < 2^128, and k P = (+-k1) P + (+-k2) phi(P)
+// runs as Straus over 32 windows of 4 bits with the tables of 1..15 times
+// +-P and +-phi(P), where phi(X, Y, ZZ, ZZZ) = (beta X, Y, ZZ, ZZZ).  The term
+// of scalar 1 is added to the result; the error output's quads first sum
+// their terms in LDS.
 __global__ __launch_bounds__(ACC_NT) void acc_fold_g1_kernel(const uint32_t* __restrict__ C,
                                                              const uint32_t* __restrict__ C2, uint32_t k,
                                                              const uint32_t* __restrict__ E,
                                                              const uint32_t* __restrict__ E2,
                                                              const uint32_t* __restrict__ Ej, uint32_t d,
-                                                             const uint32_t* __restrict__ gamma,
+                                                             const uint32_t* __restrict__ gamma, uint32_t nwc,
                                                              uint32_t* __restrict__ C_out,
                                                              uint32_t* __restrict__ E_out,
                                                              uint32_t* __restrict__ scratch) {
-  const uint32_t o = (blockIdx.x * ACC_NT + threadIdx.x) >> 2;  // output of this quad
-  if (o > k) return;                                              // whole quads leave together
-  const uint32_t c = quad_lane();
-  const uint32_t nterm = o < k ? 2u : d + 1;
-  uint32_t* tab = scratch + (size_t)o * (ACC_MAX_D + 1) * (TAB_WORDS + 8);
-  uint32_t* sc = tab + (size_t)(ACC_MAX_D + 1) * TAB_WORDS;  // scalars gamma^t, 8 words each
-  // scalars gamma^t, canonical: every lane of the quad computes and stores
-  // the same words, so each lane later reads back its own stores
-  {
-    uint32_t gw[8];
-    ld8w(gamma, gw);
-    const f29 gm = reduce_full<FrP>(to_mont<FrP>(unpack(gw)));
-    f29 p = f29_from(FrP::ONE);
-    for (uint32_t t = 0; t < nterm; t++) {
-      uint32_t w[8];
-      pack(from_mont<FrP>(p), w);
-      st8w(sc + t * 8, w);
-      p = reduce_full<FrP>(mont_mul<FrP>(p, gm));
+  __shared__ uint32_t sm[16 * 36];
+  const uint32_t wave = blockIdx.x, q = threadIdx.x >> 2, c = quad_lane();
+  const bool err = wave == nwc;
+  const uint32_t o = err ? k : wave * 16 + q;  // output
+  const uint32_t t = err ? q + 1 : 1;          // term
+  const bool active = err ? t <= d : o < k;    // uniform over each quad
+  f29 acc = f29_zero();
+  if (active) {
+    // scalar gamma^t, canonical words, computed alike by the lanes of the quad
+    uint32_t sw[8];
+    {
+      uint32_t gw[8];
+      ld8w(gamma, gw);
+      const f29 gm = reduce_full<FrP>(to_mont<FrP>(unpack(gw)));
+      f29 p = gm;
+      for (uint32_t i = 1; i < t; i++) p = reduce_full<FrP>(mont_mul<FrP>(p, gm));
+      pack(from_mont<FrP>(p), sw);
+    }
+    uint32_t k1[4], k2[4];
+    bool n1, n2;
+    glv_split(sw, k1, n1, k2, n2);
+    // tables: T1[m] = m (+-P), T2[m] = m (+-phi(P)), m = 1..15
+    uint32_t* T1 = scratch + ((size_t)wave * 16 + q) * 2 * TAB_WORDS;
+    uint32_t* T2 = T1 + TAB_WORDS;
+    {
+      uint32_t w[16];
+      const uint32_t* P = term_point(C, C2, E, E2, Ej, k, d, o, t);
+      ld8w(P, w);
+      ld8w(P + 8, w + 8);
+      aff a;
+      const bool fin = aff_from_plain_words(w, a);
+      const xyzz p1 = fin ? from_aff(a) : xyzz_inf();
+      const f29 base = quad_cneg(quad_coord(p1, c), c, fin && n1);
+      stq(T1 + 36, c, base);
+      f29 cur = quad_dbl(base);
+      stq(T1 + 2 * 36, c, cur);
+      for (uint32_t m = 3; m < 16; m++) {
+        cur = quad_add(cur, base);
+        stq(T1 + m * 36, c, cur);
+      }
+      uint32_t bw[8];
+#pragma unroll
+      for (int i = 0; i < 8; i++) bw[i] = GlvConst::BETA[i];
+      const f29 beta = reduce_full<Fq>(to_mont<Fq>(unpack(bw)));
+      for (uint32_t m = 1; m < 16; m++) {
+        f29 v = ldq(T1 + m * 36, c);
+        if (c == 0) v = mont_mul<Fq>(v, beta);
+        stq(T2 + m * 36, c, quad_cneg(v, c, fin && n1 != n2));
+      }
+    }
+    // Straus over both halves: 32 windows of 4 bits from the top
+    for (int32_t win = 31; win >= 0; --win) {
+      if (win != 31) {
+        acc = quad_dbl(acc);
+        acc = quad_dbl(acc);
+        acc = quad_dbl(acc);
+        acc = quad_dbl(acc);
+      }
+      const uint32_t d1 = (k1[win >> 3] >> ((win & 7) * 4)) & 15u;
+      const uint32_t d2 = (k2[win >> 3] >> ((win & 7) * 4)) & 15u;
+      if (d1) acc = quad_add(acc, ldq(T1 + d1 * 36, c));
+      if (d2) acc = quad_add(acc, ldq(T2 + d2 * 36, c));
     }
   }
-  // tables: multiple m of term t's point at tab[t][m] (m = 1..15)
-  for (uint32_t t = 0; t < nterm; t++) {
+  if (!err) {
+    if (!active) return;  // whole quads leave together
+  } else {
+    // the error output: the terms of quads 0 .. d-1 (zero elsewhere) summed by a tree
+    stq(sm + q * 36, c, acc);
+    __syncthreads();
+    for (uint32_t h = 8; h > 0; h >>= 1) {
+      if (q < h) {
+        acc = quad_add(acc, ldq(sm + (q + h) * 36, c));
+        stq(sm + q * 36, c, acc);
+      }
+      __syncthreads();
+    }
+    if (q != 0) return;
+  }
+  // plus the term of scalar 1 (C2[o], or E2)
+  {
     uint32_t w[16];
-    const uint32_t* P = term_point(C, C2, E, E2, Ej, k, d, o, t);
+    const uint32_t* P = term_point(C, C2, E, E2, Ej, k, d, o, 0);
     ld8w(P, w);
     ld8w(P + 8, w + 8);
     aff a;
-    const bool fin = aff_from_plain_words(w, a);
-    const xyzz p1 = fin ? from_aff(a) : xyzz_inf();
-    const f29 base = quad_coord(p1, c);
-    uint32_t* tt = tab + (size_t)t * TAB_WORDS;
-    stq(tt + 36, c, base);
-    f29 cur = quad_dbl(base);
-    stq(tt + 2 * 36, c, cur);
-    for (uint32_t m = 3; m < 16; m++) {
-      cur = quad_add(cur, base);
-      stq(tt + m * 36, c, cur);
-    }
-  }
-  // Straus: 64 windows of 4 bits from the top
-  f29 acc = f29_zero();
-  for (int32_t win = 63; win >= 0; --win) {
-    if (win != 63) {
-      acc = quad_dbl(acc);
-      acc = quad_dbl(acc);
-      acc = quad_dbl(acc);
-      acc = quad_dbl(acc);
-    }
-    for (uint32_t t = 0; t < nterm; t++) {
-      const uint32_t digit = (sc[t * 8 + (win >> 3)] >> ((win & 7) * 4)) & 15u;
-      if (digit) acc = quad_add(acc, ldq(tab + (size_t)t * TAB_WORDS + digit * 36, c));
-    }
+    if (aff_from_plain_words(w, a)) acc = quad_add(acc, quad_coord(from_aff(a), c));
   }
   xyzz r = quad_gather(acc);
   if (c == 0) {
     force_vgpr(r);
     uint32_t out[16];
     to_affine_words(r, out);
-    uint32_t* dst = o < k ? C_out + (size_t)o * 16 : E_out;
+    uint32_t* dst = err ? E_out : C_out + (size_t)o * 16;
     st8w(dst, out);
     st8w(dst + 8, out + 8);
   }
@@ -258,18 +310,21 @@ __global__ void transcript_kernel(const uint8_t* __restrict__ data, uint64_t byt
 
 }  // namespace
 
+// Waves of the commitment outputs (16 quads each); the error output takes one more.
+static uint32_t acc_commit_waves(uint32_t k) { return (k + 15) / 16; }
+
 size_t acc_fold_g1_scratch_bytes(uint32_t k, uint32_t d) {
   (void)d;
-  return (size_t)(k + 1) * (ACC_MAX_D + 1) * (TAB_WORDS + 8) * 4;
+  return (size_t)(acc_commit_waves(k) + 1) * 16 * 2 * TAB_WORDS * 4;
 }
 
 hipError_t acc_fold_g1(const uint32_t* C, const uint32_t* C2, uint32_t k, const uint32_t* E, const uint32_t* E2,
                        const uint32_t* Ej, uint32_t d, const uint32_t* gamma, uint32_t* C_out, uint32_t* E_out,
                        void* scratch, hipStream_t s) {
-  const uint32_t threads = (k + 1) * 4;
+  const uint32_t nwc = acc_commit_waves(k);
   const ProfToken tok = prof_begin("acc.fold_g1", s);
-  hipLaunchKernelGGL(acc_fold_g1_kernel, dim3((threads + ACC_NT - 1) / ACC_NT), dim3(ACC_NT), 0, s, C, C2, k, E,
-                     E2, Ej, d, gamma, C_out, E_out, static_cast<uint32_t*>(scratch));
+  hipLaunchKernelGGL(acc_fold_g1_kernel, dim3(nwc + 1), dim3(ACC_NT), 0, s, C, C2, k, E, E2, Ej, d, gamma, nwc,
+                     C_out, E_out, static_cast<uint32_t*>(scratch));
   prof_end(tok, s);
   return hipGetLastError();
 }

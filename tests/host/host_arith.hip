@@ -8,6 +8,7 @@
 
 #include "../../paper_2507_07031_amd/csrc/curve.h"
 #include "../../paper_2507_07031_amd/csrc/g2.h"
+#include "../../paper_2507_07031_amd/csrc/glv.h"
 
 using namespace zk;
 
@@ -224,5 +225,33 @@ void host_g2_neg(const uint32_t* pt, uint32_t* out) {
 }
 
 int host_g2_valid(const uint32_t* pt) { return g2_words_valid(pt) ? 1 : 0; }
+
+// k (8 words, < r) -> out: k1 (4 words), k2 (4 words), sign of k1, sign of k2.
+void host_glv_split(const uint32_t* k, uint32_t* out) {
+  uint32_t kk[8], k1[4], k2[4];
+  for (int i = 0; i < 8; i++) kk[i] = k[i];
+  bool n1 = false, n2 = false;
+  glv_split(kk, k1, n1, k2, n2);
+  for (int i = 0; i < 4; i++) {
+    out[i] = k1[i];
+    out[4 + i] = k2[i];
+  }
+  out[8] = n1 ? 1u : 0u;
+  out[9] = n2 ? 1u : 0u;
+}
+
+// The endomorphism as the kernels apply it: X of an XYZZ point times beta
+// (Montgomery product), then affine.  It maps 2P, whose ZZ is not 1, so
+// out = phi(2P).
+void host_glv_phi(const uint32_t* pt, uint32_t* out) {
+  aff a;
+  if (!aff_from_plain_words(pt, a)) {
+    for (int i = 0; i < 16; i++) out[i] = 0;
+    return;
+  }
+  xyzz p = dbl(from_aff(a));  // a point with ZZ != 1
+  p.X = mont_mul<Fq>(p.X, load_mont<Fq>(GlvConst::BETA));
+  to_affine_words(p, out);
+}
 
 }  // extern "C"

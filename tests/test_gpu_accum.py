@@ -73,10 +73,11 @@ def _dev_pts(zk, pts):
 @pytest.mark.parametrize("k,d,len_v,len_e,gkind", [
     (1, 1, 0, 0, "rand"), (3, 2, 5, 4, "rand"), (17, 3, 1000, 257, "rand"), (2, 5, 3, 3, "zero"),
     (5, 4, 7, 9, "one"), (64, 2, 1 << 16, 1 << 12, "rand"),
+    (16, 15, 3, 2, "rand"), (33, 7, 0, 0, "minus1"),
 ])
 def test_acc_fold_exact(zk, k, d, len_v, len_e, gkind):
     seed = 9400 + 7 * k + d
-    gam = {"zero": 0, "one": 1}.get(gkind)
+    gam = {"zero": 0, "one": 1, "minus1": R - 1}.get(gkind)
     if gam is None:
         gam = limbs_to_ints(gen.uniform_fr(seed, 1, tag=8))[0]
     C = _rand_points(seed, k, with_inf=True)

@@ -43,7 +43,7 @@ def lib():
 
 def _sources():
     csrc = os.path.join(os.path.dirname(HERE), "paper_2507_07031_amd", "csrc")
-    return [SRC] + [os.path.join(csrc, f) for f in ("field.h", "curve.h", "field_constants.h", "g2.h")]
+    return [SRC] + [os.path.join(csrc, f) for f in ("field.h", "curve.h", "field_constants.h", "g2.h", "glv.h")]
 
 
 def _w(vals):
@@ -383,3 +383,56 @@ def test_g2_validity_check(lib):
         if found >= 2:
             break
     assert found >= 2
+
+
+def _cube_roots_of_unity(m):
+    """The two primitive cube roots of unity mod a prime m = 1 (mod 3)."""
+    for g in range(2, 200):
+        w = pow(g, (m - 1) // 3, m)
+        if w != 1:
+            return w, w * w % m
+    raise AssertionError("no cube root found")
+
+
+def test_glv_split_identity_and_size(lib):
+    # k = (-1)^n1 k1 + (-1)^n2 k2 lambda (mod r) for one fixed primitive cube
+    # root of unity lambda, with |k1|, |k2| < 2^128
+    rng = np.random.default_rng(41)
+    ks = [0, 1, 2, R - 1, R - 2, (R - 1) // 2, (R + 1) // 2, 1 << 127, (1 << 128) - 1, 1 << 200, 1 << 253]
+    ks += [int.from_bytes(rng.bytes(32), "little") % R for _ in range(3000)]
+    lams = _cube_roots_of_unity(R)
+    ok = {lam: True for lam in lams}
+    for k in ks:
+        kw, kp = _w([k])
+        o, op = _out(10)
+        lib.host_glv_split(kp, op)
+        k1 = limbs_to_ints(np.concatenate([o[:4], np.zeros(4, np.uint32)])[None, :])[0]
+        k2 = limbs_to_ints(np.concatenate([o[4:8], np.zeros(4, np.uint32)])[None, :])[0]
+        assert k1 < (1 << 128) and k2 < (1 << 128)
+        s1 = -k1 if o[8] else k1
+        s2 = -k2 if o[9] else k2
+        for lam in lams:
+            ok[lam] = ok[lam] and (s1 + s2 * lam - k) % R == 0
+    assert sum(ok.values()) == 1, ok
+
+
+def test_glv_endomorphism_is_the_split_lambda(lib):
+    # phi(P) = (beta x, y) equals lambda P for the lambda the split uses
+    lams = _cube_roots_of_unity(R)
+    k = (1 << 200) + 12345  # a scalar whose split has k2 != 0, which singles out lambda
+    kw, kp = _w([k])
+    o, op = _out(10)
+    lib.host_glv_split(kp, op)
+    k1 = limbs_to_ints(np.concatenate([o[:4], np.zeros(4, np.uint32)])[None, :])[0]
+    k2 = limbs_to_ints(np.concatenate([o[4:8], np.zeros(4, np.uint32)])[None, :])[0]
+    s1, s2 = (-k1 if o[8] else k1), (-k2 if o[9] else k2)
+    assert s2 != 0
+    found = [l for l in lams if (s1 + s2 * l - k) % R == 0]
+    assert len(found) == 1
+    lam = found[0]
+    for k in (1, 2, 12345, R - 1):
+        pt = g1.gen_mul(k)
+        a, ap = _pt_words([pt])
+        out, outp = _out(16)
+        lib.host_glv_phi(ap, outp)
+        assert _read_pt(out) == g1.mul(lam, g1.mul(2, pt))  # the entry maps 2P (ZZ != 1)
