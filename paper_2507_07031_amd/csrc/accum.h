@@ -19,6 +19,15 @@ hipError_t acc_fold_g1(const uint32_t* C, const uint32_t* C2, uint32_t k, const 
                        const uint32_t* Ej, uint32_t d, const uint32_t* gamma, uint32_t* C_out, uint32_t* E_out,
                        void* scratch, hipStream_t s);
 
+// out[j] = sum_(i<m) sigma_i P(i, j) for j < k, points P(i, j) at pts[(i k + j) * 16]
+// (canonical plain affine words, (0, 0) = infinity), sigma: m canonical Fr
+// words; every term on its own quad (one scalar multiple's latency), for
+// m <= G1_RLC_TERMS_MAX.  scratch: g1_rlc_scratch_bytes(m, k).
+constexpr uint32_t G1_RLC_TERMS_MAX = 1024;
+size_t g1_rlc_scratch_bytes(uint32_t m, uint32_t k);
+hipError_t g1_rlc(const uint32_t* pts, const uint32_t* sigma, uint32_t m, uint32_t k, uint32_t* out, void* scratch,
+                  hipStream_t s);
+
 // out[i] = v0[i] + sum_(t=1)^(d-1) gamma^t vmid[(t-1) len + i] + gamma^d vlast[i], i < len.
 hipError_t fr_rlc(const uint32_t* v0, const uint32_t* vmid, const uint32_t* vlast, uint32_t d, uint64_t len,
                   const uint32_t* gamma, uint32_t* out, hipStream_t s);

@@ -58,15 +58,64 @@ __device__ __forceinline__ f29 quad_cneg(const f29& v, uint32_t c, bool neg) {
   return (neg && c == 1) ? sub_k(f29_zero(), v, Fq::K4) : v;
 }
 
+// k P on a quad for canonical k < r and a plain affine point P (words;
+// (0, 0) = infinity): k is split by the endomorphism (glv.h),
+// k = +-k1 +- k2 lambda with k1, k2 < 2^128, and k P = (+-k1) P + (+-k2) phi(P)
+// runs as Straus over 32 windows of 4 bits with tables of 1..15 times +-P
+// and +-phi(P) at T1 and T1 + TAB_WORDS, where
+// phi(X, Y, ZZ, ZZZ) = (beta X, Y, ZZ, ZZZ).  Returns lane c's coordinate.
+__device__ f29 glv_quad_mul(const uint32_t (&sw)[8], const uint32_t* __restrict__ P, uint32_t* __restrict__ T1,
+                            uint32_t c) {
+  uint32_t k1[4], k2[4];
+  bool n1, n2;
+  glv_split(sw, k1, n1, k2, n2);
+  uint32_t* T2 = T1 + TAB_WORDS;
+  {
+    uint32_t w[16];
+    ld8w(P, w);
+    ld8w(P + 8, w + 8);
+    aff a;
+    const bool fin = aff_from_plain_words(w, a);
+    const xyzz p1 = fin ? from_aff(a) : xyzz_inf();
+    const f29 base = quad_cneg(quad_coord(p1, c), c, fin && n1);
+    stq(T1 + 36, c, base);
+    f29 cur = quad_dbl(base);
+    stq(T1 + 2 * 36, c, cur);
+    for (uint32_t m = 3; m < 16; m++) {
+      cur = quad_add(cur, base);
+      stq(T1 + m * 36, c, cur);
+    }
+    uint32_t bw[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) bw[i] = GlvConst::BETA[i];
+    const f29 beta = reduce_full<Fq>(to_mont<Fq>(unpack(bw)));
+    for (uint32_t m = 1; m < 16; m++) {
+      f29 v = ldq(T1 + m * 36, c);
+      if (c == 0) v = mont_mul<Fq>(v, beta);
+      stq(T2 + m * 36, c, quad_cneg(v, c, fin && n1 != n2));
+    }
+  }
+  f29 acc = f29_zero();
+  for (int32_t win = 31; win >= 0; --win) {
+    if (win != 31) {
+      acc = quad_dbl(acc);
+      acc = quad_dbl(acc);
+      acc = quad_dbl(acc);
+      acc = quad_dbl(acc);
+    }
+    const uint32_t d1 = (k1[win >> 3] >> ((win & 7) * 4)) & 15u;
+    const uint32_t d2 = (k2[win >> 3] >> ((win & 7) * 4)) & 15u;
+    if (d1) acc = quad_add(acc, ldq(T1 + d1 * 36, c));
+    if (d2) acc = quad_add(acc, ldq(T2 + d2 * 36, c));
+  }
+  return acc;
+}
+
 // One quad per (output, term) whose scalar gamma^t is not 1, all at once:
 // quad q of wave w < nwc computes gamma C[16 w + q] for output 16 w + q < k,
 // and quad q of the last wave gamma^(q+1) P_(q+1) of the error output for
-// q < d.  Each scalar is split by the endomorphism (glv.h),
-// k = +-k1 +- k2 lambda with k1, k2 < 2^128, and k P = (+-k1) P + (+-k2) phi(P)
-// runs as Straus over 32 windows of 4 bits with the tables of 1..15 times
-// +-P and +-phi(P), where phi(X, Y, ZZ, ZZZ) = (beta X, Y, ZZ, ZZZ).  The term
-// of scalar 1 is added to the result; the error output's quads first sum
-// their terms in LDS.
+// q < d (glv_quad_mul).  The term of scalar 1 is added to the result; the
+// error output's quads first sum their terms in LDS.
 __global__ __launch_bounds__(ACC_NT) void acc_fold_g1_kernel(const uint32_t* __restrict__ C,
                                                              const uint32_t* __restrict__ C2, uint32_t k,
                                                              const uint32_t* __restrict__ E,
@@ -94,51 +143,8 @@ __global__ __launch_bounds__(ACC_NT) void acc_fold_g1_kernel(const uint32_t* __r
       for (uint32_t i = 1; i < t; i++) p = reduce_full<FrP>(mont_mul<FrP>(p, gm));
       pack(from_mont<FrP>(p), sw);
     }
-    uint32_t k1[4], k2[4];
-    bool n1, n2;
-    glv_split(sw, k1, n1, k2, n2);
-    // tables: T1[m] = m (+-P), T2[m] = m (+-phi(P)), m = 1..15
-    uint32_t* T1 = scratch + ((size_t)wave * 16 + q) * 2 * TAB_WORDS;
-    uint32_t* T2 = T1 + TAB_WORDS;
-    {
-      uint32_t w[16];
-      const uint32_t* P = term_point(C, C2, E, E2, Ej, k, d, o, t);
-      ld8w(P, w);
-      ld8w(P + 8, w + 8);
-      aff a;
-      const bool fin = aff_from_plain_words(w, a);
-      const xyzz p1 = fin ? from_aff(a) : xyzz_inf();
-      const f29 base = quad_cneg(quad_coord(p1, c), c, fin && n1);
-      stq(T1 + 36, c, base);
-      f29 cur = quad_dbl(base);
-      stq(T1 + 2 * 36, c, cur);
-      for (uint32_t m = 3; m < 16; m++) {
-        cur = quad_add(cur, base);
-        stq(T1 + m * 36, c, cur);
-      }
-      uint32_t bw[8];
-#pragma unroll
-      for (int i = 0; i < 8; i++) bw[i] = GlvConst::BETA[i];
-      const f29 beta = reduce_full<Fq>(to_mont<Fq>(unpack(bw)));
-      for (uint32_t m = 1; m < 16; m++) {
-        f29 v = ldq(T1 + m * 36, c);
-        if (c == 0) v = mont_mul<Fq>(v, beta);
-        stq(T2 + m * 36, c, quad_cneg(v, c, fin && n1 != n2));
-      }
-    }
-    // Straus over both halves: 32 windows of 4 bits from the top
-    for (int32_t win = 31; win >= 0; --win) {
-      if (win != 31) {
-        acc = quad_dbl(acc);
-        acc = quad_dbl(acc);
-        acc = quad_dbl(acc);
-        acc = quad_dbl(acc);
-      }
-      const uint32_t d1 = (k1[win >> 3] >> ((win & 7) * 4)) & 15u;
-      const uint32_t d2 = (k2[win >> 3] >> ((win & 7) * 4)) & 15u;
-      if (d1) acc = quad_add(acc, ldq(T1 + d1 * 36, c));
-      if (d2) acc = quad_add(acc, ldq(T2 + d2 * 36, c));
-    }
+    acc = glv_quad_mul(sw, term_point(C, C2, E, E2, Ej, k, d, o, t),
+                       scratch + ((size_t)wave * 16 + q) * 2 * TAB_WORDS, c);
   }
   if (!err) {
     if (!active) return;  // whole quads leave together
@@ -172,6 +178,63 @@ __global__ __launch_bounds__(ACC_NT) void acc_fold_g1_kernel(const uint32_t* __r
     uint32_t* dst = err ? E_out : C_out + (size_t)o * 16;
     st8w(dst, out);
     st8w(dst + 8, out + 8);
+  }
+}
+
+// Linear combination of m points per component by per-term scalar multiples:
+// block (b, j) computes sigma_i P_(i, j) for its 64 terms i = 64 b + q on
+// quads q (glv_quad_mul) and sums them by an LDS tree into partial (b, j);
+// the finishing kernel sums a component's partials and writes it affine.
+constexpr uint32_t RLC_TERMS_NT = 256;  // 64 quads
+__global__ __launch_bounds__(RLC_TERMS_NT) void g1_rlc_terms_kernel(const uint32_t* __restrict__ pts,
+                                                                    const uint32_t* __restrict__ sigma, uint32_t m,
+                                                                    uint32_t k, uint32_t* __restrict__ tabs,
+                                                                    uint32_t* __restrict__ partial) {
+  __shared__ uint32_t sm[64 * 36];
+  const uint32_t b = blockIdx.x, j = blockIdx.y, q = threadIdx.x >> 2, c = quad_lane();
+  const uint32_t i = b * 64 + q;
+  const size_t slot = (size_t)j * gridDim.x + b;
+  f29 acc = f29_zero();
+  if (i < m) {  // uniform over each quad
+    uint32_t sw[8];
+    ld8w(sigma + (size_t)i * 8, sw);
+    acc = glv_quad_mul(sw, pts + ((size_t)i * k + j) * 16, tabs + (slot * 64 + q) * 2 * TAB_WORDS, c);
+  }
+  stq(sm + q * 36, c, acc);
+  __syncthreads();
+  for (uint32_t h = 32; h > 0; h >>= 1) {
+    if (q < h) {
+      acc = quad_add(acc, ldq(sm + (q + h) * 36, c));
+      stq(sm + q * 36, c, acc);
+    }
+    __syncthreads();
+  }
+  if (q == 0) stq(partial + slot * 36, c, acc);
+}
+
+__global__ __launch_bounds__(64) void g1_rlc_finish_kernel(const uint32_t* __restrict__ partial, uint32_t nblk,
+                                                          uint32_t* __restrict__ out) {
+  __shared__ uint32_t sm[16 * 36];
+  const uint32_t j = blockIdx.x, q = threadIdx.x >> 2, c = quad_lane();
+  f29 acc = f29_zero();
+  for (uint32_t b = q; b < nblk; b += 16) acc = quad_add(acc, ldq(partial + ((size_t)j * nblk + b) * 36, c));
+  stq(sm + q * 36, c, acc);
+  __syncthreads();
+  for (uint32_t h = 8; h > 0; h >>= 1) {
+    if (q < h) {
+      acc = quad_add(acc, ldq(sm + (q + h) * 36, c));
+      stq(sm + q * 36, c, acc);
+    }
+    __syncthreads();
+  }
+  if (q != 0) return;
+  xyzz r = quad_gather(acc);
+  if (c == 0) {
+    force_vgpr(r);
+    uint32_t o[16];
+    to_affine_words(r, o);
+    st8w(out + (size_t)j * 16, o);
+    st8w(out + (size_t)j * 16 + 8, o + 8);
   }
 }
 
@@ -325,6 +388,24 @@ hipError_t acc_fold_g1(const uint32_t* C, const uint32_t* C2, uint32_t k, const 
   const ProfToken tok = prof_begin("acc.fold_g1", s);
   hipLaunchKernelGGL(acc_fold_g1_kernel, dim3(nwc + 1), dim3(ACC_NT), 0, s, C, C2, k, E, E2, Ej, d, gamma, nwc,
                      C_out, E_out, static_cast<uint32_t*>(scratch));
+  prof_end(tok, s);
+  return hipGetLastError();
+}
+
+size_t g1_rlc_scratch_bytes(uint32_t m, uint32_t k) {
+  const size_t nblk = (m + 63) / 64;
+  return (size_t)k * nblk * 64 * 2 * TAB_WORDS * 4 + (size_t)k * nblk * 36 * 4;
+}
+
+hipError_t g1_rlc(const uint32_t* pts, const uint32_t* sigma, uint32_t m, uint32_t k, uint32_t* out, void* scratch,
+                  hipStream_t s) {
+  if (m == 0 || k == 0 || m > G1_RLC_TERMS_MAX) return hipErrorInvalidValue;
+  const uint32_t nblk = (m + 63) / 64;
+  uint32_t* tabs = static_cast<uint32_t*>(scratch);
+  uint32_t* partial = tabs + (size_t)k * nblk * 64 * 2 * TAB_WORDS;
+  const ProfToken tok = prof_begin("fold.terms", s);
+  hipLaunchKernelGGL(g1_rlc_terms_kernel, dim3(nblk, k), dim3(RLC_TERMS_NT), 0, s, pts, sigma, m, k, tabs, partial);
+  hipLaunchKernelGGL(g1_rlc_finish_kernel, dim3(k), dim3(64), 0, s, partial, nblk, out);
   prof_end(tok, s);
   return hipGetLastError();
 }

@@ -1186,13 +1186,23 @@ zk_status zk_fold(const zk_g1* inst, const zk_fr* gammas, uint32_t m, uint32_t k
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
   if ((st = check_inputs(c, s, {{inst, (uint64_t)m * k, true}, {gammas, m - 1ull, false}}, "zk_fold"))) return st;
+  // few instances: every term sigma_i C_i on its own quad (the latency of one
+  // scalar multiple); many: one Pippenger MSM per component
+  const bool per_term = m <= G1_RLC_TERMS_MAX && (uint64_t)m * k <= (1u << 16);
   Scratch ws;
-  st = scratch_alloc(ws, (size_t)m * (32 + 64 + 64) + 512, s);
+  const size_t sig_bytes = ((size_t)m * 32 + 255) / 256 * 256;
+  st = scratch_alloc(ws, per_term ? sig_bytes + g1_rlc_scratch_bytes(m, k) : (size_t)m * (32 + 64 + 64) + 512, s);
   if (st) return st;
   uint32_t* sigma = static_cast<uint32_t*>(ws.p);
+  ZK_HIP(fold_sigmas(reinterpret_cast<const uint32_t*>(gammas), m, sigma, s), "fold sigmas");
+  if (per_term) {
+    ZK_HIP(g1_rlc(reinterpret_cast<const uint32_t*>(inst), sigma, m, k, reinterpret_cast<uint32_t*>(out),
+                  static_cast<char*>(ws.p) + sig_bytes, s),
+           "fold terms");
+    return ZK_OK;
+  }
   uint32_t* col = sigma + (size_t)m * 8;
   uint32_t* mont = col + (size_t)m * 16;
-  ZK_HIP(fold_sigmas(reinterpret_cast<const uint32_t*>(gammas), m, sigma, s), "fold sigmas");
   const MsmPlan plan = msm_plan_generic(m, msm_default_c(m));
   for (uint32_t j = 0; j < k; j++) {
     ZK_HIP(gather_component(reinterpret_cast<const uint32_t*>(inst), m, k, j, col, s), "fold gather");

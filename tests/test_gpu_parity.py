@@ -389,7 +389,10 @@ def test_msm_batch_quantized_segments(zk, tau, srs_big):
 
 # ------------------------------------------------------------------ fold
 
-@pytest.mark.parametrize("m,k", [(1, 1), (2, 3), (3, 1), (5, 2), (64, 1)])
+# per-term path up to 1024 instances and 2^16 points (one block of 64 terms,
+# several, and the limit), Pippenger beyond either bound
+@pytest.mark.parametrize("m,k", [(1, 1), (2, 3), (3, 1), (5, 2), (64, 1), (65, 2), (1024, 1), (1025, 1),
+                                 (300, 250)])
 def test_fold_matches_tree(zk, tau, srs_big, m, k):
     pts, _ = srs_big
     t = tau[1]
@@ -407,6 +410,24 @@ def test_fold_matches_tree(zk, tau, srs_big, m, k):
     if m <= 5:
         inst_pts = [[osrs.srs_point(t, idx[i * k + j]) for j in range(k)] for i in range(m)]
         assert out == ofold.tree_fold(inst_pts, gv)
+
+
+def test_fold_with_points_at_infinity(zk, tau, srs_big):
+    pts, _ = srs_big
+    t = tau[1]
+    m, k = 6, 2
+    idx = [5 + 3 * i for i in range(m * k)]
+    host = zk.to_host(pts[idx].contiguous()).reshape(m * k, 16).copy()
+    zero = {1, 4, 11}  # (0, 0) entries
+    host[list(zero)] = 0
+    inst = zk.to_device(host).reshape(m, k, 16)
+    gam = gen.uniform_fr(1077, m - 1)
+    log("fold with infinity entries")
+    out = points_from_host(_host(zk, zk.fold(inst, _dev(zk, gam))))
+    sig = ofold.flat_coefficients(m, fr_from_host(gam))
+    for j in range(k):
+        logsum = sum(sig[i] * pow(t, idx[i * k + j], R) for i in range(m) if i * k + j not in zero) % R
+        assert out[j] == g1.gen_mul(logsum), j
 
 
 # ------------------------------------------------------------------ input validation
