@@ -328,32 +328,75 @@ __device__ __forceinline__ void sha256_block(uint32_t h[8], const uint32_t blk[1
   h[0] += a; h[1] += b; h[2] += c; h[3] += d; h[4] += e; h[5] += f; h[6] += g; h[7] += hh;
 }
 
-// Both messages 0x00 || data and 0x01 || data have the same padded layout;
-// per 64-byte block, lanes 0..15 assemble the big-endian words in LDS and
-// lanes 0 and 1 compress them for prefix 0 and 1 (lane 1 patches the prefix
-// byte of the first word).  Lane 0 then reduces the 512-bit little-endian
-// concatenation of the two digests modulo r.
+// Compression of one block from its full 64-word message schedule.
+__device__ __forceinline__ void sha256_rounds(uint32_t h[8], const uint32_t* __restrict__ W) {
+  uint32_t a = h[0], b = h[1], c = h[2], d = h[3], e = h[4], f = h[5], g = h[6], hh = h[7];
+#pragma unroll
+  for (int t = 0; t < 64; t++) {
+    const uint32_t S1 = rotr(e, 6) ^ rotr(e, 11) ^ rotr(e, 25);
+    const uint32_t ch = (e & f) ^ (~e & g);
+    const uint32_t t1 = hh + S1 + ch + SHA_K[t] + W[t];
+    const uint32_t S0 = rotr(a, 2) ^ rotr(a, 13) ^ rotr(a, 22);
+    const uint32_t mj = (a & b) ^ (a & c) ^ (b & c);
+    hh = g;
+    g = f;
+    f = e;
+    e = d + t1;
+    d = c;
+    c = b;
+    b = a;
+    a = t1 + S0 + mj;
+  }
+  h[0] += a; h[1] += b; h[2] += c; h[3] += d; h[4] += e; h[5] += f; h[6] += g; h[7] += hh;
+}
+
+// Both messages 0x00 || data and 0x01 || data have the same padded layout
+// and differ only in their first byte.  For 64 blocks at a time, lane b
+// gathers block b's big-endian words and expands its message schedule into
+// LDS; lanes 0 and 1 then run the rounds for prefix 0 and 1, the sequential
+// part.  Block 0 is compressed inline by each of the two lanes with its own
+// first byte.  Lane 0 then reduces the 512-bit little-endian concatenation
+// of the two digests modulo r.
+constexpr uint32_t TR_CHUNK = 64;  // blocks prepared per round of the 64 lanes
 __global__ void transcript_kernel(const uint8_t* __restrict__ data, uint64_t bytes, f29 c_2_256,
                                   uint32_t* __restrict__ out) {
-  __shared__ uint32_t blk[16];
+  __shared__ uint32_t Wsh[TR_CHUNK * 64];
   __shared__ uint32_t dig[2][8];
   const uint32_t lane = threadIdx.x;
   const uint64_t L = bytes + 1;
   const uint64_t total = ((L + 8) / 64 + 1) * 64;
+  const uint64_t nblk = total / 64;
   uint32_t h[8];
   for (int i = 0; i < 8; i++) h[i] = SHA_H0[i];
-  for (uint64_t base = 0; base < total; base += 64) {
-    if (lane < 16) {
-      uint32_t v = 0;
-      for (int q = 0; q < 4; q++) v = (v << 8) | msg_byte(data, bytes, 0, total, base + 4 * lane + q);
-      blk[lane] = v;
+  for (uint64_t c0 = 0; c0 < nblk; c0 += TR_CHUNK) {
+    const uint64_t bi = c0 + lane;
+    if (lane < TR_CHUNK && bi < nblk) {
+      uint32_t* W = Wsh + lane * 64;
+      for (int t = 0; t < 16; t++) {
+        uint32_t v = 0;
+        for (int q = 0; q < 4; q++) v = (v << 8) | msg_byte(data, bytes, 0, total, bi * 64 + 4 * t + q);
+        W[t] = v;
+      }
+      for (int t = 16; t < 64; t++) {
+        const uint32_t w15 = W[t - 15], w2 = W[t - 2];
+        const uint32_t s0 = rotr(w15, 7) ^ rotr(w15, 18) ^ (w15 >> 3);
+        const uint32_t s1 = rotr(w2, 17) ^ rotr(w2, 19) ^ (w2 >> 10);
+        W[t] = W[t - 16] + s0 + W[t - 7] + s1;
+      }
     }
     __syncthreads();
     if (lane < 2) {
-      uint32_t w[16];
-      for (int t = 0; t < 16; t++) w[t] = blk[t];
-      if (base == 0) w[0] = (w[0] & 0x00ffffffu) | (lane << 24);
-      sha256_block(h, w);
+      const uint64_t n = min((uint64_t)TR_CHUNK, nblk - c0);
+      for (uint64_t b = 0; b < n; b++) {
+        if (c0 + b == 0) {
+          uint32_t w[16];
+          for (int t = 0; t < 16; t++) w[t] = Wsh[t];
+          w[0] = (w[0] & 0x00ffffffu) | (lane << 24);
+          sha256_block(h, w);
+        } else {
+          sha256_rounds(h, Wsh + b * 64);
+        }
+      }
     }
     __syncthreads();
   }
