@@ -52,6 +52,17 @@ __device__ __forceinline__ const uint32_t* term_point(const uint32_t* C, const u
   return Ej + (size_t)(t - 1) * 16;
 }
 
+// Lane c's coordinate of an affine point in XYZZ form on a quad (x, y, 1, 1;
+// all zero for infinity), selected limb by limb so that no copy of the
+// whole point is indexed by the lane number.
+__device__ __forceinline__ f29 quad_aff_coord(const aff& a, bool fin, uint32_t c) {
+  const f29 one = f29_from(Fq::ONE);
+  f29 r;
+#pragma unroll
+  for (int i = 0; i < 9; i++) r.l[i] = !fin ? 0u : c == 0 ? a.x.l[i] : c == 1 ? a.y.l[i] : one.l[i];
+  return r;
+}
+
 // Coordinate c of a point held by a quad, negated when neg is set (the y
 // coordinate, lane 1): 4q - Y keeps the coordinate bounds of the formulas.
 __device__ __forceinline__ f29 quad_cneg(const f29& v, uint32_t c, bool neg) {
@@ -64,7 +75,8 @@ __device__ __forceinline__ f29 quad_cneg(const f29& v, uint32_t c, bool neg) {
 // runs as Straus over 32 windows of 4 bits with tables of 1..15 times +-P
 // and +-phi(P) at T1 and T1 + TAB_WORDS, where
 // phi(X, Y, ZZ, ZZZ) = (beta X, Y, ZZ, ZZZ).  Returns lane c's coordinate.
-__device__ f29 glv_quad_mul(const uint32_t (&sw)[8], const uint32_t* __restrict__ P, uint32_t* __restrict__ T1,
+__device__ __forceinline__ f29 glv_quad_mul(const uint32_t (&sw)[8], const uint32_t* __restrict__ P,
+                                            uint32_t* __restrict__ T1,
                             uint32_t c) {
   uint32_t k1[4], k2[4];
   bool n1, n2;
@@ -76,8 +88,7 @@ __device__ f29 glv_quad_mul(const uint32_t (&sw)[8], const uint32_t* __restrict_
     ld8w(P + 8, w + 8);
     aff a;
     const bool fin = aff_from_plain_words(w, a);
-    const xyzz p1 = fin ? from_aff(a) : xyzz_inf();
-    const f29 base = quad_cneg(quad_coord(p1, c), c, fin && n1);
+    const f29 base = quad_cneg(quad_aff_coord(a, fin, c), c, fin && n1);
     stq(T1 + 36, c, base);
     f29 cur = quad_dbl(base);
     stq(T1 + 2 * 36, c, cur);
@@ -95,18 +106,24 @@ __device__ f29 glv_quad_mul(const uint32_t (&sw)[8], const uint32_t* __restrict_
       stq(T2 + m * 36, c, quad_cneg(v, c, fin && n1 != n2));
     }
   }
+  // windows from the top: word wi of each half (constant after unrolling,
+  // so the halves stay in registers), eight 4-bit digits per word
   f29 acc = f29_zero();
-  for (int32_t win = 31; win >= 0; --win) {
-    if (win != 31) {
-      acc = quad_dbl(acc);
-      acc = quad_dbl(acc);
-      acc = quad_dbl(acc);
-      acc = quad_dbl(acc);
+#pragma unroll
+  for (int wi = 3; wi >= 0; --wi) {
+    const uint32_t w1 = k1[wi], w2 = k2[wi];
+    for (int sub = 7; sub >= 0; --sub) {
+      if (wi != 3 || sub != 7) {
+        acc = quad_dbl(acc);
+        acc = quad_dbl(acc);
+        acc = quad_dbl(acc);
+        acc = quad_dbl(acc);
+      }
+      const uint32_t d1 = (w1 >> (sub * 4)) & 15u;
+      const uint32_t d2 = (w2 >> (sub * 4)) & 15u;
+      if (d1) acc = quad_add(acc, ldq(T1 + d1 * 36, c));
+      if (d2) acc = quad_add(acc, ldq(T2 + d2 * 36, c));
     }
-    const uint32_t d1 = (k1[win >> 3] >> ((win & 7) * 4)) & 15u;
-    const uint32_t d2 = (k2[win >> 3] >> ((win & 7) * 4)) & 15u;
-    if (d1) acc = quad_add(acc, ldq(T1 + d1 * 36, c));
-    if (d2) acc = quad_add(acc, ldq(T2 + d2 * 36, c));
   }
   return acc;
 }
@@ -168,7 +185,7 @@ __global__ __launch_bounds__(ACC_NT) void acc_fold_g1_kernel(const uint32_t* __r
     ld8w(P, w);
     ld8w(P + 8, w + 8);
     aff a;
-    if (aff_from_plain_words(w, a)) acc = quad_add(acc, quad_coord(from_aff(a), c));
+    if (aff_from_plain_words(w, a)) acc = quad_add(acc, quad_aff_coord(a, true, c));
   }
   xyzz r = quad_gather(acc);
   if (c == 0) {
@@ -183,13 +200,15 @@ __global__ __launch_bounds__(ACC_NT) void acc_fold_g1_kernel(const uint32_t* __r
 
 // Linear combination of m points per component by per-term scalar multiples:
 // block (b, j) computes sigma_i P_(i, j) for its 64 terms i = 64 b + q on
-// quads q (glv_quad_mul) and sums them by an LDS tree into partial (b, j);
-// the finishing kernel sums a component's partials and writes it affine.
+// quads q (glv_quad_mul) and sums them by an LDS tree into partial (b, j),
+// or, with one workgroup per component, writes the sum affine itself; the
+// finishing kernel sums a component's partials and writes it affine.
 constexpr uint32_t RLC_TERMS_NT = 256;  // 64 quads
 __global__ __launch_bounds__(RLC_TERMS_NT) void g1_rlc_terms_kernel(const uint32_t* __restrict__ pts,
                                                                     const uint32_t* __restrict__ sigma, uint32_t m,
                                                                     uint32_t k, uint32_t* __restrict__ tabs,
-                                                                    uint32_t* __restrict__ partial) {
+                                                                    uint32_t* __restrict__ partial,
+                                                                    uint32_t* __restrict__ out) {
   __shared__ uint32_t sm[64 * 36];
   const uint32_t b = blockIdx.x, j = blockIdx.y, q = threadIdx.x >> 2, c = quad_lane();
   const uint32_t i = b * 64 + q;
@@ -209,7 +228,20 @@ __global__ __launch_bounds__(RLC_TERMS_NT) void g1_rlc_terms_kernel(const uint32
     }
     __syncthreads();
   }
-  if (q == 0) stq(partial + slot * 36, c, acc);
+  if (q != 0) return;
+  if (!out) {
+    stq(partial + slot * 36, c, acc);
+    return;
+  }
+  // a single workgroup per component: the sum is final, written affine here
+  xyzz r = quad_gather(acc);
+  if (c == 0) {
+    force_vgpr(r);
+    uint32_t o[16];
+    to_affine_words(r, o);
+    st8w(out + (size_t)j * 16, o);
+    st8w(out + (size_t)j * 16 + 8, o + 8);
+  }
 }
 
 __global__ __launch_bounds__(64) void g1_rlc_finish_kernel(const uint32_t* __restrict__ partial, uint32_t nblk,
@@ -447,8 +479,9 @@ hipError_t g1_rlc(const uint32_t* pts, const uint32_t* sigma, uint32_t m, uint32
   uint32_t* tabs = static_cast<uint32_t*>(scratch);
   uint32_t* partial = tabs + (size_t)k * nblk * 64 * 2 * TAB_WORDS;
   const ProfToken tok = prof_begin("fold.terms", s);
-  hipLaunchKernelGGL(g1_rlc_terms_kernel, dim3(nblk, k), dim3(RLC_TERMS_NT), 0, s, pts, sigma, m, k, tabs, partial);
-  hipLaunchKernelGGL(g1_rlc_finish_kernel, dim3(k), dim3(64), 0, s, partial, nblk, out);
+  hipLaunchKernelGGL(g1_rlc_terms_kernel, dim3(nblk, k), dim3(RLC_TERMS_NT), 0, s, pts, sigma, m, k, tabs, partial,
+                     nblk == 1 ? out : nullptr);
+  if (nblk > 1) hipLaunchKernelGGL(g1_rlc_finish_kernel, dim3(k), dim3(64), 0, s, partial, nblk, out);
   prof_end(tok, s);
   return hipGetLastError();
 }

@@ -1088,17 +1088,28 @@ zk_status zk_acc_fold(uint32_t k, const zk_g1* C, const zk_g1* C2, uint32_t d, c
   Scratch ws;
   if ((st = scratch_alloc(ws, acc_fold_g1_scratch_bytes(k, d), s))) return st;
   const uint32_t* gw = reinterpret_cast<const uint32_t*>(gamma);
+  // the Fr parts (HBM streams) run on the companion stream beside the G1
+  // part (a few waves of dependent point operations); the caller's stream
+  // waits for both
+  hipStream_t side = nullptr;
+  if ((st = side_stream(s, &side))) return st;
+  SyncEvents ev;
+  if ((st = sync_events(ev))) return st;
+  ZK_HIP(hipEventRecord(ev.e[0], s), "hipEventRecord");
+  ZK_HIP(hipStreamWaitEvent(side, ev.e[0], 0), "hipStreamWaitEvent");
+  ZK_HIP(fr_rlc(reinterpret_cast<const uint32_t*>(v2), nullptr, reinterpret_cast<const uint32_t*>(v), 1, len_v, gw,
+                reinterpret_cast<uint32_t*>(v_out), side),
+         "acc fold fr");
+  ZK_HIP(fr_rlc(reinterpret_cast<const uint32_t*>(e2), reinterpret_cast<const uint32_t*>(ej),
+                reinterpret_cast<const uint32_t*>(e), d, len_e, gw, reinterpret_cast<uint32_t*>(e_out), side),
+         "acc fold errors");
   ZK_HIP(acc_fold_g1(reinterpret_cast<const uint32_t*>(C), reinterpret_cast<const uint32_t*>(C2), k,
                      reinterpret_cast<const uint32_t*>(E), reinterpret_cast<const uint32_t*>(E2),
                      reinterpret_cast<const uint32_t*>(Ej), d, gw, reinterpret_cast<uint32_t*>(C_out),
                      reinterpret_cast<uint32_t*>(E_out), ws.p, s),
          "acc fold g1");
-  ZK_HIP(fr_rlc(reinterpret_cast<const uint32_t*>(v2), nullptr, reinterpret_cast<const uint32_t*>(v), 1, len_v, gw,
-                reinterpret_cast<uint32_t*>(v_out), s),
-         "acc fold fr");
-  ZK_HIP(fr_rlc(reinterpret_cast<const uint32_t*>(e2), reinterpret_cast<const uint32_t*>(ej),
-                reinterpret_cast<const uint32_t*>(e), d, len_e, gw, reinterpret_cast<uint32_t*>(e_out), s),
-         "acc fold errors");
+  ZK_HIP(hipEventRecord(ev.e[1], side), "hipEventRecord");
+  ZK_HIP(hipStreamWaitEvent(s, ev.e[1], 0), "hipStreamWaitEvent");
   return ZK_OK;
 }
 
