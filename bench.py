@@ -328,27 +328,6 @@ def main():
                            "int_tops": round(mads / (t_ms / 1e3) / 1e12, 3),
                            "int_frac": round(mads / (t_ms / 1e3) / 1e12 / PEAK_MAD_TOPS, 4),
                            "bound": "alu"}
-        # the largest transform, 2^28 points (three LDS passes): a dense input
-        # of canonical values (top word cut to 29 bits, below r's)
-        log("ntt 2^28")
-        N28 = 1 << 28
-        big = torch.randint(-2 ** 31, 2 ** 31 - 1, (N28, 8), dtype=torch.int32, device="cuda")
-        big[:, 7] &= 0x1FFFFFFF
-        big_out = torch.empty_like(big)
-        t28 = timed(lambda: zk.ntt(big, out=big_out), reps=5)
-        t28i = timed(lambda: zk.intt(big_out, out=big), reps=5)
-        for name, t_ms in (("ntt_2^28", t28), ("intt_2^28", t28i)):
-            hbm_bytes = 3 * 2 * 32 * N28
-            mads = (N28 // 2) * 28 * MADS_PER_MONT
-            roofs[name] = {"ms": round(t_ms, 4), "passes": 3,
-                           "hbm_gbs": round(hbm_bytes / (t_ms / 1e3) / 1e9, 1),
-                           "hbm_frac": round(hbm_bytes / (t_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
-                           "int_tops": round(mads / (t_ms / 1e3) / 1e12, 3),
-                           "int_frac": round(mads / (t_ms / 1e3) / 1e12 / PEAK_MAD_TOPS, 4),
-                           "bound": "alu"}
-        del big, big_out
-        torch.cuda.empty_cache()
-        zk.release_cached_memory()
         extras["ntt_rooflines"] = roofs
 
         # per-step latency distribution of the commit job (each step bracketed
@@ -390,6 +369,16 @@ def main():
                 def run_open():
                     zk.kzg_open_batch(srs, polys, xw, gw, ys=ys8, proof=pi)
             t_open = timed(run_open, reps=10)
+            # each call bracketed by its own events: shows whether time above
+            # the kernels' sum sits in every call or in a few
+            per_call = []
+            for _ in range(10):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                run_open()
+                e1.record()
+                torch.cuda.synchronize()
+                per_call.append(e0.elapsed_time(e1))
             for reg in ("open.scan", "msm.sort", "msm.accumulate", "msm.reduce"):
                 zk.profile_read(reg)
             zk.profile_enable(True)
@@ -404,6 +393,8 @@ def main():
             products = (2 * m_open - 1) * n
             kzg["open_m%d" % m_open] = {
                 "polys": m_open, "coeffs": n, "ms": round(t_open, 4), "openings_per_s": round(1e3 / t_open, 2),
+                "call_ms_median": round(float(np.median(per_call)), 4),
+                "call_ms_min": round(float(np.min(per_call)), 4), "call_ms_max": round(float(np.max(per_call)), 4),
                 "scan_ms": round(scan_ms, 4), "msm_ms_profiled": round(msm_ms, 4),
                 "scan_hbm_gbs": round(alg_bytes / (scan_ms / 1e3) / 1e9, 1),
                 "scan_hbm_frac": round(alg_bytes / (scan_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
@@ -569,6 +560,29 @@ def main():
 
         log("serving")
         extras["serving"] = serving_runs(zk, srs, args.serve_jobs)
+        # the largest transform, 2^28 points (three LDS passes), on a dense
+        # input of canonical values (top word cut to 29 bits, below r's); run
+        # last, so that no other timed section follows the release of its
+        # 24 GB of buffers
+        log("ntt 2^28")
+        N28 = 1 << 28
+        big = torch.randint(-2 ** 31, 2 ** 31 - 1, (N28, 8), dtype=torch.int32, device="cuda")
+        big[:, 7] &= 0x1FFFFFFF
+        big_out = torch.empty_like(big)
+        t28 = timed(lambda: zk.ntt(big, out=big_out), reps=5)
+        t28i = timed(lambda: zk.intt(big_out, out=big), reps=5)
+        for name, t_ms in (("ntt_2^28", t28), ("intt_2^28", t28i)):
+            hbm_bytes = 3 * 2 * 32 * N28
+            mads = (N28 // 2) * 28 * MADS_PER_MONT
+            extras["ntt_rooflines"][name] = {"ms": round(t_ms, 4), "passes": 3,
+                                             "hbm_gbs": round(hbm_bytes / (t_ms / 1e3) / 1e9, 1),
+                                             "hbm_frac": round(hbm_bytes / (t_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+                                             "int_tops": round(mads / (t_ms / 1e3) / 1e12, 3),
+                                             "int_frac": round(mads / (t_ms / 1e3) / 1e12 / PEAK_MAD_TOPS, 4),
+                                             "bound": "alu"}
+        del big, big_out
+        torch.cuda.empty_cache()
+        zk.release_cached_memory()
 
     cpu = None
     if not args.no_cpu_baseline:
