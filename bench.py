@@ -15,6 +15,8 @@ Printed as one JSON line, with
   recorded by the library on its launch stream over the timed region,
 * a Poisson stream of commit jobs (2^10..2^22 points) through the serving
   loop: p50 / p99 latency and jobs/s, continuous admission vs serial,
+* the same job with its host transfers (evaluations in from pinned memory,
+  commitment back), beside the device-resident figure,
 * `cpu_baseline`: the CPU oracle on a bounded sample of the same job.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -344,6 +346,68 @@ def main():
         extras["step_latency_ms"] = {"median": round(float(np.median(lat)), 4),
                                      "p90": round(float(np.percentile(lat, 90)), 4),
                                      "min": round(float(lat.min()), 4), "reps": int(lat.size)}
+
+        log("commit job with host transfers")
+        # end to end with the host transfers: the 2^20 evaluations copied in
+        # from pinned host memory, the commit job, the commitment copied back
+        # (the coset evaluations stay resident for the next prover step);
+        # reported beside the device-resident figure, never in its place
+        ev_pin = torch.empty(evals.shape, dtype=torch.int32, pin_memory=True)
+        ev_pin.copy_(evals.cpu())
+        com_pin = torch.empty(com.shape, dtype=torch.int32, pin_memory=True)
+        evals_in = torch.empty_like(evals)
+        com_ref = com.clone()
+
+        def e2e():
+            evals_in.copy_(ev_pin, non_blocking=True)
+            zk.commit_job(srs, evals_in, log_blowup=2, coeffs=coeffs, com=com, coset=coset)
+            com_pin.copy_(com, non_blocking=True)
+
+        t_e2e = timed(e2e, reps=20)
+        same = bool(torch.equal(com_pin, com_ref.cpu()))
+        t_h2d = timed(lambda: evals_in.copy_(ev_pin, non_blocking=True), reps=20)
+
+        # a stream of such jobs: the next job's evaluations are copied in on a
+        # copy stream (default priority) while the current job computes, into
+        # one of two input buffers
+        copy_s = torch.cuda.Stream()
+        main_s = torch.cuda.current_stream()
+        bufs = [evals_in, torch.empty_like(evals)]
+        ready = [torch.cuda.Event(), torch.cuda.Event()]
+        free = [torch.cuda.Event(), torch.cuda.Event()]
+        coms = torch.empty((2, 16), dtype=torch.int32, pin_memory=True)
+
+        def copy_in(k):
+            with torch.cuda.stream(copy_s):
+                if k >= 2:
+                    copy_s.wait_event(free[k % 2])
+                bufs[k % 2].copy_(ev_pin, non_blocking=True)
+                ready[k % 2].record(copy_s)
+
+        def pipelined(jobs):
+            copy_in(0)
+            for k in range(jobs):
+                if k + 1 < jobs:
+                    copy_in(k + 1)
+                main_s.wait_event(ready[k % 2])
+                zk.commit_job(srs, bufs[k % 2], log_blowup=2, coeffs=coeffs, com=com, coset=coset)
+                free[k % 2].record(main_s)
+                coms[k % 2].copy_(com[0], non_blocking=True)
+
+        pipelined(4)
+        torch.cuda.synchronize()
+        jobs = 20
+        t0p = time.perf_counter()
+        pipelined(jobs)
+        torch.cuda.synchronize()
+        t_pipe = (time.perf_counter() - t0p) * 1e3 / jobs
+        same = same and bool(torch.equal(coms[(jobs - 1) % 2], com_ref.cpu()[0]))
+        extras["commit_job_with_host_transfers"] = {
+            "ms": round(t_e2e, 4), "points_per_s": n / (t_e2e / 1e3),
+            "pipelined_ms_per_job": round(t_pipe, 4), "pipelined_points_per_s": n / (t_pipe / 1e3),
+            "h2d_ms": round(t_h2d, 4), "h2d_gbs": round(32 * n / (t_h2d / 1e3) / 1e9, 1),
+            "device_resident_ms": round(ms_step, 4), "commitment_matches": same}
+        del ev_pin, com_pin, evals_in, com_ref, bufs, coms
 
         log("kzg opening 2^20")
         # KZG opening of the committed polynomial at a point (quotient by
