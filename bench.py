@@ -590,12 +590,15 @@ def main():
         N22 = 1 << 22
         q = zk.to_device(gen.quantized_fr(gen.CONFIG_SEEDS["quantized"], N22))
         u = zk.to_device(gen.uniform_fr(gen.CONFIG_SEEDS["quantized"], N22, tag=5))
+        q8 = zk.to_device(gen.quantized_fr(gen.CONFIG_SEEDS["quantized"], N22, bits=8))
         t_q = timed(lambda: zk.msm_srs(srs, q, out=com), reps=5)
+        t_q8 = timed(lambda: zk.msm_srs(srs, q8, out=com), reps=5)
         t_u = timed(lambda: zk.msm_srs(srs, u, out=com), reps=3)
         extras["quantized_2^22"] = {"msm_ms": round(t_q, 4), "points_per_s": N22 / (t_q / 1e3),
+                                    "int8_msm_ms": round(t_q8, 4), "int8_points_per_s": N22 / (t_q8 / 1e3),
                                     "uniform_msm_ms": round(t_u, 4), "uniform_points_per_s": N22 / (t_u / 1e3),
                                     "speedup_vs_uniform": round(t_u / t_q, 3)}
-        del q, u
+        del q, q8, u
 
         log("batched 256")
         sizes = gen.log_uniform_sizes(gen.CONFIG_SEEDS["batched"], 256, 8, 18)

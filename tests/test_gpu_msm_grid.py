@@ -7,7 +7,7 @@ slice comes from the sorted total, which zero digits make smaller.  The cases:
   * a few hundred nonzero scalars among 2^20 (most threads get no entries);
   * 2^20 - 1 points, a grid one thread short of a power of two;
   * scalars that are 1 (one digit each, a single bucket holding every entry);
-  * quantized activations at a small size.
+  * quantized activations (int16 and int8), small and at 2^20.
 """
 import numpy as np
 import pytest
@@ -93,8 +93,9 @@ def test_single_bucket(zk, tau, srs):
     assert _commit(zk, srs, s) == omsm.srs_msm_closed_form(tau[1], [1] * n)
 
 
-@pytest.mark.parametrize("n", [1 << 10, (1 << 14) + 3])
-def test_quantized_small(zk, tau, srs, n):
-    s = gen.quantized_fr(6005 + n, n)
-    log("msm grid: quantized n=%d" % n)
+@pytest.mark.parametrize("n,bits", [(1 << 10, 16), ((1 << 14) + 3, 16), ((1 << 16) + 5, 8), (1 << 20, 8)])
+def test_quantized_small(zk, tau, srs, n, bits):
+    # int16 and int8 activations: one live window after the negation trick
+    s = gen.quantized_fr(6005 + n, n, bits=bits)
+    log("msm grid: quantized int%d n=%d" % (bits, n))
     assert _commit(zk, srs, s) == omsm.srs_msm_closed_form(tau[1], fr_from_host(s))
