@@ -136,7 +136,7 @@ def _oracle_naive_sum(args):
 def cpu_baseline(tau_int, log_n=12):
     """The oracle on a 2^12-point commit job: inverse transform, naive MSM over
     the oracle's own SRS (split over every host core), 4x coset evaluation."""
-    from oracle import g1, ntt as ontt
+    from oracle import g1, msm as omsm, ntt as ontt
     n = 1 << log_n
     cores = len(os.sched_getaffinity(0))
     evals = gen.limbs_to_ints(gen.uniform_fr(gen.CONFIG_SEEDS["commit"], n, tag=99))
@@ -151,9 +151,31 @@ def cpu_baseline(tau_int, log_n=12):
             acc = g1.add(acc, g1.decode(p))
         ontt.coset_evals(coeffs, 2, 5)
         dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
+    base = {"value": n / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
             "sample": "2^12-point commit job (oracle iNTT 2^12, naive MSM of 2^12 points split over %d "
                       "processes, 4x coset 2^12->2^14); %.1f s wall" % (cores, dt)}
+    # single-core figures of the oracle's routines: the naive MSM at 2^10
+    # (linear in n, so its 2^20 time is an extrapolation and labelled so),
+    # the DFT at 2^12 and the recursive FFT at 2^20, timed directly
+    pts = [p for part in srs_parts for p in part][:1 << 10]
+    sc = gen.limbs_to_ints(gen.uniform_fr(gen.CONFIG_SEEDS["commit"], 1 << 10, tag=98))
+    t0 = time.perf_counter()
+    omsm.naive_msm(pts, sc)
+    t_msm = time.perf_counter() - t0
+    a12 = gen.limbs_to_ints(gen.uniform_fr(gen.CONFIG_SEEDS["commit"], 1 << 12, tag=97))
+    t0 = time.perf_counter()
+    ontt.dft(a12)
+    t_dft = time.perf_counter() - t0
+    a20 = gen.limbs_to_ints(gen.uniform_fr(gen.CONFIG_SEEDS["commit"], 1 << 20, tag=96))
+    t0 = time.perf_counter()
+    ontt.fft(a20)
+    t_fft = time.perf_counter() - t0
+    detail = {"cores": 1,
+              "naive_msm_2^10_s": round(t_msm, 3), "naive_msm_points_per_s": round((1 << 10) / t_msm, 1),
+              "naive_msm_2^20_s_extrapolated": round(t_msm * 1024, 1),
+              "dft_2^12_s": round(t_dft, 3), "fft_2^20_s": round(t_fft, 3),
+              "fft_2^20_elems_per_s": round((1 << 20) / t_fft, 1)}
+    return base, detail
 
 
 # ----------------------------------------------------------------- GPU
@@ -654,7 +676,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(tau_int)
+        cpu, oracle_timings = cpu_baseline(tau_int)
+        extras["oracle_timings"] = oracle_timings
 
     rec = {
         "metric": "MSM points/s (2^20) + NTT elems/s; batched vs per-call throughput, p99 latency",
