@@ -323,6 +323,11 @@ def test_commit_job(zk, tau, srs_big, logn, logb, custom):
     assert np.array_equal(cos_h, _host(zk, zk.coset_ntt(cf_ref, logb, shift=shift)))
     cv = fr_from_host(cf_h)
     assert points_from_host(com_h)[0] == omsm.srs_msm_closed_form(tau[1], cv)
+    # the commitment straight from the evaluations: [f(tau)]_1 with f(tau) in
+    # barycentric form, independent of any inverse transform (about 25 s of
+    # oracle time at 2^20, the benchmarked size)
+    log("commit job", logn, "barycentric")
+    assert points_from_host(com_h)[0] == g1.gen_mul(ontt.barycentric_eval(fr_from_host(_host(zk, ev)), tau[1]))
     Ev = fr_from_host(cos_h)
     m = n << logb
     for j in sorted({0, 1, m - 1, (7 * m) // 3 % m}):
