@@ -72,7 +72,7 @@ typedef int zk_status;
 #define ZK_ENOMEM (-2)      /* device allocation failed                      */
 #define ZK_EDEVICE (-3)     /* HIP runtime / kernel launch error             */
 #define ZK_EBUDGET (-4)     /* scratch would exceed zk_set_scratch_budget    */
-#define ZK_EUNSUPPORTED (-5) /* valid request outside this build's limits    */
+#define ZK_EUNSUPPORTED (-5) /* valid request outside the library's limits  */
 
 /* Largest transform: log_n (+ log_blowup) <= ZK_MAX_LOG_NTT. */
 #define ZK_MAX_LOG_NTT 28
