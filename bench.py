@@ -114,11 +114,6 @@ def g2_nonzero_digits(scalars_u32):
     return count
 
 
-def msm_window_bits(n):
-    """Window width the library uses for one commitment of n points."""
-    return 8 if n < (1 << 15) else (20 if n >= (1 << 21) else 16)
-
-
 # ----------------------------------------------------------------- CPU oracle
 
 def _oracle_srs_chunk(args):
@@ -289,7 +284,9 @@ def main():
 
     # algorithmic work of one accumulation launch
     coeffs_h = zk.to_host(coeffs)
-    madds = nonzero_digits(coeffs_h, msm_window_bits(n))
+    # the window width the SRS's table policy picks for this size
+    c_bits = zk.srs_window_bits(srs, n)
+    madds = nonzero_digits(coeffs_h, c_bits)
     acc_avg_s = acc_ms / max(acc_n, 1) / 1e3
     achieved = madds * MONT_PER_MADD * MADS_PER_MONT / acc_avg_s / 1e12
     traffic = ACCUMULATE_TRAFFIC["bytes"] if kernel_sources_hash() == ACCUMULATE_TRAFFIC["sources_sha256_16"] else None
@@ -693,7 +690,7 @@ def main():
         "dtype": "u32 limbs (BN254 Fr/Fq, exact)",
         "data": "synthetic: seeded uniform Fr evaluations; SRS [tau^i]G from a seeded tau",
         "config": {"workload": "commit job: iNTT 2^20 -> MSM 2^20 vs SRS -> 4x coset NTT 2^20->2^22",
-                   "n": n, "curve": "BN254", "msm_window_bits": msm_window_bits(n)},
+                   "n": n, "curve": "BN254", "msm_window_bits": c_bits},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

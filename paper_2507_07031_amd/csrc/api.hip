@@ -68,7 +68,6 @@ struct DeviceCtx {
   f29* coset5inv[2] = {nullptr, nullptr};               // 5^-e lo / hi
   f29* ninv = nullptr;                                  // 2^-L, L = 0..28
   uint32_t* gtab = nullptr;                             // 2^j G table for the setup
-  uint32_t* vflag = nullptr;                            // input-check findings (zk_set_validate)
 };
 
 std::mutex g_mu;
@@ -99,7 +98,6 @@ zk_status ctx_get(DeviceCtx** out) {
   for (int i = 0; i < 2; i++) ZK_HIP(hipMalloc(&c.coset5inv[i], tsz), "hipMalloc(coset)");
   ZK_HIP(hipMalloc(&c.ninv, sizeof(f29) * 29), "hipMalloc(ninv)");
   ZK_HIP(hipMalloc(&c.gtab, srs_gtab_words() * 4), "hipMalloc(gtab)");
-  ZK_HIP(hipMalloc(&c.vflag, 4), "hipMalloc(vflag)");
   // roots omega_(2^28), its inverse, and the coset shift 5 (host arithmetic, same field code)
   Words8 wf, wi, w5;
   std::memcpy(wf.w, FR_OMEGA_2_28, 32);
@@ -273,18 +271,32 @@ struct Scratch {
   ~Scratch() { block_free(blk); }
 };
 
+zk_status scratch_alloc(Scratch& sc, size_t bytes, hipStream_t s) {
+  zk_status st = block_alloc(sc.blk, bytes, s);
+  sc.p = sc.blk.p;
+  return st;
+}
+
+// Input checks of one call.  Each validated call ORs its findings into a flag
+// word of its own (a scratch block on its stream), so concurrent validated
+// calls on other streams or threads neither clear nor read each other's.
 zk_status check_inputs(DeviceCtx* c, hipStream_t s, std::initializer_list<InputCheck> checks, const char* who) {
+  (void)c;
   if (!g_validate.load(std::memory_order_relaxed)) return ZK_OK;
-  ZK_HIP(hipMemsetAsync(c->vflag, 0, 4, s), "hipMemsetAsync");
+  Scratch flag;
+  zk_status st = scratch_alloc(flag, 256, s);
+  if (st) return st;
+  uint32_t* vflag = static_cast<uint32_t*>(flag.p);
+  ZK_HIP(hipMemsetAsync(vflag, 0, 4, s), "hipMemsetAsync");
   for (const InputCheck& k : checks) {
     const uint32_t* w = static_cast<const uint32_t*>(k.p);
-    ZK_HIP(k.kind == 2   ? validate_g2(w, k.n, c->vflag, s)
-           : k.kind == 1 ? validate_g1(w, k.n, c->vflag, s)
-                         : validate_fr(w, k.n, c->vflag, s),
+    ZK_HIP(k.kind == 2   ? validate_g2(w, k.n, vflag, s)
+           : k.kind == 1 ? validate_g1(w, k.n, vflag, s)
+                         : validate_fr(w, k.n, vflag, s),
            "input check");
   }
   uint32_t found = 0;
-  ZK_HIP(hipMemcpyAsync(&found, c->vflag, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  ZK_HIP(hipMemcpyAsync(&found, vflag, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
   ZK_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
   if (found & VALIDATE_FR) return fail(ZK_EINVAL, std::string(who) + ": an Fr input is not canonical (>= r)");
   if (found & VALIDATE_G1)
@@ -294,11 +306,6 @@ zk_status check_inputs(DeviceCtx* c, hipStream_t s, std::initializer_list<InputC
   return ZK_OK;
 }
 
-zk_status scratch_alloc(Scratch& sc, size_t bytes, hipStream_t s) {
-  zk_status st = block_alloc(sc.blk, bytes, s);
-  sc.p = sc.blk.p;
-  return st;
-}
 
 // ---------------------------------------------------------------- NTT driver
 // A transform of 2^L points: one LDS pass up to the tile size, two four-step

@@ -14,7 +14,9 @@ and limbs, and checks
   formulas assume (a fixed point), so chains of any length stay bounded.
 
 It imports nothing from the rest of the repository; the constants mirror the
-tables in field.h (checked by tests/test_host_bounds.py).
+tables in field_constants.h and the sub_k multiples in curve.h, and
+tests/test_host_bounds.py checks both against those sources and runs
+check_all().
 """
 from fractions import Fraction
 

@@ -254,7 +254,8 @@ class SRS:
 
 
 def srs_set_table_policy(srs, small_max, large_min):
-    """n < small_max: 8-bit-window table; n >= large_min: 20-bit (if built)."""
+    """n < small_max: 12-bit-window table (first 2^16 points); n >= large_min:
+    20-bit (if built); 16-bit otherwise."""
     _check(lib.zk_srs_set_table_policy(srs.handle, int(small_max), int(large_min)))
 
 

@@ -96,3 +96,54 @@ def test_errors_stay_on_their_thread(zk):
         x.join(timeout=30)
     assert msgs["bad"][0] == zk.ZK_EINVAL and "NULL" in msgs["bad"][1]
     assert msgs["good"][0] == zk.ZK_OK and "NULL" not in msgs["good"][1]
+
+
+def test_validation_findings_stay_on_their_call(zk):
+    # with validation on, two threads on their own streams enter the library
+    # together many times: one always passes a non-canonical Fr input, the
+    # other canonical inputs.  Each validated call has its own flag word, so
+    # the bad call is refused every time and the good call never is.
+    import numpy as np
+    import torch
+    n = 1 << 14
+    good_h = gen.uniform_fr(7100, n)
+    bad_h = good_h.copy()
+    bad_h[n // 2] = gen.ints_to_limbs([gen.FR_MODULUS])[0]   # r itself
+    good, bad = zk.to_device(good_h), zk.to_device(bad_h)
+    ref = zk.to_host(zk.ntt(good))
+    iters = 40
+    status = {"good": [], "bad": []}
+    errors = []
+    barrier = threading.Barrier(2)
+
+    def work(name, x):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                out = torch.empty_like(x)
+                barrier.wait()
+                for _ in range(iters):
+                    st = zk.lib.zk_ntt(zk._ptr(x), zk._ptr(out), 14, zk._stream(x))
+                    status[name].append(st)
+                    if name == "good" and st == zk.ZK_OK:
+                        s.synchronize()
+                        if not np.array_equal(zk.to_host(out), ref):
+                            errors.append("good output differs")
+        except Exception as e:  # reported below, in the main thread
+            errors.append(repr(e))
+
+    log("threads: validated calls, one bad input thread and one good")
+    zk.set_validate(True)
+    try:
+        th = [threading.Thread(target=work, args=("good", good)), threading.Thread(target=work, args=("bad", bad))]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join(timeout=120)
+        assert not any(x.is_alive() for x in th), "a thread did not finish"
+    finally:
+        zk.set_validate(False)
+    torch.cuda.synchronize()
+    assert not errors, errors
+    assert status["good"] == [zk.ZK_OK] * iters
+    assert status["bad"] == [zk.ZK_EINVAL] * iters
