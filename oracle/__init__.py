@@ -33,6 +33,10 @@ Accumulation"):
   Commitment: open, batching), plus the verifier equation with tau known.
 * ``quotient`` -- the Mul block's quotient t = (f h - g) / (X^n - 1) from the
   witness vectors, by transform-based product and long division (Mul).
+* ``polyiop`` -- the quotient Q of a Poly-IOP constraint,
+  R(f_1(x), .., f_N(x), f_1(omega x), .., f_N(omega x)) = Q(x) (x^n - 1), for
+  R given as a sum of monomial terms (Basic blocks based on a Poly-IOP:
+  BooleanCheck, Sub Check, i-thIsZero).
 
 Every function here is pinned by a CPU test against something other than
 itself (closed forms, invariants, brute force); see ``tests/test_oracle_*``.

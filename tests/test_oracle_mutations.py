@@ -245,3 +245,35 @@ def test_run_structured_missing_inverse_scale_is_caught(monkeypatch):
         return ntt.sum_runs_at(runs, points, base)
     monkeypatch.setattr(ntt, "ntt_runs_at", bad)
     _fails(tn.test_run_structured_outputs_match_dense_transforms, random.Random(4), 6)
+
+
+def test_polyiop_backward_shift_is_caught(monkeypatch):
+    from oracle import polyiop
+    from tests import test_oracle_polyiop as tp
+
+    def bad_shifted(coeffs):
+        n = len(coeffs)
+        w = field.fr_inv(ntt.root_of_unity(n))
+        return [int(c) * pow(w, i, R) % R for i, c in enumerate(coeffs)]
+    monkeypatch.setattr(polyiop, "shifted", bad_shifted)
+    _fails(tp.test_divisible_exactly_when_satisfied, random.Random(11))
+
+
+def test_polyiop_dropped_term_is_caught(monkeypatch):
+    from oracle import polyiop
+    from tests import test_oracle_polyiop as tp
+    good = polyiop.constraint_poly
+    monkeypatch.setattr(polyiop, "constraint_poly", lambda polys, terms: good(polys, terms[:-1]))
+    _fails(tp.test_constraint_poly_matches_scalar_evaluation, random.Random(12))
+
+
+def test_polyiop_quotient_cut_to_n_is_caught(monkeypatch):
+    from oracle import polyiop
+    from tests import test_oracle_polyiop as tp
+    good = polyiop.polyiop_quotient
+
+    def cut(vectors, terms):
+        q, rem, polys = good(vectors, terms)
+        return q[:len(vectors[0])], rem, polys
+    monkeypatch.setattr(polyiop, "polyiop_quotient", cut)
+    _fails(tp.test_degree_bound, random.Random(13))
