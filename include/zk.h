@@ -171,6 +171,25 @@ zk_status zk_msm_srs(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1*
 zk_status zk_commit_job(const zk_srs* srs, const zk_fr* evals, uint32_t log_n, uint32_t log_blowup,
                         const zk_fr* shift_host, zk_fr* coeffs, zk_g1* commitment, zk_fr* coset, void* stream);
 
+/* zk_msm_srs for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments and result as zk_msm_srs (the commitment sum_{i<n} scalars[i]
+ * [tau^i]_1 over the first n prepared points, n = 0 gives (0, 0)).  Its
+ * scratch is a fixed 128 MiB device array in the library, one copy per GPU,
+ * held until the process ends; the call makes no allocation, no memset and
+ * no host synchronisation (unless zk_set_validate is on), so a sequence of
+ * such calls can be captured into a HIP graph (profiling off; the first call
+ * in the process should run before capture starts).
+ *  - Limit: the MSM's scratch must fit the array: up to 2^18 points under the
+ *    default table policy.  A larger n returns ZK_EUNSUPPORTED, with the
+ *    needed and available bytes in zk_last_error; use zk_msm_srs then.
+ *  - Every call on one GPU shares that GPU's array: calls that overlap in
+ *    time (on different streams, or from different threads) race and give
+ *    wrong results.  Calls ordered on one stream are safe.  Each call clears
+ *    what it needs; nothing carries over between calls.
+ *  - The current device must be the SRS's device (ZK_EINVAL otherwise). */
+zk_status zk_msm_srs_noalloc(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream);
+
 /* zk_msm_srs that also records `accumulate_done_event` (a hipEvent_t, may be
  * NULL) on `stream` as soon as its bucket-accumulation kernel is enqueued.
  * What follows on the stream is a latency-bound reduction that leaves most

@@ -60,6 +60,21 @@ struct InputCheck {
   } while (0)
 
 // ---------------------------------------------------------------- device context
+// Scratch of zk_msm_srs_noalloc: a fixed device array, one copy per GPU the
+// library runs on, held until the process ends.  Host code never uses the
+// array's name as a device address: ctx_get looks up each device's copy with
+// hipGetSymbolAddress and the entry point passes that address to the kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(128) << 20;
+}  // namespace
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+namespace {
+
+// Clears the validation finding word of a zk_msm_srs_noalloc call (a kernel
+// rather than a memset, so the call's work stays capturable).
+__global__ void noalloc_zero_kernel(uint32_t* w) {
+  if (threadIdx.x == 0) w[0] = 0;
+}
+
 struct DeviceCtx {
   bool ready = false;
   f29* tw[4] = {nullptr, nullptr, nullptr, nullptr};   // fwd lo, fwd hi, inv lo, inv hi
@@ -68,6 +83,7 @@ struct DeviceCtx {
   f29* coset5inv[2] = {nullptr, nullptr};               // 5^-e lo / hi
   f29* ninv = nullptr;                                  // 2^-L, L = 0..28
   uint32_t* gtab = nullptr;                             // 2^j G table for the setup
+  uint8_t* noalloc = nullptr;                           // this device's copy of `scratch`
 };
 
 std::mutex g_mu;
@@ -98,6 +114,9 @@ zk_status ctx_get(DeviceCtx** out) {
   for (int i = 0; i < 2; i++) ZK_HIP(hipMalloc(&c.coset5inv[i], tsz), "hipMalloc(coset)");
   ZK_HIP(hipMalloc(&c.ninv, sizeof(f29) * 29), "hipMalloc(ninv)");
   ZK_HIP(hipMalloc(&c.gtab, srs_gtab_words() * 4), "hipMalloc(gtab)");
+  // this device's copy of the no-allocation scratch (the device is current)
+  ZK_HIP(hipGetSymbolAddress(reinterpret_cast<void**>(&c.noalloc), HIP_SYMBOL(scratch)),
+         "hipGetSymbolAddress(scratch)");
   // roots omega_(2^28), its inverse, and the coset shift 5 (host arithmetic, same field code)
   Words8 wf, wi, w5;
   std::memcpy(wf.w, FR_OMEGA_2_28, 32);
@@ -919,6 +938,47 @@ zk_status zk_msm_srs(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1*
   if ((st = check_inputs(c, (hipStream_t)stream, {{scalars, n, false}}, "zk_msm_srs"))) return st;
   return msm_srs_one(srs, reinterpret_cast<const uint32_t*>(scalars), n, reinterpret_cast<uint32_t*>(out),
                      (hipStream_t)stream);
+}
+
+zk_status zk_msm_srs_noalloc(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream) {
+  if (!srs || !out || (n && !scalars)) return fail(ZK_EINVAL, "zk_msm_srs_noalloc: NULL argument");
+  if (n > srs->n) return fail(ZK_EINVAL, "zk_msm_srs_noalloc: n exceeds the SRS size");
+  int dev = 0;
+  ZK_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != srs->device) return fail(ZK_EINVAL, "zk_msm_srs_noalloc: the SRS belongs to another device");
+  // the SRS's creation set up this device's context (and its scratch
+  // address); nothing here allocates
+  uint8_t* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (dev >= 0 && dev < 64 && g_ctx[dev].ready) base = g_ctx[dev].noalloc;
+  }
+  if (!base) return fail(ZK_EINVAL, "zk_msm_srs_noalloc: device context not set up");
+  const uint64_t off[2] = {0, n};
+  const MsmPlan plan = srs_plan(srs, n, off);
+  const size_t need = msm_workspace_bytes(plan) + 256;
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(ZK_EUNSUPPORTED, "zk_msm_srs_noalloc: " + std::to_string(n) + " points need " +
+                                     std::to_string(need) + " bytes of scratch, above the fixed " +
+                                     std::to_string(NOALLOC_SCRATCH_BYTES) + " (use zk_msm_srs)");
+  const hipStream_t s = (hipStream_t)stream;
+  if (g_validate.load(std::memory_order_relaxed)) {
+    // the first 256 bytes hold this call's finding word
+    uint32_t* vflag = reinterpret_cast<uint32_t*>(base);
+    hipLaunchKernelGGL(noalloc_zero_kernel, dim3(1), dim3(64), 0, s, vflag);
+    ZK_HIP(hipGetLastError(), "input check");
+    ZK_HIP(validate_fr(reinterpret_cast<const uint32_t*>(scalars), n, vflag, s), "input check");
+    uint32_t found = 0;
+    ZK_HIP(hipMemcpyAsync(&found, vflag, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    ZK_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (found) return fail(ZK_EINVAL, "zk_msm_srs_noalloc: an Fr input is not canonical (>= r)");
+  }
+  const SrsTable t = srs_table_for(srs, n);
+  const uint32_t* tab = t == SrsTable::small ? srs->tab_small : t == SrsTable::large ? srs->tab_large : srs->tab;
+  const MsmBuffers b = msm_carve(plan, base + 256);
+  ZK_HIP(msm_run(plan, off, tab, reinterpret_cast<const uint32_t*>(scalars), b, reinterpret_cast<uint32_t*>(out), s),
+         "msm");
+  return ZK_OK;
 }
 
 zk_status zk_msm_batch(const zk_srs* srs, const zk_fr* scalars, const uint64_t* offsets_host, uint32_t batch,

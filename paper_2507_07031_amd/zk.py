@@ -27,7 +27,7 @@ EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_s
            "zk_kzg_open_batch", "zk_quotient_mul",
            "zk_srs_lagrange_setup", "zk_transcript_challenge", "zk_acc_fold",
            "zk_srs_g2_setup", "zk_srs_g2_create", "zk_srs_g2_destroy", "zk_srs_g2_size", "zk_msm_g2_srs",
-           "zk_srs_set_table_policy", "zk_srs_window_bits", "zk_set_scratch_budget", "zk_scratch_held")
+           "zk_srs_set_table_policy", "zk_srs_window_bits", "zk_set_scratch_budget", "zk_scratch_held", "zk_msm_srs_noalloc")
 
 
 class ZkError(RuntimeError):
@@ -54,6 +54,7 @@ def _load():
         "zk_srs_size": ([P], U64),
         "zk_msm_srs": ([P, P, U64, P, P], I),
         "zk_msm_srs_ex": ([P, P, U64, P, P, P], I),
+        "zk_msm_srs_noalloc": ([P, P, U64, P, P], I),
         "zk_profile_only": ([ctypes.c_char_p], I),
         "zk_set_validate": ([I], I),
         "zk_commit_job": ([P, P, I, I, P, P, P, P, P], I),
@@ -271,6 +272,18 @@ def msm_srs(srs, scalars, n=None, out=None):
     if out is None:
         out = _torch().empty((1, 16), dtype=_torch().int32, device=scalars.device)
     _check(lib.zk_msm_srs(srs.handle, _ptr(scalars), n, _ptr(out), _stream(scalars)))
+    return out
+
+
+def msm_srs_noalloc(srs, scalars, out, n=None):
+    """msm_srs with the library's fixed scratch array (no allocation; up to
+    2^18 points).  `out` is required: a (1, 16) device tensor."""
+    scalars = _dev_words(scalars, 8, "scalars")
+    out = _dev_words(out, 16, "out")
+    n = int(n if n is not None else scalars.shape[0])
+    if n > scalars.shape[0]:
+        raise ValueError("n exceeds the scalars")
+    _check(lib.zk_msm_srs_noalloc(srs.handle, _ptr(scalars), n, _ptr(out), _stream(scalars)))
     return out
 
 
