@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import field, fold as ofold, g1, msm as omsm, ntt as ontt, srs as osrs
-from tests.gpu_helpers import fr_from_host, log, points_from_host
+from tests.gpu_helpers import fr_from_host, log, points_from_host, points_to_host
 from workloads import generators as gen
 from workloads import limbs_to_ints
 
@@ -479,32 +479,38 @@ def test_validation_rejects_out_of_range_inputs(zk, tau, srs_big):
 # ------------------------------------------------------------------ serving
 
 def test_serving_mix_equals_alone(zk, tau, srs_big):
-    # jobs admitted while others run overlap on the device; every result must
-    # be bit-identical to the same job run alone
+    # commit-and-fold jobs admitted while others run overlap on the device;
+    # every result (commitment, coset evaluations, folded accumulator) must be
+    # bit-identical to the same job run alone, including a 2^22 job
     from paper_2507_07031_amd.serve import GpuExecutor, Job, serve
-    _, h = srs_big
-    pool = _dev(zk, gen.uniform_fr(gen.CONFIG_SEEDS["serving"], 1 << 21, tag=1))
-    sizes = [1000, 1 << 12, 70000, 1 << 18, 333, 1 << 16, 5000, 1 << 20, 1, 2]
+    pts, h = srs_big
+    pool = _dev(zk, gen.uniform_fr(gen.CONFIG_SEEDS["serving"], 1 << 23, tag=1))
+    acc_pool = pts[:4096].contiguous()
+    sizes = [1000, 1 << 12, 70000, 1 << 18, 333, 1 << 16, 5000, 1 << 20, 1, 2, (1 << 21) + 77, 3000]
     rng = np.random.default_rng(3)
-    offs = [int(rng.integers(0, (1 << 21) - (1 << 20))) for _ in sizes]
+    offs = [int(rng.integers(0, (1 << 23) - (1 << 22))) for _ in sizes]
+    accs = [int(rng.integers(0, 4096)) for _ in sizes]
 
     def mk():
-        return [Job(i, n, 1e-4 * i, o) for i, (n, o) in enumerate(zip(sizes, offs))]
+        return [Job(i, n, 1e-4 * i, o, a) for i, (n, o, a) in enumerate(zip(sizes, offs, accs))]
 
     log("serving mix")
-    ex = GpuExecutor(zk, h, pool, slots=4, keep_results=True)
+    ex = GpuExecutor(zk, h, pool, slots=4, acc_pool=acc_pool, budget=64 << 30, keep_results=True)
     fin, rej, _ = serve(mk(), ex, 64 << 30, 4)
     assert not rej and len(fin) == len(sizes)
+    assert all(j.error is None for j in fin)
     mixed = {j.jid: j.result for j in fin}
     assert max(j.start for j in fin) < max(j.finish for j in fin)
+    zk.set_scratch_budget(0)
     for job in mk():
-        ex1 = GpuExecutor(zk, h, pool, slots=1, keep_results=True)
+        ex1 = GpuExecutor(zk, h, pool, slots=1, acc_pool=acc_pool, keep_results=True)
         f1, _, _ = serve([job], ex1, 64 << 30, 1)
-        com, coset = f1[0].result
-        assert np.array_equal(com, mixed[job.jid][0]), job.jid
-        assert np.array_equal(coset, mixed[job.jid][1]), job.jid
+        for a, b in zip(f1[0].result, mixed[job.jid]):
+            assert np.array_equal(a, b), job.jid
     # the smallest padded job against the oracle: commitment straight from the
-    # evaluations (barycentric) and coset samples from the coefficients
+    # evaluations (barycentric), coset samples from the coefficients, and the
+    # fold gamma * acc + com with gamma the transcript of (acc, com)
+    from oracle import transcript as otr
     j = 0
     N = 1024
     ev = fr_from_host(_host(zk, pool[offs[j]:offs[j] + sizes[j]])) + [0] * (N - sizes[j])
@@ -514,3 +520,6 @@ def test_serving_mix_equals_alone(zk, tau, srs_big):
     cos = fr_from_host(mixed[j][1])
     for k in (0, 5, 4 * N - 1):
         assert cos[k] == ontt.coset_eval_at(coeffs, 2, k, 5)
+    acc = osrs.srs_point(tau[1], accs[j])
+    gamma = otr.challenge(np.concatenate([points_to_host([acc]), points_to_host([com])]).tobytes())
+    assert points_from_host(mixed[j][2])[0] == ofold.tree_fold([[acc], [com]], [gamma])[0]

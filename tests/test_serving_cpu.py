@@ -2,7 +2,7 @@
 only models durations and bytes (no device code)."""
 import numpy as np
 
-from paper_2507_07031_amd.serve import Admission, Job, serve, summarize
+from paper_2507_07031_amd.serve import Admission, Busy, Job, serve, summarize
 from workloads import generators as gen
 
 
@@ -153,3 +153,39 @@ def test_failed_jobs_are_isolated():
     s = summarize(fin, wall)
     assert s["jobs"] == 37 and s["failed"] == 3
     assert not ex.live  # every slot and byte released
+
+
+class BusyExecutor(MockExecutor):
+    """Refuses (Busy) any start while `cap` jobs already run, as the library
+    does when cached and in-use scratch reach its budget."""
+
+    def __init__(self, clock, budget, slots, cap):
+        super().__init__(clock, budget, slots)
+        self.cap = cap
+        self.refusals = 0
+
+    def start(self, job):
+        if len(self.live) >= self.cap:
+            self.refusals += 1
+            raise Busy("scratch at the budget")
+        super().start(job)
+
+
+def test_busy_is_back_pressure():
+    clock = FakeClock()
+    jobs = _jobs(60, seed=13)
+    ex = BusyExecutor(clock, 10 ** 12, 4, cap=2)
+    fin, rej, wall = serve(jobs, ex, 10 ** 12, 4, clock=clock, sleep=clock.tick)
+    assert not rej and len(fin) == 60
+    assert all(j.error is None for j in fin)
+    assert ex.refusals > 0 and ex.max_live <= 2
+    assert ex.starts == sorted(ex.starts)        # retried jobs keep their place
+    assert summarize(fin, wall)["retried"] > 0
+
+
+def test_busy_alone_fails_the_job():
+    clock = FakeClock()
+    ex = BusyExecutor(clock, 10 ** 12, 2, cap=0)
+    fin, rej, _ = serve([Job(0, 8, 0.0), Job(1, 8, 0.0)], ex, 10 ** 12, 2, clock=clock, sleep=clock.tick)
+    assert not rej and len(fin) == 2
+    assert all(j.error is not None and j.error.startswith("failed") for j in fin)
