@@ -263,6 +263,44 @@ zk_status zk_quotient_mul(const zk_srs* srs, const zk_fr* a, const zk_fr* b, con
                           uint32_t log_blowup, const zk_fr* shift_host, zk_fr* t_coeffs, zk_g1* t_commit,
                           void* stream);
 
+/* One term c * x_a * x_b * ... of a Poly-IOP constraint R (Basic blocks based
+ * on a Poly-IOP): factor index a < N names the witness polynomial f_a(x),
+ * N <= a < 2N names f_(a-N)(omega x); nfactors = 0 is the constant c. */
+#define ZK_POLYIOP_MAX_WITNESS 8
+#define ZK_POLYIOP_MAX_TERMS 16
+#define ZK_POLYIOP_MAX_DEGREE 4
+typedef struct zk_constraint_term {
+  zk_fr coeff;                             /* canonical                      */
+  uint32_t nfactors;                       /* 0 .. ZK_POLYIOP_MAX_DEGREE     */
+  uint32_t factor[ZK_POLYIOP_MAX_DEGREE];  /* each < 2N; unused slots ignored */
+} zk_constraint_term;
+
+/* Quotient of a Poly-IOP constraint (Basic blocks based on a Poly-IOP,
+ * protocol step 1): for N witness vectors on H, evals[k * n + i] =
+ * f_k(omega^i) (n = 2^log_n, 1 <= N <= ZK_POLYIOP_MAX_WITNESS), and R the
+ * sum of the nterms terms (1 .. ZK_POLYIOP_MAX_TERMS) of degree d (the
+ * largest nfactors),
+ *   Q(X)        = R(f_0(X), .., f_(N-1)(X), f_0(omega X), .., f_(N-1)(omega X)) / (X^n - 1),
+ *   q_coeffs[i] = Q_i, i < max(d - 1, 1) n    (deg Q <= d (n - 1) - n),
+ *   *q_commit   = [Q(tau)]_1 over the first max(d - 1, 1) n SRS points.
+ * The paper's instances: BooleanCheck (N = 1, R = x_0 - x_0^2), Sub Check
+ * (N = 2, R = x_1 + x_0 - x_2), i-thIsZero (N = 2, R = x_0 x_1).
+ * Computed on the coset s H_(B n), B = 2^log_blowup (1 <= log_blowup <= 4,
+ * B >= d): the coset evaluations of every f_k, the pointwise R / (X^n - 1)
+ * (f_k(omega x) at coset point j is point j + B of the same coset vector;
+ * X^n - 1 takes B distinct values there), the inverse coset transform and
+ * the commitment.  shift_host: s as a host zk_fr, or NULL for s = 5; a
+ * shift whose coset meets a root of X^n - 1 is rejected.  If the witnesses
+ * do not satisfy R on H there is no such Q: the result is then the
+ * interpolant of R / (X^n - 1) on the coset, cut to the length above.  The
+ * paper's blinding f + (X^n - 1) b is not applied (the caller's witnesses
+ * carry it).  terms_host: host array.  ZK_EINVAL for counts, indices or a
+ * blowup out of range, or an SRS shorter than the quotient.  Scratch:
+ * 32 (n + (N + 1) B n) bytes from the library cache. */
+zk_status zk_quotient_polyiop(const zk_srs* srs, const zk_fr* evals, uint32_t N, uint32_t log_n,
+                              const zk_constraint_term* terms_host, uint32_t nterms, uint32_t log_blowup,
+                              const zk_fr* shift_host, zk_fr* q_coeffs, zk_g1* q_commit, void* stream);
+
 /* Fiat-Shamir challenge from a transcript (the random oracles rho_acc and
  * rho_NARK of Parallel Accumulation, which the paper leaves unspecified):
  *   *challenge = (SHA-256(0x00 || data) || SHA-256(0x01 || data)) mod r,
@@ -344,6 +382,13 @@ zk_status zk_set_scratch_budget(uint64_t bytes);
 /* Scratch bytes the library holds on the current device, cached blocks
  * included (0 if there is no device). */
 uint64_t zk_scratch_held(void);
+
+/* Calibration of the integer-multiply roof: runs `blocks` workgroups of 256
+ * threads, each thread 8 independent chains of iters * 16 dependent
+ * v_mad_u64_u32 products (the only multiply of the Montgomery products), on
+ * the current device and stream, and returns the sustained rate in products
+ * per second (timed with events; synchronises the stream). */
+zk_status zk_calibrate_mad_rate(uint32_t blocks, uint32_t iters, double* mads_per_s, void* stream);
 
 /* Observability: when enabled, the library brackets named kernel regions
  * with HIP events recorded on the stream the kernels run on.  Regions:

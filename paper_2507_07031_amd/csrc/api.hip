@@ -1041,6 +1041,37 @@ zk_status zk_kzg_open(const zk_srs* srs, const zk_fr* coeffs, uint64_t n, const 
   return zk_kzg_open_batch(srs, coeffs, 1, n, x_host, nullptr, y, quotient, proof, stream);
 }
 
+// Shift s of the coset s H_(B n) (host canonical words, default 5) and the
+// inverses of the B values s^n omega_B^k - 1 that X^n - 1 takes there:
+// times 2^522 (times_r2) for a Montgomery product with a value divided by
+// 2^261, else times 2^261 (the Montgomery form of the inverse).
+static zk_status coset_vanishing(const zk_fr* shift_host, uint32_t log_n, uint32_t log_blowup, bool times_r2,
+                                 const char* who, uint32_t sw[8], f29& sm, QuotZinv& zi) {
+  const uint32_t five[8] = {5, 0, 0, 0, 0, 0, 0, 0};
+  std::memcpy(sw, shift_host ? shift_host->v : five, 32);
+  unsigned br = 0;
+  for (int i = 0; i < 8; i++) (void)__builtin_subc(sw[i], FrP::M32[i], br, &br);
+  if (!br) return fail(ZK_EINVAL, std::string(who) + ": shift not canonical (>= r)");
+  const f29 one = f29_from(FrP::ONE);
+  sm = reduce_full<FrP>(to_mont<FrP>(unpack(sw)));
+  if (f29_is_zero_limbs(sm)) return fail(ZK_EINVAL, std::string(who) + ": shift is zero");
+  f29 sn = sm;  // s^n by log_n squarings
+  for (uint32_t i = 0; i < log_n; i++) sn = reduce_full<FrP>(mont_mul<FrP>(sn, sn));
+  f29 wb = reduce_full<FrP>(to_mont<FrP>(unpack(FR_OMEGA_2_28)));  // omega_B = omega_(2^28)^(2^(28 - log_b))
+  for (uint32_t i = 0; i < 28 - log_blowup; i++) wb = reduce_full<FrP>(mont_mul<FrP>(wb, wb));
+  f29 pk = sn;
+  for (uint32_t k = 0; k < (1u << log_blowup); k++) {
+    const f29 z = reduce_full<FrP>(sub_k(pk, one, FrP::K2));
+    if (f29_is_zero_limbs(z))
+      return fail(ZK_EINVAL, std::string(who) + ": X^n - 1 vanishes on the coset (bad shift)");
+    const f29 zinv = reduce_full<FrP>(mont_inv<FrP>(z));
+    zi.zinv_r2[k] = times_r2 ? reduce_full<FrP>(mont_mul<FrP>(zinv, f29_from(FrP::R2))) : zinv;
+    pk = reduce_full<FrP>(mont_mul<FrP>(pk, wb));
+  }
+  for (uint32_t k = 1u << log_blowup; k < (1u << QUOT_MAX_LOG_BLOWUP); k++) zi.zinv_r2[k] = f29_zero();
+  return ZK_OK;
+}
+
 zk_status zk_quotient_mul(const zk_srs* srs, const zk_fr* a, const zk_fr* b, const zk_fr* c_evals, uint32_t log_n,
                           uint32_t log_blowup, const zk_fr* shift_host, zk_fr* t_coeffs, zk_g1* t_commit,
                           void* stream) {
@@ -1051,32 +1082,11 @@ zk_status zk_quotient_mul(const zk_srs* srs, const zk_fr* a, const zk_fr* b, con
     return fail(ZK_EUNSUPPORTED, "zk_quotient_mul: log_n + log_blowup > ZK_MAX_LOG_NTT");
   const uint64_t n = 1ull << log_n;
   if (n > srs->n) return fail(ZK_EINVAL, "zk_quotient_mul: 2^log_n exceeds the SRS size");
-  // shift s (Montgomery form) and the B values s^n omega_B^k - 1 of the vanishing polynomial
-  uint32_t sw[8] = {5, 0, 0, 0, 0, 0, 0, 0};
-  if (shift_host) {
-    std::memcpy(sw, shift_host->v, 32);
-    unsigned br = 0;
-    for (int i = 0; i < 8; i++) (void)__builtin_subc(sw[i], FrP::M32[i], br, &br);
-    if (!br) return fail(ZK_EINVAL, "zk_quotient_mul: shift not canonical (>= r)");
-  }
-  const f29 one = f29_from(FrP::ONE);
-  const f29 sm = reduce_full<FrP>(to_mont<FrP>(unpack(sw)));
-  if (f29_is_zero_limbs(sm)) return fail(ZK_EINVAL, "zk_quotient_mul: shift is zero");
-  f29 sn = sm;  // s^n by log_n squarings
-  for (uint32_t i = 0; i < log_n; i++) sn = reduce_full<FrP>(mont_mul<FrP>(sn, sn));
-  f29 wb = reduce_full<FrP>(to_mont<FrP>(unpack(FR_OMEGA_2_28)));  // omega_B = omega_(2^28)^(2^(28 - log_b))
-  for (uint32_t i = 0; i < 28 - log_blowup; i++) wb = reduce_full<FrP>(mont_mul<FrP>(wb, wb));
+  uint32_t sw[8];
+  f29 sm;
   QuotZinv zi;
-  {
-    f29 pk = sn;
-    for (uint32_t k = 0; k < (1u << log_blowup); k++) {
-      const f29 z = reduce_full<FrP>(sub_k(pk, one, FrP::K2));
-      if (f29_is_zero_limbs(z)) return fail(ZK_EINVAL, "zk_quotient_mul: X^n - 1 vanishes on the coset (bad shift)");
-      zi.zinv_r2[k] = reduce_full<FrP>(mont_mul<FrP>(mont_inv<FrP>(z), f29_from(FrP::R2)));
-      pk = reduce_full<FrP>(mont_mul<FrP>(pk, wb));
-    }
-    for (uint32_t k = 1u << log_blowup; k < (1u << QUOT_MAX_LOG_BLOWUP); k++) zi.zinv_r2[k] = f29_zero();
-  }
+  zk_status st0 = coset_vanishing(shift_host, log_n, log_blowup, true, "zk_quotient_mul", sw, sm, zi);
+  if (st0) return st0;
   DeviceCtx* c;
   zk_status st = ctx_get(&c);
   if (st) return st;
@@ -1115,6 +1125,123 @@ zk_status zk_quotient_mul(const zk_srs* srs, const zk_fr* a, const zk_fr* b, con
   if ((st = run_ntt(c, E[0], E[0], L, true, nullptr, nullptr, (uint32_t)big, s))) return st;
   ZK_HIP(quot_scale_powers(E[0], n, ilo, ihi, reinterpret_cast<uint32_t*>(t_coeffs), s), "quotient scale");
   return msm_srs_one(srs, reinterpret_cast<const uint32_t*>(t_coeffs), n, reinterpret_cast<uint32_t*>(t_commit), s);
+}
+
+zk_status zk_quotient_polyiop(const zk_srs* srs, const zk_fr* evals, uint32_t N, uint32_t log_n,
+                              const zk_constraint_term* terms_host, uint32_t nterms, uint32_t log_blowup,
+                              const zk_fr* shift_host, zk_fr* q_coeffs, zk_g1* q_commit, void* stream) {
+  if (!srs || !evals || !terms_host || !q_coeffs || !q_commit)
+    return fail(ZK_EINVAL, "zk_quotient_polyiop: NULL argument");
+  if (N < 1 || N > ZK_POLYIOP_MAX_WITNESS) return fail(ZK_EINVAL, "zk_quotient_polyiop: N must be 1..8");
+  if (nterms < 1 || nterms > ZK_POLYIOP_MAX_TERMS) return fail(ZK_EINVAL, "zk_quotient_polyiop: nterms must be 1..16");
+  if (log_blowup < 1 || log_blowup > QUOT_MAX_LOG_BLOWUP)
+    return fail(ZK_EINVAL, "zk_quotient_polyiop: log_blowup must be 1..4");
+  if (log_n > ZK_MAX_LOG_NTT || log_n + log_blowup > ZK_MAX_LOG_NTT)
+    return fail(ZK_EUNSUPPORTED, "zk_quotient_polyiop: log_n + log_blowup > ZK_MAX_LOG_NTT");
+  static_assert(ZK_POLYIOP_MAX_WITNESS == POLYIOP_MAX_N && ZK_POLYIOP_MAX_TERMS == POLYIOP_MAX_TERMS &&
+                    ZK_POLYIOP_MAX_DEGREE == POLYIOP_MAX_DEG,
+                "Poly-IOP limits of the header and the kernel agree");
+  // the terms: coefficient c * 2^(261 d) in Montgomery limbs (a chain of
+  // d - 1 products of plain operands and one with it gives the plain term)
+  PolyIopTerms T{};
+  T.nterms = nterms;
+  T.N = N;
+  uint32_t d = 0;
+  for (uint32_t t = 0; t < nterms; t++) {
+    const zk_constraint_term& in = terms_host[t];
+    if (in.nfactors > ZK_POLYIOP_MAX_DEGREE)
+      return fail(ZK_EINVAL, "zk_quotient_polyiop: a term has more than 4 factors");
+    uint32_t cw[8];
+    std::memcpy(cw, in.coeff.v, 32);
+    unsigned br = 0;
+    for (int i = 0; i < 8; i++) (void)__builtin_subc(cw[i], FrP::M32[i], br, &br);
+    if (!br) return fail(ZK_EINVAL, "zk_quotient_polyiop: a coefficient is not canonical (>= r)");
+    uint32_t packed = 0;
+    for (uint32_t i = 0; i < in.nfactors; i++) {
+      if (in.factor[i] >= 2 * N) return fail(ZK_EINVAL, "zk_quotient_polyiop: factor index >= 2N");
+      packed |= in.factor[i] << (8 * i);
+    }
+    T.nfac[t] = in.nfactors;
+    T.fac[t] = packed;
+    f29 c = reduce_full<FrP>(unpack(cw));  // plain c
+    for (uint32_t i = 0; i < in.nfactors; i++) c = reduce_full<FrP>(to_mont<FrP>(c));  // c 2^(261 i)
+    T.coeff[t] = c;
+    const bool is_one = cw[0] == 1 && !(cw[1] | cw[2] | cw[3] | cw[4] | cw[5] | cw[6] | cw[7]);
+    T.ident[t] = (in.nfactors == 1 && is_one) ? 1u : 0u;
+    d = std::max(d, in.nfactors);
+  }
+  if ((1u << log_blowup) < d) return fail(ZK_EINVAL, "zk_quotient_polyiop: blowup 2^log_blowup below the degree");
+  const uint64_t n = 1ull << log_n;
+  const uint64_t qlen = (uint64_t)(d > 1 ? d - 1 : 1) * n;  // deg Q <= d (n - 1) - n
+  if (qlen > srs->n) return fail(ZK_EINVAL, "zk_quotient_polyiop: the quotient has more coefficients than the SRS points");
+  uint32_t sw[8];
+  f29 sm;
+  QuotZinv zi;
+  zk_status st = coset_vanishing(shift_host, log_n, log_blowup, false, "zk_quotient_polyiop", sw, sm, zi);
+  if (st) return st;
+  DeviceCtx* c;
+  if ((st = ctx_get(&c))) return st;
+  const hipStream_t s = (hipStream_t)stream;
+  if ((st = check_inputs(c, s, {{evals, (uint64_t)N * n, false}}, "zk_quotient_polyiop"))) return st;
+  const uint32_t L = log_n + log_blowup;
+  const uint64_t big = 1ull << L;
+  const size_t tsz = sizeof(f29) << 14;
+  Scratch ws;
+  if ((st = scratch_alloc(ws, (size_t)32 * (n + (N + 1) * big) + (shift_host ? 4 * tsz : 0), s))) return st;
+  uint32_t* coef = static_cast<uint32_t*>(ws.p);
+  uint32_t* E = coef + 8 * n;                // N coset vectors of big points each
+  uint32_t* V = E + 8 * (size_t)N * big;     // R / Z on the coset, then its inverse transform
+  const f29 *lo = c->coset5[0], *hi = c->coset5[1], *ilo = c->coset5inv[0], *ihi = c->coset5inv[1];
+  if (shift_host) {
+    f29* t = reinterpret_cast<f29*>(V + 8 * big);
+    Words8 fw, iw;
+    std::memcpy(fw.w, sw, 32);
+    host_words(from_mont<FrP>(mont_inv<FrP>(sm)), iw.w);
+    ZK_HIP(ntt_make_pow_tables(fw, t, t + (1u << 14), s), "shift tables");
+    ZK_HIP(ntt_make_pow_tables(iw, t + (2u << 14), t + (3u << 14), s), "shift tables");
+    lo = t;
+    hi = t + (1u << 14);
+    ilo = t + (2u << 14);
+    ihi = t + (3u << 14);
+  }
+  // every witness on the coset: coefficients, then the coset transform
+  for (uint32_t k = 0; k < N; k++) {
+    if ((st = run_ntt(c, reinterpret_cast<const uint32_t*>(evals) + 8 * (size_t)k * n, coef, log_n, true, nullptr,
+                      nullptr, (uint32_t)n, s)))
+      return st;
+    if ((st = run_ntt(c, coef, E + 8 * (size_t)k * big, L, false, lo, hi, (uint32_t)n, s))) return st;
+  }
+  // Q on the coset, then its coefficients: inverse transform, times s^-i
+  ZK_HIP(quot_polyiop_pointwise(E, big, log_blowup, T, zi, V, s), "quotient pointwise");
+  if ((st = run_ntt(c, V, V, L, true, nullptr, nullptr, (uint32_t)big, s))) return st;
+  ZK_HIP(quot_scale_powers(V, qlen, ilo, ihi, reinterpret_cast<uint32_t*>(q_coeffs), s), "quotient scale");
+  return msm_srs_one(srs, reinterpret_cast<const uint32_t*>(q_coeffs), qlen, reinterpret_cast<uint32_t*>(q_commit),
+                     s);
+}
+
+zk_status zk_calibrate_mad_rate(uint32_t blocks, uint32_t iters, double* mads_per_s, void* stream) {
+  if (!mads_per_s || blocks == 0 || iters == 0) return fail(ZK_EINVAL, "zk_calibrate_mad_rate: bad argument");
+  DeviceCtx* c;
+  zk_status st = ctx_get(&c);
+  if (st) return st;
+  const hipStream_t s = (hipStream_t)stream;
+  Scratch sink;
+  if ((st = scratch_alloc(sink, 256, s))) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ZK_HIP(hipEventCreate(&e0), "hipEventCreate");
+  hipError_t e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = prof_mad_rate_launch(blocks, iters, static_cast<uint32_t*>(sink.p), s);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  if (e == hipSuccess) e = prof_mad_rate_launch(blocks, iters, static_cast<uint32_t*>(sink.p), s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "zk_calibrate_mad_rate");
+  *mads_per_s = ms > 0 ? (double)prof_mad_count(blocks, iters) / (ms * 1e-3) : 0.0;
+  return ZK_OK;
 }
 
 zk_status zk_transcript_challenge(const void* data, uint64_t bytes, zk_fr* challenge, void* stream) {

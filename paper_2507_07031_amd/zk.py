@@ -27,7 +27,8 @@ EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_s
            "zk_kzg_open_batch", "zk_quotient_mul",
            "zk_srs_lagrange_setup", "zk_transcript_challenge", "zk_acc_fold",
            "zk_srs_g2_setup", "zk_srs_g2_create", "zk_srs_g2_destroy", "zk_srs_g2_size", "zk_msm_g2_srs",
-           "zk_srs_set_table_policy", "zk_srs_window_bits", "zk_set_scratch_budget", "zk_scratch_held", "zk_msm_srs_noalloc")
+           "zk_srs_set_table_policy", "zk_srs_window_bits", "zk_set_scratch_budget", "zk_scratch_held", "zk_msm_srs_noalloc",
+           "zk_quotient_polyiop", "zk_calibrate_mad_rate")
 
 
 class ZkError(RuntimeError):
@@ -61,6 +62,8 @@ def _load():
         "zk_msm_batch": ([P, P, P, U32, P, P], I),
         "zk_kzg_open": ([P, P, U64, P, P, P, P, P], I),
         "zk_quotient_mul": ([P, P, P, P, U32, U32, P, P, P, P], I),
+        "zk_quotient_polyiop": ([P, P, U32, U32, P, U32, U32, P, P, P, P], I),
+        "zk_calibrate_mad_rate": ([U32, U32, ctypes.POINTER(ctypes.c_double), P], I),
         "zk_transcript_challenge": ([P, U64, P, P], I),
         "zk_srs_g2_setup": ([P, U64, P, P], I),
         "zk_srs_g2_create": ([P, U64, ctypes.POINTER(ctypes.c_void_p), P], I),
@@ -381,6 +384,57 @@ def quotient_mul(srs, a, b, c, log_blowup=1, shift=None, t=None, com=None):
     return t, com
 
 
+POLYIOP_MAX_WITNESS, POLYIOP_MAX_TERMS, POLYIOP_MAX_DEGREE = 8, 16, 4
+
+
+class ConstraintTerm(ctypes.Structure):
+    """zk_constraint_term: coeff (8 words), nfactors, factor[4]."""
+    _fields_ = [("coeff", ctypes.c_uint32 * 8), ("nfactors", ctypes.c_uint32),
+                ("factor", ctypes.c_uint32 * POLYIOP_MAX_DEGREE)]
+
+
+def _terms_array(terms):
+    arr = (ConstraintTerm * max(len(terms), 1))()
+    for t, (c, factors) in enumerate(terms):
+        c = int(c)
+        for i in range(8):
+            arr[t].coeff[i] = (c >> (32 * i)) & 0xFFFFFFFF
+        arr[t].nfactors = len(factors)
+        for i, a in enumerate(list(factors)[:POLYIOP_MAX_DEGREE]):
+            arr[t].factor[i] = int(a)
+    return arr
+
+
+def quotient_polyiop(srs, evals, terms, log_blowup=1, shift=None, q=None, com=None):
+    """Poly-IOP quotient Q = R(f(x), f(omega x)) / (X^n - 1) and [Q(tau)]_1.
+    evals: (N, n, 8) device tensor of witness vectors on H; terms: list of
+    (coefficient int < r, [factor indices]) with index a < N for f_a(x) and
+    N <= a < 2N for f_(a-N)(omega x).  Returns (q (max(d - 1, 1) n, 8), com)."""
+    torch = _torch()
+    if (not isinstance(evals, torch.Tensor) or not evals.is_cuda or evals.dim() != 3 or evals.shape[2] != 8
+            or evals.dtype != torch.int32 or not evals.is_contiguous()):
+        raise TypeError("evals must be a contiguous int32 device tensor of shape (N, n, 8)")
+    N, n = int(evals.shape[0]), int(evals.shape[1])
+    L = n.bit_length() - 1
+    if (1 << L) != n:
+        raise ValueError("length must be a power of two")
+    d = max((len(f) for _, f in terms), default=0)
+    qlen = max(d - 1, 1) * n
+    if q is None:
+        q = torch.empty((qlen, 8), dtype=torch.int32, device=evals.device)
+    elif q.shape[0] < qlen:
+        raise ValueError("q needs %d rows" % qlen)
+    if com is None:
+        com = torch.empty((1, 16), dtype=torch.int32, device=evals.device)
+    arr = _terms_array(terms)
+    sp = None
+    if shift is not None:
+        sa, sp = _host_fr(shift)
+    _check(lib.zk_quotient_polyiop(srs.handle, _ptr(evals), N, L, ctypes.cast(arr, ctypes.c_void_p), len(terms),
+                                   int(log_blowup), sp, _ptr(q), _ptr(com), _stream(evals)))
+    return q, com
+
+
 def transcript_challenge(data, out=None):
     """Challenge (SHA-256(0||data) || SHA-256(1||data)) mod r of the bytes of
     the contiguous device tensor `data`.  Returns a (1, 8) device tensor."""
@@ -524,6 +578,15 @@ def release_cached_memory():
 
 
 # ---------------------------------------------------------------- observability
+
+def calibrate_mad_rate(blocks=2048, iters=4096):
+    """Sustained v_mad_u64_u32 products per second on the current device."""
+    torch = _torch()
+    rate = ctypes.c_double()
+    _check(lib.zk_calibrate_mad_rate(int(blocks), int(iters), ctypes.byref(rate),
+                                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return rate.value
+
 
 def profile_enable(on=True):
     _check(lib.zk_profile_enable(1 if on else 0))
