@@ -175,29 +175,50 @@ def cpu_baseline(tau_int, log_n=12):
 
 # ----------------------------------------------------------------- GPU
 
-def serving_runs(zk, srs, count):
-    """Poisson stream (mean 200 jobs/s) of commit jobs, sizes log-uniform
-    2^10..2^22, through the continuous-admission loop: 4 stream slots at a
-    generous and at a tight HBM budget, and one slot (plain per-call serial
-    execution of the same stream)."""
+def serving_runs(zk, srs, srs_pts, count):
+    """Poisson streams of commit-and-fold jobs (sizes log-uniform 2^10..2^22;
+    each job commits its witness and folds the commitment into its input
+    accumulator) through the continuous-admission loop, swept over the
+    offered rate: 4 stream slots against one slot (plain per-call serial
+    execution of the same stream), both at a 64 GiB budget, plus 4 slots at
+    a tight 4 GiB budget at the workload's 200 jobs/s.  Each record gives
+    achieved jobs/s, p50/p99 latency and the peak HBM the jobs held (caller
+    buffers, and the library's scratch including its cache)."""
     from paper_2507_07031_amd.serve import GpuExecutor, Job, serve, summarize
+    import torch
     seed = gen.CONFIG_SEEDS["serving"]
     sizes = gen.log_uniform_sizes(seed, count, 10, 22)
-    arrivals = gen.poisson_arrivals(seed, count, 200.0)
     pool_n = 1 << 23
     pool = zk.to_device(gen.uniform_fr(seed, pool_n, tag=1))
+    acc_pool = srs_pts[:4096].contiguous()
     rng = gen.rng_for(seed, 2)
     offs = rng.integers(0, pool_n - (1 << 22), size=count)
-    out = {"offered_jobs_per_s": 200.0, "jobs": count, "size_log2_range": [10, 22]}
-    for name, slots, budget in (("continuous_4slots_64GiB", 4, 64 << 30),
-                                ("continuous_4slots_4GiB", 4, 4 << 30),
-                                ("serial_1slot", 1, 64 << 30)):
-        jobs = [Job(i, int(n), float(a), int(o)) for i, (n, a, o) in enumerate(zip(sizes, arrivals, offs))]
-        ex = GpuExecutor(zk, srs, pool, slots)
+    accs = rng.integers(0, 4096, size=count)
+    out = {"jobs_per_point": count, "size_log2_range": [10, 22], "job": "commit (iNTT, MSM, 4x coset) + fold",
+           "points": []}
+    runs = [(rate, "continuous_4slots", 4, 64 << 30) for rate in (200.0, 400.0, 800.0, 1600.0)]
+    runs += [(rate, "serial_1slot", 1, 64 << 30) for rate in (200.0, 400.0, 800.0, 1600.0)]
+    runs += [(200.0, "continuous_4slots_4GiB", 4, 4 << 30)]
+    for rate, mode, slots, budget in runs:
+        arrivals = gen.poisson_arrivals(seed, count, rate)
+        jobs = [Job(i, int(n), float(a), int(o), int(c))
+                for i, (n, a, o, c) in enumerate(zip(sizes, arrivals, offs, accs))]
+        zk.release_cached_memory()
+        torch.cuda.synchronize()
+        ex = GpuExecutor(zk, srs, pool, slots, acc_pool=acc_pool, budget=budget)
         fin, rej, wall = serve(jobs, ex, budget, slots)
+        torch.cuda.synchronize()
         rec = summarize(fin, wall)
-        rec["rejected"] = len(rej)
-        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rec.items()}
+        rec.update({"offered_jobs_per_s": rate, "mode": mode, "slots": slots, "budget_gib": budget >> 30,
+                    "rejected": len(rej), "peak_scratch_held_mb": round(ex.peak_scratch / 2 ** 20, 1),
+                    "peak_caller_mb": round(ex.peak_caller / 2 ** 20, 1), "busy_refusals": ex.busy_events})
+        out["points"].append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in rec.items()})
+        log("serving %s %.0f/s: %.1f jobs/s p99 %.2f ms" % (mode, rate, rec.get("jobs_per_s", 0),
+                                                             rec.get("p99_ms", 0)))
+    zk.set_scratch_budget(0)
+    for mode in ("continuous_4slots", "serial_1slot"):
+        pts = [p for p in out["points"] if p["mode"] == mode]
+        out["saturation_jobs_per_s_" + mode] = max(p.get("jobs_per_s", 0) for p in pts)
     return out
 
 
@@ -208,9 +229,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--serve-jobs", type=int, default=2000)
+    ap.add_argument("--serve-jobs", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--mad-calibration", action="store_true",
+                    help="only measure the sustained v_mad_u64_u32 rate (the integer roof's basis)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -230,6 +253,15 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": 1 << 30, "dispatches": 3}))
+        return
+    if args.mad_calibration:
+        # 2048 workgroups x 256 threads x 8 dependent chains x 4096 x 16 steps
+        rates = [zk.calibrate_mad_rate(2048, 4096) for _ in range(5)]
+        best = max(rates)
+        print(json.dumps({"mad_rate_tops": [round(r / 1e12, 3) for r in rates], "best_tops": round(best / 1e12, 3),
+                          "issue_peak_tops": round(PEAK_MAD_TOPS, 3),
+                          "sustained_over_issue_peak": round(best / 1e12 / PEAK_MAD_TOPS, 4),
+                          "products_per_run": 2048 * 256 * 4096 * 16 * 8}))
         return
     n = 1 << 20
     tau = gen.tau_scalar()
@@ -519,6 +551,50 @@ def main():
         extras["quotient_mul_2^20"] = quot
         del qa, qb, qc, qt
 
+        log("poly-iop quotient 2^20")
+        # the Poly-IOP quotient Q = R(f(x), f(omega x)) / (X^n - 1) on a 2x
+        # coset for two constraints over 2^20-point witnesses: BooleanCheck
+        # R = f (1 - f) (one witness) and a running product
+        # R = z(omega x) - z(x) f(x) (two witnesses, one read omega-shifted)
+        pseed = gen.CONFIG_SEEDS["commit"]
+        Rm = gen.FR_MODULUS
+        bits = gen.rng_for(pseed, 41).integers(0, 2, size=n).astype(np.uint32)
+        bool_h = np.zeros((1, n, 8), dtype=np.uint32)
+        bool_h[0, :, 0] = bits
+        fv = [v or 1 for v in gen.limbs_to_ints(gen.uniform_fr(pseed, n, tag=42))]
+        prod = 1
+        for v in fv[:-1]:
+            prod = prod * v % Rm
+        fv[-1] = pow(prod, -1, Rm)
+        zv = [gen.limbs_to_ints(gen.uniform_fr(pseed, 1, tag=43))[0] or 1]
+        for i in range(n - 1):
+            zv.append(zv[-1] * fv[i] % Rm)
+        rp_h = np.stack([gen.ints_to_limbs(zv), gen.ints_to_limbs(fv)])
+        cases = {"boolean_check": (zk.to_device(bool_h), [(1, [0]), (Rm - 1, [0, 0])]),
+                 "running_product": (zk.to_device(rp_h), [(1, [2]), (Rm - 1, [0, 1])])}
+        piop = {}
+        for name, (ev_d, terms) in cases.items():
+            qbuf = torch.empty((n, 8), dtype=torch.int32, device=dev)
+            t_p = timed(lambda: zk.quotient_polyiop(srs, ev_d, terms, log_blowup=1, q=qbuf, com=com), reps=5)
+            for reg in ("quot.pointwise", "ntt.pass", "msm.sort", "msm.accumulate", "msm.reduce"):
+                zk.profile_read(reg)
+            zk.profile_enable(True)
+            for _ in range(5):
+                zk.quotient_polyiop(srs, ev_d, terms, log_blowup=1, q=qbuf, com=com)
+            torch.cuda.synchronize()
+            zk.profile_enable(False)
+            pw = zk.profile_read("quot.pointwise")[0] / 5
+            nt = zk.profile_read("ntt.pass")[0] / 5
+            ms_ = sum(zk.profile_read(reg)[0] for reg in ("msm.sort", "msm.accumulate", "msm.reduce")) / 5
+            nwit = int(ev_d.shape[0])
+            big = 2 * n
+            piop[name] = {"witnesses": nwit, "ms": round(t_p, 4), "quotients_per_s": round(1e3 / t_p, 2),
+                          "transforms_ms": round(nt, 4), "msm_ms": round(ms_, 4), "pointwise_ms": round(pw, 4),
+                          "pointwise_hbm_frac": round((nwit + 1) * 32 * big / (pw / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+            del qbuf
+        extras["polyiop_quotient_2^20"] = piop
+        del cases, bool_h, rp_h, zv, fv
+
         log("lagrange commit 2^20")
         # commitments to a 2^20 vector of quantized activations as evaluations
         # on H: against the Lagrange-basis SRS (the vector's entries are the
@@ -631,11 +707,33 @@ def main():
             for b in range(256):
                 zk.msm_srs(srs, views[b], out=outs[b:b + 1])
         t_call = timed(per_call, reps=3)
+        per_call_outs = zk.to_host(outs).copy()
+        # the same 256 commitments as zk_msm_srs_noalloc calls (no allocation,
+        # no host synchronisation): run directly, and captured once into a
+        # HIP graph (torch.cuda.graph on one stream) and replayed
+        cap = torch.empty((256, 16), dtype=torch.int32, device=dev)
+
+        def noalloc_calls():
+            for b in range(256):
+                zk.msm_srs_noalloc(srs, views[b], cap[b:b + 1])
+        t_noalloc = timed(noalloc_calls, reps=3)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            noalloc_calls()
+        torch.cuda.synchronize()
+        cap.fill_(0)
+        t_graph = timed(graph.replay, reps=3)
+        graph_same = bool(np.array_equal(zk.to_host(cap), per_call_outs))
+        del graph
         tot = int(off[-1])
         extras["batched_256"] = {"total_points": tot, "batched_ms": round(t_batch, 3),
                                  "per_call_ms": round(t_call, 3), "batched_points_per_s": tot / (t_batch / 1e3),
                                  "per_call_points_per_s": tot / (t_call / 1e3),
-                                 "batched_over_per_call": round(t_call / t_batch, 3)}
+                                 "batched_over_per_call": round(t_call / t_batch, 3),
+                                 "noalloc_per_call_ms": round(t_noalloc, 3),
+                                 "graph_replay_ms": round(t_graph, 3),
+                                 "graph_points_per_s": tot / (t_graph / 1e3),
+                                 "graph_matches_per_call": graph_same}
         log("fold 64")
         inst = outs[:64].contiguous().reshape(64, 1, 16)
         gam = zk.to_device(gen.uniform_fr(gen.CONFIG_SEEDS["batched"], 63, tag=2))
@@ -645,7 +743,7 @@ def main():
         del sc, outs
 
         log("serving")
-        extras["serving"] = serving_runs(zk, srs, args.serve_jobs)
+        extras["serving"] = serving_runs(zk, srs, srs_pts, args.serve_jobs)
         # the largest transform, 2^28 points (three LDS passes), on a dense
         # input of canonical values (top word cut to 29 bits, below r's); run
         # last, so that no other timed section follows the release of its

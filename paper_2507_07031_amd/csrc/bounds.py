@@ -70,6 +70,17 @@ def mul(a, b, q=None):
     return norm((a.val - 1) * (b.val - 1) // MONT_R + q + 1)
 
 
+def mul2(a, b, c, d, q=None):
+    """(a b + c d) / 2^261 with one reduction: both products' column sums
+    share the 64-bit accumulators."""
+    q = q or Q
+    la, lb = max(a.limb, a.top), max(b.limb, b.top)
+    lc, ld = max(c.limb, c.top), max(d.limb, d.top)
+    col = 9 * (la - 1) * (lb - 1) + 9 * (lc - 1) * (ld - 1) + 9 * MASK * MASK + (1 << 64) // (1 << LIMB)
+    assert col < (1 << 64), "column accumulator overflow"
+    return norm(((a.val - 1) * (b.val - 1) + (c.val - 1) * (d.val - 1)) // MONT_R + q + 1)
+
+
 def add(a, b):
     return V(a.val + b.val - 1, a.limb + b.limb - 1, a.top + b.top - 1)
 
@@ -91,10 +102,14 @@ def sub(a, b, c, q=None):
     return norm(a.val + c * q)
 
 
-# Subtraction multiples used by the kernels (field.h: K2, K4, K8).
-SUB_K = {"madd.P": 8, "madd.R": 8, "madd.X3": 4, "madd.QX": 8, "madd.Y3": 2,
-         "add.P": 8, "add.R": 8, "add.X3": 4, "add.QX": 8, "add.Y3": 2,
+# Subtraction multiples used by the kernels (field.h: K2, K4, K8).  In the
+# additions Y3 = R (Q - X3) - S PPP is one reduction of R (Q - X3) + (K - S) PPP,
+# with "nY1" / "nS1" the negation K - S.
+SUB_K = {"madd.P": 8, "madd.R": 8, "madd.X3": 4, "madd.QX": 8, "madd.nY1": 8,
+         "add.P": 8, "add.R": 8, "add.X3": 4, "add.QX": 8, "add.nS1": 8,
          "dbl.X3": 4, "dbl.SX": 8, "dbl.Y3": 2}
+
+ZERO = V(1, 1, 1)  # the constant 0 (bounds are exclusive)
 
 
 def madd(X1, Y1, ZZ1, ZZZ1, x2, y2):
@@ -109,9 +124,8 @@ def madd(X1, Y1, ZZ1, ZZZ1, x2, y2):
     T = add(add(PPP, Qv), Qv)
     X3 = sub(R2, T, SUB_K["madd.X3"])
     QX = sub(Qv, X3, SUB_K["madd.QX"])
-    A = mul(Rv, QX)
-    B = mul(Y1, PPP)
-    Y3 = sub(A, B, SUB_K["madd.Y3"])
+    nY1 = sub(ZERO, Y1, SUB_K["madd.nY1"])
+    Y3 = mul2(Rv, QX, nY1, PPP)
     return X3, Y3, mul(ZZ1, PP), mul(ZZZ1, PPP)
 
 
@@ -129,9 +143,8 @@ def add_xyzz(X1, Y1, ZZ1, ZZZ1, X2, Y2, ZZ2, ZZZ2):
     T = add(add(PPP, Qv), Qv)
     X3 = sub(R2, T, SUB_K["add.X3"])
     QX = sub(Qv, X3, SUB_K["add.QX"])
-    A = mul(Rv, QX)
-    B = mul(S1, PPP)
-    Y3 = sub(A, B, SUB_K["add.Y3"])
+    nS1 = sub(ZERO, S1, SUB_K["add.nS1"])
+    Y3 = mul2(Rv, QX, nS1, PPP)
     return X3, Y3, mul(mul(ZZ1, ZZ2), PP), mul(mul(ZZZ1, ZZZ2), PPP)
 
 

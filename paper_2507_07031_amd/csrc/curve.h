@@ -7,7 +7,9 @@
 // Formulas: mixed addition madd-2008-s, addition add-2008-s and doubling
 // dbl-2008-s-1 of the Explicit-Formulas Database for XYZZ coordinates
 // (a = 0).  The subtraction multiples (K2/K4/K8) are the ones bounds.py
-// proves safe.
+// proves safe.  Both additions form Y3 = R (Q - X3) - S PPP (S = Y1, or
+// S1 = Y1 ZZZ2) as one Montgomery reduction of both products' column sums
+// (mont_mul2), with -S written as 8q - S.
 #pragma once
 #include "field.h"
 
@@ -100,7 +102,8 @@ ZK_HD xyzz madd(const xyzz& a, const aff& p) {
   const f29 Q = mont_mul<Fq>(a.X, PP);
   xyzz r;
   r.X = sub_k(mont_sqr<Fq>(R), add(add(PPP, Q), Q), Fq::K4);
-  r.Y = sub_k(mont_mul<Fq>(R, sub_k(Q, r.X, Fq::K8)), mont_mul<Fq>(a.Y, PPP), Fq::K2);
+  // Y3 = R (Q - X3) - Y1 PPP with one reduction: -Y1 as 8q - Y1
+  r.Y = mont_mul2<Fq>(R, sub_k(Q, r.X, Fq::K8), sub_k(f29_zero(), a.Y, Fq::K8), PPP);
   r.ZZ = mont_mul<Fq>(a.ZZ, PP);
   r.ZZZ = mont_mul<Fq>(a.ZZZ, PPP);
   return r;
@@ -124,7 +127,8 @@ ZK_HD xyzz add(const xyzz& a, const xyzz& b) {
   const f29 Q = mont_mul<Fq>(U1, PP);
   xyzz r;
   r.X = sub_k(mont_sqr<Fq>(R), add(add(PPP, Q), Q), Fq::K4);
-  r.Y = sub_k(mont_mul<Fq>(R, sub_k(Q, r.X, Fq::K8)), mont_mul<Fq>(S1, PPP), Fq::K2);
+  // Y3 = R (Q - X3) - S1 PPP with one reduction: -S1 as 8q - S1
+  r.Y = mont_mul2<Fq>(R, sub_k(Q, r.X, Fq::K8), sub_k(f29_zero(), S1, Fq::K8), PPP);
   r.ZZ = mont_mul<Fq>(mont_mul<Fq>(a.ZZ, b.ZZ), PP);
   r.ZZZ = mont_mul<Fq>(mont_mul<Fq>(a.ZZZ, b.ZZZ), PPP);
   return r;

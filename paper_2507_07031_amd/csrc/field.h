@@ -112,16 +112,18 @@ ZK_HD f29 sub_k(const f29& a, const f29& b, const uint32_t (&k)[N]) {
   return normalize(r);
 }
 
-// Montgomery product a * b * 2^-261 mod q (lazily reduced, normalised limbs).
-template <class F>
-ZK_HD f29 mont_mul(const f29& a, const f29& b) {
-  uint64_t acc[18];
-#pragma unroll
-  for (int k = 0; k < 18; k++) acc[k] = 0;
+// Column sums of a * b: acc[i + j] += a_i b_j (one v_mad_u64_u32 each).
+ZK_HD void mul_cols(uint64_t (&acc)[18], const f29& a, const f29& b) {
 #pragma unroll
   for (int i = 0; i < 9; i++)
 #pragma unroll
     for (int j = 0; j < 9; j++) acc[i + j] += (uint64_t)a.l[i] * b.l[j];
+}
+
+// Montgomery reduction of 18 column sums: value * 2^-261 mod q (lazily
+// reduced, normalised limbs).
+template <class F>
+ZK_HD f29 mont_reduce(uint64_t (&acc)[18]) {
 #pragma unroll
   for (int k = 0; k < 9; k++) {
     const uint32_t m = ((uint32_t)acc[k] * F::INV) & MASK29;
@@ -139,6 +141,31 @@ ZK_HD f29 mont_mul(const f29& a, const f29& b) {
   return r;
 }
 
+// Montgomery product a * b * 2^-261 mod q (lazily reduced, normalised limbs).
+template <class F>
+ZK_HD f29 mont_mul(const f29& a, const f29& b) {
+  uint64_t acc[18];
+#pragma unroll
+  for (int k = 0; k < 18; k++) acc[k] = 0;
+  mul_cols(acc, a, b);
+  return mont_reduce<F>(acc);
+}
+
+// (a * b + c * d) * 2^-261 mod q with one reduction: the two products'
+// column sums share the accumulators (18 terms per column, still far below
+// 2^64 for normalised limbs), which saves a whole reduction where a formula
+// subtracts one product from another (pass the subtrahend's negation, a
+// multiple of q minus it, as c).
+template <class F>
+ZK_HD f29 mont_mul2(const f29& a, const f29& b, const f29& c, const f29& d) {
+  uint64_t acc[18];
+#pragma unroll
+  for (int k = 0; k < 18; k++) acc[k] = 0;
+  mul_cols(acc, a, b);
+  mul_cols(acc, c, d);
+  return mont_reduce<F>(acc);
+}
+
 // Squaring: cross products once, doubled, plus the diagonal.
 template <class F>
 ZK_HD f29 mont_sqr(const f29& a) {
@@ -153,21 +180,7 @@ ZK_HD f29 mont_sqr(const f29& a) {
   for (int k = 0; k < 18; k++) acc[k] <<= 1;
 #pragma unroll
   for (int i = 0; i < 9; i++) acc[2 * i] += (uint64_t)a.l[i] * a.l[i];
-#pragma unroll
-  for (int k = 0; k < 9; k++) {
-    const uint32_t m = ((uint32_t)acc[k] * F::INV) & MASK29;
-#pragma unroll
-    for (int j = 0; j < 9; j++) acc[k + j] += (uint64_t)m * F::M[j];
-    acc[k + 1] += acc[k] >> 29;
-  }
-  f29 r;
-#pragma unroll
-  for (int k = 9; k < 17; k++) {
-    r.l[k - 9] = (uint32_t)acc[k] & MASK29;
-    acc[k + 1] += acc[k] >> 29;
-  }
-  r.l[8] = (uint32_t)acc[17];
-  return r;
+  return mont_reduce<F>(acc);
 }
 
 // If a >= c*q (normalised limbs, c*q given normalised) return a - c*q else a.

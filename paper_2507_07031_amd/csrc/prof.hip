@@ -36,7 +36,39 @@ hipEvent_t take_event() {
   return e;
 }
 
+// Issue-rate calibration of v_mad_u64_u32 (the Montgomery products' only
+// multiply): 8 independent dependent chains per thread, each step
+// acc = lo32(acc) * b + acc, so the compiler can neither fold nor hoist the
+// products.  MAD_UNROLL * 8 products per thread per iteration.
+constexpr uint32_t MAD_UNROLL = 16;
+
+__global__ __launch_bounds__(256) void mad_rate_kernel(uint32_t iters, uint32_t seed, uint32_t* sink) {
+  uint64_t acc[8];
+  const uint32_t b = seed ^ (threadIdx.x * 2654435761u) ^ 1u;
+#pragma unroll
+  for (int k = 0; k < 8; k++) acc[k] = (uint64_t)(seed + k) * 0x9e3779b97f4a7c15ull + threadIdx.x;
+  for (uint32_t it = 0; it < iters; it++) {
+#pragma unroll
+    for (uint32_t r = 0; r < MAD_UNROLL; r++)
+#pragma unroll
+      for (int k = 0; k < 8; k++) acc[k] += (uint64_t)(uint32_t)acc[k] * b;
+  }
+  uint64_t x = 0;
+#pragma unroll
+  for (int k = 0; k < 8; k++) x ^= acc[k];
+  if ((uint32_t)x == seed) sink[0] = (uint32_t)(x >> 32);  // keeps every chain live
+}
+
 }  // namespace
+
+uint64_t prof_mad_count(uint32_t blocks, uint32_t iters) {
+  return (uint64_t)blocks * 256 * iters * MAD_UNROLL * 8;
+}
+
+hipError_t prof_mad_rate_launch(uint32_t blocks, uint32_t iters, uint32_t* sink, hipStream_t s) {
+  hipLaunchKernelGGL(mad_rate_kernel, dim3(blocks), dim3(256), 0, s, iters, 0x2545f491u, sink);
+  return hipGetLastError();
+}
 
 bool prof_enabled() { return g_on.load(std::memory_order_relaxed); }
 

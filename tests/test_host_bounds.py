@@ -51,8 +51,8 @@ def test_sub_multiples_match_curve_formulas(bounds):
     # sub_k's multiple is written before the outer one's), against the names
     # bounds.py gives them in the order its replay performs them
     order = {
-        "ZK_HD xyzz madd(": ["madd.P", "madd.R", "madd.X3", "madd.QX", "madd.Y3"],
-        "ZK_HD xyzz add(const xyzz& a, const xyzz& b)": ["add.P", "add.R", "add.X3", "add.QX", "add.Y3"],
+        "ZK_HD xyzz madd(": ["madd.P", "madd.R", "madd.X3", "madd.QX", "madd.nY1"],
+        "ZK_HD xyzz add(const xyzz& a, const xyzz& b)": ["add.P", "add.R", "add.X3", "add.QX", "add.nS1"],
         "ZK_HD xyzz dbl(": ["dbl.X3", "dbl.SX", "dbl.Y3"],
     }
     for sig, names in order.items():
