@@ -6,6 +6,10 @@ hash to the field: the 512-bit little-endian integer formed by
 SHA-256(0x00 || data) followed by SHA-256(0x01 || data), reduced mod r (two
 digests, so the reduction's bias is below 2^-250).  SHA-256 is the standard
 library's.
+
+Parity unpinned: the paper fixes no instantiation of these oracles, so no
+value outside this build pins the composition; the tests pin only the
+SHA-256 it calls (FIPS 180-4 example digests) and the challenge's range.
 """
 import hashlib
 
