@@ -153,6 +153,38 @@ zk_status zk_srs_set_table_policy(zk_srs* srs, uint64_t small_max, uint64_t larg
  * for NULL / n > zk_srs_size. */
 uint32_t zk_srs_window_bits(const zk_srs* srs, uint64_t n);
 
+/* Launch schedule of the MSM and transform kernels on the current device:
+ * the knobs paper_2507_07031_amd/autotune.py tunes besides the table policy.
+ * No result depends on them, only times.  In zk_set_schedule a field of 0
+ * keeps the built-in value (and a NULL schedule restores every default);
+ * zk_get_schedule returns the values in effect.  Set while no call on the
+ * device is being enqueued.
+ *  acc_max_slice      most sorted (bucket, point) entries one accumulating
+ *                     thread takes per round of workgroups, 16..4096 (256)
+ *  acc_blocks_per_cu  accumulation workgroups per compute unit and round, 1..4 (2)
+ *  reduce_chunk       buckets per chunk of the running-sum bucket reduction,
+ *                     a power of two <= 64 (built-in: 4, 8 or 16 by bucket count)
+ *  sort_chunk         scalars per coarse-sort workgroup, a power of two in
+ *                     256..16384 (1024)
+ *  sort_bin_entries   entries per coarse bin the two-level bucket sort aims
+ *                     at, a power of two in 2^10..2^20 (2^15)
+ *  ntt_tile_log       preferred transform tile, 11 (2^11 points where both
+ *                     passes fit it) or 12 (2^12 points) (12)
+ *  ntt_unit_log       transform stages per LDS round trip: 3 (each thread
+ *                     holds 8 points) or 2 (4 points, more threads) (3)
+ * ZK_EINVAL for a value out of range (nothing is changed then). */
+typedef struct zk_schedule {
+  uint32_t acc_max_slice;
+  uint32_t acc_blocks_per_cu;
+  uint32_t reduce_chunk;
+  uint32_t sort_chunk;
+  uint32_t sort_bin_entries;
+  uint32_t ntt_tile_log;
+  uint32_t ntt_unit_log;
+} zk_schedule;
+zk_status zk_set_schedule(const zk_schedule* schedule_host);
+zk_status zk_get_schedule(zk_schedule* schedule_host);
+
 /* KZG commitment to coefficients: *out = sum_{i<n} scalars[i] [tau^i]_1 over
  * the first n points of the prepared SRS (n <= zk_srs_size(srs)). */
 zk_status zk_msm_srs(const zk_srs* srs, const zk_fr* scalars, uint64_t n, zk_g1* out, void* stream);

@@ -15,6 +15,7 @@
 
 #include "../../include/zk.h"
 #include "accum.h"
+#include "device.h"
 #include "field.h"
 #include "g2msm.h"
 #include "msm.h"
@@ -342,6 +343,8 @@ struct NttRun {
 zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t L, bool inverse, const f29* pre_lo,
                       const f29* pre_hi, uint32_t valid_n, hipStream_t s, NttRun& r) {
   const uint32_t T = ntt_tile_log();
+  const Schedule sched = device_schedule();
+  r.a.unit_log = r.b.unit_log = r.c.unit_log = sched.ntt_unit_log;
   const f29* lo = inverse ? c->tw[2] : c->tw[0];
   const f29* hi = inverse ? c->tw[3] : c->tw[1];
   const f29* scale = inverse ? c->ninv + L : nullptr;
@@ -372,8 +375,9 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   // transforms and its strided reads move more than one element at a time
   const uint32_t mA = three ? (L + 2) / 3 : L / 2, mB = L - mA;
   const uint32_t N1 = 1u << mB, N2 = 1u << mA;
-  // tiles of 2048 points where both passes fit (two workgroups per CU), else 4096
-  const uint32_t tile = !three && mB <= T - 1 ? (1u << (T - 1)) : (1u << T);
+  // tiles of 2048 points where both passes fit (two workgroups per CU) and
+  // the schedule prefers them, else 4096
+  const uint32_t tile = !three && mB <= T - 1 && sched.ntt_tile_log < T ? (1u << (T - 1)) : (1u << T);
   zk_status st = scratch_alloc(r.tmp, (size_t)32 << L, s);
   if (st) return st;
   uint32_t* Y = static_cast<uint32_t*>(r.tmp.p);
@@ -587,6 +591,64 @@ uint64_t zk_scratch_held(void) {
   }
   std::lock_guard<std::mutex> lk(g_cache_mu);
   return g_held[dev];
+}
+
+zk_status zk_set_schedule(const zk_schedule* sch) {
+  const int dev = schedule_device();
+  if (dev < 0) return fail(ZK_EDEVICE, "zk_set_schedule: no device");
+  Schedule v;
+  if (sch) {
+    auto pow2 = [](uint32_t x) { return x && !(x & (x - 1)); };
+    if (sch->acc_max_slice) {
+      if (sch->acc_max_slice < 16 || sch->acc_max_slice > 4096)
+        return fail(ZK_EINVAL, "zk_set_schedule: acc_max_slice must be 16..4096");
+      v.acc_max_slice = sch->acc_max_slice;
+    }
+    if (sch->acc_blocks_per_cu) {
+      if (sch->acc_blocks_per_cu > 4) return fail(ZK_EINVAL, "zk_set_schedule: acc_blocks_per_cu must be 1..4");
+      v.acc_blocks_per_cu = sch->acc_blocks_per_cu;
+    }
+    if (sch->reduce_chunk) {
+      if (!pow2(sch->reduce_chunk) || sch->reduce_chunk > 64)
+        return fail(ZK_EINVAL, "zk_set_schedule: reduce_chunk must be a power of two <= 64");
+      v.reduce_chunk = sch->reduce_chunk;
+    }
+    if (sch->sort_chunk) {
+      if (!pow2(sch->sort_chunk) || sch->sort_chunk < 256 || sch->sort_chunk > 16384)
+        return fail(ZK_EINVAL, "zk_set_schedule: sort_chunk must be a power of two in 256..16384");
+      v.sort_chunk = sch->sort_chunk;
+    }
+    if (sch->sort_bin_entries) {
+      if (!pow2(sch->sort_bin_entries) || sch->sort_bin_entries < (1u << 10) || sch->sort_bin_entries > (1u << 20))
+        return fail(ZK_EINVAL, "zk_set_schedule: sort_bin_entries must be a power of two in 2^10..2^20");
+      v.sort_bin_entries = sch->sort_bin_entries;
+    }
+    if (sch->ntt_tile_log) {
+      if (sch->ntt_tile_log != 11 && sch->ntt_tile_log != 12)
+        return fail(ZK_EINVAL, "zk_set_schedule: ntt_tile_log must be 11 or 12");
+      v.ntt_tile_log = sch->ntt_tile_log;
+    }
+    if (sch->ntt_unit_log) {
+      if (sch->ntt_unit_log != 2 && sch->ntt_unit_log != 3)
+        return fail(ZK_EINVAL, "zk_set_schedule: ntt_unit_log must be 2 or 3");
+      v.ntt_unit_log = sch->ntt_unit_log;
+    }
+  }
+  schedule_slots()[dev] = v;
+  return ZK_OK;
+}
+
+zk_status zk_get_schedule(zk_schedule* sch) {
+  if (!sch) return fail(ZK_EINVAL, "zk_get_schedule: NULL argument");
+  const Schedule v = device_schedule();
+  sch->acc_max_slice = v.acc_max_slice;
+  sch->acc_blocks_per_cu = v.acc_blocks_per_cu;
+  sch->reduce_chunk = v.reduce_chunk;
+  sch->sort_chunk = v.sort_chunk;
+  sch->sort_bin_entries = v.sort_bin_entries;
+  sch->ntt_tile_log = v.ntt_tile_log;
+  sch->ntt_unit_log = v.ntt_unit_log;
+  return ZK_OK;
 }
 
 zk_status zk_set_validate(int on) {

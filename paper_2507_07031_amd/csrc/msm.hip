@@ -948,15 +948,12 @@ uint32_t msm_default_c(uint32_t n) {
 // 4096 takes MSMs of 2^14 / 2^16 points from 0.51 / 0.61 ms to 0.40 / 0.50
 // ms (four times the workgroups to spread the digit counting over), with
 // 2^20 and 2^22 unchanged within run-to-run noise.
-constexpr uint32_t MSM_SORT_CHUNK = 1024;
-constexpr uint32_t ACC_BLOCKS_PER_CU = 2;
 constexpr uint32_t ACC_MIN_L = 4;
-constexpr uint64_t ACC_MAX_L = 256;
 
-static void plan_common(MsmPlan& p) {
+static void plan_common(MsmPlan& p, const Schedule& sch) {
   p.groups = p.nseg * p.Wb;
   p.nbins = p.groups * p.K;
-  // coarse bins of 2^S bins each, sized for about 32768 entries per coarse
+  // coarse bins of 2^S bins each, sized for about sort_bin_entries (32768 by default) entries per coarse
   // bin when digits are spread evenly: a fine-level block of 4096 entries
   // then meets one or two coarse bins (few distinct bins, long runs), while
   // coarse-level blocks still write runs of useful length (measured best of
@@ -964,27 +961,29 @@ static void plan_common(MsmPlan& p) {
   {
     const uint64_t ent = (uint64_t)p.n * p.W;
     uint32_t S = 0;
-    while (S < 8 && S + 1 < p.c && (ent << (S + 1)) <= 32768ull * p.nbins) S++;
+    while (S < 8 && S + 1 < p.c && (ent << (S + 1)) <= (uint64_t)sch.sort_bin_entries * p.nbins) S++;
     // a coarse-level block histograms Wb*K >> S coarse bins in LDS (<= 64 KB)
     while (((p.Wb * p.K) >> S) > 16384u) S++;
     p.S = S;
   }
   p.ncoarse = p.nbins >> p.S;
   const uint64_t entries = (uint64_t)p.n * p.W;
-  // Accumulation grid: whole rounds of ACC_BLOCKS_PER_CU workgroups per
+  // Accumulation grid: whole rounds of acc_blocks_per_cu workgroups per
   // compute unit (a round is resident at once, so no unit waits on a partial
-  // last one), as few rounds as keep slices within ACC_MAX_L entries, and
+  // last one), as few rounds as keep slices within acc_max_slice entries, and
   // fewer workgroups when the n * W bound gives under ACC_MIN_L entries per
   // thread.  The kernel spreads the sorted total, known only on the device,
   // over the grid.
-  const uint64_t per_round = (uint64_t)device_compute_units() * ACC_BLOCKS_PER_CU * MSM_NT;
-  const uint64_t rounds = std::max<uint64_t>(1, (entries + per_round * ACC_MAX_L - 1) / (per_round * ACC_MAX_L));
+  const uint64_t per_round = (uint64_t)device_compute_units() * sch.acc_blocks_per_cu * MSM_NT;
+  const uint64_t max_l = sch.acc_max_slice;
+  const uint64_t rounds = std::max<uint64_t>(1, (entries + per_round * max_l - 1) / (per_round * max_l));
   p.L = ACC_MIN_L;
   p.acc_blocks = (uint32_t)cdiv(std::min<uint64_t>(rounds * per_round, cdiv(entries, ACC_MIN_L)), MSM_NT);
   if (p.acc_blocks == 0) p.acc_blocks = 1;
   // chunk length: short chains for one or a few bucket sets (latency), longer
   // ones when many sets already fill the chip (less bit-slice work)
   uint32_t lb = (uint64_t)p.groups * p.K >= (1u << 20) ? 16 : (p.K > (1u << 15) ? 8 : 4);
+  if (sch.reduce_chunk) lb = sch.reduce_chunk;
   if (lb > p.K) lb = p.K;
   p.LB = lb;
   p.lgLB = 31 - __builtin_clz(lb);
@@ -1007,9 +1006,10 @@ MsmPlan msm_plan_generic(uint32_t n, uint32_t c) {
   p.nseg = 1;
   p.Wb = p.W;
   p.tab_stride = 0;
-  p.chunk = MSM_SORT_CHUNK;
+  const Schedule sch = device_schedule();
+  p.chunk = sch.sort_chunk;
   p.nitems = cdiv(n, p.chunk);
-  plan_common(p);
+  plan_common(p, sch);
   return p;
 }
 
@@ -1023,10 +1023,11 @@ MsmPlan msm_plan_table(const uint64_t* off, uint32_t nmsm, uint32_t c, uint32_t 
   p.nseg = nmsm;
   p.Wb = 1;
   p.tab_stride = tab_stride;
-  p.chunk = MSM_SORT_CHUNK;
+  const Schedule sch = device_schedule();
+  p.chunk = sch.sort_chunk;
   p.nitems = 0;
   for (uint32_t b = 0; b < nmsm; b++) p.nitems += cdiv(off[b + 1] - off[b], p.chunk);
-  plan_common(p);
+  plan_common(p, sch);
   return p;
 }
 

@@ -32,6 +32,7 @@ struct NttPass {
   const f29* pre_lo;   // coset: multiply input i by g^i (nullptr: none)
   const f29* pre_hi;
   const f29* post_scale;  // multiply every output by this constant (nullptr: none)
+  uint32_t unit_log;   // stages per LDS round trip at most: 3 (8 points a thread) or 2 (4 points)
 };
 
 hipError_t ntt_pass_setup();

@@ -160,8 +160,13 @@ __device__ __forceinline__ void dit_stages(uint32_t* lds, uint32_t s, uint32_t m
   }
 }
 
-__global__ void __launch_bounds__(NTT_THREADS)
-ntt_pass_kernel(NttPass a) {
+// MAXR = 3: a thread holds 8 points and runs up to three stages per LDS round
+// trip (fewer round trips; 178 VGPRs, two waves per SIMD).  MAXR = 2: 4
+// points and two stages (more round trips, but at most 128 VGPRs, so the two
+// workgroups a compute unit's LDS holds fill four waves per SIMD, which
+// hides the twiddle and LDS latencies better).
+template <int MAXR>
+__device__ __forceinline__ void ntt_pass_body(const NttPass& a) {
   extern __shared__ uint32_t lds[];
   const uint32_t M = 1u << a.m;
   const uint32_t g0 = blockIdx.x * a.G;
@@ -189,17 +194,15 @@ ntt_pass_kernel(NttPass a) {
   }
   __syncthreads();
 
-  // ---- decimation-in-time stages, up to three per LDS round trip
+  // ---- decimation-in-time stages, up to MAXR per LDS round trip
   for (uint32_t st = 1; st <= a.m;) {
     const uint32_t left = a.m - st + 1;
-    if (left >= 3 || left == 1) {
-      if (left == 1) {
-        dit_stages<1>(lds, st, a.m, TE, a.ladder);
-        st += 1;
-      } else {
-        dit_stages<3>(lds, st, a.m, TE, a.ladder);
-        st += 3;
-      }
+    if (left == 1) {
+      dit_stages<1>(lds, st, a.m, TE, a.ladder);
+      st += 1;
+    } else if (MAXR >= 3 && left >= 3) {
+      dit_stages<MAXR>(lds, st, a.m, TE, a.ladder);
+      st += MAXR;
     } else {
       dit_stages<2>(lds, st, a.m, TE, a.ladder);
       st += 2;
@@ -225,6 +228,13 @@ ntt_pass_kernel(NttPass a) {
                                  : (size_t)bb * a.b_out;
     st8(a.out + (ob + (size_t)k * a.s_out) * 8, w);
   }
+}
+
+__global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(NttPass a) { ntt_pass_body<3>(a); }
+
+__global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+ntt_pass_kernel_r2(NttPass a) {
+  ntt_pass_body<2>(a);
 }
 
 // Ladder of in-tile twiddles: ladder[2^(k-1) + j] = omega_(2^k)^j for
@@ -259,17 +269,24 @@ hipError_t ntt_launch_pass(const NttPass& p, hipStream_t s) {
   // workgroups share a CU, so one's loads and stores overlap the other's
   // butterflies
   const uint32_t te = (1u << p.m) * p.G;
-  uint32_t threads = te / 8;
+  const bool r2 = p.unit_log == 2;
+  uint32_t threads = te / (r2 ? 4 : 8);
   if (threads < 64) threads = 64;
   if (threads > NTT_THREADS) threads = NTT_THREADS;
   const ProfToken t = prof_begin("ntt.pass", s);
-  hipLaunchKernelGGL(ntt_pass_kernel, dim3(blocks), dim3(threads), (size_t)(te + te / 8 + 1) * 32, s, p);
+  if (r2)
+    hipLaunchKernelGGL(ntt_pass_kernel_r2, dim3(blocks), dim3(threads), (size_t)(te + te / 8 + 1) * 32, s, p);
+  else
+    hipLaunchKernelGGL(ntt_pass_kernel, dim3(blocks), dim3(threads), (size_t)(te + te / 8 + 1) * 32, s, p);
   prof_end(t, s);
   return hipGetLastError();
 }
 
 hipError_t ntt_pass_setup() {
-  return hipFuncSetAttribute((const void*)ntt_pass_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void*)ntt_pass_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)ntt_pass_lds_bytes());
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)ntt_pass_kernel_r2, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)ntt_pass_lds_bytes());
 }
 

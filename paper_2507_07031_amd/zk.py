@@ -28,7 +28,7 @@ EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_s
            "zk_srs_lagrange_setup", "zk_transcript_challenge", "zk_acc_fold",
            "zk_srs_g2_setup", "zk_srs_g2_create", "zk_srs_g2_destroy", "zk_srs_g2_size", "zk_msm_g2_srs",
            "zk_srs_set_table_policy", "zk_srs_window_bits", "zk_set_scratch_budget", "zk_scratch_held", "zk_msm_srs_noalloc",
-           "zk_quotient_polyiop", "zk_calibrate_mad_rate")
+           "zk_quotient_polyiop", "zk_calibrate_mad_rate", "zk_set_schedule", "zk_get_schedule")
 
 
 class ZkError(RuntimeError):
@@ -64,6 +64,8 @@ def _load():
         "zk_quotient_mul": ([P, P, P, P, U32, U32, P, P, P, P], I),
         "zk_quotient_polyiop": ([P, P, U32, U32, P, U32, U32, P, P, P, P], I),
         "zk_calibrate_mad_rate": ([U32, U32, ctypes.POINTER(ctypes.c_double), P], I),
+        "zk_set_schedule": ([P], I),
+        "zk_get_schedule": ([P], I),
         "zk_transcript_challenge": ([P, U64, P, P], I),
         "zk_srs_g2_setup": ([P, U64, P, P], I),
         "zk_srs_g2_create": ([P, U64, ctypes.POINTER(ctypes.c_void_p), P], I),
@@ -261,6 +263,33 @@ def srs_set_table_policy(srs, small_max, large_min):
     """n < small_max: 12-bit-window table (first 2^16 points); n >= large_min:
     20-bit (if built); 16-bit otherwise."""
     _check(lib.zk_srs_set_table_policy(srs.handle, int(small_max), int(large_min)))
+
+
+SCHEDULE_FIELDS = ("acc_max_slice", "acc_blocks_per_cu", "reduce_chunk", "sort_chunk", "sort_bin_entries",
+                   "ntt_tile_log", "ntt_unit_log")
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint32) for f in SCHEDULE_FIELDS]
+
+
+def set_schedule(values=None):
+    """Launch schedule of the current device from a dict of SCHEDULE_FIELDS
+    (missing or 0: built-in value); None restores every default."""
+    if values is None:
+        _check(lib.zk_set_schedule(None))
+        return
+    unknown = set(values) - set(SCHEDULE_FIELDS)
+    if unknown:
+        raise ValueError("unknown schedule fields: %s" % sorted(unknown))
+    sch = Schedule(*[int(values.get(f, 0)) for f in SCHEDULE_FIELDS])
+    _check(lib.zk_set_schedule(ctypes.byref(sch)))
+
+
+def get_schedule():
+    sch = Schedule()
+    _check(lib.zk_get_schedule(ctypes.byref(sch)))
+    return {f: int(getattr(sch, f)) for f in SCHEDULE_FIELDS}
 
 
 def srs_window_bits(srs, n):

@@ -36,3 +36,30 @@ def test_derive_policy_follows_timings():
     # the small-table threshold never passes the table's 2^16 points
     t3 = {1 << 16: {12: 0.1, 16: 0.2}}
     assert autotune.derive_policy(t3)["small_max"] == 1 << 16
+
+
+class FakeZkSchedule(FakeZk):
+    def __init__(self):
+        super().__init__()
+        self.schedule = None
+
+    def set_schedule(self, values):
+        self.schedule = values
+
+
+def test_apply_sets_schedule():
+    z = FakeZkSchedule()
+    autotune.apply(z, object(), {"small_max": 0, "large_min": 1 << 21, "schedule": {"sort_chunk": 2048}})
+    assert z.policy == (0, 1 << 21) and z.schedule == {"sort_chunk": 2048}
+
+
+def test_schedule_candidates_are_valid():
+    # the built-in value comes first, and every value is inside the range
+    # zk_set_schedule accepts
+    c = autotune.SCHEDULE_CANDIDATES
+    assert c["acc_max_slice"][0] == 256 and all(16 <= v <= 4096 for v in c["acc_max_slice"])
+    assert c["acc_blocks_per_cu"][0] == 2 and all(1 <= v <= 4 for v in c["acc_blocks_per_cu"])
+    assert c["reduce_chunk"][0] == 0 and all(v == 0 or (v & (v - 1)) == 0 and v <= 64 for v in c["reduce_chunk"])
+    assert c["sort_chunk"][0] == 1024 and all((v & (v - 1)) == 0 and 256 <= v <= 16384 for v in c["sort_chunk"])
+    assert all((v & (v - 1)) == 0 and 1 << 10 <= v <= 1 << 20 for v in c["sort_bin_entries"])
+    assert c["ntt_tile_log"] == [12, 11] and c["ntt_unit_log"] == [3, 2]

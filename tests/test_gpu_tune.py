@@ -74,3 +74,53 @@ def test_autotuner_policy(zk, tau, srs):
     with pytest.raises(zk.ZkError):
         zk.srs_set_table_policy(srs, (1 << 16) + 1, NEVER)
     zk.srs_set_table_policy(srs, 0, 1 << 21)
+
+
+def test_result_independent_of_schedule(zk, tau, srs):
+    # every candidate value of every launch-schedule knob (one at a time, the
+    # others at their built-in values) gives the identical commitment (2^16
+    # and 2^20 + 3 points, against the closed form), batch and transforms
+    import numpy as np
+    import torch
+    from paper_2507_07031_amd import autotune
+    s_h = gen.uniform_fr(9500, (1 << 20) + 3)
+    s = zk.to_device(s_h)
+    sv = fr_from_host(s_h)
+    want = {n: omsm.srs_msm_closed_form(tau[1], sv[:n]) for n in (1 << 16, (1 << 20) + 3)}
+    off = np.array([0, 3000, 3000 + (1 << 15), 3000 + (1 << 15) + 70000], dtype=np.uint64)
+    ev = zk.to_device(gen.uniform_fr(9501, 1 << 20))
+    zk.set_schedule(None)
+    ref_batch = zk.to_host(zk.msm_batch(srs, s, off)).copy()
+    ref_ntt = zk.to_host(zk.ntt(ev)).copy()
+    ref_coset = zk.to_host(zk.coset_ntt(ev, 2)).copy()
+    try:
+        for knob, values in autotune.SCHEDULE_CANDIDATES.items():
+            for v in values:
+                zk.set_schedule({knob: v})
+                assert zk.get_schedule()[knob] == v
+                log("schedule %s=%d" % (knob, v))
+                for n, w in want.items():
+                    assert _commit(zk, srs, s, n) == w, (knob, v, n)
+                assert np.array_equal(zk.to_host(zk.msm_batch(srs, s, off)), ref_batch), (knob, v)
+                assert np.array_equal(zk.to_host(zk.ntt(ev)), ref_ntt), (knob, v)
+                assert np.array_equal(zk.to_host(zk.coset_ntt(ev, 2)), ref_coset), (knob, v)
+        with pytest.raises(zk.ZkError) as ei:
+            zk.set_schedule({"sort_chunk": 1000})
+        assert ei.value.code == zk.ZK_EINVAL
+    finally:
+        zk.set_schedule(None)
+        torch.cuda.synchronize()
+
+
+def test_schedule_tuner_runs(zk, srs):
+    from paper_2507_07031_amd import autotune
+    s = zk.to_device(gen.uniform_fr(9600, 1 << 20))
+    ev = zk.to_device(gen.uniform_fr(9601, 1 << 20))
+    log("schedule tuner (one round)")
+    try:
+        res = autotune.tune_schedule(zk, srs, s, ev, reps=1)
+        assert set(res["schedule"]) == set(zk.SCHEDULE_FIELDS)
+        assert res["mix_ms"] <= res["default_mix_ms"]
+        assert zk.get_schedule() == res["schedule"]
+    finally:
+        zk.set_schedule(None)
