@@ -49,7 +49,7 @@ G2_FQ_PER_MADD = 28
 # HBM bytes of one accumulate dispatch of this workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE scaled by a plain-copy calibration (x2.0 / x1.0);
 # valid only for the kernel sources whose hash is recorded with it.
-ACCUMULATE_TRAFFIC = {"sources_sha256_16": "33f820a03327a8dc", "bytes": 2602378137}
+ACCUMULATE_TRAFFIC = {"sources_sha256_16": "3a8307ae2f1a6b69", "bytes": 3893451005}
 TRAFFIC_SOURCES = ("msm_accumulate.hip", "msm_store.h", "msm.h", "curve.h", "field.h", "field_constants.h")
 
 
@@ -231,7 +231,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain 1 GiB device copy (counter calibration)")
+                    help="only run a plain 1 GiB device copy and a 2^24-element Fr fold (counter calibration)")
     ap.add_argument("--mad-calibration", action="store_true",
                     help="only measure the sustained v_mad_u64_u32 rate (the integer roof's basis)")
     args = ap.parse_args()
@@ -252,7 +252,19 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": 1 << 30, "dispatches": 3}))
+        # a second kernel of known traffic: the accumulation step's Fr part
+        # v'' = gamma v + v' over 2^24 elements (fr_rlc_kernel reads 64 B and
+        # writes 32 B per element: 1 GiB in, 0.5 GiB out per dispatch)
+        ln = 1 << 24
+        va = zk.to_device(gen.uniform_fr(7, ln, tag=1))
+        vb = zk.to_device(gen.uniform_fr(7, ln, tag=2))
+        gam = zk.to_device(gen.uniform_fr(7, 1, tag=3))
+        pt = zk.srs_setup(gen.tau_scalar(), 1)
+        for _ in range(3):
+            zk.acc_fold(gam, pt, pt, pt, pt, None, va, vb)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 1 << 30, "dispatches": 3,
+                          "fr_rlc_read_bytes": 64 * ln, "fr_rlc_write_bytes": 32 * ln, "fr_rlc_dispatches": 3}))
         return
     if args.mad_calibration:
         # 2048 workgroups x 256 threads x 8 dependent chains x 4096 x 16 steps

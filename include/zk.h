@@ -172,6 +172,9 @@ uint32_t zk_srs_window_bits(const zk_srs* srs, uint64_t n);
  *                     passes fit it) or 12 (2^12 points) (12)
  *  ntt_unit_log       transform stages per LDS round trip: 3 (each thread
  *                     holds 8 points) or 2 (4 points, more threads) (3)
+ *  ntt_overlap_tile_log  tile of a transform the library runs beside other
+ *                     kernels (zk_commit_job's coset transform beside the
+ *                     MSM's reduction), 11 or 12 (11)
  * ZK_EINVAL for a value out of range (nothing is changed then). */
 typedef struct zk_schedule {
   uint32_t acc_max_slice;
@@ -181,6 +184,7 @@ typedef struct zk_schedule {
   uint32_t sort_bin_entries;
   uint32_t ntt_tile_log;
   uint32_t ntt_unit_log;
+  uint32_t ntt_overlap_tile_log;
 } zk_schedule;
 zk_status zk_set_schedule(const zk_schedule* schedule_host);
 zk_status zk_get_schedule(zk_schedule* schedule_host);

@@ -104,6 +104,7 @@ SCHEDULE_CANDIDATES = {
     "sort_bin_entries": [32768, 8192, 131072],
     "ntt_tile_log": [12, 11],
     "ntt_unit_log": [3, 2],
+    "ntt_overlap_tile_log": [11, 12],
 }
 
 

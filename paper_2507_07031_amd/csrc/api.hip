@@ -341,7 +341,7 @@ struct NttRun {
 };
 
 zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t L, bool inverse, const f29* pre_lo,
-                      const f29* pre_hi, uint32_t valid_n, hipStream_t s, NttRun& r) {
+                      const f29* pre_hi, uint32_t valid_n, hipStream_t s, NttRun& r, bool overlapped = false) {
   const uint32_t T = ntt_tile_log();
   const Schedule sched = device_schedule();
   r.a.unit_log = r.b.unit_log = r.c.unit_log = sched.ntt_unit_log;
@@ -376,8 +376,11 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   const uint32_t mA = three ? (L + 2) / 3 : L / 2, mB = L - mA;
   const uint32_t N1 = 1u << mB, N2 = 1u << mA;
   // tiles of 2048 points where both passes fit (two workgroups per CU) and
-  // the schedule prefers them, else 4096
-  const uint32_t tile = !three && mB <= T - 1 && sched.ntt_tile_log < T ? (1u << (T - 1)) : (1u << T);
+  // the schedule prefers them, else 4096; a transform that runs beside other
+  // kernels (overlapped) has its own preference: a 4096-point tile's 144 KB
+  // of LDS leaves a compute unit no room for the other kernels' workgroups
+  const uint32_t pref = overlapped ? sched.ntt_overlap_tile_log : sched.ntt_tile_log;
+  const uint32_t tile = !three && mB <= T - 1 && pref < T ? (1u << (T - 1)) : (1u << T);
   zk_status st = scratch_alloc(r.tmp, (size_t)32 << L, s);
   if (st) return st;
   uint32_t* Y = static_cast<uint32_t*>(r.tmp.p);
@@ -628,6 +631,11 @@ zk_status zk_set_schedule(const zk_schedule* sch) {
         return fail(ZK_EINVAL, "zk_set_schedule: ntt_tile_log must be 11 or 12");
       v.ntt_tile_log = sch->ntt_tile_log;
     }
+    if (sch->ntt_overlap_tile_log) {
+      if (sch->ntt_overlap_tile_log != 11 && sch->ntt_overlap_tile_log != 12)
+        return fail(ZK_EINVAL, "zk_set_schedule: ntt_overlap_tile_log must be 11 or 12");
+      v.ntt_overlap_tile_log = sch->ntt_overlap_tile_log;
+    }
     if (sch->ntt_unit_log) {
       if (sch->ntt_unit_log != 2 && sch->ntt_unit_log != 3)
         return fail(ZK_EINVAL, "zk_set_schedule: ntt_unit_log must be 2 or 3");
@@ -648,6 +656,7 @@ zk_status zk_get_schedule(zk_schedule* sch) {
   sch->sort_bin_entries = v.sort_bin_entries;
   sch->ntt_tile_log = v.ntt_tile_log;
   sch->ntt_unit_log = v.ntt_unit_log;
+  sch->ntt_overlap_tile_log = v.ntt_overlap_tile_log;
   return ZK_OK;
 }
 
@@ -970,7 +979,7 @@ zk_status zk_commit_job(const zk_srs* srs, const zk_fr* evals, uint32_t log_n, u
   }
   NttRun r;
   if ((st = ntt_prepare(c, cf, reinterpret_cast<uint32_t*>(coset), log_n + log_blowup, false, lo, hi, (uint32_t)n,
-                        side, r)))
+                        side, r, true)))
     return st;
   if ((st = ntt_first(r, side))) return st;
   if ((st = ntt_second(r, side))) return st;

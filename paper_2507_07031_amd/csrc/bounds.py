@@ -41,6 +41,15 @@ def borrowed(cq):
     return k
 
 
+def borrowed30(cq):
+    """K = cq with limbs 0..7 raised by 2^30 (borrowing 2 from the next limb)."""
+    d = digits(cq)
+    k = [d[0] + (1 << 30)] + [d[i] + (1 << 30) - 2 for i in range(1, 8)] + [d[8] - 2]
+    assert sum(v << (LIMB * i) for i, v in enumerate(k)) == cq
+    assert all(v >= 0 for v in k)
+    return k
+
+
 class V:
     """Upper bounds of a non-negative value and of each of its limbs."""
 
@@ -68,6 +77,20 @@ def mul(a, b, q=None):
     col = 9 * (la - 1) * (lb - 1) + 9 * MASK * MASK + (1 << 64) // (1 << LIMB)
     assert col < (1 << 64), "column accumulator overflow"
     return norm((a.val - 1) * (b.val - 1) // MONT_R + q + 1)
+
+
+def sub_raw(a, b, c, q=None):
+    """a - b computed as a + c*q - b with c*q in 2^30-raised limbs, left
+    unnormalised: limb i of the result is below a's limb bound + k_i."""
+    q = q or Q
+    k = borrowed30(c * q)
+    assert c * q >= b.val - 1, "K = %dq does not exceed the subtrahend" % c
+    assert all(k[i] >= b.limb - 1 for i in range(8)), "limb borrow too small"
+    assert k[8] >= b.top - 1, "top limb borrow too small"
+    limb = max(a.limb + k[i] for i in range(8))
+    top = a.top + k[8]
+    assert limb <= (1 << 32) and top <= (1 << 32), "32-bit limb overflow"
+    return V(a.val + c * q, limb, top)
 
 
 def mul2(a, b, c, d, q=None):
@@ -102,12 +125,19 @@ def sub(a, b, c, q=None):
     return norm(a.val + c * q)
 
 
-# Subtraction multiples used by the kernels (field.h: K2, K4, K8).  In the
-# additions Y3 = R (Q - X3) - S PPP is one reduction of R (Q - X3) + (K - S) PPP,
-# with "nY1" / "nS1" the negation K - S.
-SUB_K = {"madd.P": 8, "madd.R": 8, "madd.X3": 4, "madd.QX": 8, "madd.nY1": 8,
-         "add.P": 8, "add.R": 8, "add.X3": 4, "add.QX": 8, "add.nS1": 8,
-         "dbl.X3": 4, "dbl.SX": 8, "dbl.Y3": 2}
+# Subtraction tables used by the kernels (field_constants.h): "K<c>" is c q in
+# 2^31-raised limbs (sub_k, normalised result), "H<c>" c q in 2^30-raised
+# limbs (sub_raw, unnormalised result).  In the additions Y3 = R (Q - X3) -
+# S PPP is one reduction of R (Q - X3) + (K - S) PPP, with "nY1" / "nS1" the
+# negation K - S and Q - X3 unnormalised.
+SUB_K = {"madd.P": "K8", "madd.R": "K8", "madd.X3": "K4", "madd.QX": "H8", "madd.nY1": "K8",
+         "add.P": "K8", "add.R": "K8", "add.X3": "K4", "add.QX": "H8", "add.nS1": "K8",
+         "dbl.X3": "K4", "dbl.SX": "K8", "dbl.Y3": "K2"}
+
+
+def _sub(name, a, b):
+    t = SUB_K[name]
+    return (sub_raw if t[0] == "H" else sub)(a, b, int(t[1:]))
 
 ZERO = V(1, 1, 1)  # the constant 0 (bounds are exclusive)
 
@@ -115,16 +145,19 @@ ZERO = V(1, 1, 1)  # the constant 0 (bounds are exclusive)
 def madd(X1, Y1, ZZ1, ZZZ1, x2, y2):
     U2 = mul(x2, ZZ1)
     S2 = mul(y2, ZZZ1)
-    Pv = sub(U2, X1, SUB_K["madd.P"])
-    Rv = sub(S2, Y1, SUB_K["madd.R"])
+    Pv = _sub("madd.P", U2, X1)
+    Rv = _sub("madd.R", S2, Y1)
+    # the signed form: -p gives R = 8q - (S2 + Y1); both must hold, keep the larger
+    Rneg = _sub("madd.R", ZERO, add(S2, Y1))
+    Rv = Rv if Rv.val >= Rneg.val and Rv.limb >= Rneg.limb and Rv.top >= Rneg.top else Rneg
     PP = mul(Pv, Pv)
     PPP = mul(Pv, PP)
     Qv = mul(X1, PP)
     R2 = mul(Rv, Rv)
     T = add(add(PPP, Qv), Qv)
-    X3 = sub(R2, T, SUB_K["madd.X3"])
-    QX = sub(Qv, X3, SUB_K["madd.QX"])
-    nY1 = sub(ZERO, Y1, SUB_K["madd.nY1"])
+    X3 = _sub("madd.X3", R2, T)
+    QX = _sub("madd.QX", Qv, X3)
+    nY1 = _sub("madd.nY1", ZERO, Y1)
     Y3 = mul2(Rv, QX, nY1, PPP)
     return X3, Y3, mul(ZZ1, PP), mul(ZZZ1, PPP)
 
@@ -134,16 +167,16 @@ def add_xyzz(X1, Y1, ZZ1, ZZZ1, X2, Y2, ZZ2, ZZZ2):
     U2 = mul(X2, ZZ1)
     S1 = mul(Y1, ZZZ2)
     S2 = mul(Y2, ZZZ1)
-    Pv = sub(U2, U1, SUB_K["add.P"])
-    Rv = sub(S2, S1, SUB_K["add.R"])
+    Pv = _sub("add.P", U2, U1)
+    Rv = _sub("add.R", S2, S1)
     PP = mul(Pv, Pv)
     PPP = mul(Pv, PP)
     Qv = mul(U1, PP)
     R2 = mul(Rv, Rv)
     T = add(add(PPP, Qv), Qv)
-    X3 = sub(R2, T, SUB_K["add.X3"])
-    QX = sub(Qv, X3, SUB_K["add.QX"])
-    nS1 = sub(ZERO, S1, SUB_K["add.nS1"])
+    X3 = _sub("add.X3", R2, T)
+    QX = _sub("add.QX", Qv, X3)
+    nS1 = _sub("add.nS1", ZERO, S1)
     Y3 = mul2(Rv, QX, nS1, PPP)
     return X3, Y3, mul(mul(ZZ1, ZZ2), PP), mul(mul(ZZZ1, ZZZ2), PPP)
 
@@ -156,11 +189,11 @@ def dbl_xyzz(X1, Y1, ZZ1, ZZZ1):
     X1sq = mul(X1, X1)
     M = addn(add(X1sq, X1sq), X1sq)
     M2 = mul(M, M)
-    X3 = sub(M2, add(S, S), SUB_K["dbl.X3"])
-    SX = sub(S, X3, SUB_K["dbl.SX"])
+    X3 = _sub("dbl.X3", M2, add(S, S))
+    SX = _sub("dbl.SX", S, X3)
     A = mul(M, SX)
     B = mul(W, Y1)
-    Y3 = sub(A, B, SUB_K["dbl.Y3"])
+    Y3 = _sub("dbl.Y3", A, B)
     return X3, Y3, mul(Vv, ZZ1), mul(W, ZZZ1)
 
 

@@ -9,7 +9,8 @@
 // (a = 0).  The subtraction multiples (K2/K4/K8) are the ones bounds.py
 // proves safe.  Both additions form Y3 = R (Q - X3) - S PPP (S = Y1, or
 // S1 = Y1 ZZZ2) as one Montgomery reduction of both products' column sums
-// (mont_mul2), with -S written as 8q - S.
+// (mont_mul2), with -S written as 8q - S and Q - X3 left unnormalised
+// (sub_raw with the 2^30-raised 8q).
 #pragma once
 #include "field.h"
 
@@ -102,8 +103,40 @@ ZK_HD xyzz madd(const xyzz& a, const aff& p) {
   const f29 Q = mont_mul<Fq>(a.X, PP);
   xyzz r;
   r.X = sub_k(mont_sqr<Fq>(R), add(add(PPP, Q), Q), Fq::K4);
-  // Y3 = R (Q - X3) - Y1 PPP with one reduction: -Y1 as 8q - Y1
-  r.Y = mont_mul2<Fq>(R, sub_k(Q, r.X, Fq::K8), sub_k(f29_zero(), a.Y, Fq::K8), PPP);
+  // Y3 = R (Q - X3) - Y1 PPP with one reduction: -Y1 as 8q - Y1, and Q - X3
+  // left unnormalised (limbs below 2^31)
+  r.Y = mont_mul2<Fq>(R, sub_raw(Q, r.X, Fq::H8), sub_k(f29_zero(), a.Y, Fq::K8), PPP);
+  r.ZZ = mont_mul<Fq>(a.ZZ, PP);
+  r.ZZZ = mont_mul<Fq>(a.ZZZ, PPP);
+  return r;
+}
+
+// a + (neg ? -p : p) with p affine and not infinity: the sign enters only
+// R = +-S2 - Y1 (for -p, R = 8q - (S2 + Y1)), so no negated copy of p is
+// formed except on the rare doubling path.
+ZK_HD xyzz madd_signed(const xyzz& a, const aff& p, bool neg) {
+  if (is_inf(a)) return from_aff(neg ? aff_neg(p) : p);
+  const f29 U2 = mont_mul<Fq>(p.x, a.ZZ);
+  const f29 S2 = mont_mul<Fq>(p.y, a.ZZZ);
+  const f29 P = sub_k(U2, a.X, Fq::K8);
+  f29 ra, rb;
+  const f29 s2y = add(S2, a.Y);
+#pragma unroll
+  for (int i = 0; i < 9; i++) {
+    ra.l[i] = neg ? 0u : S2.l[i];
+    rb.l[i] = neg ? s2y.l[i] : a.Y.l[i];
+  }
+  const f29 R = sub_k(ra, rb, Fq::K8);
+  if (is_zero_mod<Fq>(P)) {
+    if (is_zero_mod<Fq>(R)) return mdbl(neg ? aff_neg(p) : p);
+    return xyzz_inf();
+  }
+  const f29 PP = mont_sqr<Fq>(P);
+  const f29 PPP = mont_mul<Fq>(P, PP);
+  const f29 Q = mont_mul<Fq>(a.X, PP);
+  xyzz r;
+  r.X = sub_k(mont_sqr<Fq>(R), add(add(PPP, Q), Q), Fq::K4);
+  r.Y = mont_mul2<Fq>(R, sub_raw(Q, r.X, Fq::H8), sub_k(f29_zero(), a.Y, Fq::K8), PPP);
   r.ZZ = mont_mul<Fq>(a.ZZ, PP);
   r.ZZZ = mont_mul<Fq>(a.ZZZ, PPP);
   return r;
@@ -127,8 +160,9 @@ ZK_HD xyzz add(const xyzz& a, const xyzz& b) {
   const f29 Q = mont_mul<Fq>(U1, PP);
   xyzz r;
   r.X = sub_k(mont_sqr<Fq>(R), add(add(PPP, Q), Q), Fq::K4);
-  // Y3 = R (Q - X3) - S1 PPP with one reduction: -S1 as 8q - S1
-  r.Y = mont_mul2<Fq>(R, sub_k(Q, r.X, Fq::K8), sub_k(f29_zero(), S1, Fq::K8), PPP);
+  // Y3 = R (Q - X3) - S1 PPP with one reduction: -S1 as 8q - S1, and Q - X3
+  // left unnormalised (limbs below 2^31)
+  r.Y = mont_mul2<Fq>(R, sub_raw(Q, r.X, Fq::H8), sub_k(f29_zero(), S1, Fq::K8), PPP);
   r.ZZ = mont_mul<Fq>(mont_mul<Fq>(a.ZZ, b.ZZ), PP);
   r.ZZZ = mont_mul<Fq>(mont_mul<Fq>(a.ZZZ, b.ZZZ), PPP);
   return r;

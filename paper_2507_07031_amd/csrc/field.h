@@ -112,6 +112,18 @@ ZK_HD f29 sub_k(const f29& a, const f29& b, const uint32_t (&k)[N]) {
   return normalize(r);
 }
 
+// a - b + K limb-wise without carry normalisation, for K a multiple of q in
+// limbs raised by 2^30 (the H tables): for normalised a, b every limb stays
+// below 2^31, small enough for one operand of a product whose other
+// operand is normalised (bounds.py checks each use).
+template <int N>
+ZK_HD f29 sub_raw(const f29& a, const f29& b, const uint32_t (&k)[N]) {
+  f29 r;
+#pragma unroll
+  for (int i = 0; i < 9; i++) r.l[i] = a.l[i] + k[i] - b.l[i];
+  return r;
+}
+
 // Column sums of a * b: acc[i + j] += a_i b_j (one v_mad_u64_u32 each).
 ZK_HD void mul_cols(uint64_t (&acc)[18], const f29& a, const f29& b) {
 #pragma unroll

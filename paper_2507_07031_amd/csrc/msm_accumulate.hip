@@ -94,8 +94,7 @@ accumulate_kernel(const uint32_t* __restrict__ entries, const uint32_t* __restri
       aff pt;
       pt.x = unpack(w);
       pt.y = unpack(w + 8);
-      if (v >> 31) pt = aff_neg(pt);
-      acc = madd(acc, pt);
+      acc = madd_signed(acc, pt, (v >> 31) != 0);
     }
     v = nv;
 #pragma unroll

@@ -266,7 +266,7 @@ def srs_set_table_policy(srs, small_max, large_min):
 
 
 SCHEDULE_FIELDS = ("acc_max_slice", "acc_blocks_per_cu", "reduce_chunk", "sort_chunk", "sort_bin_entries",
-                   "ntt_tile_log", "ntt_unit_log")
+                   "ntt_tile_log", "ntt_unit_log", "ntt_overlap_tile_log")
 
 
 class Schedule(ctypes.Structure):

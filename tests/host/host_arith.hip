@@ -145,6 +145,22 @@ void host_xyzz_madd_raw(const uint32_t* a, const uint32_t* pt, uint32_t* out) {
   store_xyzz_raw(madd(load_xyzz_raw(a), p), out);
 }
 
+void host_xyzz_madd_signed_raw(const uint32_t* a, const uint32_t* pt, int neg, uint32_t* out) {
+  aff p;
+  aff_from_plain_words(pt, p);
+  store_xyzz_raw(madd_signed(load_xyzz_raw(a), p, neg != 0), out);
+}
+
+// sum of +-points (signs[i] != 0: subtract) by the signed mixed addition.
+void host_g1_sum_madd_signed(const uint32_t* pts, const int* signs, uint64_t n, uint32_t* out) {
+  xyzz acc = xyzz_inf();
+  for (uint64_t i = 0; i < n; i++) {
+    aff p;
+    if (aff_from_plain_words(pts + 16 * i, p)) acc = madd_signed(acc, p, signs[i] != 0);
+  }
+  to_affine_words(acc, out);
+}
+
 void host_xyzz_dbl_raw(const uint32_t* a, uint32_t* out) {
   store_xyzz_raw(dbl(load_xyzz_raw(a)), out);
 }

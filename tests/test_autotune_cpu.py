@@ -63,3 +63,4 @@ def test_schedule_candidates_are_valid():
     assert c["sort_chunk"][0] == 1024 and all((v & (v - 1)) == 0 and 256 <= v <= 16384 for v in c["sort_chunk"])
     assert all((v & (v - 1)) == 0 and 1 << 10 <= v <= 1 << 20 for v in c["sort_bin_entries"])
     assert c["ntt_tile_log"] == [12, 11] and c["ntt_unit_log"] == [3, 2]
+    assert c["ntt_overlap_tile_log"] == [11, 12]

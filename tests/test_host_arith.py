@@ -195,6 +195,32 @@ def test_point_sums_and_special_cases(lib):
         assert _read_pt(o) == expect
 
 
+def test_signed_madd_sums_and_special_cases(lib):
+    # the accumulation's signed mixed addition: sums of +-P, through every
+    # special case (P + P, P - P, -P - P, infinity inputs)
+    rng = random.Random(14)
+    pts = _rand_points(rng, 5)
+    a = pts[0]
+    cases = [
+        (pts, [0, 1, 0, 1, 1]),
+        ([a, a], [1, 1]),                     # -P - P (doubling of -P)
+        ([a, a], [0, 1]),                     # P - P
+        ([a, a], [1, 0]),                     # -P + P
+        ([a, a, pts[1]], [0, 1, 1]),          # through infinity
+        ([None, a, None], [1, 1, 0]),         # infinity inputs
+        ([a, a, a], [1, 1, 0]),               # -2P + P
+    ]
+    for case, signs in cases:
+        expect = None
+        for pt, sg in zip(case, signs):
+            expect = g1.add(expect, g1.neg(pt) if sg else pt)
+        arr, ptr = _pt_words(case)
+        sv = (ctypes.c_int * len(signs))(*signs)
+        o, op = _out(16)
+        lib.host_g1_sum_madd_signed(ptr, sv, ctypes.c_uint64(len(case)), op)
+        assert _read_pt(o) == expect, signs
+
+
 def test_dbl_mul_small_neg(lib):
     rng = random.Random(5)
     for pt in _rand_points(rng, 4) + [g1.G, None]:
@@ -249,6 +275,11 @@ def test_formulas_at_edge_of_bound_box(lib):
         assert _xyzz_value(o) == g1.add(a, b)
         vals = [_from_limbs29(o[9 * i:9 * i + 9]) for i in range(4)]
         assert vals[0] < 6 * P and vals[1] < 4 * P and vals[2] < P + P // 4 and vals[3] < P + P // 4
+        for neg in (0, 1):
+            lib.host_xyzz_madd_signed_raw(ptr(wa), pp, ctypes.c_int(neg), ptr(o))
+            assert _xyzz_value(o) == g1.add(a, g1.neg(b) if neg else b)
+            vals = [_from_limbs29(o[9 * i:9 * i + 9]) for i in range(4)]
+            assert vals[0] < 6 * P and vals[1] < 4 * P and vals[2] < P + P // 4 and vals[3] < P + P // 4
         lib.host_xyzz_dbl_raw(ptr(wa), ptr(o))
         assert _xyzz_value(o) == g1.double(a)
         oa = np.zeros(16, dtype=np.uint32)

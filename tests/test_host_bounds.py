@@ -52,20 +52,21 @@ def test_sub_multiples_match_curve_formulas(bounds):
     # bounds.py gives them in the order its replay performs them
     order = {
         "ZK_HD xyzz madd(": ["madd.P", "madd.R", "madd.X3", "madd.QX", "madd.nY1"],
+        "ZK_HD xyzz madd_signed(": ["madd.P", "madd.R", "madd.X3", "madd.QX", "madd.nY1"],
         "ZK_HD xyzz add(const xyzz& a, const xyzz& b)": ["add.P", "add.R", "add.X3", "add.QX", "add.nS1"],
         "ZK_HD xyzz dbl(": ["dbl.X3", "dbl.SX", "dbl.Y3"],
     }
     for sig, names in order.items():
         body = _function_body(src, sig)
-        used = [int(k) for k in re.findall(r"Fq::K(\d+)", body)]
+        used = re.findall(r"Fq::([KH]\d+)", body)
         assert used == [bounds.SUB_K[n] for n in names], (sig, used)
 
 
 def test_borrowed_tables_match_field_constants(bounds):
     src = _read("field_constants.h")
     fq = src[src.index("struct FqP"):src.index("struct FrP")]
-    for c in (1, 2, 4, 8, 16):
-        m = re.search(r"K%d\[9\] = \{([^}]*)\}" % c, fq)
-        assert m, c
+    for name, c, fn in [("K%d" % c, c, bounds.borrowed) for c in (1, 2, 4, 8, 16)] + [("H8", 8, bounds.borrowed30)]:
+        m = re.search(r"%s\[9\] = \{([^}]*)\}" % name, fq)
+        assert m, name
         words = [int(w.strip().rstrip("u"), 16) for w in m.group(1).split(",")]
-        assert words == bounds.borrowed(c * bounds.P), c
+        assert words == fn(c * bounds.P), name
