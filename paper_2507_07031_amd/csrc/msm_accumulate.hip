@@ -8,11 +8,24 @@ namespace zk {
 
 namespace {
 
-__device__ __forceinline__ void ld_pt_words(const uint32_t* __restrict__ points, uint32_t v, uint4 q[4]) {
+// The next gathered point travels straight to LDS (global_load_lds, no VGPRs
+// held while it is in flight).  Each wave owns a 4 KiB stage: 16-byte chunk k
+// of lane l's point lands at chunk k * 64 + l (the instruction writes its 64
+// lanes' 16 bytes contiguously from the wave-uniform base it is given).
+constexpr uint32_t STAGE_CHUNKS = MSM_NT / 64 * 4 * 64;
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ void stage_pt(const uint32_t* __restrict__ points, uint32_t v, uint4* wave_stage) {
   const uint4* src = reinterpret_cast<const uint4*>(points + (size_t)(v & 0x7fffffffu) * 16);
 #pragma unroll
-  for (int k = 0; k < 4; k++) q[k] = src[k];
+  for (int k = 0; k < 4; k++)
+    __builtin_amdgcn_global_load_lds(src + k, (lds_void*)(wave_stage + k * 64), 16, 0, 0);
 }
+
+// s_waitcnt immediates (gfx9 encoding): vmcnt(0) alone, lgkmcnt(0) alone
+constexpr int WAIT_VM0 = 0x0F70;
+constexpr int WAIT_LGKM0 = 0xC07F;
 
 __device__ __forceinline__ void st_rec_xyzz(uint32_t* rec, uint32_t key, uint32_t flag, const xyzz& a) {
   reinterpret_cast<uint4*>(rec)[0] = make_uint4(key, flag, 0, 0);
@@ -24,7 +37,8 @@ __device__ __forceinline__ void st_rec_xyzz(uint32_t* rec, uint32_t key, uint32_
 // entry's position (found once by binary search, then followed).  Runs of
 // one bucket strictly inside the range are complete and go straight to HBM;
 // the first and last run of the range become the thread's two records,
-// finished by the record levels.  The next point is loaded one step ahead.
+// finished by the record levels.  The next point is staged in LDS one step
+// ahead, the entry after it two steps ahead.
 __global__ void __launch_bounds__(MSM_NT) __attribute__((amdgpu_waves_per_eu(3, 3)))
 accumulate_kernel(const uint32_t* __restrict__ entries, const uint32_t* __restrict__ offsets, uint32_t nbins,
                   const uint32_t* __restrict__ points, uint32_t lmin, uint32_t* __restrict__ buckets,
@@ -54,18 +68,15 @@ accumulate_kernel(const uint32_t* __restrict__ entries, const uint32_t* __restri
   }
   uint32_t cur = lo;
   uint32_t bend = offsets[cur + 1];
+  __shared__ uint4 stage[STAGE_CHUNKS];
+  const uint32_t lane = threadIdx.x & 63;
+  uint4* wave_stage = stage + (threadIdx.x >> 6) * 256;
   uint32_t v = entries[tb];
-  uint4 q[4];
-  ld_pt_words(points, v, q);
+  uint32_t nv = tb + 1 < te ? entries[tb + 1] : v;
+  stage_pt(points, v, wave_stage);
   bool first_done = false;
   xyzz acc = xyzz_inf();
   for (uint32_t e = (uint32_t)tb; e < te; e++) {
-    uint32_t nv = v;
-    uint4 nq[4] = {q[0], q[1], q[2], q[3]};
-    if (e + 1 < te) {
-      nv = entries[e + 1];
-      ld_pt_words(points, nv, nq);
-    }
     if (e == bend) {
       if (!first_done) {
         st_rec_xyzz(r0, cur, 1, acc);
@@ -79,13 +90,23 @@ accumulate_kernel(const uint32_t* __restrict__ entries, const uint32_t* __restri
       } while (bend == e);
       acc = xyzz_inf();
     }
+    // this entry's point, staged one entry ago
+    __builtin_amdgcn_s_waitcnt(WAIT_VM0);
     uint32_t w[16];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-      w[4 * k] = q[k].x;
-      w[4 * k + 1] = q[k].y;
-      w[4 * k + 2] = q[k].z;
-      w[4 * k + 3] = q[k].w;
+      const uint4 c = wave_stage[k * 64 + lane];
+      w[4 * k] = c.x;
+      w[4 * k + 1] = c.y;
+      w[4 * k + 2] = c.z;
+      w[4 * k + 3] = c.w;
+    }
+    // the stage is read before the next point overwrites it
+    __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
+    uint32_t nnv = nv;
+    if (e + 1 < te) {
+      stage_pt(points, nv, wave_stage);
+      if (e + 2 < te) nnv = entries[e + 2];
     }
     uint32_t o = 0;
 #pragma unroll
@@ -97,8 +118,7 @@ accumulate_kernel(const uint32_t* __restrict__ entries, const uint32_t* __restri
       acc = madd_signed(acc, pt, (v >> 31) != 0);
     }
     v = nv;
-#pragma unroll
-    for (int k = 0; k < 4; k++) q[k] = nq[k];
+    nv = nnv;
   }
   if (!first_done) {
     st_rec_xyzz(r0, cur, 1, acc);
