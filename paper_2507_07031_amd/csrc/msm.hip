@@ -192,7 +192,7 @@ __device__ __forceinline__ uint4 block_item(const MsmPlan& p, const uint4* __res
 
 __global__ void __launch_bounds__(MSM_NT)
 coarse_count_kernel(const uint32_t* __restrict__ scalars, MsmPlan p, const uint4* __restrict__ items,
-                    uint32_t* __restrict__ ccounts) {
+                    uint32_t* __restrict__ ccounts, uint32_t* __restrict__ block_counts) {
   extern __shared__ uint32_t h[];
   const uint4 it = block_item(p, items);
   const uint32_t span = coarse_span(p), cbase = bin_base(p, it.x, 0) >> p.S;
@@ -203,8 +203,11 @@ coarse_count_kernel(const uint32_t* __restrict__ scalars, MsmPlan p, const uint4
       atomicAdd(&h[((bin_base(p, it.x, w) + mag - 1) >> p.S) - cbase], 1u);
     });
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < span; b += MSM_NT)
+  for (uint32_t b = threadIdx.x; b < span; b += MSM_NT) {
     if (h[b]) atomicAdd(&ccounts[cbase + b], h[b]);
+    // one segment: the block's counts, for the staged scatter
+    if (block_counts) block_counts[(size_t)blockIdx.x * span + b] = h[b];
+  }
 }
 
 __global__ void __launch_bounds__(MSM_NT)
@@ -239,7 +242,7 @@ coarse_scatter_kernel(const uint32_t* __restrict__ scalars, MsmPlan p, const uin
 // Staged coarse scatter, for one segment with few coarse bins.  The direct
 // scatter above has every lane write its own 8-byte pair into one of the
 // block's bins, so a wave's writes land on up to 64 lines.  Here the block
-// counts its digits per coarse bin, claims each bin's global range, ranks
+// takes its digits' counts per coarse bin (kept by the counting kernel), claims each bin's global range, ranks
 // every digit into an LDS copy of its pairs ordered by bin, and writes the
 // copy out in order: consecutive lanes write consecutive positions of one
 // bin's run.  LDS: counts / rank cursors, stage offsets and claimed global
@@ -252,8 +255,9 @@ __host__ __device__ inline size_t staged_lds_words(uint32_t span) {
 }
 
 __global__ void __launch_bounds__(STAGED_NT)
-coarse_scatter_staged_kernel(const uint32_t* __restrict__ scalars, MsmPlan p, uint32_t* __restrict__ ccursor,
-                             uint2* __restrict__ pairs, const uint32_t* __restrict__ ctotal, uint32_t dense_min) {
+coarse_scatter_staged_kernel(const uint32_t* __restrict__ scalars, MsmPlan p, const uint32_t* __restrict__ block_counts,
+                             uint32_t* __restrict__ ccursor, uint2* __restrict__ pairs,
+                             const uint32_t* __restrict__ ctotal, uint32_t dense_min) {
   extern __shared__ uint32_t sm[];
   if (*ctotal < dense_min) return;  // sparse digits: the direct kernel
   const uint32_t span = coarse_span(p);  // one segment: coarse bins [0, span)
@@ -269,12 +273,8 @@ coarse_scatter_staged_kernel(const uint32_t* __restrict__ scalars, MsmPlan p, ui
   // launch that finds sparse digits ends at once
   for (uint32_t item = blockIdx.x; item < p.nitems; item += gridDim.x) {
     const uint32_t g0 = item * p.chunk, g1 = min(g0 + p.chunk, p.n);
-    for (uint32_t b = tid; b < span; b += STAGED_NT) cnt[b] = 0;
-    __syncthreads();
-    for (uint32_t i = g0 + tid; i < g1; i += STAGED_NT)
-      for_each_digit(scalars + (size_t)i * 8, p.c, p.W, [&](uint32_t w, uint32_t mag, uint32_t) {
-        atomicAdd(&cnt[(bin_base(p, 0, w) + mag - 1) >> p.S], 1u);
-      });
+    // the counting kernel's counts of this block
+    for (uint32_t b = tid; b < span; b += STAGED_NT) cnt[b] = block_counts[(size_t)item * span + b];
     __syncthreads();
     // exclusive scan of the counts: thread t sums bins [b0, b1), the thread
     // sums are scanned in LDS (Hillis-Steele)
@@ -379,9 +379,8 @@ fine_scatter_kernel(const uint2* __restrict__ pairs, const uint32_t* __restrict_
   }
 }
 
-// Fine scatter, staged (for coarse bins of 2^7 buckets or more, where a
-// block's pairs spread over so many buckets that the direct scatter writes
-// short runs): the block's pairs are read once into LDS, counted
+// Fine scatter, staged (for dense digits; the direct kernel above serves
+// sparse ones): the block's pairs are read once into LDS, counted
 // and ranked there by bin, and the entries written out in bin order, so
 // consecutive lanes write consecutive positions of one bucket's run.  A block
 // whose bins span more than FINE_STAGED_BINS (sparse pairs) claims each
@@ -389,6 +388,7 @@ fine_scatter_kernel(const uint2* __restrict__ pairs, const uint32_t* __restrict_
 // entries and their bin indices, per-bin counts / rank cursors and
 // position offsets, the scan's thread sums.
 constexpr uint32_t FINE_STAGED_BINS = 1024;
+constexpr size_t FINE_LITE_LDS = (size_t)FINE_CHUNK * 4 + FINE_CHUNK * 2 + 2 * FINE_STAGED_BINS * 4 + MSM_NT * 4;
 constexpr size_t FINE_STAGED_LDS =
     (size_t)FINE_CHUNK * 8 + FINE_CHUNK * 4 + FINE_CHUNK * 2 + 2 * FINE_STAGED_BINS * 4 + MSM_NT * 4;
 
@@ -411,6 +411,75 @@ fine_scatter_staged_kernel(const uint2* __restrict__ pairs, const uint32_t* __re
     const uint32_t ne = min(FINE_CHUNK, E - e0);
     for (uint32_t k = tid; k < ne; k += MSM_NT) in[k] = pairs[e0 + k];
     __syncthreads();
+    // bins of the chunk: whole coarse bins from the first pair's to the last's
+    const uint32_t lo = (in[0].y >> p.S) << p.S;
+    const uint32_t hi = ((in[ne - 1].y >> p.S) + 1) << p.S;
+    const uint32_t range = hi - lo;
+    if (range > FINE_STAGED_BINS) {
+      for (uint32_t k = tid; k < ne; k += MSM_NT) entries[atomicAdd(&cursor[in[k].y], 1u)] = in[k].x;
+      __syncthreads();
+      continue;
+    }
+    for (uint32_t b = tid; b < range; b += MSM_NT) cnt[b] = 0;
+    __syncthreads();
+    for (uint32_t k = tid; k < ne; k += MSM_NT) atomicAdd(&cnt[in[k].y - lo], 1u);
+    __syncthreads();
+    // exclusive scan of the counts (thread sums of contiguous bins, Hillis-Steele)
+    const uint32_t per = (range + MSM_NT - 1) / MSM_NT;
+    const uint32_t b0 = min(tid * per, range), b1 = min(b0 + per, range);
+    uint32_t run = 0;
+    for (uint32_t b = b0; b < b1; b++) run += cnt[b];
+    tsum[tid] = run;
+    __syncthreads();
+    for (uint32_t d = 1; d < MSM_NT; d <<= 1) {
+      const uint32_t v = tid >= d ? tsum[tid - d] : 0u;
+      __syncthreads();
+      tsum[tid] += v;
+      __syncthreads();
+    }
+    uint32_t at = tsum[tid] - run;
+    for (uint32_t b = b0; b < b1; b++) {
+      const uint32_t c = cnt[b];
+      // entry j of bin b goes to its claimed start + (j - at) (mod 2^32)
+      delta[b] = (c ? atomicAdd(&cursor[lo + b], c) : 0u) - at;
+      cnt[b] = at;
+      at += c;
+    }
+    __syncthreads();
+    for (uint32_t k = tid; k < ne; k += MSM_NT) {
+      const uint2 q = in[k];
+      const uint32_t b = q.y - lo;
+      const uint32_t j = atomicAdd(&cnt[b], 1u);
+      out[j] = q.x;
+      obin[j] = (uint16_t)b;
+    }
+    __syncthreads();
+    for (uint32_t j = tid; j < ne; j += MSM_NT) entries[delta[obin[j]] + j] = out[j];
+    __syncthreads();
+  }
+}
+
+// The same with the pairs read from HBM twice instead of copied to LDS: a
+// third of the LDS, so four workgroups share a compute unit (coarse bins of
+// fewer than 2^7 buckets, where the staged copy's occupancy costs more than
+// the second read).
+__global__ void __launch_bounds__(MSM_NT)
+fine_scatter_lite_kernel(const uint2* __restrict__ pairs, const uint32_t* __restrict__ ctotal, MsmPlan p,
+                           uint32_t* __restrict__ cursor, uint32_t* __restrict__ entries, uint32_t dense_min) {
+  extern __shared__ uint32_t sm[];
+  const uint32_t E = *ctotal;
+  if (E < dense_min) return;  // sparse digits: the direct kernel
+  uint32_t* out = sm;
+  uint16_t* obin = reinterpret_cast<uint16_t*>(out + FINE_CHUNK);
+  uint32_t* cnt = out + FINE_CHUNK + FINE_CHUNK / 2;
+  uint32_t* delta = cnt + FINE_STAGED_BINS;
+  uint32_t* tsum = delta + FINE_STAGED_BINS;
+  const uint32_t tid = threadIdx.x;
+  // a grid of as many workgroups as the LDS holds at once walks the chunks
+  for (uint64_t c0 = (uint64_t)blockIdx.x * FINE_CHUNK; c0 < E; c0 += (uint64_t)gridDim.x * FINE_CHUNK) {
+    const uint32_t e0 = (uint32_t)c0;
+    const uint32_t ne = min(FINE_CHUNK, E - e0);
+    const uint2* in = pairs + e0;
     // bins of the chunk: whole coarse bins from the first pair's to the last's
     const uint32_t lo = (in[0].y >> p.S) << p.S;
     const uint32_t hi = ((in[ne - 1].y >> p.S) + 1) << p.S;
@@ -1300,6 +1369,9 @@ static hipError_t set_lds_limits() {
   if ((e = hipFuncSetAttribute((const void*)fine_scatter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                fine_lds)))
     return e;
+  if ((e = hipFuncSetAttribute((const void*)fine_scatter_lite_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)FINE_LITE_LDS)))
+    return e;
   if ((e = hipFuncSetAttribute((const void*)fine_scatter_staged_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)FINE_STAGED_LDS)))
     return e;
@@ -1359,8 +1431,15 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points
   hipLaunchKernelGGL(fill_zero2_kernel, dim3(std::min(cdiv(p.nbins, 256), 1024u)), dim3(256), 0, s, b.counts,
                      p.nbins, b.ccounts, p.ncoarse);
   const size_t clds = (size_t)((p.Wb * p.K) >> p.S) * 4;
+  // the staged scatter serves one segment whose block's pairs and bins fit
+  // LDS; the counting kernel keeps its blocks' counts for it in the entries
+  // buffer, which the fine level fills only later
+  const size_t slds = staged_lds_words((p.Wb * p.K) >> p.S) * 4 + (size_t)p.chunk * p.W * 8;
+  const bool staged_coarse = !items && slds <= STAGED_MAX_LDS &&
+                             (uint64_t)p.nitems * ((p.Wb * p.K) >> p.S) <= (uint64_t)p.n * p.W;
   if (p.nitems) {
-    hipLaunchKernelGGL(coarse_count_kernel, dim3(p.nitems), dim3(MSM_NT), clds, s, scalars, p, items, b.ccounts);
+    hipLaunchKernelGGL(coarse_count_kernel, dim3(p.nitems), dim3(MSM_NT), clds, s, scalars, p, items, b.ccounts,
+                       staged_coarse ? b.entries : nullptr);
   }
   if ((e = scan_exclusive(b.ccounts, b.coff, p.ncoarse, b.scan_tmp, s, b.ccursor))) return e;
   // Staged scatters pay off when most digits are nonzero (uniform scalars);
@@ -1369,15 +1448,12 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points
   // launched; each reads the sorted total and only one of them runs.
   const uint32_t dense_min = (uint32_t)std::min<uint64_t>((uint64_t)p.n * p.W / 2, UINT32_MAX - 1);
   if (p.nitems) {
-    // the staged scatter serves one segment whose block's pairs and bins fit LDS
-    const size_t slds = staged_lds_words((p.Wb * p.K) >> p.S) * 4 + (size_t)p.chunk * p.W * 8;
-    const bool staged = !items && slds <= STAGED_MAX_LDS;
     hipLaunchKernelGGL(coarse_scatter_kernel, dim3(p.nitems), dim3(MSM_NT), clds, s, scalars, p, items,
-                       b.seg_off, b.ccursor, b.pairs, b.coff + p.ncoarse, staged ? dense_min : UINT32_MAX);
-    if (staged) {
+                       b.seg_off, b.ccursor, b.pairs, b.coff + p.ncoarse, staged_coarse ? dense_min : UINT32_MAX);
+    if (staged_coarse) {
       hipLaunchKernelGGL(coarse_scatter_staged_kernel, dim3(std::min(p.nitems, device_compute_units())),
-                         dim3(STAGED_NT), slds, s, scalars, p,
-                         b.ccursor, b.pairs, b.coff + p.ncoarse, dense_min);
+                         dim3(STAGED_NT), slds, s, scalars, p, b.entries, b.ccursor, b.pairs, b.coff + p.ncoarse,
+                         dense_min);
     }
   }
   const uint32_t fine_blocks = (uint32_t)cdiv((uint64_t)p.n * p.W, FINE_CHUNK);
@@ -1388,13 +1464,16 @@ hipError_t msm_run(const MsmPlan& p, const uint64_t* off, const uint32_t* points
   }
   if ((e = scan_exclusive(b.counts, b.offsets, p.nbins, b.scan_tmp, s, b.cursor))) return e;
   if (fine_blocks) {
-    const bool staged = p.S >= 7;
     hipLaunchKernelGGL(fine_scatter_kernel, dim3(fine_blocks), dim3(MSM_NT), flds, s, b.pairs, b.coff + p.ncoarse,
-                       p, b.cursor, b.entries, staged ? dense_min : UINT32_MAX);
-    if (staged) {
+                       p, b.cursor, b.entries, dense_min);
+    if (p.S >= 7) {
       hipLaunchKernelGGL(fine_scatter_staged_kernel, dim3(std::min(fine_blocks, 2 * device_compute_units())),
-                         dim3(MSM_NT), FINE_STAGED_LDS, s, b.pairs,
-                         b.coff + p.ncoarse, p, b.cursor, b.entries, dense_min);
+                         dim3(MSM_NT), FINE_STAGED_LDS, s, b.pairs, b.coff + p.ncoarse, p, b.cursor, b.entries,
+                         dense_min);
+    } else {
+      hipLaunchKernelGGL(fine_scatter_lite_kernel, dim3(std::min(fine_blocks, 4 * device_compute_units())),
+                         dim3(MSM_NT), FINE_LITE_LDS, s, b.pairs, b.coff + p.ncoarse, p, b.cursor, b.entries,
+                         dense_min);
     }
   }
   prof_end(t_sort, s);

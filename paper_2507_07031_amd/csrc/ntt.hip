@@ -101,12 +101,30 @@ __device__ __forceinline__ void mul_tw_2q(const uint32_t a[8], const f29& w, uin
   pack(mont_mul<FrP>(unpack(a), w), r);
 }
 
+// Twiddles of a unit's R stages: stage s+T uses omega_(2^(s+T))^(j + qlow h)
+// for qlow < 2^T, ladder entry 2^(s+T-1) + j + qlow h, kept at index
+// 2^T - 1 + qlow.  All 2^R - 1 are loaded before the unit's points, so
+// their latency overlaps the LDS reads and the first butterflies instead of
+// stalling each product.
+template <int R>
+struct UnitTw {
+  f29 w[(1 << R) - 1];
+};
+
+template <int R>
+__device__ __forceinline__ void load_unit_tw(UnitTw<R>& tw, uint32_t s, uint32_t j, uint32_t h,
+                                             const f29* __restrict__ ladder) {
+#pragma unroll
+  for (int T = 0; T < R; T++)
+#pragma unroll
+    for (int ql = 0; ql < (1 << T); ql++) tw.w[(1 << T) - 1 + ql] = ldf29(ladder, (1u << (s + T - 1)) + j + ql * h);
+}
+
 // One butterfly of stage s+T on registers x[q], x[q + 2^T] of a unit (q with
 // bit T clear); its twiddle is omega_(2^(s+T))^jt, jt = j + (q mod 2^T) h.
 // Twiddles that are 1 (j = 0 in the first stage of a tile) are skipped.
-template <int Q, int T, int P>
-__device__ __forceinline__ void dit_butterflies(uint32_t (&x)[Q][8], uint32_t s, uint32_t j, uint32_t h,
-                                                const f29* __restrict__ ladder) {
+template <int Q, int R, int T, int P>
+__device__ __forceinline__ void dit_butterflies(uint32_t (&x)[Q][8], uint32_t s, const UnitTw<R>& tw) {
   constexpr uint32_t q = ((P >> T) << (T + 1)) | (P & ((1u << T) - 1));
   constexpr uint32_t r = q + (1u << T);
   constexpr uint32_t qlow = q & ((1u << T) - 1);
@@ -115,9 +133,7 @@ __device__ __forceinline__ void dit_butterflies(uint32_t (&x)[Q][8], uint32_t s,
 #pragma unroll
     for (int w = 0; w < 8; w++) tv[w] = x[r][w];
   } else {
-    // omega_(2^(s+T))^jt from the ladder: consecutive jt are adjacent entries
-    const uint32_t jt = j + qlow * h;
-    mul_tw_2q(x[r], ldf29(ladder, (1u << (s + T - 1)) + jt), tv);
+    mul_tw_2q(x[r], tw.w[(1u << T) - 1 + qlow], tv);
   }
   add_2q(x[q], tv, x[r]);
   sub_2q(x[q], tv, tv);
@@ -127,14 +143,13 @@ __device__ __forceinline__ void dit_butterflies(uint32_t (&x)[Q][8], uint32_t s,
     x[r][w] = tv[w];
     x[q][w] = sum;
   }
-  if constexpr (P + 1 < Q / 2) dit_butterflies<Q, T, P + 1>(x, s, j, h, ladder);
+  if constexpr (P + 1 < Q / 2) dit_butterflies<Q, R, T, P + 1>(x, s, tw);
 }
 
 template <int Q, int T, int R>
-__device__ __forceinline__ void dit_levels(uint32_t (&x)[Q][8], uint32_t s, uint32_t j, uint32_t h,
-                                           const f29* __restrict__ ladder) {
-  dit_butterflies<Q, T, 0>(x, s, j, h, ladder);
-  if constexpr (T + 1 < R) dit_levels<Q, T + 1, R>(x, s, j, h, ladder);
+__device__ __forceinline__ void dit_levels(uint32_t (&x)[Q][8], uint32_t s, const UnitTw<R>& tw) {
+  dit_butterflies<Q, R, T, 0>(x, s, tw);
+  if constexpr (T + 1 < R) dit_levels<Q, T + 1, R>(x, s, tw);
 }
 
 // R consecutive decimation-in-time stages s .. s+R-1 on the LDS tile, each
@@ -151,10 +166,12 @@ __device__ __forceinline__ void dit_stages(uint32_t* lds, uint32_t s, uint32_t m
     const uint32_t b = u >> (m - R), ul = u & (units_per_tr - 1);
     const uint32_t j = ul & (h - 1), grp = ul >> (s - 1);
     const uint32_t base = (b << m) + (grp << (s + R - 1)) + j;
+    UnitTw<R> tw;
+    load_unit_tw<R>(tw, s, j, h, ladder);
     uint32_t x[Q][8];
 #pragma unroll
     for (int q = 0; q < Q; q++) ld8(lds_at(lds, base + q * h), x[q]);
-    dit_levels<Q, 0, R>(x, s, j, h, ladder);
+    dit_levels<Q, 0, R>(x, s, tw);
 #pragma unroll
     for (int q = 0; q < Q; q++) st8(lds_at(lds, base + q * h), x[q]);
   }
