@@ -11,6 +11,8 @@ Printed as one JSON line, with
 * the quantized-activation MSM at 2^22 against uniform scalars at 2^22,
 * 256 uneven MSMs (log-uniform 2^8..2^18) batched vs one call each, and the
   fold of 64 of the resulting commitments,
+* small commitments (2^8..2^14) on the small-multiples table and as bucket
+  runs,
 * `roofline` of the dominant kernel (bucket accumulation) from HIP events
   recorded by the library on its launch stream over the timed region,
 * a Poisson stream of commit jobs (2^10..2^22 points) through the serving
@@ -753,6 +755,23 @@ def main():
         t_fold = timed(lambda: zk.fold(inst, gam, out=fout), reps=5)
         extras["fold_64"] = {"latency_ms": round(t_fold, 4)}
         del sc, outs
+
+        # small commitments: the small-multiples table (up to 4096 points)
+        # against the bucket run of the same commitment
+        log("small commitments")
+        small = {}
+        sc = zk.to_device(gen.uniform_fr(gen.CONFIG_SEEDS["batched"], 1 << 14, tag=5))
+        for lg in (8, 10, 12, 14):
+            row = {}
+            for label, tmax in (("small_multiples_ms", 4096), ("bucket_ms", 0)):
+                zk.srs_set_tiny_max(srs, tmax)
+                if tmax and (1 << lg) > tmax:
+                    continue
+                row[label] = round(timed(lambda: zk.msm_srs(srs, sc, n=1 << lg, out=com), reps=20), 4)
+            small["2^%d" % lg] = row
+        zk.srs_set_tiny_max(srs, 4096)
+        extras["msm_small"] = small
+        del sc
 
         log("serving")
         extras["serving"] = serving_runs(zk, srs, srs_pts, args.serve_jobs)

@@ -127,7 +127,8 @@ zk_status zk_srs_lagrange_setup(const zk_fr* tau_host, uint32_t log_n, zk_g1* ou
 /* Prepare an SRS (any n affine points, e.g. from zk_srs_setup or a
  * ceremony) for commitments.  Allocates 16 * 64 * n bytes (the points times
  * 2^(16 w), w < 16), 22 * 64 * min(n, 2^16) bytes (times 2^(12 w), for
- * small commitments) and, for n >= 2^21, 13 * 64 * n bytes (times 2^(20 w))
+ * small commitments), 32768 * min(n, 4096) bytes (the small multiples of
+ * zk_srs_set_tiny_max) and, for n >= 2^21, 13 * 64 * n bytes (times 2^(20 w))
  * of device memory owned by the handle; the work is enqueued on `stream`.
  * The handle is bound to the current device. */
 zk_status zk_srs_create(const zk_g1* points, uint64_t n, zk_srs** srs, void* stream);
@@ -149,8 +150,19 @@ uint64_t zk_srs_size(const zk_srs* srs);
  * ZK_EINVAL.  Set it while no call on this SRS is being enqueued. */
 zk_status zk_srs_set_table_policy(zk_srs* srs, uint64_t small_max, uint64_t large_min);
 
-/* Window bits (12, 16 or 20) the policy picks for an n-point commitment, or 0
- * for NULL / n > zk_srs_size. */
+/* Small commitments (§2.1, the KZG commitment [f(tau)]_1 = sum_i f_i
+ * [tau^i]_1, for few coefficients): an n-point commitment with
+ * 0 < n <= tiny_max runs on the handle's table of small multiples
+ * m 16^w [tau^i]_1 (m = 1..8, w < 64, i < min(zk_srs_size, 4096): 32 KB per
+ * point, built by zk_srs_create), one table point per nonzero signed 4-bit
+ * digit summed by trees, instead of a bucket (Pippenger) run; the result
+ * is the same.  Default 4096; 0 turns the path off.  tiny_max <= 4096, else
+ * ZK_EINVAL.  Set it while no call on this SRS is being enqueued. */
+zk_status zk_srs_set_tiny_max(zk_srs* srs, uint64_t tiny_max);
+
+/* Window bits the policy picks for an n-point commitment (4 on the
+ * small-multiples table, else 12, 16 or 20), or 0 for NULL /
+ * n > zk_srs_size. */
 uint32_t zk_srs_window_bits(const zk_srs* srs, uint64_t n);
 
 /* Launch schedule of the MSM and transform kernels on the current device:

@@ -7,7 +7,9 @@ this), only times:
   20-bit windows); which one serves an n-point commitment is a per-SRS
   threshold policy (`zk_srs_set_table_policy`).  The 12-bit table has a
   short reduction (2048 buckets) but more windows, the 20-bit one fewer
-  additions but 16 times the buckets.  `tune` times every feasible table on
+  additions but 16 times the buckets.  Up to 4096 points a commitment can
+  also run on the table of small multiples (4-bit digits summed by trees,
+  no buckets; `zk_srs_set_tiny_max`).  `tune` times every feasible path on
   the running GPU for power-of-two sizes and picks the thresholds that
   follow the measurements.
 * Launch schedule (`zk_set_schedule`, per device): the accumulation slice
@@ -27,7 +29,8 @@ import argparse
 import json
 
 SMALL_CAP = 1 << 16      # the small table covers the first 2^16 points
-SMALL, MAIN, LARGE = 12, 16, 20   # window bits of the three tables
+TINY_CAP = 1 << 12       # the small-multiples table covers the first 4096 points
+TINY, SMALL, MAIN, LARGE = 4, 12, 16, 20   # window bits of the four paths
 NEVER = 1 << 62
 
 
@@ -48,9 +51,9 @@ def _time_ms(zk, srs, scalars, n, out, reps):
 
 
 def tune(zk, srs, scalars, min_log=10, max_log=22, reps=5):
-    """Median time of each feasible table for n = 2^min_log .. 2^max_log
+    """Median time of each feasible path for n = 2^min_log .. 2^max_log
     (n <= srs.n, scalars: device (>= n, 8) tensor) and the policy they imply.
-    Returns {"small_max", "large_min", "timings": {n: {window_bits: ms}}}."""
+    Returns {"tiny_max", "small_max", "large_min", "timings": {n: {window_bits: ms}}}."""
     import torch
     out = torch.empty((1, 16), dtype=torch.int32, device=scalars.device)
     forced = {SMALL: (SMALL_CAP, NEVER), MAIN: (0, NEVER), LARGE: (0, 0)}
@@ -60,6 +63,7 @@ def tune(zk, srs, scalars, min_log=10, max_log=22, reps=5):
         if n > srs.n or n > scalars.shape[0]:
             break
         row = {}
+        zk.srs_set_tiny_max(srs, 0)
         for bits, (small_max, large_min) in forced.items():
             if bits == SMALL and n >= SMALL_CAP:
                 continue
@@ -67,6 +71,10 @@ def tune(zk, srs, scalars, min_log=10, max_log=22, reps=5):
             if zk.srs_window_bits(srs, n) != bits:
                 continue  # table not built for this SRS
             row[bits] = _time_ms(zk, srs, scalars, n, out, reps)
+        if n <= TINY_CAP:
+            zk.srs_set_tiny_max(srs, TINY_CAP)
+            if zk.srs_window_bits(srs, n) == TINY:
+                row[TINY] = _time_ms(zk, srs, scalars, n, out, reps)
         timings[n] = row
     policy = derive_policy(timings)
     policy["timings"] = {str(n): {str(b): round(t, 4) for b, t in row.items()} for n, row in timings.items()}
@@ -75,9 +83,20 @@ def tune(zk, srs, scalars, min_log=10, max_log=22, reps=5):
 
 
 def derive_policy(timings):
-    """Thresholds from {n: {window_bits: ms}}: the small table up to the first
-    size where it stops being fastest; the 20-bit table from the first size
-    after which it stays fastest."""
+    """Thresholds from {n: {window_bits: ms}}: the small-multiples path up to
+    the last size of the run of sizes (from the smallest) where it is fastest;
+    among the tables, the small one up to the first size where it stops
+    being fastest and the 20-bit one from the first size after which it stays
+    fastest."""
+    tiny_max = 0
+    for n in sorted(timings):
+        row = timings[n]
+        if TINY in row and row[TINY] <= min(row.values()):
+            tiny_max = n
+        else:
+            break
+    tables = {n: {b: t for b, t in row.items() if b != TINY} for n, row in timings.items()}
+    timings = {n: row for n, row in tables.items() if row}
     small_max = 0
     for n in sorted(timings):
         row = timings[n]
@@ -92,7 +111,7 @@ def derive_policy(timings):
             large_min = n
         else:
             break
-    return {"small_max": min(small_max, SMALL_CAP), "large_min": large_min}
+    return {"tiny_max": min(tiny_max, TINY_CAP), "small_max": min(small_max, SMALL_CAP), "large_min": large_min}
 
 
 # Candidate values per schedule knob (the built-in value first).
@@ -174,6 +193,7 @@ def tune_schedule(zk, srs, scalars, evals, reps=7, rounds=1, gain=0.02):
 
 def apply(zk, srs, policy):
     zk.srs_set_table_policy(srs, int(policy["small_max"]), int(policy["large_min"]))
+    zk.srs_set_tiny_max(srs, int(policy.get("tiny_max", TINY_CAP)))
     if policy.get("schedule"):
         zk.set_schedule(policy["schedule"])
 
@@ -217,7 +237,8 @@ def main():
         policy["mix_ms"], policy["default_mix_ms"] = sched["mix_ms"], sched["default_mix_ms"]
     name = torch.cuda.get_device_name(0)
     save(policy, args.out, name)
-    print(json.dumps({"device": name, "small_max": policy["small_max"], "large_min": policy["large_min"],
+    print(json.dumps({"device": name, "tiny_max": policy["tiny_max"], "small_max": policy["small_max"],
+                      "large_min": policy["large_min"],
                       "schedule": policy.get("schedule"), "mix_ms": policy.get("mix_ms"),
                       "default_mix_ms": policy.get("default_mix_ms")}))
 

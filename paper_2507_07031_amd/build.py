@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libzk.so")
-SOURCES = ["api.hip", "ntt.hip", "msm.hip", "msm_accumulate.hip", "prof.hip", "validate.hip", "open.hip", "quotient.hip", "accum.hip", "g2msm.hip"]
+SOURCES = ["api.hip", "ntt.hip", "msm.hip", "msm_accumulate.hip", "msm_tiny.hip", "prof.hip", "validate.hip", "open.hip", "quotient.hip", "accum.hip", "g2msm.hip"]
 HIPCC = os.environ.get("HIPCC", "hipcc")
 ARCH = "gfx950"
 

@@ -539,6 +539,9 @@ constexpr uint64_t SRS_LARGE_MIN = 1ull << 21; // MSMs from this size use the la
 // longer the bottleneck), so the 8-bit table serves no size unless a policy
 // asks for it; the 20-bit table wins from 2^21.
 constexpr uint64_t SRS_SMALL_POLICY = 0;
+// Commitments of at most this many points run on the small-multiples table
+// (msm_tiny.hip) by default.
+constexpr uint64_t SRS_TINY_POLICY = TINY_MAX;
 
 }  // namespace
 
@@ -557,6 +560,9 @@ struct zk_srs {
   uint32_t* tab_large;  // W_large * n points for large MSMs (n >= SRS_LARGE_MIN only)
   uint64_t small_max;   // table policy: n < small_max -> small table,
   uint64_t large_min;   //               n >= large_min -> large table (if built), else main
+  uint32_t n_tiny;      // min(n, TINY_MAX)
+  uint32_t* tab_tiny;   // m 16^w P_i, m = 1..8, w < 64, i < n_tiny (msm_tiny.hip)
+  uint64_t tiny_max;    // policy: 0 < n <= tiny_max -> the small-multiples run
 };
 
 struct zk_srs_g2 {
@@ -825,12 +831,17 @@ zk_status zk_srs_create(const zk_g1* points, uint64_t n, zk_srs** srs, void* str
   h->tab_large = nullptr;
   h->small_max = SRS_SMALL_POLICY;
   h->large_min = SRS_LARGE_MIN;
+  h->n_tiny = (uint32_t)std::min<uint64_t>(n, TINY_MAX);
+  h->tab_tiny = nullptr;
+  h->tiny_max = SRS_TINY_POLICY;
   if (n) {
     const uint32_t* pts = reinterpret_cast<const uint32_t*>(points);
     hipError_t e = hipMalloc(&h->tab, (size_t)h->W * n * 64);
     if (e == hipSuccess) e = hipMalloc(&h->tab_small, (size_t)h->W_small * h->n_small * 64);
     if (e == hipSuccess && n >= SRS_LARGE_MIN) e = hipMalloc(&h->tab_large, (size_t)h->W_large * n * 64);
+    if (e == hipSuccess) e = hipMalloc(&h->tab_tiny, (size_t)msm_tiny_table_points(h->n_tiny) * 64);
     if (e == hipSuccess) e = msm_build_table(pts, h->tab, n, h->c, h->W, (hipStream_t)stream);
+    if (e == hipSuccess) e = msm_build_tiny_table(h->tab, n, h->n_tiny, h->tab_tiny, (hipStream_t)stream);
     if (e == hipSuccess)
       e = msm_build_table(pts, h->tab_small, h->n_small, h->c_small, h->W_small, (hipStream_t)stream);
     if (e == hipSuccess && h->tab_large)
@@ -839,6 +850,7 @@ zk_status zk_srs_create(const zk_g1* points, uint64_t n, zk_srs** srs, void* str
       if (h->tab) (void)hipFree(h->tab);
       if (h->tab_small) (void)hipFree(h->tab_small);
       if (h->tab_large) (void)hipFree(h->tab_large);
+      if (h->tab_tiny) (void)hipFree(h->tab_tiny);
       delete h;
       return hip_fail(e, "zk_srs_create: table build");
     }
@@ -857,6 +869,7 @@ zk_status zk_srs_destroy(zk_srs* srs) {
     (void)hipFree(srs->tab);
     if (srs->tab_small) (void)hipFree(srs->tab_small);
     if (srs->tab_large) (void)hipFree(srs->tab_large);
+    if (srs->tab_tiny) (void)hipFree(srs->tab_tiny);
     (void)hipSetDevice(prev);
   }
   delete srs;
@@ -892,9 +905,23 @@ static MsmPlan srs_plan(const zk_srs* srs, uint64_t n, const uint64_t off[2]) {
   }
 }
 
+// Does an n-point commitment run on the small-multiples table?
+static bool srs_uses_tiny(const zk_srs* srs, uint64_t n) {
+  return srs && srs->tab_tiny && n > 0 && n <= srs->tiny_max && n <= srs->n_tiny;
+}
+
 static zk_status msm_srs_one(const zk_srs* srs, const uint32_t* scalars, uint64_t n, uint32_t* out16,
                              hipStream_t s, hipEvent_t after_accumulate = nullptr,
                              hipEvent_t before_accumulate = nullptr) {
+  if (srs_uses_tiny(srs, n)) {
+    Scratch ws;
+    zk_status st = scratch_alloc(ws, msm_tiny_workspace_bytes((uint32_t)n), s);
+    if (st) return st;
+    if (before_accumulate) ZK_HIP(hipStreamWaitEvent(s, before_accumulate, 0), "hipStreamWaitEvent");
+    ZK_HIP(msm_tiny_run(srs->tab_tiny, srs->n_tiny, scalars, (uint32_t)n, ws.p, out16, s, after_accumulate),
+           "msm (small multiples)");
+    return ZK_OK;
+  }
   const uint64_t off[2] = {0, n};
   const MsmPlan plan = srs_plan(srs, n, off);
   const SrsTable t = srs_table_for(srs, n);
@@ -910,8 +937,16 @@ zk_status zk_srs_set_table_policy(zk_srs* srs, uint64_t small_max, uint64_t larg
   return ZK_OK;
 }
 
+zk_status zk_srs_set_tiny_max(zk_srs* srs, uint64_t tiny_max) {
+  if (!srs) return fail(ZK_EINVAL, "zk_srs_set_tiny_max: NULL srs");
+  if (tiny_max > TINY_MAX) return fail(ZK_EINVAL, "zk_srs_set_tiny_max: tiny_max above 4096");
+  srs->tiny_max = tiny_max;
+  return ZK_OK;
+}
+
 uint32_t zk_srs_window_bits(const zk_srs* srs, uint64_t n) {
   if (!srs || n > srs->n) return 0;
+  if (srs_uses_tiny(srs, n)) return 4;
   switch (srs_table_for(srs, n)) {
     case SrsTable::small: return SRS_C_SMALL;
     case SrsTable::large: return SRS_C_LARGE;
@@ -921,6 +956,7 @@ uint32_t zk_srs_window_bits(const zk_srs* srs, uint64_t n) {
 
 uint64_t zk_msm_srs_workspace_bytes(const zk_srs* srs, uint64_t n) {
   if (n >= (1ull << 31) / 16) return 0;
+  if (srs_uses_tiny(srs, n)) return msm_tiny_workspace_bytes((uint32_t)n);
   const uint64_t off[2] = {0, n};
   return msm_workspace_bytes(srs_plan(srs, n, off));
 }
@@ -1025,9 +1061,10 @@ zk_status zk_msm_srs_noalloc(const zk_srs* srs, const zk_fr* scalars, uint64_t n
     if (dev >= 0 && dev < 64 && g_ctx[dev].ready) base = g_ctx[dev].noalloc;
   }
   if (!base) return fail(ZK_EINVAL, "zk_msm_srs_noalloc: device context not set up");
+  const bool tiny = srs_uses_tiny(srs, n);
   const uint64_t off[2] = {0, n};
   const MsmPlan plan = srs_plan(srs, n, off);
-  const size_t need = msm_workspace_bytes(plan) + 256;
+  const size_t need = (tiny ? msm_tiny_workspace_bytes((uint32_t)n) : msm_workspace_bytes(plan)) + 256;
   if (need > NOALLOC_SCRATCH_BYTES)
     return fail(ZK_EUNSUPPORTED, "zk_msm_srs_noalloc: " + std::to_string(n) + " points need " +
                                      std::to_string(need) + " bytes of scratch, above the fixed " +
@@ -1043,6 +1080,12 @@ zk_status zk_msm_srs_noalloc(const zk_srs* srs, const zk_fr* scalars, uint64_t n
     ZK_HIP(hipMemcpyAsync(&found, vflag, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
     ZK_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
     if (found) return fail(ZK_EINVAL, "zk_msm_srs_noalloc: an Fr input is not canonical (>= r)");
+  }
+  if (tiny) {
+    ZK_HIP(msm_tiny_run(srs->tab_tiny, srs->n_tiny, reinterpret_cast<const uint32_t*>(scalars), (uint32_t)n,
+                        base + 256, reinterpret_cast<uint32_t*>(out), s),
+           "msm (small multiples)");
+    return ZK_OK;
   }
   const SrsTable t = srs_table_for(srs, n);
   const uint32_t* tab = t == SrsTable::small ? srs->tab_small : t == SrsTable::large ? srs->tab_large : srs->tab;

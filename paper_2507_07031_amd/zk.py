@@ -27,7 +27,7 @@ EXPORTS = ("zk_last_error", "zk_ntt", "zk_intt", "zk_coset_ntt", "zk_msm", "zk_s
            "zk_kzg_open_batch", "zk_quotient_mul",
            "zk_srs_lagrange_setup", "zk_transcript_challenge", "zk_acc_fold",
            "zk_srs_g2_setup", "zk_srs_g2_create", "zk_srs_g2_destroy", "zk_srs_g2_size", "zk_msm_g2_srs",
-           "zk_srs_set_table_policy", "zk_srs_window_bits", "zk_set_scratch_budget", "zk_scratch_held", "zk_msm_srs_noalloc",
+           "zk_srs_set_table_policy", "zk_srs_set_tiny_max", "zk_srs_window_bits", "zk_set_scratch_budget", "zk_scratch_held", "zk_msm_srs_noalloc",
            "zk_quotient_polyiop", "zk_calibrate_mad_rate", "zk_set_schedule", "zk_get_schedule")
 
 
@@ -73,6 +73,7 @@ def _load():
         "zk_srs_g2_size": ([P], U64),
         "zk_msm_g2_srs": ([P, P, U64, P, P], I),
         "zk_srs_set_table_policy": ([P, U64, U64], I),
+        "zk_srs_set_tiny_max": ([P, U64], I),
         "zk_srs_window_bits": ([P, U64], U32),
         "zk_acc_fold": ([U32, P, P, U32, P, P, P, U64, P, P, U64, P, P, P, P, P, P, P, P, P], I),
         "zk_kzg_open_batch": ([P, P, U32, U64, P, P, P, P, P, P], I),
@@ -263,6 +264,12 @@ def srs_set_table_policy(srs, small_max, large_min):
     """n < small_max: 12-bit-window table (first 2^16 points); n >= large_min:
     20-bit (if built); 16-bit otherwise."""
     _check(lib.zk_srs_set_table_policy(srs.handle, int(small_max), int(large_min)))
+
+
+def srs_set_tiny_max(srs, tiny_max):
+    """Commitments of 0 < n <= tiny_max points run on the small-multiples
+    table (default 4096; 0 turns it off)."""
+    _check(lib.zk_srs_set_tiny_max(srs.handle, int(tiny_max)))
 
 
 SCHEDULE_FIELDS = ("acc_max_slice", "acc_blocks_per_cu", "reduce_chunk", "sort_chunk", "sort_bin_entries",

@@ -8,8 +8,13 @@ class FakeZk:
     def __init__(self):
         self.policy = None
 
+        self.tiny = None
+
     def srs_set_table_policy(self, srs, small_max, large_min):
         self.policy = (small_max, large_min)
+
+    def srs_set_tiny_max(self, srs, tiny_max):
+        self.tiny = tiny_max
 
 
 def test_save_load_roundtrip(tmp_path):
@@ -23,19 +28,35 @@ def test_save_load_roundtrip(tmp_path):
 def test_apply_sets_policy():
     z = FakeZk()
     autotune.apply(z, object(), {"small_max": 1024, "large_min": 1 << 20})
-    assert z.policy == (1024, 1 << 20)
+    assert z.policy == (1024, 1 << 20) and z.tiny == autotune.TINY_CAP
+    autotune.apply(z, object(), {"tiny_max": 0, "small_max": 0, "large_min": 1 << 21})
+    assert z.tiny == 0
 
 
 def test_derive_policy_follows_timings():
     t = {1024: {12: 0.1, 16: 0.2}, 2048: {12: 0.15, 16: 0.2}, 4096: {12: 0.3, 16: 0.25},
          1 << 16: {16: 1.0, 20: 1.2}, 1 << 20: {16: 2.0, 20: 1.9}, 1 << 21: {16: 4.0, 20: 3.1}}
-    assert autotune.derive_policy(t) == {"small_max": 2049, "large_min": 1 << 20}
+    assert autotune.derive_policy(t) == {"tiny_max": 0, "small_max": 2049, "large_min": 1 << 20}
     # 20-bit never fastest at the top: no large threshold; 12-bit never fastest: 0
     t2 = {1024: {12: 0.3, 16: 0.2}, 1 << 21: {16: 3.0, 20: 3.1}}
-    assert autotune.derive_policy(t2) == {"small_max": 0, "large_min": autotune.NEVER}
+    assert autotune.derive_policy(t2) == {"tiny_max": 0, "small_max": 0, "large_min": autotune.NEVER}
     # the small-table threshold never passes the table's 2^16 points
     t3 = {1 << 16: {12: 0.1, 16: 0.2}}
     assert autotune.derive_policy(t3)["small_max"] == 1 << 16
+
+
+def test_derive_policy_small_multiples():
+    # fastest up to 2048, then the tables win: tiny_max 2048, and the table
+    # thresholds are derived among the tables alone
+    t = {1024: {4: 0.1, 12: 0.3, 16: 0.35}, 2048: {4: 0.2, 12: 0.31, 16: 0.36},
+         4096: {4: 0.5, 12: 0.33, 16: 0.4}, 8192: {12: 0.5, 16: 0.45}}
+    assert autotune.derive_policy(t) == {"tiny_max": 2048, "small_max": 4097, "large_min": autotune.NEVER}
+    # not fastest at the smallest size: off, whatever happens above
+    t2 = {1024: {4: 0.5, 16: 0.4}, 2048: {4: 0.1, 16: 0.4}}
+    assert autotune.derive_policy(t2)["tiny_max"] == 0
+    # never above the table's 4096 points
+    t3 = {4096: {4: 0.1, 16: 0.4}}
+    assert autotune.derive_policy(t3)["tiny_max"] == 4096
 
 
 class FakeZkSchedule(FakeZk):

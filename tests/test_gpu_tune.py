@@ -1,6 +1,7 @@
 """The commitment does not depend on the table policy (window size), and the
-autotuner produces a valid policy: commitments under forced 12-, 16- and
-20-bit-window tables equal each other and the closed form [f(tau)]_1."""
+autotuner produces a valid policy: commitments on the small-multiples table
+and under forced 12-, 16- and 20-bit-window tables equal each other and the
+closed form [f(tau)]_1."""
 import pytest
 
 from oracle import msm as omsm
@@ -50,13 +51,18 @@ def test_result_independent_of_window_size(zk, tau, srs, n):
     s = zk.to_device(s_h)
     want = omsm.srs_msm_closed_form(tau[1], fr_from_host(s_h))
     seen = []
-    for bits, (small_max, large_min) in {12: (1 << 16, NEVER), 16: (0, NEVER), 20: (0, 0)}.items():
+    # 4: the small-multiples table (up to 4096 points); 12/16/20: the
+    # pre-shifted tables with the small-multiples path off
+    paths = {4: (4096, 0, 1 << 21), 12: (0, 1 << 16, NEVER), 16: (0, 0, NEVER), 20: (0, 0, 0)}
+    for bits, (tiny_max, small_max, large_min) in paths.items():
+        zk.srs_set_tiny_max(srs, tiny_max)
         zk.srs_set_table_policy(srs, small_max, large_min)
         if zk.srs_window_bits(srs, n) != bits:
             continue
         log("msm n=%d window bits %d" % (n, bits))
         assert _commit(zk, srs, s, n) == want, bits
         seen.append(bits)
+    zk.srs_set_tiny_max(srs, 4096)
     zk.srs_set_table_policy(srs, 0, 1 << 21)
     assert len(seen) >= 2
 
@@ -67,13 +73,15 @@ def test_autotuner_policy(zk, tau, srs):
     s = zk.to_device(s_h)
     log("autotune 2^10..2^16")
     policy = autotune.tune(zk, srs, s, min_log=10, max_log=16, reps=2)
-    assert 0 <= policy["small_max"] <= 1 << 16
+    assert 0 <= policy["small_max"] <= 1 << 16 and 0 <= policy["tiny_max"] <= 4096
     assert set(policy["timings"]) == {str(1 << k) for k in range(10, 17)}
+    assert "4" in policy["timings"][str(1 << 10)] and "4" not in policy["timings"][str(1 << 13)]
     for n in (1 << 12, (1 << 16) - 5):
         assert _commit(zk, srs, s, n) == omsm.srs_msm_closed_form(tau[1], fr_from_host(s_h[:n]))
     with pytest.raises(zk.ZkError):
         zk.srs_set_table_policy(srs, (1 << 16) + 1, NEVER)
     zk.srs_set_table_policy(srs, 0, 1 << 21)
+    zk.srs_set_tiny_max(srs, 4096)
 
 
 def test_result_independent_of_schedule(zk, tau, srs):
