@@ -19,6 +19,7 @@
 #include "field.h"
 #include "g2msm.h"
 #include "msm.h"
+#include "msm_tiny.h"
 #include "ntt.h"
 #include "open.h"
 #include "prof.h"

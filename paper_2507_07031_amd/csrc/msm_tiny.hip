@@ -17,6 +17,7 @@
 #include "curve_quad.h"
 #include "msm.h"
 #include "msm_store.h"
+#include "msm_tiny.h"
 
 namespace zk {
 
