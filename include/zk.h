@@ -181,7 +181,7 @@ uint32_t zk_srs_window_bits(const zk_srs* srs, uint64_t n);
  *  sort_bin_entries   entries per coarse bin the two-level bucket sort aims
  *                     at, a power of two in 2^10..2^20 (2^15)
  *  ntt_tile_log       preferred transform tile, 11 (2^11 points where both
- *                     passes fit it) or 12 (2^12 points) (12)
+ *                     passes fit it) or 12 (2^12 points) (11)
  *  ntt_unit_log       transform stages per LDS round trip: 3 (each thread
  *                     holds 8 points) or 2 (4 points, more threads) (3)
  *  ntt_overlap_tile_log  tile of a transform the library runs beside other

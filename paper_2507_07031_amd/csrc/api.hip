@@ -341,6 +341,18 @@ struct NttRun {
   Scratch tmp;  // intermediate of the two- and three-pass forms
 };
 
+// Leading stages a pass with input stride s_in over transforms of 2^m points
+// can skip: with valid_n = 2^v s_in, the input indices below valid_n are
+// exactly the first 2^v points of every transform (its batch index is below
+// s_in), so the other 2^m - 2^v are zero padding.
+static uint32_t ntt_zero_log(uint32_t valid_n, uint32_t s_in, uint32_t m) {
+  if (valid_n == 0 || valid_n % s_in) return 0;
+  const uint32_t V = valid_n / s_in;
+  if (V & (V - 1)) return 0;
+  const uint32_t v = 31 - __builtin_clz(V);
+  return v < m ? m - v : 0;
+}
+
 zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t L, bool inverse, const f29* pre_lo,
                       const f29* pre_hi, uint32_t valid_n, hipStream_t s, NttRun& r, bool overlapped = false) {
   const uint32_t T = ntt_tile_log();
@@ -367,6 +379,7 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
     p.pre_lo = pre_lo;
     p.pre_hi = pre_hi;
     p.post_scale = scale;
+    p.zero_log = ntt_zero_log(valid_n, 1, L);
     r.passes = 1;
     return ZK_OK;
   }
@@ -401,6 +414,7 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   a.post_tw_L = L;
   a.pre_lo = pre_lo;
   a.pre_hi = pre_hi;
+  a.zero_log = ntt_zero_log(valid_n, N1, mA);
   NttPass& b = r.b;
   b.in = Y;
   b.out = out;

@@ -34,7 +34,7 @@ struct Schedule {
   uint32_t reduce_chunk = 0;         // buckets per running-sum chunk (0: 4, 8 or 16 by bucket count)
   uint32_t sort_chunk = 1024;        // scalars per coarse-sort workgroup
   uint32_t sort_bin_entries = 32768; // entries per coarse bin the two-level sort aims at
-  uint32_t ntt_tile_log = 12;        // preferred transform tile (11: 2^11 where both passes fit it, else 2^12)
+  uint32_t ntt_tile_log = 11;        // preferred transform tile (11: 2^11 where both passes fit it, else 2^12)
   uint32_t ntt_unit_log = 3;         // transform stages per LDS round trip: 3 (8 points a thread) or 2
   uint32_t ntt_overlap_tile_log = 11;  // tile of a transform the library runs beside other kernels
 };

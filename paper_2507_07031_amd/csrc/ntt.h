@@ -33,6 +33,8 @@ struct NttPass {
   const f29* pre_hi;
   const f29* post_scale;  // multiply every output by this constant (nullptr: none)
   uint32_t unit_log;   // stages per LDS round trip at most: 3 (8 points a thread) or 2 (4 points)
+  uint32_t zero_log;   // points i >= 2^(m - zero_log) of every transform are zero padding (input index
+                       // >= valid_n): the first zero_log stages only copy, and are not run
 };
 
 hipError_t ntt_pass_setup();

@@ -177,6 +177,17 @@ __device__ __forceinline__ void dit_stages(uint32_t* lds, uint32_t s, uint32_t m
   }
 }
 
+// Workgroups go to the eight XCDs round robin (block b to XCD b mod 8), each
+// XCD with its own L2.  Blocks are renumbered so that every XCD runs one
+// contiguous range of tiles: neighbouring tiles read the two halves (or
+// quarters) of the same 128-byte lines in a strided pass, and then fetch
+// each line into one L2 only.  A bijection of [0, nb) for any nb.
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t nb) {
+  constexpr uint32_t XCDS = 8;
+  const uint32_t q = nb / XCDS, r = nb % XCDS, x = b % XCDS;
+  return x * q + min(x, r) + b / XCDS;
+}
+
 // MAXR = 3: a thread holds 8 points and runs up to three stages per LDS round
 // trip (fewer round trips; 178 VGPRs, two waves per SIMD).  MAXR = 2: 4
 // points and two stages (more round trips, but at most 128 VGPRs, so the two
@@ -186,13 +197,20 @@ template <int MAXR>
 __device__ __forceinline__ void ntt_pass_body(const NttPass& a) {
   extern __shared__ uint32_t lds[];
   const uint32_t M = 1u << a.m;
-  const uint32_t g0 = blockIdx.x * a.G;
+  const uint32_t g0 = xcd_contiguous(blockIdx.x, gridDim.x) * a.G;
   const uint32_t G = min(a.G, a.nbatch - g0);
   const uint32_t TE = M * G;
   const uint32_t tid = threadIdx.x;
 
-  // ---- load (bit-reversed into LDS), coset pre-scale, zero padding
-  for (uint32_t e = tid; e < TE; e += blockDim.x) {
+  // ---- load (bit-reversed into LDS), coset pre-scale, zero padding.  Only
+  // the first 2^(m - z) points of each transform can be nonzero (z =
+  // zero_log); in bit-reversed order they sit at slots that are multiples of
+  // 2^z, and the first z stages turn each such group [v, 0, ..., 0] into
+  // [v, v, ..., v], so v is written to its 2^z slots and those stages are
+  // skipped.
+  const uint32_t z = a.zero_log;
+  const uint32_t TL = TE >> z;
+  for (uint32_t e = tid; e < TL; e += blockDim.x) {
     const uint32_t b = e % G, i = e / G;
     const uint32_t gi = (g0 + b) + i * a.s_in;
     uint32_t w[8];
@@ -207,12 +225,12 @@ __device__ __forceinline__ void ntt_pass_body(const NttPass& a) {
       for (int q = 0; q < 8; q++) w[q] = 0;
     }
     const uint32_t slot = b * M + (a.m ? (__brev(i) >> (32 - a.m)) : 0);
-    st8(lds_at(lds, slot), w);
+    for (uint32_t r = 0; r < (1u << z); r++) st8(lds_at(lds, slot + r), w);
   }
   __syncthreads();
 
   // ---- decimation-in-time stages, up to MAXR per LDS round trip
-  for (uint32_t st = 1; st <= a.m;) {
+  for (uint32_t st = 1 + z; st <= a.m;) {
     const uint32_t left = a.m - st + 1;
     if (left == 1) {
       dit_stages<1>(lds, st, a.m, TE, a.ladder);
@@ -290,6 +308,7 @@ hipError_t ntt_launch_pass(const NttPass& p, hipStream_t s) {
   uint32_t threads = te / (r2 ? 4 : 8);
   if (threads < 64) threads = 64;
   if (threads > NTT_THREADS) threads = NTT_THREADS;
+  if (p.zero_log > p.m) return hipErrorInvalidValue;
   const ProfToken t = prof_begin("ntt.pass", s);
   if (r2)
     hipLaunchKernelGGL(ntt_pass_kernel_r2, dim3(blocks), dim3(threads), (size_t)(te + te / 8 + 1) * 32, s, p);
