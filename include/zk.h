@@ -180,13 +180,14 @@ uint32_t zk_srs_window_bits(const zk_srs* srs, uint64_t n);
  *                     256..16384 (1024)
  *  sort_bin_entries   entries per coarse bin the two-level bucket sort aims
  *                     at, a power of two in 2^10..2^20 (2^15)
- *  ntt_tile_log       preferred transform tile, 11 (2^11 points where both
- *                     passes fit it) or 12 (2^12 points) (11)
+ *  ntt_tile_log       preferred transform tile, 10, 11 or 12 (2^10, 2^11 or
+ *                     2^12 points, used where both passes' transforms fit
+ *                     it, else the smallest tile that holds them) (11)
  *  ntt_unit_log       transform stages per LDS round trip: 3 (each thread
  *                     holds 8 points) or 2 (4 points, more threads) (3)
  *  ntt_overlap_tile_log  tile of a transform the library runs beside other
  *                     kernels (zk_commit_job's coset transform beside the
- *                     MSM's reduction), 11 or 12 (11)
+ *                     MSM's reduction), 10, 11 or 12 (11)
  * ZK_EINVAL for a value out of range (nothing is changed then). */
 typedef struct zk_schedule {
   uint32_t acc_max_slice;

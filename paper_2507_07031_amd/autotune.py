@@ -121,9 +121,9 @@ SCHEDULE_CANDIDATES = {
     "reduce_chunk": [0, 4, 8, 16, 32],
     "sort_chunk": [1024, 512, 2048, 4096],
     "sort_bin_entries": [32768, 8192, 131072],
-    "ntt_tile_log": [11, 12],
+    "ntt_tile_log": [11, 12, 10],
     "ntt_unit_log": [3, 2],
-    "ntt_overlap_tile_log": [11, 12],
+    "ntt_overlap_tile_log": [11, 12, 10],
 }
 
 

@@ -389,12 +389,13 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   // transforms and its strided reads move more than one element at a time
   const uint32_t mA = three ? (L + 2) / 3 : L / 2, mB = L - mA;
   const uint32_t N1 = 1u << mB, N2 = 1u << mA;
-  // tiles of 2048 points where both passes fit (two workgroups per CU) and
-  // the schedule prefers them, else 4096; a transform that runs beside other
-  // kernels (overlapped) has its own preference: a 4096-point tile's 144 KB
-  // of LDS leaves a compute unit no room for the other kernels' workgroups
+  // the schedule's preferred tile (2^10, 2^11 or 2^12 points: four, two or
+  // one workgroups per CU) where both passes' transforms fit it, else the
+  // smallest that holds them; a transform that runs beside other kernels
+  // (overlapped) has its own preference: a 4096-point tile's 144 KB of LDS
+  // leaves a compute unit no room for the other kernels' workgroups
   const uint32_t pref = overlapped ? sched.ntt_overlap_tile_log : sched.ntt_tile_log;
-  const uint32_t tile = !three && mB <= T - 1 && pref < T ? (1u << (T - 1)) : (1u << T);
+  const uint32_t tile = three ? (1u << T) : (1u << std::max(mB, std::min(pref, T)));
   zk_status st = scratch_alloc(r.tmp, (size_t)32 << L, s);
   if (st) return st;
   uint32_t* Y = static_cast<uint32_t*>(r.tmp.p);
@@ -648,13 +649,13 @@ zk_status zk_set_schedule(const zk_schedule* sch) {
       v.sort_bin_entries = sch->sort_bin_entries;
     }
     if (sch->ntt_tile_log) {
-      if (sch->ntt_tile_log != 11 && sch->ntt_tile_log != 12)
-        return fail(ZK_EINVAL, "zk_set_schedule: ntt_tile_log must be 11 or 12");
+      if (sch->ntt_tile_log < 10 || sch->ntt_tile_log > 12)
+        return fail(ZK_EINVAL, "zk_set_schedule: ntt_tile_log must be 10, 11 or 12");
       v.ntt_tile_log = sch->ntt_tile_log;
     }
     if (sch->ntt_overlap_tile_log) {
-      if (sch->ntt_overlap_tile_log != 11 && sch->ntt_overlap_tile_log != 12)
-        return fail(ZK_EINVAL, "zk_set_schedule: ntt_overlap_tile_log must be 11 or 12");
+      if (sch->ntt_overlap_tile_log < 10 || sch->ntt_overlap_tile_log > 12)
+        return fail(ZK_EINVAL, "zk_set_schedule: ntt_overlap_tile_log must be 10, 11 or 12");
       v.ntt_overlap_tile_log = sch->ntt_overlap_tile_log;
     }
     if (sch->ntt_unit_log) {

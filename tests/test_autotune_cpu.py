@@ -83,5 +83,5 @@ def test_schedule_candidates_are_valid():
     assert c["reduce_chunk"][0] == 0 and all(v == 0 or (v & (v - 1)) == 0 and v <= 64 for v in c["reduce_chunk"])
     assert c["sort_chunk"][0] == 1024 and all((v & (v - 1)) == 0 and 256 <= v <= 16384 for v in c["sort_chunk"])
     assert all((v & (v - 1)) == 0 and 1 << 10 <= v <= 1 << 20 for v in c["sort_bin_entries"])
-    assert c["ntt_tile_log"] == [11, 12] and c["ntt_unit_log"] == [3, 2]
-    assert c["ntt_overlap_tile_log"] == [11, 12]
+    assert c["ntt_tile_log"] == [11, 12, 10] and c["ntt_unit_log"] == [3, 2]
+    assert c["ntt_overlap_tile_log"] == [11, 12, 10]

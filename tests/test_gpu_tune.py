@@ -132,3 +132,30 @@ def test_schedule_tuner_runs(zk, srs):
         assert zk.get_schedule() == res["schedule"]
     finally:
         zk.set_schedule(None)
+
+
+@pytest.mark.parametrize("log_n", [10, 13, 14, 17, 20, 21])
+def test_transforms_independent_of_tile(zk, log_n):
+    # every transform tile (2^10..2^12 points) and stages per LDS round trip
+    # (2 or 3) gives the identical NTT, iNTT and 4x coset evaluations; at
+    # 2^21 and above a 2^10 tile cannot hold the transforms and the planner
+    # takes the smallest tile that does
+    import numpy as np
+    import torch
+    ev = zk.to_device(gen.uniform_fr(9600 + log_n, 1 << log_n))
+    zk.set_schedule(None)
+    refs = [zk.to_host(f(ev)).copy() for f in (zk.ntt, zk.intt, lambda x: zk.coset_ntt(x, 2))]
+    try:
+        for tile in (10, 11, 12):
+            for unit in (2, 3):
+                zk.set_schedule({"ntt_tile_log": tile, "ntt_unit_log": unit, "ntt_overlap_tile_log": tile})
+                log("transforms 2^%d tile 2^%d unit %d" % (log_n, tile, unit))
+                got = [zk.to_host(f(ev)) for f in (zk.ntt, zk.intt, lambda x: zk.coset_ntt(x, 2))]
+                for g, r in zip(got, refs):
+                    assert np.array_equal(g, r), (log_n, tile, unit)
+        with pytest.raises(zk.ZkError) as ei:
+            zk.set_schedule({"ntt_tile_log": 9})
+        assert ei.value.code == zk.ZK_EINVAL
+    finally:
+        zk.set_schedule(None)
+        torch.cuda.synchronize()
