@@ -857,7 +857,7 @@ zk_status zk_srs_create(const zk_g1* points, uint64_t n, zk_srs** srs, void* str
     if (e == hipSuccess && n >= SRS_LARGE_MIN) e = hipMalloc(&h->tab_large, (size_t)h->W_large * n * 64);
     if (e == hipSuccess) e = hipMalloc(&h->tab_tiny, (size_t)msm_tiny_table_points(h->n_tiny) * 64);
     if (e == hipSuccess) e = msm_build_table(pts, h->tab, n, h->c, h->W, (hipStream_t)stream);
-    if (e == hipSuccess) e = msm_build_tiny_table(h->tab, n, h->n_tiny, h->tab_tiny, (hipStream_t)stream);
+    if (e == hipSuccess) e = msm_build_tiny_table(h->tab, h->c, h->W, n, h->n_tiny, h->tab_tiny, (hipStream_t)stream);
     if (e == hipSuccess)
       e = msm_build_table(pts, h->tab_small, h->n_small, h->c_small, h->W_small, (hipStream_t)stream);
     if (e == hipSuccess && h->tab_large)

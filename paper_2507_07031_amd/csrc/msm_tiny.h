@@ -16,8 +16,10 @@ constexpr uint32_t TINY_MAX = 4096;
 constexpr uint32_t TINY_NT = 256;
 // Points in the table of nt points (64 B each).
 uint64_t msm_tiny_table_points(uint32_t nt);
-// tab16: the 16-bit-window pre-shifted table (rows w < 16, row stride tab_n).
-hipError_t msm_build_tiny_table(const uint32_t* tab16, uint64_t tab_n, uint32_t nt, uint32_t* tiny, hipStream_t s);
+// tab16: the 16-bit-window pre-shifted table (rows w < 16, row stride tab_n);
+// hipErrorInvalidValue unless tab_c = 16, tab_W >= 16 and nt <= tab_n.
+hipError_t msm_build_tiny_table(const uint32_t* tab16, uint32_t tab_c, uint32_t tab_W, uint64_t tab_n, uint32_t nt,
+                                uint32_t* tiny, hipStream_t s);
 size_t msm_tiny_workspace_bytes(uint32_t n);
 // 0 < n <= min(nt, TINY_MAX); workspace of msm_tiny_workspace_bytes(n);
 // out16: canonical affine.  after_terms: if not null, recorded after the

@@ -181,8 +181,11 @@ tiny_sum_kernel(const uint32_t* __restrict__ in, uint32_t count, uint32_t* __res
 
 uint64_t msm_tiny_table_points(uint32_t nt) { return (uint64_t)TINY_WINDOWS * TINY_MULTS * nt; }
 
-hipError_t msm_build_tiny_table(const uint32_t* tab16, uint64_t tab_n, uint32_t nt, uint32_t* tiny, hipStream_t s) {
+hipError_t msm_build_tiny_table(const uint32_t* tab16, uint32_t tab_c, uint32_t tab_W, uint64_t tab_n, uint32_t nt,
+                                uint32_t* tiny, hipStream_t s) {
   if (nt == 0) return hipSuccess;
+  // the build reads rows 0 .. 15 (16^(4 r) P_i) of a 16-bit-window table
+  if (tab_c != 16 || tab_W < TINY_WINDOWS / 4 || nt > tab_n) return hipErrorInvalidValue;
   const uint64_t threads = (uint64_t)TINY_WINDOWS * nt;
   hipLaunchKernelGGL(tiny_build_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, tab16, tab_n, nt,
                      tiny);
