@@ -51,7 +51,7 @@ G2_FQ_PER_MADD = 28
 # HBM bytes of one accumulate dispatch of this workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE scaled by a plain-copy calibration (x2.0 / x1.0);
 # valid only for the kernel sources whose hash is recorded with it.
-ACCUMULATE_TRAFFIC = {"sources_sha256_16": "a8d23e57ae929d82", "bytes": 2725548111}
+ACCUMULATE_TRAFFIC = {"sources_sha256_16": "a8d23e57ae929d82", "bytes": 2728932970}
 TRAFFIC_SOURCES = ("msm_accumulate.hip", "msm_store.h", "msm.h", "curve.h", "field.h", "field_constants.h")
 
 
@@ -236,6 +236,9 @@ def main():
                     help="only run a plain 1 GiB device copy and a 2^24-element Fr fold (counter calibration)")
     ap.add_argument("--mad-calibration", action="store_true",
                     help="only measure the sustained v_mad_u64_u32 rate (the integer roof's basis)")
+    ap.add_argument("--transforms-only", action="store_true",
+                    help="only run the commit workload's transforms (NTT, iNTT 2^20, 4x coset 2^20 -> 2^22), "
+                         "for counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -278,6 +281,23 @@ def main():
                           "products_per_run": 2048 * 256 * 4096 * 16 * 8}))
         return
     n = 1 << 20
+    if args.transforms_only:
+        # the transforms of the 2^20 commit workload, each called `steps` times
+        x = zk.to_device(gen.uniform_fr(gen.CONFIG_SEEDS["commit"], n))
+        y = torch.empty_like(x)
+        cos = torch.empty((4 * n, 8), dtype=torch.int32, device=dev)
+        res = {}
+        for name, fn in (("ntt_2^20", lambda: zk.ntt(x, out=y)), ("intt_2^20", lambda: zk.intt(x, out=y)),
+                         ("coset_2^20->2^22", lambda: zk.coset_ntt(x, 2, out=cos))):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            res[name + "_ms"] = round((time.perf_counter() - t0) * 1e3 / args.steps, 4)
+        print(json.dumps({"transforms_only": res, "calls_each": args.steps + 1}))
+        return
     tau = gen.tau_scalar()
     tau_int = gen.limbs_to_ints(tau[None, :])[0]
 
