@@ -189,10 +189,9 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t nb) {
 }
 
 // MAXR = 3: a thread holds 8 points and runs up to three stages per LDS round
-// trip (fewer round trips; 178 VGPRs, two waves per SIMD).  MAXR = 2: 4
-// points and two stages (more round trips, but at most 128 VGPRs, so the two
-// workgroups a compute unit's LDS holds fill four waves per SIMD, which
-// hides the twiddle and LDS latencies better).
+// trip (fewer round trips; 206 VGPRs, two waves per SIMD).  MAXR = 2: 4
+// points and two stages (more round trips, but at most 128 VGPRs, so the
+// workgroups a compute unit's LDS holds fill four waves per SIMD).
 template <int MAXR>
 __device__ __forceinline__ void ntt_pass_body(const NttPass& a) {
   extern __shared__ uint32_t lds[];
@@ -300,9 +299,9 @@ size_t ntt_pass_lds_bytes() { return (size_t)(TILE + TILE / 8 + 1) * 32; }
 
 hipError_t ntt_launch_pass(const NttPass& p, hipStream_t s) {
   const uint32_t blocks = (p.nbatch + p.G - 1) / p.G;
-  // LDS and threads sized to the tile: 2048-point tiles (64 KB) let two
+  // LDS and threads sized to the tile: 2048-point tiles (74 KB) let two
   // workgroups share a CU, so one's loads and stores overlap the other's
-  // butterflies
+  // butterflies; 1024-point tiles, four
   const uint32_t te = (1u << p.m) * p.G;
   const bool r2 = p.unit_log == 2;
   uint32_t threads = te / (r2 ? 4 : 8);
