@@ -301,7 +301,7 @@ hipError_t ntt_launch_pass(const NttPass& p, hipStream_t s) {
   const uint32_t blocks = (p.nbatch + p.G - 1) / p.G;
   // LDS and threads sized to the tile: 2048-point tiles (74 KB) let two
   // workgroups share a CU, so one's loads and stores overlap the other's
-  // butterflies; 1024-point tiles, four
+  // butterflies (1024-point tiles let four share it)
   const uint32_t te = (1u << p.m) * p.G;
   const bool r2 = p.unit_log == 2;
   uint32_t threads = te / (r2 ? 4 : 8);
