@@ -395,7 +395,10 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   // (overlapped) has its own preference: a 4096-point tile's 144 KB of LDS
   // leaves a compute unit no room for the other kernels' workgroups
   const uint32_t pref = overlapped ? sched.ntt_overlap_tile_log : sched.ntt_tile_log;
-  const uint32_t tile = three ? (1u << T) : (1u << std::max(mB, std::min(pref, T)));
+  // above 2^(2T), pass B's factor splits into P1 * P2 transforms of 2^p1 and
+  // 2^p2 points (p2 = ceil(mB / 2)); every pass's transforms must fit the tile
+  const uint32_t need = three ? std::max(mA, (mB + 1) / 2) : mB;
+  const uint32_t tile = 1u << std::max(need, std::min(pref, T));
   zk_status st = scratch_alloc(r.tmp, (size_t)32 << L, s);
   if (st) return st;
   uint32_t* Y = static_cast<uint32_t*>(r.tmp.p);
@@ -440,7 +443,7 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   b.out = out;
   b.m = p2;
   b.nbatch = N2 * P1;
-  b.G = std::min((1u << T) / P2, b.nbatch);
+  b.G = std::min(tile / P2, b.nbatch);
   b.s_in = N2 * P1;
   b.s_out = N2;
   b.b_out = 1;
@@ -454,7 +457,7 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   c3.out = out;
   c3.m = p1;
   c3.nbatch = N2 * P2;
-  c3.G = std::min((1u << T) / P1, c3.nbatch);
+  c3.G = std::min(tile / P1, c3.nbatch);
   c3.s_in = N2 * P2;
   c3.s_out = N2 * P2;
   c3.b_out = 1;

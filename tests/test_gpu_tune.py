@@ -134,28 +134,40 @@ def test_schedule_tuner_runs(zk, srs):
         zk.set_schedule(None)
 
 
-@pytest.mark.parametrize("log_n", [10, 13, 14, 17, 20, 21])
+@pytest.mark.parametrize("log_n", [10, 13, 14, 17, 20, 21, 25])
 def test_transforms_independent_of_tile(zk, log_n):
     # every transform tile (2^10..2^12 points) and stages per LDS round trip
-    # (2 or 3) gives the identical NTT, iNTT and 4x coset evaluations; at
-    # 2^21 and above a 2^10 tile cannot hold the transforms and the planner
-    # takes the smallest tile that does
-    import numpy as np
+    # (2 or 3) gives the identical NTT, iNTT and 4x coset evaluations; where a
+    # tile cannot hold a pass's transforms (2^21 and up for 2^10-point tiles)
+    # the planner takes the smallest tile that does; 2^25 runs three passes
     import torch
-    ev = zk.to_device(gen.uniform_fr(9600 + log_n, 1 << log_n))
+    n = 1 << log_n
+    if log_n <= 21:
+        ev = zk.to_device(gen.uniform_fr(9600 + log_n, n))
+    else:
+        # canonical values made on the device: random words below 2^253 < r
+        g = torch.Generator(device="cuda")
+        g.manual_seed(9600 + log_n)
+        ev = torch.randint(-(1 << 31), (1 << 31) - 1, (n, 8), dtype=torch.int32, device="cuda", generator=g)
+        ev[:, 7] &= 0x1FFFFFFF
     zk.set_schedule(None)
-    refs = [zk.to_host(f(ev)).copy() for f in (zk.ntt, zk.intt, lambda x: zk.coset_ntt(x, 2))]
+    fns = (zk.ntt, zk.intt, lambda x: zk.coset_ntt(x, 2))
+    refs = [f(ev).clone() for f in fns]
     try:
         for tile in (10, 11, 12):
             for unit in (2, 3):
                 zk.set_schedule({"ntt_tile_log": tile, "ntt_unit_log": unit, "ntt_overlap_tile_log": tile})
                 log("transforms 2^%d tile 2^%d unit %d" % (log_n, tile, unit))
-                got = [zk.to_host(f(ev)) for f in (zk.ntt, zk.intt, lambda x: zk.coset_ntt(x, 2))]
-                for g, r in zip(got, refs):
-                    assert np.array_equal(g, r), (log_n, tile, unit)
+                for f, r in zip(fns, refs):
+                    got = f(ev)
+                    assert torch.equal(got, r), (log_n, tile, unit)
+                    del got
         with pytest.raises(zk.ZkError) as ei:
             zk.set_schedule({"ntt_tile_log": 9})
         assert ei.value.code == zk.ZK_EINVAL
     finally:
         zk.set_schedule(None)
         torch.cuda.synchronize()
+        del refs
+        torch.cuda.empty_cache()
+        zk.release_cached_memory()
