@@ -355,6 +355,7 @@ ZK_HD bool w8_is_one(const uint32_t a[8]) {
 // Inversion" (IACR ePrint 2020/972); the loop runs until a = 0, and a
 // Fermat inversion backs it up should the iteration bound ever be reached.
 constexpr int BGCD_STEPS = 30;
+static_assert(BGCD_STEPS <= 30, "a round's matrix entries must fit in 32-bit words");
 
 ZK_HD bool w8_is_zero(const uint32_t a[8]) {
   uint32_t o = 0;
@@ -490,14 +491,16 @@ ZK_HD bool inv_bgcd32(const uint32_t x[8], uint32_t out[8]) {
       xa = (w8_bits_at(a, p) << BGCD_STEPS) | (a[0] & lowmask);
       xb = (w8_bits_at(b, p) << BGCD_STEPS) | (b[0] & lowmask);
     }
-    int64_t f0 = 1, g0 = 0, f1 = 0, g1 = 1;
+    // after k steps |f0| + |g0| <= 2^k and |f1| + |g1| <= 2^k, so the
+    // matrix stays within 32-bit words for the 30 steps of a round
+    int32_t f0 = 1, g0 = 0, f1 = 0, g1 = 1;
 #pragma unroll
     for (int k = 0; k < BGCD_STEPS; k++) {
       const bool odd = (xa & 1u) != 0;
       const bool sw = odd && xa < xb;
       const uint64_t ta = sw ? xb : xa, tb = sw ? xa : xb;
-      const int64_t tf0 = sw ? f1 : f0, tg0 = sw ? g1 : g0;
-      const int64_t tf1 = sw ? f0 : f1, tg1 = sw ? g0 : g1;
+      const int32_t tf0 = sw ? f1 : f0, tg0 = sw ? g1 : g0;
+      const int32_t tf1 = sw ? f0 : f1, tg1 = sw ? g0 : g1;
       xa = (odd ? ta - tb : ta) >> 1;
       xb = tb;
       f0 = odd ? tf0 - tf1 : tf0;
