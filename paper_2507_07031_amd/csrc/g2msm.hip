@@ -249,7 +249,11 @@ __global__ __launch_bounds__(G2_NT) void g2_scatter_kernel(const uint32_t* __res
   }
 }
 
-__global__ __launch_bounds__(G2_NT) void g2_accumulate_kernel(const uint32_t* __restrict__ tab,
+// A mixed G2 addition keeps about 300 registers live; held to 256 (two waves
+// per SIMD, about 280 bytes per lane spilled to scratch) the accumulation
+// runs 5% faster than with one wave per SIMD and no spills, because the
+// second wave hides the first's dependent-chain and load latency.
+__global__ __launch_bounds__(G2_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void g2_accumulate_kernel(const uint32_t* __restrict__ tab,
                                                               const uint32_t* __restrict__ entries,
                                                               const uint32_t* __restrict__ off,
                                                               const uint32_t* __restrict__ tp, uint32_t L,
