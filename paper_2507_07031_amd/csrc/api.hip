@@ -84,6 +84,7 @@ struct DeviceCtx {
   f29* coset5[2] = {nullptr, nullptr};                  // 5^e lo / hi
   f29* coset5inv[2] = {nullptr, nullptr};               // 5^-e lo / hi
   f29* ninv = nullptr;                                  // 2^-L, L = 0..28
+  f29* tw_inv_n = nullptr;                              // inverse lo table times 2^-L, L = 13..28
   uint32_t* gtab = nullptr;                             // 2^j G table for the setup
   uint8_t* noalloc = nullptr;                           // this device's copy of `scratch`
 };
@@ -154,6 +155,10 @@ zk_status ctx_get(DeviceCtx** out) {
     for (int L = 1; L < 29; L++) ninv[L] = reduce_full<FrP>(mont_mul<FrP>(ninv[L - 1], h));
   }
   ZK_HIP(hipMemcpy(c.ninv, ninv, sizeof(ninv), hipMemcpyHostToDevice), "hipMemcpy");
+  // multi-pass inverse transforms fold 2^-L into their first pass's twiddles
+  ZK_HIP(hipMalloc(&c.tw_inv_n, tsz * (28 - ntt_tile_log())), "hipMalloc(scaled twiddles)");
+  ZK_HIP(ntt_scale_tables(c.tw[2], c.ninv + ntt_tile_log() + 1, 28 - ntt_tile_log(), c.tw_inv_n, 0),
+         "scaled twiddle tables");
   ZK_HIP(hipDeviceSynchronize(), "table init");
   c.ready = true;
   *out = &c;
@@ -419,6 +424,12 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   a.pre_lo = pre_lo;
   a.pre_hi = pre_hi;
   a.zero_log = ntt_zero_log(valid_n, N1, mA);
+  // an inverse transform's 2^-L rides on pass A's four-step twiddles (a lo
+  // table scaled by it), so no pass multiplies by it on its own
+  if (inverse) {
+    a.tw_lo = c->tw_inv_n + ((size_t)(L - T - 1) << 14);
+    a.tw_scaled = 1;
+  }
   NttPass& b = r.b;
   b.in = Y;
   b.out = out;
@@ -432,7 +443,6 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   b.tw_lo = lo;
   b.tw_hi = hi;
   b.ladder = ladder;
-  b.post_scale = scale;
   r.passes = 2;
   if (!three) return ZK_OK;
   // pass B of N1 = P1 * P2 points, i1 = j1 + P1 j2: B1 runs the P2-point
@@ -465,7 +475,6 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   c3.tw_lo = lo;
   c3.tw_hi = hi;
   c3.ladder = ladder;
-  c3.post_scale = scale;
   r.passes = 3;
   return ZK_OK;
 }

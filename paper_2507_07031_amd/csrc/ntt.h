@@ -26,6 +26,8 @@ struct NttPass {
   const f29* tw_hi;    // omega^(e 2^14)
   const f29* ladder;   // in-tile twiddles: ladder[2^(k-1) + j] = omega_(2^k)^j
   uint32_t post_tw_L;  // 0: none; else multiply (b, k) by omega_(2^L)^((b >> tw_shift) k)
+  uint32_t tw_scaled;  // tw_lo holds omega^e times a constant c (every (b, k) is then multiplied by c
+                       // times its twiddle, exponent 0 included)
   uint32_t tw_shift;
   uint32_t b_hi_log;   // 0: plain batch stride b_out
   uint32_t b_out_hi;
@@ -49,6 +51,8 @@ size_t ntt_pass_lds_bytes();
 // ladder[2^(k-1) + j] = omega_(2^k)^j (k <= tile log) from a "hi" table; entries: ntt_ladder_entries()
 size_t ntt_ladder_entries();
 hipError_t ntt_make_ladder(const f29* hi, f29* ladder, hipStream_t s);
+// out[l 2^14 + e] = lo[e] * scales[l] (canonical Montgomery form), l < nscales.
+hipError_t ntt_scale_tables(const f29* lo, const f29* scales, uint32_t nscales, f29* out, hipStream_t s);
 uint32_t ntt_tile_log();
 
 }  // namespace zk

@@ -59,11 +59,13 @@ __device__ __forceinline__ f29 ldf29(const f29* t, uint32_t i) { return t[i]; }
 // strides put the lanes of an access on the same banks.
 __device__ __forceinline__ uint32_t* lds_at(uint32_t* lds, uint32_t e) { return lds + (e + (e >> 3)) * 8; }
 
-// omega^(e) of the 2^28-th root for e < 2^28, from the split tables.
-__device__ __forceinline__ f29 pow28(const f29* lo, const f29* hi, uint32_t E) {
+// omega^(e) of the 2^28-th root for e < 2^28, from the split tables (times
+// the constant of a scaled lo table, which then also serves e < 2^14 alone
+// but never lets hi stand alone).
+__device__ __forceinline__ f29 pow28(const f29* lo, const f29* hi, uint32_t E, bool scaled = false) {
   const uint32_t a = E & 0x3fffu, b = E >> 14;
   if (b == 0) return ldf29(lo, a);
-  if (a == 0) return ldf29(hi, b);
+  if (a == 0 && !scaled) return ldf29(hi, b);
   return mont_mul<FrP>(ldf29(lo, a), ldf29(hi, b));
 }
 
@@ -254,7 +256,7 @@ __device__ __forceinline__ void ntt_pass_body(const NttPass& a) {
     const uint32_t bb = g0 + b;
     if (a.post_tw_L) {
       const uint32_t ex = ((bb >> a.tw_shift) * k) & ((1u << a.post_tw_L) - 1);
-      if (ex) mul_tw_2q(w, pow28(a.tw_lo, a.tw_hi, ex << (28 - a.post_tw_L)), w);
+      if (ex || a.tw_scaled) mul_tw_2q(w, pow28(a.tw_lo, a.tw_hi, ex << (28 - a.post_tw_L), a.tw_scaled != 0), w);
     }
     if (a.post_scale) mul_tw_2q(w, *a.post_scale, w);
     canon32<FrP>(w);
@@ -280,6 +282,14 @@ __global__ void ladder_kernel(const f29* __restrict__ hi, f29* __restrict__ ladd
   const uint32_t k = 32 - __clz(idx);  // 2^(k-1) <= idx < 2^k
   const uint32_t j = idx - (1u << (k - 1));
   ladder[idx] = hi[j << (14 - k)];
+}
+
+// out[l 2^14 + e] = lo[e] * scales[l], canonical.
+__global__ void scale_tables_kernel(const f29* __restrict__ lo, const f29* __restrict__ scales, uint32_t nscales,
+                                    f29* __restrict__ out) {
+  const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (nscales << 14)) return;
+  out[idx] = reduce_full<FrP>(mont_mul<FrP>(lo[idx & 0x3fffu], scales[idx >> 14]));
 }
 
 // lo[e] = base^e, hi[e] = base^(e * 2^14) for e < 2^14 (Montgomery form).
@@ -333,6 +343,12 @@ hipError_t ntt_make_pow_tables(Words8 base, f29* lo, f29* hi, hipStream_t s) {
 uint32_t ntt_tile_log() { return TILE_LOG; }
 
 size_t ntt_ladder_entries() { return TILE; }
+
+hipError_t ntt_scale_tables(const f29* lo, const f29* scales, uint32_t nscales, f29* out, hipStream_t s) {
+  if (nscales == 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_tables_kernel, dim3((nscales << 14) / 256), dim3(256), 0, s, lo, scales, nscales, out);
+  return hipGetLastError();
+}
 
 hipError_t ntt_make_ladder(const f29* hi, f29* ladder, hipStream_t s) {
   hipLaunchKernelGGL(ladder_kernel, dim3(TILE / 256), dim3(256), 0, s, hi, ladder);
