@@ -17,6 +17,7 @@
 //   final    sum_b (b + 1) B_b as the sum of the buckets' suffix sums, affine
 // Field and point arithmetic: g2.h.
 #include "g2.h"
+#include "g2_quad.h"
 #include "g2msm.h"
 #include "prof.h"
 
@@ -27,7 +28,7 @@ namespace {
 constexpr uint32_t G2_NT = 256;
 constexpr uint32_t G2_L = 32;               // entries per accumulation thread, at least
 constexpr uint32_t G2_XYZZ_WORDS = 72;      // four Fq2 coordinates, 9 limbs per component
-constexpr uint32_t G2_BUCKET_NT = 128;      // threads of a bucket workgroup
+constexpr uint32_t G2_BUCKET_NT = 512;      // threads of a bucket workgroup (128 quads)
 
 struct Words8x {
   uint32_t w[8];
@@ -284,55 +285,58 @@ __global__ __launch_bounds__(G2_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) v
   st_xyzz(partial + (size_t)t * G2_XYZZ_WORDS, acc);
 }
 
-// One workgroup per bucket: B_b = sum of the bucket's partials.
+// One workgroup per bucket: B_b = sum of the bucket's partials.  Each quad
+// of lanes carries one running sum (g2_quad.h), a chain of quad additions
+// over the partials it owns, then a tree over the quads.
 __global__ __launch_bounds__(G2_BUCKET_NT) void g2_bucket_kernel(const uint32_t* __restrict__ partial,
                                                                  const uint32_t* __restrict__ tp,
                                                                  uint32_t* __restrict__ bsum) {
-  __shared__ uint32_t lds[G2_BUCKET_NT * G2_XYZZ_WORDS];
+  constexpr uint32_t NQ = G2_BUCKET_NT / 4;
+  __shared__ uint32_t lds[NQ * G2_XYZZ_WORDS];
   const uint32_t b = blockIdx.x;
+  const uint32_t q = threadIdx.x >> 2, c = threadIdx.x & 3u;
   const uint32_t first = tp[b], last = tp[b + 1];
-  g2xyzz acc = g2_inf();
-  for (uint32_t t = first + threadIdx.x; t < last; t += G2_BUCKET_NT)
-    acc = g2_add(acc, ld_xyzz(partial + (size_t)t * G2_XYZZ_WORDS));
-  st_xyzz(lds + threadIdx.x * G2_XYZZ_WORDS, acc);
+  fp2 acc = fp2_zero();
+  for (uint32_t t = first + q; t < last; t += NQ) acc = g2q_add(acc, ldq2(partial + (size_t)t * G2_XYZZ_WORDS, c));
+  stq2(lds + q * G2_XYZZ_WORDS, c, acc);
   __syncthreads();
-  for (uint32_t h = G2_BUCKET_NT / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) {
-      const g2xyzz o = ld_xyzz(lds + (threadIdx.x + h) * G2_XYZZ_WORDS);
-      acc = g2_add(acc, o);
-      st_xyzz(lds + threadIdx.x * G2_XYZZ_WORDS, acc);
+  for (uint32_t h = NQ / 2; h > 0; h >>= 1) {
+    if (q < h) {
+      acc = g2q_add(acc, ldq2(lds + (q + h) * G2_XYZZ_WORDS, c));
+      stq2(lds + q * G2_XYZZ_WORDS, c, acc);
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) st_xyzz(bsum + (size_t)b * G2_XYZZ_WORDS, acc);
+  if (q == 0) stq2(bsum + (size_t)b * G2_XYZZ_WORDS, c, acc);
 }
 
-// sum_b (b + 1) B_b = sum_b S_b with S_b = sum_(b' >= b) B_b': one thread per
+// sum_b (b + 1) B_b = sum_b S_b with S_b = sum_(b' >= b) B_b': one quad per
 // bucket, an inclusive suffix scan (7 Hillis-Steele levels, two LDS buffers)
-// and a tree sum (7 levels), then the affine result.
-__global__ __launch_bounds__(G2_K) void g2_final_kernel(const uint32_t* __restrict__ bsum, uint32_t* __restrict__ out) {
+// and a tree sum (7 levels) of quad additions, then the affine result.
+__global__ __launch_bounds__(4 * G2_K) void g2_final_kernel(const uint32_t* __restrict__ bsum, uint32_t* __restrict__ out) {
   __shared__ uint32_t buf[2][G2_K * G2_XYZZ_WORDS];
-  const uint32_t b = threadIdx.x;
-  g2xyzz v = ld_xyzz(bsum + (size_t)b * G2_XYZZ_WORDS);
-  st_xyzz(buf[0] + b * G2_XYZZ_WORDS, v);
+  const uint32_t b = threadIdx.x >> 2, c = threadIdx.x & 3u;
+  fp2 v = ldq2(bsum + (size_t)b * G2_XYZZ_WORDS, c);
+  stq2(buf[0] + b * G2_XYZZ_WORDS, c, v);
   __syncthreads();
   uint32_t cur = 0;
   for (uint32_t d = 1; d < G2_K; d <<= 1) {
-    if (b + d < G2_K) v = g2_add(v, ld_xyzz(buf[cur] + (b + d) * G2_XYZZ_WORDS));
-    st_xyzz(buf[cur ^ 1] + b * G2_XYZZ_WORDS, v);
+    if (b + d < G2_K) v = g2q_add(v, ldq2(buf[cur] + (b + d) * G2_XYZZ_WORDS, c));
+    stq2(buf[cur ^ 1] + b * G2_XYZZ_WORDS, c, v);
     cur ^= 1;
     __syncthreads();
   }
   for (uint32_t h = G2_K / 2; h > 0; h >>= 1) {
     if (b < h) {
-      v = g2_add(v, ld_xyzz(buf[cur] + (b + h) * G2_XYZZ_WORDS));
-      st_xyzz(buf[cur] + b * G2_XYZZ_WORDS, v);
+      v = g2q_add(v, ldq2(buf[cur] + (b + h) * G2_XYZZ_WORDS, c));
+      stq2(buf[cur] + b * G2_XYZZ_WORDS, c, v);
     }
     __syncthreads();
   }
-  if (b == 0) {
+  const g2xyzz r = g2q_gather(v);
+  if (threadIdx.x == 0) {
     uint32_t o[32];
-    g2_to_words(v, o);
+    g2_to_words(r, o);
     stw(out, o, 8);
   }
 }
@@ -404,7 +408,7 @@ hipError_t g2_msm(const uint32_t* tab, uint64_t n_tab, const uint32_t* scalars, 
                      partial);
   prof_end(acc, s);
   hipLaunchKernelGGL(g2_bucket_kernel, dim3(G2_K), dim3(G2_BUCKET_NT), 0, s, partial, tp, bsum);
-  hipLaunchKernelGGL(g2_final_kernel, dim3(1), dim3(G2_K), 0, s, bsum, out);
+  hipLaunchKernelGGL(g2_final_kernel, dim3(1), dim3(4 * G2_K), 0, s, bsum, out);
   prof_end(tok, s);
   return hipGetLastError();
 }
