@@ -310,26 +310,56 @@ __global__ __launch_bounds__(G2_BUCKET_NT) void g2_bucket_kernel(const uint32_t*
   if (q == 0) stq2(bsum + (size_t)b * G2_XYZZ_WORDS, c, acc);
 }
 
-// sum_b (b + 1) B_b = sum_b S_b with S_b = sum_(b' >= b) B_b': one quad per
-// bucket, an inclusive suffix scan (7 Hillis-Steele levels, two LDS buffers)
-// and a tree sum (7 levels) of quad additions, then the affine result.
-__global__ __launch_bounds__(4 * G2_K) void g2_final_kernel(const uint32_t* __restrict__ bsum, uint32_t* __restrict__ out) {
-  __shared__ uint32_t buf[2][G2_K * G2_XYZZ_WORDS];
-  const uint32_t b = threadIdx.x >> 2, c = threadIdx.x & 3u;
-  fp2 v = ldq2(bsum + (size_t)b * G2_XYZZ_WORDS, c);
-  stq2(buf[0] + b * G2_XYZZ_WORDS, c, v);
-  __syncthreads();
-  uint32_t cur = 0;
-  for (uint32_t d = 1; d < G2_K; d <<= 1) {
-    if (b + d < G2_K) v = g2q_add(v, ldq2(buf[cur] + (b + d) * G2_XYZZ_WORDS, c));
-    stq2(buf[cur ^ 1] + b * G2_XYZZ_WORDS, c, v);
-    cur ^= 1;
+// sum_b (b + 1) B_b = sum_j 2^j T_j, where T_j is the sum of the B_b whose
+// b + 1 has bit j set (j < 8; T_7 = B_127).  One workgroup per j, on its own
+// compute unit: T_j as an LDS tree of quad additions over its 64 buckets
+// (g2_quad.h), then j quad doublings.  The eight workgroups run side by side,
+// so the dependent chain is 6 additions and at most 7 doublings instead of
+// a 128-bucket suffix scan and tree on one compute unit.
+constexpr uint32_t G2_BITS = 8;   // bits of b + 1 <= G2_K
+static_assert((1u << (G2_BITS - 1)) == G2_K, "b + 1 <= G2_K needs G2_BITS bits");
+
+__global__ __launch_bounds__(2 * G2_K) void g2_bitsum_kernel(const uint32_t* __restrict__ bsum,
+                                                               uint32_t* __restrict__ tsum) {
+  constexpr uint32_t NQ = G2_K / 2;  // buckets with bit j of b + 1 set, j < 7
+  __shared__ uint32_t lds[NQ * G2_XYZZ_WORDS];
+  const uint32_t j = blockIdx.x, q = threadIdx.x >> 2, c = threadIdx.x & 3u;
+  fp2 v;
+  if (j + 1 < G2_BITS) {
+    // the q-th value in [1, 128) with bit j set: q with a one inserted at bit j
+    const uint32_t val = ((q >> j) << (j + 1)) | (1u << j) | (q & ((1u << j) - 1));
+    v = ldq2(bsum + (size_t)(val - 1) * G2_XYZZ_WORDS, c);
+    stq2(lds + q * G2_XYZZ_WORDS, c, v);
     __syncthreads();
+    for (uint32_t h = NQ / 2; h > 0; h >>= 1) {
+      if (q < h) {
+        v = g2q_add(v, ldq2(lds + (q + h) * G2_XYZZ_WORDS, c));
+        stq2(lds + q * G2_XYZZ_WORDS, c, v);
+      }
+      __syncthreads();
+    }
+  } else {
+    v = ldq2(bsum + (size_t)(G2_K - 1) * G2_XYZZ_WORDS, c);
   }
-  for (uint32_t h = G2_K / 2; h > 0; h >>= 1) {
-    if (b < h) {
-      v = g2q_add(v, ldq2(buf[cur] + (b + h) * G2_XYZZ_WORDS, c));
-      stq2(buf[cur] + b * G2_XYZZ_WORDS, c, v);
+  if (q == 0) {
+    for (uint32_t i = 0; i < j; i++) v = g2q_dbl(v);
+    stq2(tsum + (size_t)j * G2_XYZZ_WORDS, c, v);
+  }
+}
+
+// The eight 2^j T_j summed (one quad each, an LDS tree of three levels) and
+// the result made affine.
+__global__ __launch_bounds__(4 * G2_BITS) void g2_final_kernel(const uint32_t* __restrict__ tsum,
+                                                               uint32_t* __restrict__ out) {
+  __shared__ uint32_t lds[G2_BITS * G2_XYZZ_WORDS];
+  const uint32_t q = threadIdx.x >> 2, c = threadIdx.x & 3u;
+  fp2 v = ldq2(tsum + (size_t)q * G2_XYZZ_WORDS, c);
+  stq2(lds + q * G2_XYZZ_WORDS, c, v);
+  __syncthreads();
+  for (uint32_t h = G2_BITS / 2; h > 0; h >>= 1) {
+    if (q < h) {
+      v = g2q_add(v, ldq2(lds + (q + h) * G2_XYZZ_WORDS, c));
+      stq2(lds + q * G2_XYZZ_WORDS, c, v);
     }
     __syncthreads();
   }
@@ -374,7 +404,8 @@ size_t g2_msm_scratch_bytes(uint64_t n) {
   const uint64_t ent = (uint64_t)G2_W * n;
   const uint64_t thr = ent / g2_entries_per_thread(ent) + G2_K + 1;
   return align256(nblk * G2_K * 4) + 3 * align256((G2_K + 1) * 4) + align256(ent * 4) +
-         align256(thr * G2_XYZZ_WORDS * 4) + align256((size_t)G2_K * G2_XYZZ_WORDS * 4);
+         align256(thr * G2_XYZZ_WORDS * 4) + align256((size_t)G2_K * G2_XYZZ_WORDS * 4) +
+         align256((size_t)G2_BITS * G2_XYZZ_WORDS * 4);
 }
 
 hipError_t g2_msm(const uint32_t* tab, uint64_t n_tab, const uint32_t* scalars, uint64_t n, uint32_t* out,
@@ -397,6 +428,8 @@ hipError_t g2_msm(const uint32_t* tab, uint64_t n_tab, const uint32_t* scalars, 
   uint32_t* partial = reinterpret_cast<uint32_t*>(p);
   p += align256(thr * G2_XYZZ_WORDS * 4);
   uint32_t* bsum = reinterpret_cast<uint32_t*>(p);
+  p += align256((size_t)G2_K * G2_XYZZ_WORDS * 4);
+  uint32_t* tsum = reinterpret_cast<uint32_t*>(p);
 
   const ProfToken tok = prof_begin("g2.msm", s);
   hipLaunchKernelGGL(g2_count_kernel, dim3(nblk), dim3(G2_NT), 0, s, scalars, n, blockhist);
@@ -408,7 +441,8 @@ hipError_t g2_msm(const uint32_t* tab, uint64_t n_tab, const uint32_t* scalars, 
                      partial);
   prof_end(acc, s);
   hipLaunchKernelGGL(g2_bucket_kernel, dim3(G2_K), dim3(G2_BUCKET_NT), 0, s, partial, tp, bsum);
-  hipLaunchKernelGGL(g2_final_kernel, dim3(1), dim3(4 * G2_K), 0, s, bsum, out);
+  hipLaunchKernelGGL(g2_bitsum_kernel, dim3(G2_BITS), dim3(2 * G2_K), 0, s, bsum, tsum);
+  hipLaunchKernelGGL(g2_final_kernel, dim3(1), dim3(4 * G2_BITS), 0, s, tsum, out);
   prof_end(tok, s);
   return hipGetLastError();
 }
