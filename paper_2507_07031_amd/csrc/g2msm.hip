@@ -285,19 +285,24 @@ __global__ __launch_bounds__(G2_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) v
   st_xyzz(partial + (size_t)t * G2_XYZZ_WORDS, acc);
 }
 
-// One workgroup per bucket: B_b = sum of the bucket's partials.  Each quad
-// of lanes carries one running sum (g2_quad.h), a chain of quad additions
-// over the partials it owns, then a tree over the quads.
+// G2_SPLIT workgroups per bucket (so that the 128 buckets fill the compute
+// units): workgroup (b, h) sums every G2_SPLIT-th block of the bucket's
+// partials into bsum[G2_SPLIT b + h]; B_b is the sum of those.  Each quad of
+// lanes carries one running sum (g2_quad.h), a chain of quad additions over
+// the partials it owns, then a tree over the quads.
+constexpr uint32_t G2_SPLIT = 2;
+
 __global__ __launch_bounds__(G2_BUCKET_NT) void g2_bucket_kernel(const uint32_t* __restrict__ partial,
                                                                  const uint32_t* __restrict__ tp,
                                                                  uint32_t* __restrict__ bsum) {
   constexpr uint32_t NQ = G2_BUCKET_NT / 4;
   __shared__ uint32_t lds[NQ * G2_XYZZ_WORDS];
-  const uint32_t b = blockIdx.x;
+  const uint32_t b = blockIdx.x / G2_SPLIT, h0 = blockIdx.x % G2_SPLIT;
   const uint32_t q = threadIdx.x >> 2, c = threadIdx.x & 3u;
   const uint32_t first = tp[b], last = tp[b + 1];
   fp2 acc = fp2_zero();
-  for (uint32_t t = first + q; t < last; t += NQ) acc = g2q_add(acc, ldq2(partial + (size_t)t * G2_XYZZ_WORDS, c));
+  for (uint32_t t = first + h0 * NQ + q; t < last; t += G2_SPLIT * NQ)
+    acc = g2q_add(acc, ldq2(partial + (size_t)t * G2_XYZZ_WORDS, c));
   stq2(lds + q * G2_XYZZ_WORDS, c, acc);
   __syncthreads();
   for (uint32_t h = NQ / 2; h > 0; h >>= 1) {
@@ -307,7 +312,14 @@ __global__ __launch_bounds__(G2_BUCKET_NT) void g2_bucket_kernel(const uint32_t*
     }
     __syncthreads();
   }
-  if (q == 0) stq2(bsum + (size_t)b * G2_XYZZ_WORDS, c, acc);
+  if (q == 0) stq2(bsum + (size_t)blockIdx.x * G2_XYZZ_WORDS, c, acc);
+}
+
+// B_b from its G2_SPLIT workgroup sums.
+__device__ __forceinline__ fp2 g2_bucket_sum(const uint32_t* bsum, uint32_t b, uint32_t c) {
+  fp2 v = ldq2(bsum + (size_t)G2_SPLIT * b * G2_XYZZ_WORDS, c);
+  for (uint32_t h = 1; h < G2_SPLIT; h++) v = g2q_add(v, ldq2(bsum + (size_t)(G2_SPLIT * b + h) * G2_XYZZ_WORDS, c));
+  return v;
 }
 
 // sum_b (b + 1) B_b = sum_j 2^j T_j, where T_j is the sum of the B_b whose
@@ -328,7 +340,7 @@ __global__ __launch_bounds__(2 * G2_K) void g2_bitsum_kernel(const uint32_t* __r
   if (j + 1 < G2_BITS) {
     // the q-th value in [1, 128) with bit j set: q with a one inserted at bit j
     const uint32_t val = ((q >> j) << (j + 1)) | (1u << j) | (q & ((1u << j) - 1));
-    v = ldq2(bsum + (size_t)(val - 1) * G2_XYZZ_WORDS, c);
+    v = g2_bucket_sum(bsum, val - 1, c);
     stq2(lds + q * G2_XYZZ_WORDS, c, v);
     __syncthreads();
     for (uint32_t h = NQ / 2; h > 0; h >>= 1) {
@@ -339,7 +351,7 @@ __global__ __launch_bounds__(2 * G2_K) void g2_bitsum_kernel(const uint32_t* __r
       __syncthreads();
     }
   } else {
-    v = ldq2(bsum + (size_t)(G2_K - 1) * G2_XYZZ_WORDS, c);
+    v = g2_bucket_sum(bsum, G2_K - 1, c);
   }
   if (q == 0) {
     for (uint32_t i = 0; i < j; i++) v = g2q_dbl(v);
@@ -392,7 +404,7 @@ hipError_t g2_build_table(const uint32_t* points, uint32_t* tab, uint64_t n, hip
 
 // Entries per accumulation thread: at least G2_L, more once the threads
 // exceed about 2^17 (enough waves), which keeps the partial sums per bucket
-// (summed by one workgroup each) few.
+// (summed by G2_SPLIT workgroups each) few.
 uint32_t g2_entries_per_thread(uint64_t ent) {
   uint64_t L = ent >> 17;
   if (L < G2_L) L = G2_L;
@@ -404,7 +416,7 @@ size_t g2_msm_scratch_bytes(uint64_t n) {
   const uint64_t ent = (uint64_t)G2_W * n;
   const uint64_t thr = ent / g2_entries_per_thread(ent) + G2_K + 1;
   return align256(nblk * G2_K * 4) + 3 * align256((G2_K + 1) * 4) + align256(ent * 4) +
-         align256(thr * G2_XYZZ_WORDS * 4) + align256((size_t)G2_K * G2_XYZZ_WORDS * 4) +
+         align256(thr * G2_XYZZ_WORDS * 4) + align256((size_t)G2_SPLIT * G2_K * G2_XYZZ_WORDS * 4) +
          align256((size_t)G2_BITS * G2_XYZZ_WORDS * 4);
 }
 
@@ -428,7 +440,7 @@ hipError_t g2_msm(const uint32_t* tab, uint64_t n_tab, const uint32_t* scalars, 
   uint32_t* partial = reinterpret_cast<uint32_t*>(p);
   p += align256(thr * G2_XYZZ_WORDS * 4);
   uint32_t* bsum = reinterpret_cast<uint32_t*>(p);
-  p += align256((size_t)G2_K * G2_XYZZ_WORDS * 4);
+  p += align256((size_t)G2_SPLIT * G2_K * G2_XYZZ_WORDS * 4);
   uint32_t* tsum = reinterpret_cast<uint32_t*>(p);
 
   const ProfToken tok = prof_begin("g2.msm", s);
@@ -440,7 +452,7 @@ hipError_t g2_msm(const uint32_t* tab, uint64_t n_tab, const uint32_t* scalars, 
   hipLaunchKernelGGL(g2_accumulate_kernel, dim3(cdiv(thr, G2_NT)), dim3(G2_NT), 0, s, tab, entries, off, tp, L,
                      partial);
   prof_end(acc, s);
-  hipLaunchKernelGGL(g2_bucket_kernel, dim3(G2_K), dim3(G2_BUCKET_NT), 0, s, partial, tp, bsum);
+  hipLaunchKernelGGL(g2_bucket_kernel, dim3(G2_SPLIT * G2_K), dim3(G2_BUCKET_NT), 0, s, partial, tp, bsum);
   hipLaunchKernelGGL(g2_bitsum_kernel, dim3(G2_BITS), dim3(2 * G2_K), 0, s, bsum, tsum);
   hipLaunchKernelGGL(g2_final_kernel, dim3(1), dim3(4 * G2_BITS), 0, s, tsum, out);
   prof_end(tok, s);
