@@ -77,6 +77,12 @@ __global__ void noalloc_zero_kernel(uint32_t* w) {
   if (threadIdx.x == 0) w[0] = 0;
 }
 
+// Two-pass transforms of 2^13 .. 2^FULL_TW_MAX_LOG points read their first
+// pass's four-step twiddles from per-size tables (36 B per point and
+// direction: 0.6 GB per device in all) rather than forming each one by a
+// Montgomery product of two split-table entries.
+constexpr uint32_t FULL_TW_MAX_LOG = 22;
+
 struct DeviceCtx {
   bool ready = false;
   f29* tw[4] = {nullptr, nullptr, nullptr, nullptr};   // fwd lo, fwd hi, inv lo, inv hi
@@ -85,6 +91,7 @@ struct DeviceCtx {
   f29* coset5inv[2] = {nullptr, nullptr};               // 5^-e lo / hi
   f29* ninv = nullptr;                                  // 2^-L, L = 0..28
   f29* tw_inv_n = nullptr;                              // inverse lo table times 2^-L, L = 13..28
+  uint32_t* tw_full[2][FULL_TW_MAX_LOG + 1] = {};       // first-pass twiddles of two-pass transforms, fwd / inv
   uint32_t* gtab = nullptr;                             // 2^j G table for the setup
   uint8_t* noalloc = nullptr;                           // this device's copy of `scratch`
 };
@@ -159,6 +166,16 @@ zk_status ctx_get(DeviceCtx** out) {
   ZK_HIP(hipMalloc(&c.tw_inv_n, tsz * (28 - ntt_tile_log())), "hipMalloc(scaled twiddles)");
   ZK_HIP(ntt_scale_tables(c.tw[2], c.ninv + ntt_tile_log() + 1, 28 - ntt_tile_log(), c.tw_inv_n, 0),
          "scaled twiddle tables");
+  // first-pass twiddles of the two-pass sizes (pass A runs 2^(L/2)-point
+  // transforms); the inverse ones carry 2^-L like tw_inv_n
+  for (uint32_t L = ntt_tile_log() + 1; L <= FULL_TW_MAX_LOG; L++) {
+    for (int d = 0; d < 2; d++) {
+      ZK_HIP(hipMalloc(&c.tw_full[d][L], (size_t)36 << L), "hipMalloc(first-pass twiddles)");
+      const f29* lo = d ? c.tw_inv_n + ((size_t)(L - ntt_tile_log() - 1) << 14) : c.tw[0];
+      ZK_HIP(ntt_full_twiddles(lo, d ? c.tw[3] : c.tw[1], (uint32_t)d, L, L / 2, c.tw_full[d][L], 0),
+             "first-pass twiddles");
+    }
+  }
   ZK_HIP(hipDeviceSynchronize(), "table init");
   c.ready = true;
   *out = &c;
@@ -430,6 +447,8 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
     a.tw_lo = c->tw_inv_n + ((size_t)(L - T - 1) << 14);
     a.tw_scaled = 1;
   }
+  // tables built for pass A of the two-pass form (mA = L / 2)
+  a.tw_full = (!three && L <= FULL_TW_MAX_LOG) ? c->tw_full[inverse ? 1 : 0][L] : nullptr;
   NttPass& b = r.b;
   b.in = Y;
   b.out = out;

@@ -37,6 +37,9 @@ struct NttPass {
   uint32_t unit_log;   // stages per LDS round trip at most: 3 (8 points a thread) or 2 (4 points)
   uint32_t zero_log;   // points i >= 2^(m - zero_log) of every transform are zero padding (input index
                        // >= valid_n): the first zero_log stages only copy, and are not run
+  const uint32_t* tw_full;  // nullptr, or the post twiddles (scale included) of every output position
+                            // b*b_out + k (s_out = 1, tw_shift = 0, b_hi_log = 0), as nine limb planes
+                            // of 2^post_tw_L words (ntt_full_twiddles); replaces tw_lo / tw_hi
 };
 
 hipError_t ntt_pass_setup();
@@ -54,5 +57,11 @@ hipError_t ntt_make_ladder(const f29* hi, f29* ladder, hipStream_t s);
 // out[l 2^14 + e] = lo[e] * scales[l] (canonical Montgomery form), l < nscales.
 hipError_t ntt_scale_tables(const f29* lo, const f29* scales, uint32_t nscales, f29* out, hipStream_t s);
 uint32_t ntt_tile_log();
+// The post twiddles of the first pass of a two-pass transform of 2^L points
+// whose first pass runs 2^mA-point transforms: entry i1 2^mA + k2 (limb l at
+// out[l 2^L + i1 2^mA + k2]) is omega_(2^L)^(i1 k2) from the split tables lo /
+// hi (times the constant of a scaled lo table).  out holds 9 * 2^L words; L <= 28.
+hipError_t ntt_full_twiddles(const f29* lo, const f29* hi, uint32_t scaled, uint32_t L, uint32_t mA, uint32_t* out,
+                             hipStream_t s);
 
 }  // namespace zk

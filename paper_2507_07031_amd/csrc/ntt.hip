@@ -254,14 +254,21 @@ __device__ __forceinline__ void ntt_pass_body(const NttPass& a) {
     uint32_t w[8];
     ld8(lds_at(lds, b * M + k), w);
     const uint32_t bb = g0 + b;
-    if (a.post_tw_L) {
+    const size_t ob = a.b_hi_log ? (size_t)(bb & ((1u << a.b_hi_log) - 1)) * a.b_out + (size_t)(bb >> a.b_hi_log) * a.b_out_hi
+                                 : (size_t)bb * a.b_out;
+    if (a.tw_full) {
+      // the twiddle of output position ob + k, read from its table (adjacent
+      // lanes, adjacent words) instead of formed by a product of two entries
+      f29 t;
+#pragma unroll
+      for (int l = 0; l < 9; l++) t.l[l] = a.tw_full[((size_t)l << a.post_tw_L) + ob + k];
+      mul_tw_2q(w, t, w);
+    } else if (a.post_tw_L) {
       const uint32_t ex = ((bb >> a.tw_shift) * k) & ((1u << a.post_tw_L) - 1);
       if (ex || a.tw_scaled) mul_tw_2q(w, pow28(a.tw_lo, a.tw_hi, ex << (28 - a.post_tw_L), a.tw_scaled != 0), w);
     }
     if (a.post_scale) mul_tw_2q(w, *a.post_scale, w);
     canon32<FrP>(w);
-    const size_t ob = a.b_hi_log ? (size_t)(bb & ((1u << a.b_hi_log) - 1)) * a.b_out + (size_t)(bb >> a.b_hi_log) * a.b_out_hi
-                                 : (size_t)bb * a.b_out;
     st8(a.out + (ob + (size_t)k * a.s_out) * 8, w);
   }
 }
@@ -290,6 +297,18 @@ __global__ void scale_tables_kernel(const f29* __restrict__ lo, const f29* __res
   const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (nscales << 14)) return;
   out[idx] = reduce_full<FrP>(mont_mul<FrP>(lo[idx & 0x3fffu], scales[idx >> 14]));
+}
+
+// Entry i = i1 2^mA + k2 of a first pass's post twiddles: omega_(2^L)^(i1 k2),
+// limb l at out[l 2^L + i].
+__global__ void full_tw_kernel(const f29* __restrict__ lo, const f29* __restrict__ hi, uint32_t scaled, uint32_t L,
+                               uint32_t mA, uint32_t* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (1u << L)) return;
+  const uint32_t ex = ((i >> mA) * (i & ((1u << mA) - 1))) & ((1u << L) - 1);
+  const f29 w = pow28(lo, hi, ex << (28 - L), scaled != 0);
+#pragma unroll
+  for (int l = 0; l < 9; l++) out[((size_t)l << L) + i] = w.l[l];
 }
 
 // lo[e] = base^e, hi[e] = base^(e * 2^14) for e < 2^14 (Montgomery form).
@@ -341,6 +360,14 @@ hipError_t ntt_make_pow_tables(Words8 base, f29* lo, f29* hi, hipStream_t s) {
 }
 
 uint32_t ntt_tile_log() { return TILE_LOG; }
+
+hipError_t ntt_full_twiddles(const f29* lo, const f29* hi, uint32_t scaled, uint32_t L, uint32_t mA, uint32_t* out,
+                             hipStream_t s) {
+  if (L == 0 || L > 28 || mA > L) return hipErrorInvalidValue;
+  const uint32_t n = 1u << L;
+  hipLaunchKernelGGL(full_tw_kernel, dim3((n + 255) / 256), dim3(256), 0, s, lo, hi, scaled, L, mA, out);
+  return hipGetLastError();
+}
 
 size_t ntt_ladder_entries() { return TILE; }
 
