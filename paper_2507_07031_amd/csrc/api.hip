@@ -80,8 +80,17 @@ __global__ void noalloc_zero_kernel(uint32_t* w) {
 // Two-pass transforms of 2^13 .. 2^FULL_TW_MAX_LOG points read their first
 // pass's four-step twiddles from per-size tables (36 B per point and
 // direction: 0.6 GB per device in all) rather than forming each one by a
-// Montgomery product of two split-table entries.
+// Montgomery product of two split-table entries; three-pass transforms do
+// the same in their second pass (B1), whose twiddles range over only 2^mB
+// entries (2^16 .. 2^18: 52 MB for both directions and the four sizes).
 constexpr uint32_t FULL_TW_MAX_LOG = 22;
+constexpr uint32_t NTT_MAX_LOG = 28;
+static_assert(NTT_MAX_LOG == ZK_MAX_LOG_NTT, "pass B1 tables cover every three-pass size");
+
+// pass shapes of the three-pass form (the factors of ntt_prepare)
+inline uint32_t three_pass_mA(uint32_t L) { return (L + 2) / 3; }
+inline uint32_t three_pass_mB(uint32_t L) { return L - three_pass_mA(L); }
+inline uint32_t three_pass_p2(uint32_t L) { return (three_pass_mB(L) + 1) / 2; }
 
 struct DeviceCtx {
   bool ready = false;
@@ -92,6 +101,7 @@ struct DeviceCtx {
   f29* ninv = nullptr;                                  // 2^-L, L = 0..28
   f29* tw_inv_n = nullptr;                              // inverse lo table times 2^-L, L = 13..28
   uint32_t* tw_full[2][FULL_TW_MAX_LOG + 1] = {};       // first-pass twiddles of two-pass transforms, fwd / inv
+  uint32_t* tw_b1[2][NTT_MAX_LOG + 1] = {};              // pass B1 twiddles of three-pass transforms, fwd / inv
   uint32_t* gtab = nullptr;                             // 2^j G table for the setup
   uint8_t* noalloc = nullptr;                           // this device's copy of `scratch`
 };
@@ -174,6 +184,14 @@ zk_status ctx_get(DeviceCtx** out) {
       const f29* lo = d ? c.tw_inv_n + ((size_t)(L - ntt_tile_log() - 1) << 14) : c.tw[0];
       ZK_HIP(ntt_full_twiddles(lo, d ? c.tw[3] : c.tw[1], (uint32_t)d, L, L / 2, c.tw_full[d][L], 0),
              "first-pass twiddles");
+    }
+  }
+  for (uint32_t L = 2 * ntt_tile_log() + 1; L <= NTT_MAX_LOG; L++) {
+    const uint32_t mB = three_pass_mB(L);
+    for (int d = 0; d < 2; d++) {
+      ZK_HIP(hipMalloc(&c.tw_b1[d][L], (size_t)36 << mB), "hipMalloc(pass B1 twiddles)");
+      ZK_HIP(ntt_full_twiddles(c.tw[2 * d], c.tw[2 * d + 1], 0, mB, three_pass_p2(L), c.tw_b1[d][L], 0),
+             "pass B1 twiddles");
     }
   }
   ZK_HIP(hipDeviceSynchronize(), "table init");
@@ -409,7 +427,7 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   // pass A transforms have 2^mA points; above 2^(2T) the three factors are
   // near-equal (mA >= mB1 >= mB2), so pass A's workgroups hold several
   // transforms and its strided reads move more than one element at a time
-  const uint32_t mA = three ? (L + 2) / 3 : L / 2, mB = L - mA;
+  const uint32_t mA = three ? three_pass_mA(L) : L / 2, mB = L - mA;
   const uint32_t N1 = 1u << mB, N2 = 1u << mA;
   // the schedule's preferred tile (2^10, 2^11 or 2^12 points: four, two or
   // one workgroups per CU) where both passes' transforms fit it, else the
@@ -467,7 +485,7 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   // pass B of N1 = P1 * P2 points, i1 = j1 + P1 j2: B1 runs the P2-point
   // transforms over j2 (batch k2 + N2 j1), B2 the P1-point ones over j1
   // (batch k2 + N2 k1'); see the pass equations at the top of ntt.hip
-  const uint32_t p2 = (mB + 1) / 2, p1 = mB - p2;
+  const uint32_t p2 = three_pass_p2(L), p1 = mB - p2;
   const uint32_t P1 = 1u << p1, P2 = 1u << p2;
   b.out = out;
   b.m = p2;
@@ -481,6 +499,7 @@ zk_status ntt_prepare(DeviceCtx* c, const uint32_t* in, uint32_t* out, uint32_t 
   b.post_tw_L = mB;
   b.tw_shift = mA;
   b.post_scale = nullptr;
+  b.tw_full = L <= NTT_MAX_LOG ? c->tw_b1[inverse ? 1 : 0][L] : nullptr;
   NttPass& c3 = r.c;
   c3.in = out;
   c3.out = out;

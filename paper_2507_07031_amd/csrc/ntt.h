@@ -37,9 +37,9 @@ struct NttPass {
   uint32_t unit_log;   // stages per LDS round trip at most: 3 (8 points a thread) or 2 (4 points)
   uint32_t zero_log;   // points i >= 2^(m - zero_log) of every transform are zero padding (input index
                        // >= valid_n): the first zero_log stages only copy, and are not run
-  const uint32_t* tw_full;  // nullptr, or the post twiddles (scale included) of every output position
-                            // b*b_out + k (s_out = 1, tw_shift = 0, b_hi_log = 0), as nine limb planes
-                            // of 2^post_tw_L words (ntt_full_twiddles); replaces tw_lo / tw_hi
+  const uint32_t* tw_full;  // nullptr, or the post twiddle (scale included) of every (b, k) at entry
+                            // ((b >> tw_shift) << m) + k, as nine limb planes of 2^post_tw_L words
+                            // (ntt_full_twiddles with mA = m); replaces tw_lo / tw_hi
 };
 
 hipError_t ntt_pass_setup();

@@ -257,11 +257,12 @@ __device__ __forceinline__ void ntt_pass_body(const NttPass& a) {
     const size_t ob = a.b_hi_log ? (size_t)(bb & ((1u << a.b_hi_log) - 1)) * a.b_out + (size_t)(bb >> a.b_hi_log) * a.b_out_hi
                                  : (size_t)bb * a.b_out;
     if (a.tw_full) {
-      // the twiddle of output position ob + k, read from its table (adjacent
-      // lanes, adjacent words) instead of formed by a product of two entries
+      // the twiddle of (b, k) read from its table (adjacent lanes, adjacent
+      // words) instead of formed by a product of two split-table entries
+      const size_t ti = ((size_t)(bb >> a.tw_shift) << a.m) + k;
       f29 t;
 #pragma unroll
-      for (int l = 0; l < 9; l++) t.l[l] = a.tw_full[((size_t)l << a.post_tw_L) + ob + k];
+      for (int l = 0; l < 9; l++) t.l[l] = a.tw_full[((size_t)l << a.post_tw_L) + ti];
       mul_tw_2q(w, t, w);
     } else if (a.post_tw_L) {
       const uint32_t ex = ((bb >> a.tw_shift) * k) & ((1u << a.post_tw_L) - 1);
