@@ -13,9 +13,12 @@
 //            workgroup's reserved positions
 //   accumulate  each thread adds up to L consecutive entries of one
 //            bucket (mixed additions of table points), one partial each
-//   buckets  one workgroup per bucket: its partials summed (LDS tree)
-//   final    sum_b (b + 1) B_b as the sum of the buckets' suffix sums, affine
-// Field and point arithmetic: g2.h.
+//   buckets  two workgroups per bucket: its partials summed (LDS tree)
+//   bitsum   sum_b (b + 1) B_b split by the bits of b + 1: one workgroup per
+//            bit j sums the buckets with bit j set and doubles the sum j times
+//   final    the eight bit sums added, affine
+// Field and point arithmetic: g2.h; the bucket, bit and final sums run their
+// additions on quads of lanes (g2_quad.h).
 #include "g2.h"
 #include "g2_quad.h"
 #include "g2msm.h"
