@@ -1,8 +1,9 @@
 """GPU parity of the G2 SRS setup and MSM (zk_srs_g2_setup, zk_msm_g2_srs)
 against the oracle, bit-exact: SRS points, tiny MSMs against the oracle's
 naive sum (edge scalars 0, 1, r - 1, 128 and 2^253 multiples whose digits
-carry), and MSMs of several sizes and scalar distributions against the
-closed form [sum_i s_i tau^i]_2, including points at infinity.
+carry), MSMs whose bucket and bit sums meet equal or opposite points, and
+MSMs of several sizes and scalar distributions against the closed form
+[sum_i s_i tau^i]_2, including points at infinity.
 """
 import numpy as np
 import pytest
@@ -89,6 +90,23 @@ def test_g2_msm_edge_scalars(zk, srs):
         out = zk.msm_g2_srs(h, zk.to_device(ints_to_limbs(e).reshape(-1, 8)))
         assert _g2_from_host(_host(zk, out))[0] == og2.mul(scal[i], bases[i])
     h.close()
+
+
+def test_g2_msm_equal_and_opposite_sums(zk):
+    # sums that meet equal or opposite points in the bucket, bit-slice and
+    # final trees: the doubling and cancellation paths of their additions
+    P = og2.gen_mul(limbs_to_ints(gen.uniform_fr(9710, 1, tag=1))[0])
+    cases = [
+        ("every bucket holds P", [P] * 128, list(range(1, 129)), og2.mul(128 * 129 // 2, P)),
+        ("two equal partials in a bucket", [P] * 64, [1] * 64, og2.mul(64, P)),
+        ("two opposite partials in a bucket", [P] * 32 + [og2.neg(og2.mul(32, P))], [1] * 33, None),
+    ]
+    for name, bases, scal, want in cases:
+        log("g2 msm: " + name)
+        h = zk.SRSG2(zk.to_device(_g2_to_host(bases)))
+        out = zk.msm_g2_srs(h, zk.to_device(ints_to_limbs(scal).reshape(-1, 8)))
+        assert _g2_from_host(_host(zk, out))[0] == want, name
+        h.close()
 
 
 @pytest.mark.parametrize("n,kind", [(0, "uniform"), (1, "uniform"), (5, "uniform"), (300, "uniform"),
