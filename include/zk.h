@@ -34,6 +34,10 @@
  *    freed by a call is reused by later calls (on another stream only after
  *    that stream waits on the block's last use); hipMalloc runs only when no
  *    cached block fits.  zk_release_cached_memory() returns the cache.
+ *  - The first call on a device builds that device's constant tables (NTT
+ *    twiddles, including per-size four-step twiddle tables, about 0.65 GB,
+ *    and the SRS generator table), held until the process ends; they are
+ *    outside the scratch cache and its budget.
  *  - Return: ZK_OK, or a negative code with a message in zk_last_error().
  *    Argument errors are detected before anything is enqueued.  A failed
  *    launch or allocation returns ZK_EDEVICE / ZK_ENOMEM; nothing aborts.
