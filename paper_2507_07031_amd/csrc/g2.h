@@ -71,6 +71,32 @@ ZK_HD fp2 fp2_mul(const fp2& a, const fp2& b) {
              mont_mul2<Fq>(a.c0, b.c1, a.c1, b.c0)};
 }
 
+// a b - c d, each component one Montgomery reduction of four limb products'
+// column sums (the subtracted terms as (2q - x) operands):
+//   re: a0 b0 + (2q - a1) b1 + (2q - c0) d0 + c1 d1
+//   im: a0 b1 + a1 b0 + (2q - c0) d1 + (2q - c1) d0.
+// For components below 2q a column holds at most 36 limb products below
+// 2^58 (below 2^63.2, and below 2^64 with the reduction's terms), and each
+// sum is below 16 q^2, so a component is below 16 q^2 / 2^261 + q < 1.1q.
+ZK_HD fp2 fp2_mul_sub(const fp2& a, const fp2& b, const fp2& c, const fp2& d) {
+  const f29 na1 = sub_k(f29_zero(), a.c1, Fq::K2);
+  const f29 nc0 = sub_k(f29_zero(), c.c0, Fq::K2);
+  const f29 nc1 = sub_k(f29_zero(), c.c1, Fq::K2);
+  uint64_t re[18], im[18];
+#pragma unroll
+  for (int k = 0; k < 18; k++) re[k] = im[k] = 0;
+  mul_cols(re, a.c0, b.c0);
+  mul_cols(re, na1, b.c1);
+  mul_cols(re, nc0, d.c0);
+  mul_cols(re, c.c1, d.c1);
+  const f29 r0 = mont_reduce<Fq>(re);
+  mul_cols(im, a.c0, b.c1);
+  mul_cols(im, a.c1, b.c0);
+  mul_cols(im, nc0, d.c1);
+  mul_cols(im, nc1, d.c0);
+  return fp2{r0, mont_reduce<Fq>(im)};
+}
+
 // (a0 + a1 u)^2 = (a0 + a1)(a0 - a1) + 2 a0 a1 u
 // both factors of s below 4q, so s < 1.1q; 2 t < 2.1q.
 ZK_HD fp2 fp2_sqr(const fp2& a) {
@@ -153,7 +179,7 @@ ZK_HD g2xyzz g2_madd(const g2xyzz& a, const g2aff& p) {
   const fp2 Q = fp2_mul(a.X, PP);
   g2xyzz r;
   r.X = fp2_sub(fp2_sqr(R), fp2_add(fp2_add(PPP, Q), Q));
-  r.Y = fp2_sub(fp2_mul(R, fp2_sub(Q, r.X)), fp2_mul(a.Y, PPP));
+  r.Y = fp2_mul_sub(R, fp2_sub(Q, r.X), a.Y, PPP);
   r.ZZ = fp2_mul(a.ZZ, PP);
   r.ZZZ = fp2_mul(a.ZZZ, PPP);
   return r;

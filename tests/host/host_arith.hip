@@ -206,6 +206,12 @@ void host_fq2_op_raw(int op, const uint32_t* a, const uint32_t* b, uint32_t* out
   store_fp2_raw(r, out);
 }
 
+// a b - c d by fp2_mul_sub (same raw layout).
+void host_fq2_mul_sub_raw(const uint32_t* a, const uint32_t* b, const uint32_t* c, const uint32_t* d,
+                          uint32_t* out) {
+  store_fp2_raw(fp2_mul_sub(load_fp2_raw(a), load_fp2_raw(b), load_fp2_raw(c), load_fp2_raw(d)), out);
+}
+
 // sum of affine G2 points (32 words each, (0,0,0,0) = infinity).
 void host_g2_sum_madd(const uint32_t* pts, uint64_t n, uint32_t* out) {
   g2xyzz acc = g2_inf();

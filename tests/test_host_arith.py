@@ -326,6 +326,32 @@ def test_fq2_ops_bounds_and_values(lib):
     assert Rm != 0
 
 
+def test_fq2_mul_sub_bounds_and_values(lib):
+    """a b - c d with one reduction per component, components anywhere in
+    [0, 2q) (the worst case 2q - 1 everywhere included): results below 1.1q
+    with normalised limbs, equal to the oracle's value (times 2^261)."""
+    rng = np.random.default_rng(23)
+    Rinv = pow(MONT, -1, P)
+    edge = [0, 1, P - 1, P, 2 * P - 1]
+    for t in range(300):
+        vals = [int(rng.integers(0, 2 ** 62)) * (2 ** 192) % (2 * P) for _ in range(8)]
+        if t == 0:
+            vals = [2 * P - 1] * 8
+        elif t < 40:
+            vals = [edge[(t + k * (t % 3 + 1)) % 5] for k in range(8)]
+        ops = [(vals[2 * k], vals[2 * k + 1]) for k in range(4)]
+        plain = [((x * Rinv) % P, (y * Rinv) % P) for x, y in ops]
+        want = g2.f2_sub(g2.f2_mul(plain[0], plain[1]), g2.f2_mul(plain[2], plain[3]))
+        out = np.zeros(18, dtype=np.uint32)
+        raws = [_fp2_raw(*o) for o in ops]
+        lib.host_fq2_mul_sub_raw(*[r.ctypes.data_as(ctypes.c_void_p) for r in raws],
+                                 out.ctypes.data_as(ctypes.c_void_p))
+        r = _fp2_val(out)
+        assert r[0] < 11 * P // 10 and r[1] < 11 * P // 10, t
+        assert all(x < (1 << 29) for x in out[:8]) and all(x < (1 << 29) for x in out[9:17]), t
+        assert ((r[0] * Rinv) % P, (r[1] * Rinv) % P) == want, t
+
+
 def _g2_words(pts):
     vals = []
     for p in pts:
